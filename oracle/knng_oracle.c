@@ -1,0 +1,470 @@
+/*
+ * CPU oracle for kNN-graph construction by repeated two-means bisection.
+ *
+ * Method: Zhao, Yang, Deng, "Scalable Nearest Neighbor Search based on kNN
+ * Graph" (arXiv 1701.08475), Sec. 3.1 and Algorithm 1 ("kNNG construction").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, FP64 reference
+ * that the tests, the GPU smoke check and the benchmark's CPU-baseline leg
+ * compare against.  The GPU library never links, loads or calls it, and it
+ * shares no code, header or constant table with the GPU path.
+ *
+ * Readings of the paper that this oracle fixes (the paper leaves them open):
+ *   R1  d(x_i, x_j) is the squared Euclidean distance, summed in FP64 over the
+ *       exact FP32 inputs in increasing dimension order (Sec. 1 names l1 or
+ *       l2; Eqn 2 works with squared l2).
+ *   R2  "two means clustering" is plain Lloyd 2-means on the sum-of-squares
+ *       objective (the boost k-means objective of Sec. 3.1 is not defined in
+ *       the paper).
+ *   R3  The two starting centres are two distinct members drawn with a keyed
+ *       SplitMix64 hash of (seed, tree, smallest member id, node size, j);
+ *       the tree index in the key makes every round different (Sec. 3.1
+ *       states that the clustering differs from round to round).
+ *   R4  At most I_max assignment passes; stop when no label changes or a
+ *       side is empty.  A point equidistant from both centres goes left.
+ *   R5  A node is split iff it holds more than leaf_max points ("no bigger
+ *       than a threshold", Sec. 3.1).  A side smaller than min_leaf is
+ *       repaired by re-splitting on the rank of the margin
+ *       mu = |x-c0|^2 - |x-c1|^2 (ties by id), left size clamped to
+ *       [min_leaf, m-min_leaf]; if every margin is equal the left size is
+ *       floor(m/2).
+ *   R6  "Initialize G" is an empty list per row, (-1, +inf) padding.
+ *   R7  "if <i,j> is NOT visited" is realised as de-duplication by id when
+ *       a candidate is inserted: G[i] is the k smallest (d, id) over the
+ *       distinct co-leaf members seen in all rounds, which is exactly what
+ *       Algorithm 1's update produces (a rejected pair stays rejected since
+ *       the k-th distance of a row never grows).
+ *   R8  Rows are ordered by ascending (d, id).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+#include <float.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------ */
+/* Keyed random pair (reading R3).                                     */
+/* SplitMix64 output function (Steele, Lea, Flood, OOPSLA 2014).       */
+/* ------------------------------------------------------------------ */
+#define ORC_GAMMA 0x9e3779b97f4a7c15ULL
+
+uint64_t orc_mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+/* One SplitMix64 step from state (h xor w): absorb each key word in turn. */
+uint64_t orc_key_hash(uint64_t seed, uint64_t tree, uint64_t min_id,
+                      uint64_t size, uint64_t j)
+{
+    uint64_t words[4] = {tree, min_id, size, j};
+    uint64_t h = seed;
+    for (int i = 0; i < 4; ++i)
+        h = orc_mix64((h ^ words[i]) + ORC_GAMMA);
+    return h;
+}
+
+/* Indices a != b in [0, m) of the two starting centres (m >= 2). */
+void orc_init_pair(uint64_t seed, int tree, int min_id, int64_t m,
+                   int64_t *a_out, int64_t *b_out)
+{
+    uint64_t u0 = orc_key_hash(seed, (uint64_t)tree, (uint64_t)min_id, (uint64_t)m, 0);
+    uint64_t u1 = orc_key_hash(seed, (uint64_t)tree, (uint64_t)min_id, (uint64_t)m, 1);
+    int64_t a = (int64_t)(u0 % (uint64_t)m);
+    int64_t b = (int64_t)(u1 % (uint64_t)(m - 1));
+    if (b >= a) b += 1;
+    *a_out = a;
+    *b_out = b;
+}
+
+/* ------------------------------------------------------------------ */
+/* Distances (reading R1).                                             */
+/* ------------------------------------------------------------------ */
+double orc_d64(const float *X, int D, int64_t i, int64_t j)
+{
+    const float *xi = X + (size_t)i * D, *xj = X + (size_t)j * D;
+    double s = 0.0;
+    for (int d = 0; d < D; ++d) {
+        double t = (double)xi[d] - (double)xj[d];
+        s += t * t;
+    }
+    return s;
+}
+
+static double dist_to_centre(const float *x, const double *c, int D)
+{
+    double s = 0.0;
+    for (int d = 0; d < D; ++d) {
+        double t = (double)x[d] - c[d];
+        s += t * t;
+    }
+    return s;
+}
+
+/* (d, id) lexicographic order, ids as signed ints. */
+static int pair_less(double da, int ia, double db, int ib)
+{
+    return da < db || (da == db && ia < ib);
+}
+
+/* Keep row (ids, ds, *cnt) as the k smallest (d, id) seen so far, distinct
+ * ids only.  Plain insertion into a sorted array. */
+static void row_insert(int *ids, double *ds, int *cnt, int k, int j, double d)
+{
+    for (int p = 0; p < *cnt; ++p)
+        if (ids[p] == j) return; /* already present (reading R7) */
+    if (*cnt == k && !pair_less(d, j, ds[k - 1], ids[k - 1])) return;
+    int p = (*cnt < k) ? *cnt : k - 1; /* slot that is freed */
+    while (p > 0 && pair_less(d, j, ds[p - 1], ids[p - 1])) {
+        ids[p] = ids[p - 1];
+        ds[p] = ds[p - 1];
+        --p;
+    }
+    ids[p] = j;
+    ds[p] = d;
+    if (*cnt < k) ++*cnt;
+}
+
+/* ------------------------------------------------------------------ */
+/* Exact k nearest neighbours of selected rows (brute force, FP64).    */
+/* ids/dists are [nq, k]; padded with (-1, +inf) when n-1 < k.          */
+/* ------------------------------------------------------------------ */
+int orc_exact_knn(const float *X, int64_t n, int D, int k, const int64_t *rows,
+                  int64_t nq, int32_t *ids, double *dists)
+{
+    if (n < 1 || D < 1 || k < 1) return -1;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < nq; ++q) {
+        int64_t i = rows[q];
+        int *ri = (int *)ids + q * k;
+        double *rd = dists + q * k;
+        int cnt = 0;
+        for (int p = 0; p < k; ++p) { ri[p] = -1; rd[p] = INFINITY; }
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            row_insert(ri, rd, &cnt, k, (int)j, orc_d64(X, D, i, j));
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* One two-means bisection of a member set (Sec. 3.1; readings R2-R5). */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int64_t assign_rows;   /* sum over assignment passes of members assigned */
+    int64_t passes;        /* assignment passes */
+    int64_t splits;        /* bisections performed */
+    int64_t repairs;       /* bisections repaired by margin rank */
+} orc_stats;
+
+static void assign_pass(const float *X, int D, const int32_t *mem, int64_t m,
+                        const double *c0, const double *c1, unsigned char *lab)
+{
+    for (int64_t p = 0; p < m; ++p) {
+        const float *x = X + (size_t)mem[p] * D;
+        double d0 = dist_to_centre(x, c0, D);
+        double d1 = dist_to_centre(x, c1, D);
+        lab[p] = (d1 < d0) ? 1 : 0; /* ties go left (R4) */
+    }
+}
+
+typedef struct { double mu; int32_t id; } mu_rec;
+
+static int mu_cmp(const void *a, const void *b)
+{
+    const mu_rec *x = (const mu_rec *)a, *y = (const mu_rec *)b;
+    if (x->mu < y->mu) return -1;
+    if (x->mu > y->mu) return 1;
+    return (x->id > y->id) - (x->id < y->id);
+}
+
+/* mem: member ids in increasing order, m >= 2*min_leaf.
+ * lab: output label per member (0 = left, 1 = right).
+ * c_out (optional, 2*D): the final centres (c0 then c1).
+ * Returns the number of members labelled 0. */
+/* Same as orc_split with the starting centres given as member positions
+ * a != b (orc_split draws them with the keyed hash, reading R3). */
+int64_t orc_split_init(const float *X, int D, const int32_t *mem, int64_t m,
+                       int min_leaf, int max_iter, int64_t a, int64_t b,
+                       unsigned char *lab, double *c_out, int *repaired_out,
+                       orc_stats *st)
+{
+    double *c0 = (double *)malloc(sizeof(double) * D);
+    double *c1 = (double *)malloc(sizeof(double) * D);
+    double *s0 = (double *)malloc(sizeof(double) * D);
+    double *s1 = (double *)malloc(sizeof(double) * D);
+    unsigned char *nl = (unsigned char *)malloc((size_t)m);
+
+    for (int d = 0; d < D; ++d) {
+        c0[d] = (double)X[(size_t)mem[a] * D + d];
+        c1[d] = (double)X[(size_t)mem[b] * D + d];
+    }
+    assign_pass(X, D, mem, m, c0, c1, lab);
+    int64_t passes = 1;
+
+    for (int it = 1; it < max_iter; ++it) {
+        int64_t n1 = 0;
+        for (int64_t p = 0; p < m; ++p) n1 += lab[p];
+        if (n1 == 0 || n1 == m) break; /* one side empty: nothing to move */
+        /* centres <- means of the two sides */
+        for (int d = 0; d < D; ++d) { s0[d] = 0.0; s1[d] = 0.0; }
+        for (int64_t p = 0; p < m; ++p) {
+            const float *x = X + (size_t)mem[p] * D;
+            double *s = lab[p] ? s1 : s0;
+            for (int d = 0; d < D; ++d) s[d] += (double)x[d];
+        }
+        for (int d = 0; d < D; ++d) {
+            c0[d] = s0[d] / (double)(m - n1);
+            c1[d] = s1[d] / (double)n1;
+        }
+        assign_pass(X, D, mem, m, c0, c1, nl);
+        ++passes;
+        int changed = memcmp(nl, lab, (size_t)m) != 0;
+        memcpy(lab, nl, (size_t)m);
+        if (!changed) break; /* converged */
+    }
+
+    int64_t n0 = 0;
+    for (int64_t p = 0; p < m; ++p) n0 += (lab[p] == 0);
+    int repaired = 0;
+    if (n0 < min_leaf || m - n0 < min_leaf) {
+        /* margin-rank repair (R5) */
+        repaired = 1;
+        mu_rec *r = (mu_rec *)malloc(sizeof(mu_rec) * (size_t)m);
+        for (int64_t p = 0; p < m; ++p) {
+            const float *x = X + (size_t)mem[p] * D;
+            r[p].mu = dist_to_centre(x, c0, D) - dist_to_centre(x, c1, D);
+            r[p].id = mem[p];
+        }
+        int all_equal = 1;
+        for (int64_t p = 1; p < m; ++p)
+            if (r[p].mu != r[0].mu) { all_equal = 0; break; }
+        int64_t s;
+        if (all_equal) {
+            s = m / 2;
+        } else {
+            s = n0;
+            if (s < min_leaf) s = min_leaf;
+            if (s > m - min_leaf) s = m - min_leaf;
+        }
+        qsort(r, (size_t)m, sizeof(mu_rec), mu_cmp);
+        /* members are sorted by id, so rank -> position by binary search */
+        for (int64_t q = 0; q < m; ++q) {
+            int64_t lo = 0, hi = m - 1;
+            while (lo < hi) {
+                int64_t mid = (lo + hi) / 2;
+                if (mem[mid] < r[q].id) lo = mid + 1; else hi = mid;
+            }
+            lab[lo] = (q < s) ? 0 : 1;
+        }
+        n0 = s;
+        free(r);
+    }
+
+    if (c_out) {
+        memcpy(c_out, c0, sizeof(double) * D);
+        memcpy(c_out + D, c1, sizeof(double) * D);
+    }
+    if (repaired_out) *repaired_out = repaired;
+    if (st) {
+        st->passes += passes;
+        st->assign_rows += passes * m;
+        st->splits += 1;
+        st->repairs += repaired;
+    }
+    free(c0); free(c1); free(s0); free(s1); free(nl);
+    return n0;
+}
+
+int64_t orc_split(const float *X, int D, const int32_t *mem, int64_t m,
+                  int min_leaf, int max_iter, uint64_t seed, int tree,
+                  unsigned char *lab, double *c_out, int *repaired_out,
+                  orc_stats *st)
+{
+    int64_t a, b; /* starting centres: two distinct members (R3) */
+    orc_init_pair(seed, tree, mem[0], m, &a, &b);
+    return orc_split_init(X, D, mem, m, min_leaf, max_iter, a, b, lab, c_out,
+                          repaired_out, st);
+}
+
+/* ------------------------------------------------------------------ */
+/* One tree: recursive bisection down to leaves (Alg. 1, "apply two   */
+/* means clustering" and "collect clusters set S").                    */
+/* perm is filled in depth-first order, left child first, so that      */
+/* every node is a contiguous run of perm and every leaf too.          */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    const float *X;
+    int D, leaf_max, min_leaf, max_iter, tree;
+    uint64_t seed;
+    int32_t *perm;
+    int32_t *leaf_off;   /* leaf start positions; count in n_leaves */
+    int64_t n_leaves;
+    int32_t *nodes;      /* internal nodes: (start, size, n_left, depth) */
+    int64_t n_nodes, nodes_cap;
+    int depth_max;
+    orc_stats st;
+} tree_ctx;
+
+static void build_rec(tree_ctx *cx, int32_t *mem, int64_t m, int64_t start, int depth)
+{
+    if (depth > cx->depth_max) cx->depth_max = depth;
+    if (m <= cx->leaf_max) {
+        memcpy(cx->perm + start, mem, sizeof(int32_t) * (size_t)m);
+        cx->leaf_off[cx->n_leaves++] = (int32_t)start;
+        return;
+    }
+    unsigned char *lab = (unsigned char *)malloc((size_t)m);
+    int64_t n0 = orc_split(cx->X, cx->D, mem, m, cx->min_leaf, cx->max_iter,
+                           cx->seed, cx->tree, lab, NULL, NULL, &cx->st);
+    int32_t *left = (int32_t *)malloc(sizeof(int32_t) * (size_t)n0);
+    int32_t *right = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m - n0));
+    int64_t a = 0, b = 0;
+    for (int64_t p = 0; p < m; ++p) { /* stable: keeps ids increasing */
+        if (lab[p] == 0) left[a++] = mem[p]; else right[b++] = mem[p];
+    }
+    free(lab);
+    if (cx->nodes && cx->n_nodes < cx->nodes_cap) {
+        int32_t *r = cx->nodes + 4 * cx->n_nodes;
+        r[0] = (int32_t)start; r[1] = (int32_t)m; r[2] = (int32_t)n0; r[3] = depth;
+    }
+    cx->n_nodes++;
+    build_rec(cx, left, n0, start, depth + 1);
+    build_rec(cx, right, m - n0, start + n0, depth + 1);
+    free(left);
+    free(right);
+}
+
+/* Build tree `tree`.  perm: [n]; leaf_off: capacity n+1, receives the
+ * n_leaves+1 leaf boundaries (ascending, last = n); nodes (optional,
+ * capacity nodes_cap records of 4 ints): internal nodes in pre-order.
+ * stats (optional, 6 int64): assign_rows, passes, splits, repairs,
+ * internal node count, maximum depth.  Returns the number of leaves. */
+int64_t orc_tree(const float *X, int64_t n, int D, int leaf_max, int min_leaf,
+                 int max_iter, uint64_t seed, int tree, int32_t *perm,
+                 int32_t *leaf_off, int32_t *nodes, int64_t nodes_cap,
+                 int64_t *stats)
+{
+    tree_ctx cx;
+    memset(&cx, 0, sizeof(cx));
+    cx.X = X; cx.D = D; cx.leaf_max = leaf_max; cx.min_leaf = min_leaf;
+    cx.max_iter = max_iter; cx.tree = tree; cx.seed = seed;
+    cx.perm = perm; cx.leaf_off = leaf_off; cx.nodes = nodes; cx.nodes_cap = nodes_cap;
+    int32_t *all = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) all[i] = (int32_t)i;
+    build_rec(&cx, all, n, 0, 0);
+    free(all);
+    leaf_off[cx.n_leaves] = (int32_t)n;
+    if (stats) {
+        stats[0] = cx.st.assign_rows; stats[1] = cx.st.passes;
+        stats[2] = cx.st.splits; stats[3] = cx.st.repairs;
+        stats[4] = cx.n_nodes; stats[5] = cx.depth_max;
+    }
+    return cx.n_leaves;
+}
+
+/* ------------------------------------------------------------------ */
+/* Exhaustive comparison inside each cluster and update of G (Alg. 1,  */
+/* inner loops over S_m and <i, j>, readings R6-R8).                   */
+/* ------------------------------------------------------------------ */
+static void graph_init(int32_t *ids, double *ds, int *cnt, int64_t n, int k)
+{
+    for (int64_t i = 0; i < n * k; ++i) { ids[i] = -1; ds[i] = INFINITY; }
+    memset(cnt, 0, sizeof(int) * (size_t)n);
+}
+
+/* Every unordered pair of a leaf updates both rows.  Leaves of one tree are
+ * disjoint, so distinct leaves touch distinct rows. */
+static void graph_update_tree(const float *X, int D, int k, const int32_t *perm,
+                              const int32_t *leaf_off, int64_t n_leaves,
+                              int32_t *ids, double *ds, int *cnt)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t l = 0; l < n_leaves; ++l) {
+        int64_t s = leaf_off[l], e = leaf_off[l + 1];
+        for (int64_t p = s; p < e; ++p) {
+            for (int64_t q = p + 1; q < e; ++q) {
+                int i = perm[p], j = perm[q];
+                double d = orc_d64(X, D, i, j);
+                row_insert(ids + (size_t)i * k, ds + (size_t)i * k, cnt + i, k, j, d);
+                row_insert(ids + (size_t)j * k, ds + (size_t)j * k, cnt + j, k, i, d);
+            }
+        }
+    }
+}
+
+/* Graph from given leaves.  perm: [n_trees, n]; leaf_off: the per-tree
+ * boundary arrays concatenated (n_leaves[t] + 1 entries each). */
+int orc_graph_from_leaves(const float *X, int64_t n, int D, int k, int n_trees,
+                          const int32_t *perm, const int32_t *leaf_off,
+                          const int64_t *n_leaves, int32_t *ids, double *ds)
+{
+    int *cnt = (int *)malloc(sizeof(int) * (size_t)n);
+    if (!cnt) return -1;
+    graph_init(ids, ds, cnt, n, k);
+    int64_t off = 0;
+    for (int t = 0; t < n_trees; ++t) {
+        graph_update_tree(X, D, k, perm + (size_t)t * n, leaf_off + off,
+                          n_leaves[t], ids, ds, cnt);
+        off += n_leaves[t] + 1;
+    }
+    free(cnt);
+    return 0;
+}
+
+/* Full Algorithm 1: n_trees rounds of bisection + leaf comparison.
+ * stats (optional, 6 int64): summed tree stats (max for depth). */
+int orc_graph(const float *X, int64_t n, int D, int k, int n_trees, int leaf_max,
+              int min_leaf, int max_iter, uint64_t seed, int32_t *ids, double *ds,
+              int64_t *stats)
+{
+    int32_t *perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * n_trees);
+    int32_t *loff = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1) * n_trees);
+    int64_t *nl = (int64_t *)malloc(sizeof(int64_t) * n_trees);
+    int64_t *st = (int64_t *)calloc((size_t)6 * n_trees, sizeof(int64_t));
+    int *cnt = (int *)malloc(sizeof(int) * (size_t)n);
+    if (!perm || !loff || !nl || !st || !cnt) return -1;
+    /* the rounds' partitions are independent of each other */
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int t = 0; t < n_trees; ++t)
+        nl[t] = orc_tree(X, n, D, leaf_max, min_leaf, max_iter, seed, t,
+                         perm + (size_t)t * n, loff + (size_t)t * (n + 1),
+                         NULL, 0, st + 6 * t);
+    graph_init(ids, ds, cnt, n, k);
+    for (int t = 0; t < n_trees; ++t)
+        graph_update_tree(X, D, k, perm + (size_t)t * n, loff + (size_t)t * (n + 1),
+                          nl[t], ids, ds, cnt);
+    if (stats) {
+        for (int c = 0; c < 6; ++c) stats[c] = 0;
+        for (int t = 0; t < n_trees; ++t) {
+            for (int c = 0; c < 5; ++c) stats[c] += st[6 * t + c];
+            if (st[6 * t + 5] > stats[5]) stats[5] = st[6 * t + 5];
+        }
+    }
+    free(perm); free(loff); free(nl); free(st); free(cnt);
+    return 0;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_num_threads(int t)
+{
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}

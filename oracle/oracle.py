@@ -1,0 +1,228 @@
+"""ctypes front end of the CPU oracle (``knng_oracle.c``).
+
+Test infrastructure only: the tests, the GPU smoke check and the benchmark's
+CPU-baseline leg use it.  It follows the paper's Sec. 3.1 / Algorithm 1 with
+the readings listed at the top of ``knng_oracle.c``; nothing here imports the
+GPU package.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "knng_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+GCC_FLAGS = ["-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+             "-Wall", "-Wextra", "-Wno-unused-parameter"]
+
+
+def build(force=False):
+    """Compile the oracle with gcc (plain C11, OpenMP)."""
+    if not force and os.path.exists(_LIB_PATH) and \
+            os.path.getmtime(_LIB_PATH) >= os.path.getmtime(_SRC):
+        return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", *GCC_FLAGS, _SRC, "-o", tmp, "-lm"])
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        i64, i32, u64, vp = ctypes.c_int64, ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p
+        L.orc_mix64.restype = u64
+        L.orc_mix64.argtypes = [u64]
+        L.orc_key_hash.restype = u64
+        L.orc_key_hash.argtypes = [u64, u64, u64, u64, u64]
+        L.orc_init_pair.restype = None
+        L.orc_init_pair.argtypes = [u64, i32, i32, i64, vp, vp]
+        L.orc_d64.restype = ctypes.c_double
+        L.orc_d64.argtypes = [vp, i32, i64, i64]
+        L.orc_exact_knn.restype = i32
+        L.orc_exact_knn.argtypes = [vp, i64, i32, i32, vp, i64, vp, vp]
+        L.orc_split.restype = i64
+        L.orc_split.argtypes = [vp, i32, vp, i64, i32, i32, u64, i32, vp, vp, vp, vp]
+        L.orc_split_init.restype = i64
+        L.orc_split_init.argtypes = [vp, i32, vp, i64, i32, i32, i64, i64, vp, vp, vp, vp]
+        L.orc_tree.restype = i64
+        L.orc_tree.argtypes = [vp, i64, i32, i32, i32, i32, u64, i32, vp, vp, vp, i64, vp]
+        L.orc_graph_from_leaves.restype = i32
+        L.orc_graph_from_leaves.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp, vp, vp]
+        L.orc_graph.restype = i32
+        L.orc_graph.argtypes = [vp, i64, i32, i32, i32, i32, i32, i32, u64, vp, vp, vp]
+        L.orc_num_threads.restype = i32
+        L.orc_set_num_threads.restype = None
+        L.orc_set_num_threads.argtypes = [i32]
+        _lib = L
+    return _lib
+
+
+def _f32(X):
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    assert X.ndim == 2
+    return X
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def num_threads():
+    return lib().orc_num_threads()
+
+
+def set_num_threads(t):
+    lib().orc_set_num_threads(int(t))
+
+
+def mix64(z):
+    return lib().orc_mix64(ctypes.c_uint64(z & 0xFFFFFFFFFFFFFFFF))
+
+
+def key_hash(seed, tree, min_id, size, j):
+    return lib().orc_key_hash(seed, tree, min_id, size, j)
+
+
+def init_pair(seed, tree, min_id, m):
+    a = np.zeros(1, np.int64)
+    b = np.zeros(1, np.int64)
+    lib().orc_init_pair(seed, tree, min_id, m, _p(a), _p(b))
+    return int(a[0]), int(b[0])
+
+
+def d64(X, i, j):
+    X = _f32(X)
+    return lib().orc_d64(_p(X), X.shape[1], int(i), int(j))
+
+
+def exact_knn(X, k, rows=None):
+    """Exact k nearest neighbours (FP64, ties by id) of `rows` (default all)."""
+    X = _f32(X)
+    n, D = X.shape
+    rows = np.arange(n, dtype=np.int64) if rows is None else np.ascontiguousarray(rows, np.int64)
+    ids = np.empty((len(rows), k), np.int32)
+    ds = np.empty((len(rows), k), np.float64)
+    rc = lib().orc_exact_knn(_p(X), n, D, k, _p(rows), len(rows), _p(ids), _p(ds))
+    assert rc == 0
+    return ids, ds
+
+
+def split(X, members, min_leaf, max_iter, seed, tree):
+    """One bisection of `members` (ascending ids).  Returns (labels, n_left,
+    centres[2, D], repaired)."""
+    X = _f32(X)
+    mem = np.ascontiguousarray(members, np.int32)
+    m = len(mem)
+    assert m >= 2 * min_leaf and np.all(np.diff(mem) > 0)
+    lab = np.empty(m, np.uint8)
+    c = np.empty((2, X.shape[1]), np.float64)
+    rep = ctypes.c_int(0)
+    n0 = lib().orc_split(_p(X), X.shape[1], _p(mem), m, min_leaf, max_iter, seed, tree,
+                         _p(lab), _p(c), ctypes.byref(rep), None)
+    return lab, int(n0), c, bool(rep.value)
+
+
+def split_init(X, members, min_leaf, max_iter, a, b):
+    """One bisection with the starting centres given as member positions
+    a != b.  Returns (labels, n_left, centres[2, D], repaired, passes)."""
+    X = _f32(X)
+    mem = np.ascontiguousarray(members, np.int32)
+    m = len(mem)
+    lab = np.empty(m, np.uint8)
+    c = np.empty((2, X.shape[1]), np.float64)
+    rep = ctypes.c_int(0)
+    st = np.zeros(4, np.int64)
+    n0 = lib().orc_split_init(_p(X), X.shape[1], _p(mem), m, min_leaf, max_iter, a, b,
+                              _p(lab), _p(c), ctypes.byref(rep), _p(st))
+    return lab, int(n0), c, bool(rep.value), int(st[1])
+
+
+def tree(X, leaf_max, min_leaf, max_iter, seed, t, with_nodes=False):
+    """One tree.  Returns dict(perm, leaf_off, nodes, stats)."""
+    X = _f32(X)
+    n, D = X.shape
+    perm = np.empty(n, np.int32)
+    loff = np.empty(n + 1, np.int32)
+    cap = n if with_nodes else 0
+    nodes = np.empty((max(cap, 1), 4), np.int32)
+    st = np.zeros(6, np.int64)
+    nl = lib().orc_tree(_p(X), n, D, leaf_max, min_leaf, max_iter, seed, t, _p(perm),
+                        _p(loff), _p(nodes) if with_nodes else None, cap, _p(st))
+    out = dict(perm=perm, leaf_off=loff[: nl + 1].copy(),
+               stats=dict(assign_rows=int(st[0]), passes=int(st[1]), splits=int(st[2]),
+                          repairs=int(st[3]), internal_nodes=int(st[4]), depth=int(st[5])))
+    if with_nodes:
+        out["nodes"] = nodes[: st[4]].copy()
+    return out
+
+
+def graph_from_leaves(X, k, perms, leaf_offs):
+    """G from given leaves: perms [T, n]; leaf_offs list of T boundary arrays."""
+    X = _f32(X)
+    n, D = X.shape
+    perms = np.ascontiguousarray(perms, np.int32).reshape(-1, n)
+    T = perms.shape[0]
+    assert len(leaf_offs) == T
+    cat = np.ascontiguousarray(np.concatenate([np.asarray(o, np.int32) for o in leaf_offs]))
+    nl = np.array([len(o) - 1 for o in leaf_offs], np.int64)
+    ids = np.empty((n, k), np.int32)
+    ds = np.empty((n, k), np.float64)
+    rc = lib().orc_graph_from_leaves(_p(X), n, D, k, T, _p(perms), _p(cat), _p(nl),
+                                     _p(ids), _p(ds))
+    assert rc == 0
+    return ids, ds
+
+
+def graph(X, k, n_trees, leaf_max, seed, min_leaf=None, max_iter=10):
+    """Algorithm 1 end to end.  Returns (ids [n,k] int32, dists [n,k] f64, stats)."""
+    X = _f32(X)
+    n, D = X.shape
+    ml = k + 1 if min_leaf is None else min_leaf
+    ids = np.empty((n, k), np.int32)
+    ds = np.empty((n, k), np.float64)
+    st = np.zeros(6, np.int64)
+    rc = lib().orc_graph(_p(X), n, D, k, n_trees, leaf_max, ml, max_iter, seed,
+                         _p(ids), _p(ds), _p(st))
+    assert rc == 0
+    return ids, ds, dict(assign_rows=int(st[0]), passes=int(st[1]), splits=int(st[2]),
+                         repairs=int(st[3]), internal_nodes=int(st[4]), depth=int(st[5]))
+
+
+def pair_d64(X, rows, cols):
+    """FP64 squared distances d(rows[q], cols[q, p]) (numpy, direct form)."""
+    X = _f32(X)
+    rows = np.asarray(rows, np.int64)
+    cols = np.asarray(cols, np.int64)
+    out = np.full(cols.shape, np.inf)
+    for q, i in enumerate(rows):
+        c = cols[q]
+        ok = c >= 0
+        diff = X[c[ok]].astype(np.float64) - X[i].astype(np.float64)
+        out[q, ok] = np.einsum("pd,pd->p", diff, diff)
+    return out
+
+
+def recall(X, rows, G_ids, E_ids, E_d):
+    """Tie-tolerant recall@k of graph rows G_ids[q] (for point rows[q]) against
+    exact lists (E_ids, E_d): an id counts when it is in the exact list or no
+    farther than the exact k-th neighbour."""
+    G_ids = np.asarray(G_ids)
+    k = E_ids.shape[1]
+    dG = pair_d64(X, rows, G_ids)
+    hits = 0
+    for q in range(len(rows)):
+        ex = set(E_ids[q].tolist())
+        kth = E_d[q, k - 1]
+        for p in range(k):
+            j = int(G_ids[q, p])
+            if j >= 0 and (j in ex or dG[q, p] <= kth):
+                hits += 1
+    return hits / float(len(rows) * k)
