@@ -1,0 +1,163 @@
+/*
+ * knng.h -- C ABI of libknng.so: kNN-graph construction by repeated two-means
+ * bisection on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Zhao, Yang, Deng, "Scalable Nearest Neighbor Search based on kNN
+ * Graph" (arXiv 1701.08475), Sec. 3.1 and Algorithm 1.  Input X (n x D) and
+ * k; output the kNN graph G (n x k).  Each of n_trees rounds bisects X with
+ * two-means clustering until every cluster holds at most leaf_max points,
+ * compares every pair inside each cluster, and updates both rows' k-lists.
+ *
+ * Conventions shared by every entry point
+ *   - Pointers documented as "device" are HIP device pointers owned by the
+ *     caller, row-major and contiguous, 16-byte aligned.  Pointers documented
+ *     as "host" are ordinary host memory.
+ *   - All work is ordered on `stream`; each call returns after that work has
+ *     completed (it synchronises the stream).  Scratch memory is taken with
+ *     hipMallocAsync on `stream` and freed before return.
+ *   - Return value: KNNG_OK (0) or a negative status below.  On an argument
+ *     error (KNNG_ERR_INVALID_ARG, KNNG_ERR_UNSUPPORTED) nothing is launched
+ *     and no output is written.  On KNNG_ERR_NONFINITE the outputs are not
+ *     written.  On KNNG_ERR_OOM / KNNG_ERR_HIP output contents are
+ *     unspecified.  knng_last_error() gives a message for the calling thread.
+ *   - Distances are squared Euclidean distances in FP32.  Every reported
+ *     distance is the canonical FP32 value d32(i, j): the sum over 32-wide
+ *     blocks of dimensions, in increasing order, of the in-block sequential
+ *     fused sum of (x_i[d] - x_j[d])^2.  d32(i, j) == d32(j, i) bitwise.
+ *   - Rows of G are ordered by ascending (distance, id); ids are distinct and
+ *     never the row itself; a row with fewer than k candidates is padded
+ *     with (id -1, distance +inf) -- this cannot happen when min_leaf >= k+1.
+ *   - Deterministic: equal inputs give bit-identical outputs.
+ */
+#ifndef KNNG_H
+#define KNNG_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define KNNG_OK                0
+#define KNNG_ERR_INVALID_ARG  -1  /* a precondition on an argument failed      */
+#define KNNG_ERR_UNSUPPORTED  -2  /* valid request this build cannot serve     */
+#define KNNG_ERR_OOM          -3  /* device memory allocation failed           */
+#define KNNG_ERR_HIP          -4  /* a HIP runtime call or launch failed       */
+#define KNNG_ERR_NONFINITE    -5  /* the input holds NaN or Inf                */
+
+/* leaf distance precision (first pass; output distances are always d32) */
+#define KNNG_FP32      0
+#define KNNG_BF16      1
+#define KNNG_FP16      2
+#define KNNG_FP8_E4M3  3
+
+typedef struct {
+    int32_t struct_size;    /* sizeof(knng_options); set by knng_default_options */
+    int32_t precision;      /* KNNG_FP32 (default) | KNNG_BF16 | KNNG_FP16 | KNNG_FP8_E4M3 */
+    int32_t rerank_factor;  /* reduced precision keeps rerank_factor*k candidates per
+                               row and leaf for the FP32 re-rank; default 2 */
+    int32_t min_leaf;       /* smallest side of a bisection; 0 -> k+1 (default) */
+    int32_t max_iter;       /* two-means assignment-pass budget; 0 -> 10 */
+    int32_t plain;          /* 1: unbatched schedule (trees one after another, one
+                               leaf launch per tree); 0: batched (default) */
+    int32_t check_finite;   /* 1 (default): reject NaN/Inf input */
+    int32_t reserved;
+} knng_options;
+
+typedef struct {
+    int64_t assign_rows;    /* sum over all assignment passes of rows assigned */
+    int64_t ordered_pairs;  /* sum over trees and leaves of m*(m-1) */
+    int64_t leaves;         /* leaves over all trees */
+    int64_t splits;         /* bisections over all trees */
+    int64_t repairs;        /* bisections repaired by margin rank */
+    int32_t levels;         /* deepest level + 1 */
+    int32_t launches;       /* kernel launches issued */
+    float ms_prep, ms_partition, ms_leaf, ms_merge, ms_total;  /* stream time */
+} knng_stats;
+
+/* Fill *opt with the defaults listed above. */
+void knng_default_options(knng_options* opt);
+
+/*
+ * knng_build -- Algorithm 1 (Sec. 3.1) end to end, FP32, batched schedule.
+ * Same as knng_build_ex(..., opt = NULL, stats = NULL, stream).
+ *   data       device, float[n][D], the reference set X
+ *   n          number of points, 2 <= n <= 2^31-1
+ *   D          dimension, 1 <= D <= 4096
+ *   k          neighbours per row, 1 <= k <= min(n-1, 512)
+ *   n_trees    rounds of bisection (the paper's I_0), >= 1
+ *   leaf_max   clusters hold at most leaf_max points (the paper's threshold);
+ *              leaf_max >= 2*min_leaf - 1 and leaf_max <= 512
+ *   seed       keys the random starting centres of every two-means split
+ *   ids_out    device, int32[n][k]
+ *   dists_out  device, float[n][k]
+ */
+int knng_build(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_trees,
+               int32_t leaf_max, uint64_t seed, int32_t* ids_out, float* dists_out,
+               hipStream_t stream);
+
+/*
+ * knng_build_ex -- as knng_build with options (NULL = defaults) and optional
+ * host statistics (NULL = none).
+ */
+int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_trees,
+                  int32_t leaf_max, uint64_t seed, int32_t* ids_out, float* dists_out,
+                  const knng_options* opt, knng_stats* stats_out, hipStream_t stream);
+
+/*
+ * knng_partition -- one round's clustering (Sec. 3.1: bisect repeatedly with
+ * two-means until no cluster exceeds leaf_max; Alg. 1 "apply two means
+ * clustering" and "collect clusters set S") for tree index `tree`, exactly as
+ * knng_build runs it.
+ *   perm_out          device, int32[n]: the points in depth-first leaf order
+ *                     (left child first); every cluster is a contiguous run
+ *                     and lists its ids in ascending order
+ *   leaf_offsets_out  device, int32[n+1] capacity: receives n_leaves+1
+ *                     ascending run boundaries, first 0, last n
+ *   n_leaves_out      host, receives the number of leaves
+ *   nodes_out         device, nullable, int32[n][4] capacity: every bisected
+ *                     node as (start, size, left_size, depth), start/size a
+ *                     run of perm_out; ordered by depth, then start
+ *   n_nodes_out       host, nullable, receives the number of bisected nodes
+ *   min_leaf          0 -> k+1 is not known here, so 0 means 1
+ *   max_iter          0 -> 10
+ */
+int knng_partition(const float* data, int64_t n, int32_t D, int32_t leaf_max,
+                   int32_t min_leaf, int32_t max_iter, uint64_t seed, int32_t tree,
+                   int32_t* perm_out, int32_t* leaf_offsets_out, int32_t* n_leaves_out,
+                   int32_t* nodes_out, int32_t* n_nodes_out, hipStream_t stream);
+
+/*
+ * knng_leaf_search -- Alg. 1's inner loops for given clusters: compare every
+ * pair <i, j>, i != j, inside each cluster of each tree and keep, per row, the
+ * k smallest distinct (d32, id) over all trees.
+ *   perm          device, int32[n_trees][n]: per tree, a permutation of
+ *                 0..n-1 in which every cluster is a contiguous run
+ *   leaf_offsets  device, int32: per tree n_leaves[t]+1 ascending boundaries
+ *                 into that tree's perm (first 0, last n), trees concatenated
+ *   n_leaves      host, int32[n_trees]; every cluster size <= 512
+ *   opt           nullable; precision and rerank_factor are used
+ * Malformed offsets or perm entries outside [0, n) give KNNG_ERR_INVALID_ARG
+ * before any output is written.
+ */
+int knng_leaf_search(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_trees,
+                     const int32_t* perm, const int32_t* leaf_offsets,
+                     const int32_t* n_leaves, const knng_options* opt,
+                     int32_t* ids_out, float* dists_out, hipStream_t stream);
+
+/* Static description of a status code. */
+const char* knng_status_string(int status);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* knng_last_error(void);
+
+/* ABI version of this library (major*100 + minor). */
+int knng_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KNNG_H */

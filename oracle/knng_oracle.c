@@ -468,3 +468,46 @@ void orc_set_num_threads(int t)
     (void)t;
 #endif
 }
+
+/* Rows `rows[q]` of the graph from given leaves (same result as
+ * orc_graph_from_leaves restricted to those rows).  Used where n is too large
+ * for the full graph.  perm / leaf_off / n_leaves as in orc_graph_from_leaves. */
+int orc_rows_from_leaves(const float *X, int64_t n, int D, int k, int n_trees,
+                         const int32_t *perm, const int32_t *leaf_off,
+                         const int64_t *n_leaves, const int64_t *rows, int64_t nq,
+                         int32_t *ids, double *ds)
+{
+    int32_t *inv = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * n_trees);
+    const int32_t **offs = (const int32_t **)malloc(sizeof(int32_t *) * n_trees);
+    if (!inv || !offs) return -1;
+    int64_t o = 0;
+    for (int t = 0; t < n_trees; ++t) {
+        for (int64_t p = 0; p < n; ++p) inv[(size_t)t * n + perm[(size_t)t * n + p]] = (int32_t)p;
+        offs[t] = leaf_off + o;
+        o += n_leaves[t] + 1;
+    }
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t q = 0; q < nq; ++q) {
+        int64_t i = rows[q];
+        int32_t *ri = ids + q * k;
+        double *rd = ds + q * k;
+        int cnt = 0;
+        for (int p = 0; p < k; ++p) { ri[p] = -1; rd[p] = INFINITY; }
+        for (int t = 0; t < n_trees; ++t) {
+            int64_t pos = inv[(size_t)t * n + i];
+            /* leaf l with offs[l] <= pos < offs[l+1] */
+            int64_t lo = 0, hi = n_leaves[t] - 1;
+            while (lo < hi) {
+                int64_t mid = (lo + hi + 1) / 2;
+                if (offs[t][mid] <= pos) lo = mid; else hi = mid - 1;
+            }
+            for (int64_t p = offs[t][lo]; p < offs[t][lo + 1]; ++p) {
+                int32_t j = perm[(size_t)t * n + p];
+                if (j != i) row_insert(ri, rd, &cnt, k, j, orc_d64(X, D, i, j));
+            }
+        }
+    }
+    free(inv);
+    free(offs);
+    return 0;
+}

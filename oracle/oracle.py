@@ -56,6 +56,8 @@ def lib():
         L.orc_tree.argtypes = [vp, i64, i32, i32, i32, i32, u64, i32, vp, vp, vp, i64, vp]
         L.orc_graph_from_leaves.restype = i32
         L.orc_graph_from_leaves.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp, vp, vp]
+        L.orc_rows_from_leaves.restype = i32
+        L.orc_rows_from_leaves.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp, vp, i64, vp, vp]
         L.orc_graph.restype = i32
         L.orc_graph.argtypes = [vp, i64, i32, i32, i32, i32, i32, i32, u64, vp, vp, vp]
         L.orc_num_threads.restype = i32
@@ -177,6 +179,23 @@ def graph_from_leaves(X, k, perms, leaf_offs):
     ds = np.empty((n, k), np.float64)
     rc = lib().orc_graph_from_leaves(_p(X), n, D, k, T, _p(perms), _p(cat), _p(nl),
                                      _p(ids), _p(ds))
+    assert rc == 0
+    return ids, ds
+
+
+def rows_from_leaves(X, k, perms, leaf_offs, rows):
+    """Rows `rows` of graph_from_leaves(X, k, perms, leaf_offs)."""
+    X = _f32(X)
+    n, D = X.shape
+    perms = np.ascontiguousarray(perms, np.int32).reshape(-1, n)
+    T = perms.shape[0]
+    cat = np.ascontiguousarray(np.concatenate([np.asarray(o, np.int32) for o in leaf_offs]))
+    nl = np.array([len(o) - 1 for o in leaf_offs], np.int64)
+    rows = np.ascontiguousarray(rows, np.int64)
+    ids = np.empty((len(rows), k), np.int32)
+    ds = np.empty((len(rows), k), np.float64)
+    rc = lib().orc_rows_from_leaves(_p(X), n, D, k, T, _p(perms), _p(cat), _p(nl), _p(rows),
+                                    len(rows), _p(ids), _p(ds))
     assert rc == 0
     return ids, ds
 

@@ -1,0 +1,573 @@
+// C ABI of libknng (declared in include/knng.h): argument checks, stream-
+// ordered workspace, and the order of the stages of Algorithm 1 (Sec. 3.1):
+// partition every tree (two-means bisection down to leaves), compare all
+// pairs inside every leaf, union the rounds' candidate lists into G.
+#include "knng.h"
+#include "knng_internal.hpp"
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int set_err(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+struct Resolved {
+    int precision = KNNG_FP32;
+    int rerank = 2;
+    int min_leaf = 0;
+    int max_iter = 10;
+    int plain = 0;
+    int check_finite = 1;
+};
+
+int resolve(const knng_options* opt, int k, Resolved* r) {
+    if (opt != nullptr) {
+        if (opt->struct_size != static_cast<int32_t>(sizeof(knng_options)))
+            return set_err(KNNG_ERR_INVALID_ARG, "knng_options.struct_size is %d, expected %d",
+                           opt->struct_size, static_cast<int>(sizeof(knng_options)));
+        r->precision = opt->precision;
+        r->rerank = opt->rerank_factor;
+        r->min_leaf = opt->min_leaf;
+        r->max_iter = opt->max_iter;
+        r->plain = opt->plain;
+        r->check_finite = opt->check_finite;
+    }
+    if (r->min_leaf == 0) r->min_leaf = k + 1;
+    if (r->max_iter == 0) r->max_iter = 10;
+    if (r->precision < KNNG_FP32 || r->precision > KNNG_FP8_E4M3)
+        return set_err(KNNG_ERR_INVALID_ARG, "unknown precision %d", r->precision);
+    if (r->rerank < 1) return set_err(KNNG_ERR_INVALID_ARG, "rerank_factor must be >= 1");
+    if (r->min_leaf < 1) return set_err(KNNG_ERR_INVALID_ARG, "min_leaf must be >= 1");
+    if (r->max_iter < 1) return set_err(KNNG_ERR_INVALID_ARG, "max_iter must be >= 1");
+    return KNNG_OK;
+}
+
+int check_common(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_trees,
+                 const int32_t* ids_out, const float* dists_out) {
+    if (data == nullptr || ids_out == nullptr || dists_out == nullptr)
+        return set_err(KNNG_ERR_INVALID_ARG, "null pointer argument");
+    if (!aligned16(data) || !aligned16(ids_out) || !aligned16(dists_out))
+        return set_err(KNNG_ERR_INVALID_ARG, "pointers must be 16-byte aligned");
+    if (n < 2 || n > 2147483647LL) return set_err(KNNG_ERR_INVALID_ARG, "n=%lld out of [2, 2^31-1]",
+                                                  static_cast<long long>(n));
+    if (D < 1) return set_err(KNNG_ERR_INVALID_ARG, "D=%d must be >= 1", D);
+    if (D > knng::kMaxDim || (D % 4 != 0 && D > 1024))
+        return set_err(KNNG_ERR_UNSUPPORTED, "D=%d not supported (D <= 4096, or <= 1024 if D %% 4 != 0)", D);
+    if (k < 1 || k > n - 1) return set_err(KNNG_ERR_INVALID_ARG, "k=%d out of [1, n-1]", k);
+    if (k > 512) return set_err(KNNG_ERR_UNSUPPORTED, "k=%d exceeds 512", k);
+    if (n_trees < 1) return set_err(KNNG_ERR_INVALID_ARG, "n_trees=%d must be >= 1", n_trees);
+    return KNNG_OK;
+}
+
+struct Events {
+    hipEvent_t e[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    bool ok = false;
+    explicit Events(bool want) {
+        if (!want) return;
+        ok = true;
+        for (auto& x : e)
+            if (hipEventCreate(&x) != hipSuccess) ok = false;
+    }
+    void record(int i, hipStream_t s) {
+        if (ok) hipEventRecord(e[i], s);
+    }
+    float ms(int a, int b) {
+        float t = 0.f;
+        if (ok && hipEventElapsedTime(&t, e[a], e[b]) == hipSuccess) return t;
+        return 0.f;
+    }
+    ~Events() {
+        for (auto& x : e)
+            if (x) hipEventDestroy(x);
+    }
+};
+
+int hip_fail(hipError_t e, const char* what) {
+    return set_err(e == hipErrorOutOfMemory ? KNNG_ERR_OOM : KNNG_ERR_HIP, "%s: %s", what,
+                   hipGetErrorString(e));
+}
+
+int check_finite(const float* data, int64_t count, hipStream_t s) {
+    int32_t* flag = nullptr;
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&flag), sizeof(int32_t), s);
+    if (e != hipSuccess) return hip_fail(e, "hipMallocAsync");
+    int rc = knng::prep_check_finite(data, count, flag, s);
+    int32_t h = 0;
+    if (rc == KNNG_OK) {
+        e = hipMemcpyAsync(&h, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) rc = hip_fail(e, "finite check");
+    } else {
+        rc = set_err(KNNG_ERR_HIP, "finite-check launch failed");
+    }
+    hipFreeAsync(flag, s);
+    if (rc == KNNG_OK && h) rc = set_err(KNNG_ERR_NONFINITE, "input holds NaN or Inf");
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+void knng_default_options(knng_options* o) {
+    if (o == nullptr) return;
+    std::memset(o, 0, sizeof(*o));
+    o->struct_size = static_cast<int32_t>(sizeof(knng_options));
+    o->precision = KNNG_FP32;
+    o->rerank_factor = 2;
+    o->min_leaf = 0;
+    o->max_iter = 10;
+    o->plain = 0;
+    o->check_finite = 1;
+}
+
+const char* knng_status_string(int status) {
+    switch (status) {
+        case KNNG_OK: return "ok";
+        case KNNG_ERR_INVALID_ARG: return "invalid argument";
+        case KNNG_ERR_UNSUPPORTED: return "unsupported";
+        case KNNG_ERR_OOM: return "out of device memory";
+        case KNNG_ERR_HIP: return "HIP error";
+        case KNNG_ERR_NONFINITE: return "non-finite input";
+        default: return "unknown status";
+    }
+}
+
+const char* knng_last_error(void) { return g_err; }
+
+int knng_version(void) { return 100; }
+
+int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_trees,
+                  int32_t leaf_max, uint64_t seed, int32_t* ids_out, float* dists_out,
+                  const knng_options* opt, knng_stats* stats_out, hipStream_t stream) {
+    g_err[0] = '\0';
+    int rc = check_common(data, n, D, k, n_trees, ids_out, dists_out);
+    if (rc != KNNG_OK) return rc;
+    Resolved o;
+    rc = resolve(opt, k, &o);
+    if (rc != KNNG_OK) return rc;
+    if (leaf_max < 2 * o.min_leaf - 1)
+        return set_err(KNNG_ERR_INVALID_ARG, "leaf_max=%d < 2*min_leaf-1=%d", leaf_max,
+                       2 * o.min_leaf - 1);
+    if (leaf_max > knng::kMaxLeaf)
+        return set_err(KNNG_ERR_UNSUPPORTED, "leaf_max=%d exceeds %d", leaf_max, knng::kMaxLeaf);
+    if (o.precision != KNNG_FP32)
+        return set_err(KNNG_ERR_UNSUPPORTED, "precision %d not available in this build", o.precision);
+
+    hipStream_t s = stream;
+    Events ev(stats_out != nullptr);
+    ev.record(0, s);
+    if (o.check_finite) {
+        rc = check_finite(data, n * static_cast<int64_t>(D), s);
+        if (rc != KNNG_OK) return rc;
+    }
+    ev.record(1, s);
+
+    const int T = n_trees;
+    const int slots = o.plain ? 1 : T;  // trees partitioned per call
+    const int64_t lcap = static_cast<int64_t>(slots) * knng::max_leaves_per_tree(n, o.min_leaf);
+    int32_t* perm = nullptr;
+    knng::LeafRec* leaves = nullptr;
+    int32_t* cand_ids = nullptr;
+    float* cand_d = nullptr;
+    const bool direct = (T == 1);  // one tree: its candidate lists are G
+    char err[400] = "";
+    int launches = 0;
+    knng::PartitionResult pres;
+    int64_t pairs = 0;
+    int64_t n_leaves_total = 0;
+    hipError_t e;
+    std::vector<knng::LeafRec> hl;
+
+    e = hipMallocAsync(reinterpret_cast<void**>(&perm), sizeof(int32_t) * slots * n, s);
+    if (e == hipSuccess)
+        e = hipMallocAsync(reinterpret_cast<void**>(&leaves), sizeof(knng::LeafRec) * lcap, s);
+    if (e == hipSuccess && !direct)
+        e = hipMallocAsync(reinterpret_cast<void**>(&cand_ids), sizeof(int32_t) * T * n * k, s);
+    if (e == hipSuccess && !direct)
+        e = hipMallocAsync(reinterpret_cast<void**>(&cand_d), sizeof(float) * T * n * k, s);
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "workspace allocation");
+        goto done;
+    }
+    if (direct) {
+        cand_ids = ids_out;
+        cand_d = dists_out;
+    }
+
+    for (int t0 = 0; t0 < T; t0 += slots) {
+        knng::PartitionArgs pa{};
+        pa.X = data;
+        pa.n = n;
+        pa.D = D;
+        pa.n_trees = slots;
+        pa.tree0 = t0;
+        pa.leaf_max = leaf_max;
+        pa.min_leaf = o.min_leaf;
+        pa.max_iter = o.max_iter;
+        pa.seed = seed;
+        pa.perm = perm;
+        pa.leaves = leaves;
+        pa.leaves_cap = lcap;
+        pa.node_log = nullptr;
+        pa.node_log_cap = 0;
+        pa.stream = s;
+        knng::PartitionResult r;
+        rc = knng::partition_run(pa, &r, err, sizeof(err));
+        if (rc != KNNG_OK) {
+            set_err(rc, "partition: %s", err);
+            goto done;
+        }
+        pres.assign_rows += r.assign_rows;
+        pres.splits += r.splits;
+        pres.repairs += r.repairs;
+        pres.levels = r.levels > pres.levels ? r.levels : pres.levels;
+        launches += r.launches;
+        n_leaves_total += r.n_leaves;
+        // ordered pairs (stats) need the leaf sizes
+        if (stats_out != nullptr) {
+            hl.resize(static_cast<size_t>(r.n_leaves));
+            e = hipMemcpyAsync(hl.data(), leaves, sizeof(knng::LeafRec) * r.n_leaves,
+                               hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) {
+                rc = hip_fail(e, "leaf readback");
+                goto done;
+            }
+            for (const auto& L : hl) pairs += static_cast<int64_t>(L.size) * (L.size - 1);
+        }
+        if (t0 == 0) ev.record(2, s);
+        knng::LeafArgs la{};
+        la.X = data;
+        la.n = n;
+        la.D = D;
+        la.k = k;
+        la.n_trees = slots;
+        la.perm = perm;
+        la.leaves = leaves;
+        la.n_leaves = r.n_leaves;
+        la.leaf_max = leaf_max < n ? leaf_max : static_cast<int>(n);
+        la.precision = o.precision;
+        la.rerank = o.rerank * k;
+        la.cand_ids = cand_ids + static_cast<size_t>(t0) * n * k;
+        la.cand_d = cand_d + static_cast<size_t>(t0) * n * k;
+        la.stream = s;
+        rc = knng::leaf_run(la, &launches, err, sizeof(err));
+        if (rc != KNNG_OK) {
+            set_err(rc, "leaf search: %s", err);
+            goto done;
+        }
+    }
+    ev.record(3, s);
+    if (!direct) {
+        knng::MergeArgs ma{};
+        ma.n = n;
+        ma.k = k;
+        ma.n_trees = T;
+        ma.cand_ids = cand_ids;
+        ma.cand_d = cand_d;
+        ma.ids_out = ids_out;
+        ma.dists_out = dists_out;
+        ma.stream = s;
+        rc = knng::merge_run(ma, &launches, err, sizeof(err));
+        if (rc != KNNG_OK) {
+            set_err(rc, "merge: %s", err);
+            goto done;
+        }
+    }
+    ev.record(4, s);
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = hip_fail(e, "build");
+
+done:
+    if (perm) hipFreeAsync(perm, s);
+    if (leaves) hipFreeAsync(leaves, s);
+    if (!direct) {
+        if (cand_ids) hipFreeAsync(cand_ids, s);
+        if (cand_d) hipFreeAsync(cand_d, s);
+    }
+    e = hipStreamSynchronize(s);
+    if (rc == KNNG_OK && e != hipSuccess) rc = hip_fail(e, "build");
+    if (rc == KNNG_OK && stats_out != nullptr) {
+        std::memset(stats_out, 0, sizeof(*stats_out));
+        stats_out->assign_rows = pres.assign_rows;
+        stats_out->ordered_pairs = pairs;
+        stats_out->leaves = n_leaves_total;
+        stats_out->splits = pres.splits;
+        stats_out->repairs = pres.repairs;
+        stats_out->levels = pres.levels;
+        stats_out->launches = launches;
+        stats_out->ms_prep = ev.ms(0, 1);
+        if (o.plain) {  // stages interleave per tree: report partition+leaf together
+            stats_out->ms_partition = ev.ms(1, 3);
+            stats_out->ms_leaf = 0.f;
+        } else {
+            stats_out->ms_partition = ev.ms(1, 2);
+            stats_out->ms_leaf = ev.ms(2, 3);
+        }
+        stats_out->ms_merge = ev.ms(3, 4);
+        stats_out->ms_total = ev.ms(0, 4);
+    }
+    return rc;
+}
+
+int knng_build(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_trees,
+               int32_t leaf_max, uint64_t seed, int32_t* ids_out, float* dists_out,
+               hipStream_t stream) {
+    return knng_build_ex(data, n, D, k, n_trees, leaf_max, seed, ids_out, dists_out, nullptr,
+                         nullptr, stream);
+}
+
+int knng_partition(const float* data, int64_t n, int32_t D, int32_t leaf_max, int32_t min_leaf,
+                   int32_t max_iter, uint64_t seed, int32_t tree, int32_t* perm_out,
+                   int32_t* leaf_offsets_out, int32_t* n_leaves_out, int32_t* nodes_out,
+                   int32_t* n_nodes_out, hipStream_t stream) {
+    g_err[0] = '\0';
+    if (data == nullptr || perm_out == nullptr || leaf_offsets_out == nullptr ||
+        n_leaves_out == nullptr)
+        return set_err(KNNG_ERR_INVALID_ARG, "null pointer argument");
+    if (!aligned16(data)) return set_err(KNNG_ERR_INVALID_ARG, "data must be 16-byte aligned");
+    if (n < 2 || n > 2147483647LL) return set_err(KNNG_ERR_INVALID_ARG, "n out of [2, 2^31-1]");
+    if (D < 1) return set_err(KNNG_ERR_INVALID_ARG, "D must be >= 1");
+    if (D > knng::kMaxDim || (D % 4 != 0 && D > 1024))
+        return set_err(KNNG_ERR_UNSUPPORTED, "D=%d not supported", D);
+    if (tree < 0) return set_err(KNNG_ERR_INVALID_ARG, "tree must be >= 0");
+    if (min_leaf == 0) min_leaf = 1;
+    if (max_iter == 0) max_iter = 10;
+    if (min_leaf < 1 || max_iter < 1) return set_err(KNNG_ERR_INVALID_ARG, "min_leaf, max_iter >= 1");
+    if (leaf_max < 2 * min_leaf - 1 || leaf_max < 1)
+        return set_err(KNNG_ERR_INVALID_ARG, "leaf_max < 2*min_leaf-1");
+
+    hipStream_t s = stream;
+    int rc = check_finite(data, n * static_cast<int64_t>(D), s);
+    if (rc != KNNG_OK) return rc;
+    const int64_t lcap = knng::max_leaves_per_tree(n, min_leaf);
+    knng::LeafRec* leaves = nullptr;
+    int32_t* dcount = nullptr;
+    int32_t hcount = 0;
+    char err[400] = "";
+    knng::PartitionResult r;
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&leaves), sizeof(knng::LeafRec) * lcap, s);
+    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&dcount), sizeof(int32_t), s);
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "workspace allocation");
+        goto done;
+    }
+    {
+        knng::PartitionArgs pa{};
+        pa.X = data;
+        pa.n = n;
+        pa.D = D;
+        pa.n_trees = 1;
+        pa.tree0 = tree;
+        pa.leaf_max = leaf_max;
+        pa.min_leaf = min_leaf;
+        pa.max_iter = max_iter;
+        pa.seed = seed;
+        pa.perm = perm_out;
+        pa.leaves = leaves;
+        pa.leaves_cap = lcap;
+        pa.node_log = nodes_out;
+        pa.node_log_cap = nodes_out ? n : 0;
+        pa.stream = s;
+        rc = knng::partition_run(pa, &r, err, sizeof(err));
+        if (rc != KNNG_OK) {
+            set_err(rc, "partition: %s", err);
+            goto done;
+        }
+    }
+    rc = knng::leaves_to_offsets(leaves, r.n_leaves, n, 0, leaf_offsets_out, dcount, s);
+    if (rc != KNNG_OK) {
+        set_err(rc, "leaf offsets");
+        goto done;
+    }
+    e = hipMemcpyAsync(&hcount, dcount, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "partition");
+        goto done;
+    }
+    *n_leaves_out = hcount;
+    if (n_nodes_out) *n_nodes_out = static_cast<int32_t>(r.n_log);
+
+done:
+    if (leaves) hipFreeAsync(leaves, s);
+    if (dcount) hipFreeAsync(dcount, s);
+    e = hipStreamSynchronize(s);
+    if (rc == KNNG_OK && e != hipSuccess) rc = hip_fail(e, "partition");
+    return rc;
+}
+
+}  // extern "C"
+
+namespace knng {
+namespace {
+// Turn per-tree boundary arrays into leaf records; flags malformed input.
+__global__ void k_offsets_to_leaves(const int32_t* __restrict__ off, int nl, int tree,
+                                    int64_t n, LeafRec* __restrict__ out, int32_t* __restrict__ maxsz,
+                                    int32_t* __restrict__ bad) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nl; i += gridDim.x * blockDim.x) {
+        const int32_t a = off[i], b = off[i + 1];
+        if (b <= a || a < 0 || b > n || (i == 0 && a != 0) || (i == nl - 1 && b != n))
+            atomicOr(bad, 1);
+        out[i] = LeafRec{tree, a, b - a, 0};
+        atomicMax(maxsz, b - a);
+    }
+}
+// bad <- 1 if a perm entry lies outside [0, n).
+__global__ void k_check_perm(const int32_t* __restrict__ perm, int64_t count, int64_t n,
+                             int32_t* __restrict__ bad) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < count;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        if (perm[i] < 0 || perm[i] >= n) atomicOr(bad, 1);
+}
+__global__ void k_zero2(int32_t* p) {
+    p[0] = 0;
+    p[1] = 0;
+}
+}  // namespace
+}  // namespace knng
+
+extern "C" int knng_leaf_search(const float* data, int64_t n, int32_t D, int32_t k,
+                                int32_t n_trees, const int32_t* perm,
+                                const int32_t* leaf_offsets, const int32_t* n_leaves,
+                                const knng_options* opt, int32_t* ids_out, float* dists_out,
+                                hipStream_t stream) {
+    g_err[0] = '\0';
+    int rc = check_common(data, n, D, k, n_trees, ids_out, dists_out);
+    if (rc != KNNG_OK) return rc;
+    if (perm == nullptr || leaf_offsets == nullptr || n_leaves == nullptr)
+        return set_err(KNNG_ERR_INVALID_ARG, "null pointer argument");
+    Resolved o;
+    rc = resolve(opt, k, &o);
+    if (rc != KNNG_OK) return rc;
+    if (o.precision != KNNG_FP32)
+        return set_err(KNNG_ERR_UNSUPPORTED, "precision %d not available in this build", o.precision);
+    int64_t total = 0;
+    for (int t = 0; t < n_trees; ++t) {
+        if (n_leaves[t] < 1 || n_leaves[t] > n)
+            return set_err(KNNG_ERR_INVALID_ARG, "n_leaves[%d]=%d out of [1, n]", t, n_leaves[t]);
+        total += n_leaves[t];
+    }
+    hipStream_t s = stream;
+    knng::LeafRec* leaves = nullptr;
+    int32_t* flags = nullptr;  // [0] max leaf size, [1] malformed
+    int32_t hflags[2] = {0, 0};
+    int32_t* cand_ids = nullptr;
+    float* cand_d = nullptr;
+    const bool direct = (n_trees == 1);
+    char err[400] = "";
+    int launches = 0;
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&leaves), sizeof(knng::LeafRec) * total, s);
+    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&flags), sizeof(int32_t) * 2, s);
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "workspace allocation");
+        goto done;
+    }
+    knng::k_zero2<<<1, 1, 0, s>>>(flags);
+    {
+        int64_t li = 0, oi = 0;
+        for (int t = 0; t < n_trees; ++t) {
+            knng::k_offsets_to_leaves<<<64, 256, 0, s>>>(leaf_offsets + oi, n_leaves[t], t, n,
+                                                         leaves + li, flags, flags + 1);
+            li += n_leaves[t];
+            oi += n_leaves[t] + 1;
+        }
+        knng::k_check_perm<<<1024, 256, 0, s>>>(perm, static_cast<int64_t>(n_trees) * n, n,
+                                                flags + 1);
+    }
+    e = hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "leaf table");
+        goto done;
+    }
+    if (hflags[1]) {
+        rc = set_err(KNNG_ERR_INVALID_ARG,
+                     "leaf_offsets not ascending from 0 to n, or perm entry outside [0, n)");
+        goto done;
+    }
+    if (hflags[0] > knng::kMaxLeaf) {
+        rc = set_err(KNNG_ERR_UNSUPPORTED, "leaf of %d points exceeds %d", hflags[0], knng::kMaxLeaf);
+        goto done;
+    }
+    if (o.check_finite) {
+        rc = check_finite(data, n * static_cast<int64_t>(D), s);
+        if (rc != KNNG_OK) goto done;
+    }
+    if (direct) {
+        cand_ids = ids_out;
+        cand_d = dists_out;
+    } else {
+        e = hipMallocAsync(reinterpret_cast<void**>(&cand_ids), sizeof(int32_t) * n_trees * n * k, s);
+        if (e == hipSuccess)
+            e = hipMallocAsync(reinterpret_cast<void**>(&cand_d), sizeof(float) * n_trees * n * k, s);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "workspace allocation");
+            goto done;
+        }
+    }
+    {
+        knng::LeafArgs la{};
+        la.X = data;
+        la.n = n;
+        la.D = D;
+        la.k = k;
+        la.n_trees = n_trees;
+        la.perm = perm;
+        la.leaves = leaves;
+        la.n_leaves = total;
+        la.leaf_max = hflags[0];
+        la.precision = o.precision;
+        la.rerank = o.rerank * k;
+        la.cand_ids = cand_ids;
+        la.cand_d = cand_d;
+        la.stream = s;
+        rc = knng::leaf_run(la, &launches, err, sizeof(err));
+        if (rc != KNNG_OK) {
+            set_err(rc, "leaf search: %s", err);
+            goto done;
+        }
+    }
+    if (!direct) {
+        knng::MergeArgs ma{};
+        ma.n = n;
+        ma.k = k;
+        ma.n_trees = n_trees;
+        ma.cand_ids = cand_ids;
+        ma.cand_d = cand_d;
+        ma.ids_out = ids_out;
+        ma.dists_out = dists_out;
+        ma.stream = s;
+        rc = knng::merge_run(ma, &launches, err, sizeof(err));
+        if (rc != KNNG_OK) {
+            set_err(rc, "merge: %s", err);
+            goto done;
+        }
+    }
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = hip_fail(e, "leaf search");
+done:
+    if (leaves) hipFreeAsync(leaves, s);
+    if (flags) hipFreeAsync(flags, s);
+    if (!direct) {
+        if (cand_ids) hipFreeAsync(cand_ids, s);
+        if (cand_d) hipFreeAsync(cand_d, s);
+    }
+    e = hipStreamSynchronize(s);
+    if (rc == KNNG_OK && e != hipSuccess) rc = hip_fail(e, "leaf search");
+    return rc;
+}

@@ -1,0 +1,129 @@
+// Internal interfaces of libknng: records shared by the stages and the host
+// launchers each stage exports to the C-ABI layer (api.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+
+namespace knng {
+
+// Rows of one assignment chunk; one wavefront owns one chunk.
+constexpr int kChunkRows = 1024;
+// Largest cluster the leaf kernels accept.
+constexpr int kMaxLeaf = 512;
+// Largest dimension the partition kernels accept.
+constexpr int kMaxDim = 4096;
+
+// A node of the current level: a run [start, start+size) of perm[tree].
+struct NodeRec {
+    int32_t tree;    // tree slot 0..T-1 within this call
+    int32_t start;
+    int32_t size;
+    int32_t chunk0;  // first assignment chunk of this node
+};
+
+// A finished cluster (leaf) of one tree.
+struct LeafRec {
+    int32_t tree;
+    int32_t start;
+    int32_t size;
+    int32_t pad;
+};
+
+// Counters the level-finishing kernel hands back to the host.
+struct LevelCounters {
+    int32_t n_next;     // active nodes of the next level
+    int32_t nc_next;    // assignment chunks of the next level
+    int32_t n_leaves;   // leaves so far
+    int32_t n_log;      // bisected nodes logged so far
+};
+
+// Status codes (mirror include/knng.h).
+enum Status : int {
+    kOk = 0,
+    kInvalid = -1,
+    kUnsupported = -2,
+    kOom = -3,
+    kHip = -4,
+    kNonFinite = -5,
+};
+
+// ---------------------------------------------------------------- partition
+struct PartitionArgs {
+    const float* X;
+    int64_t n;
+    int D;
+    int n_trees;      // trees tree0 .. tree0+n_trees-1 go to slots 0..n_trees-1
+    int tree0;
+    int leaf_max;
+    int min_leaf;
+    int max_iter;
+    uint64_t seed;
+    int32_t* perm;          // device [n_trees][n], output
+    LeafRec* leaves;        // device, capacity leaves_cap
+    int64_t leaves_cap;
+    int32_t* node_log;      // device nullable, [node_log_cap][4]
+    int64_t node_log_cap;
+    hipStream_t stream;
+};
+
+struct PartitionResult {
+    int64_t n_leaves = 0;
+    int64_t n_log = 0;
+    int64_t assign_rows = 0;  // rows assigned, summed over passes
+    int64_t splits = 0;
+    int64_t repairs = 0;
+    int levels = 0;
+    int launches = 0;
+};
+
+// Runs the level-synchronous bisection of all requested trees.
+int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_t errlen);
+
+// Upper bound on the number of leaves of n points in one tree.
+inline int64_t max_leaves_per_tree(int64_t n, int min_leaf) {
+    return n / (min_leaf > 0 ? min_leaf : 1) + 1;
+}
+
+// ---------------------------------------------------------------- leaves
+struct LeafArgs {
+    const float* X;
+    int64_t n;
+    int D;
+    int k;
+    int n_trees;
+    const int32_t* perm;     // device [n_trees][n]
+    const LeafRec* leaves;   // device
+    int64_t n_leaves;
+    int leaf_max;            // largest leaf size present
+    int precision;
+    int rerank;              // candidates per row for reduced precision
+    int32_t* cand_ids;       // device [n_trees][n][k]
+    float* cand_d;           // device [n_trees][n][k]
+    hipStream_t stream;
+};
+int leaf_run(const LeafArgs& a, int* launches, char* err, size_t errlen);
+
+// ---------------------------------------------------------------- merge
+struct MergeArgs {
+    int64_t n;
+    int k;
+    int n_trees;
+    const int32_t* cand_ids;  // [n_trees][n][k]
+    const float* cand_d;
+    int32_t* ids_out;         // [n][k]
+    float* dists_out;
+    hipStream_t stream;
+};
+int merge_run(const MergeArgs& a, int* launches, char* err, size_t errlen);
+
+// ---------------------------------------------------------------- prep
+// Sets *flag (device int) to 1 if X holds a NaN or Inf.
+int prep_check_finite(const float* X, int64_t count, int32_t* flag, hipStream_t s);
+
+// Converts per-tree leaf lists into sorted run boundaries (knng_partition).
+int leaves_to_offsets(const LeafRec* leaves, int64_t n_leaves, int64_t n, int tree,
+                      int32_t* offsets_out, int32_t* count_out_dev, hipStream_t s);
+
+}  // namespace knng

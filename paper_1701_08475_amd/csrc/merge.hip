@@ -1,0 +1,120 @@
+// Union of the rounds' candidate lists into G (Alg. 1: "update G[i] and G[j]"
+// over all rounds; a pair already compared is not counted twice).
+//
+// One wavefront per row: the row's candidates from every tree are sorted by
+// (d32, id) with a bitonic network, adjacent equal keys are dropped (the same
+// id always carries the same d32 bits, so duplicates are adjacent), and the
+// first k survivors are written.  When the candidates of all trees do not fit
+// one sort, trees are merged in groups into the output row.
+#include "knng_internal.hpp"
+#include "wave.hpp"
+
+#include <cstdio>
+
+namespace knng {
+namespace {
+
+template <int R>
+__global__ __launch_bounds__(256) void k_merge(int64_t n, int k, int t0, int t1,
+                                               const int32_t* __restrict__ cid,
+                                               const float* __restrict__ cd,
+                                               int32_t* __restrict__ oid, float* __restrict__ od,
+                                               int with_prev) {
+    const int64_t row = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (row >= n) return;
+    const int lane = threadIdx.x & 63;
+    const int np = with_prev ? k : 0;
+    const int total = np + (t1 - t0) * k;
+    uint64_t v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = lane * R + r;
+        v[r] = kNoKey;
+        if (e < total) {
+            int32_t id;
+            float d;
+            if (e < np) {
+                id = oid[row * k + e];
+                d = od[row * k + e];
+            } else {
+                const int q = e - np;
+                const size_t src = (static_cast<size_t>(t0 + q / k) * n + row) * k + q % k;
+                id = cid[src];
+                d = cd[src];
+            }
+            if (id >= 0) v[r] = cand_key(d, id);
+        }
+    }
+    wave_bitonic_sort<R>(v);
+    // previous element of each slot (lane-1's last slot for r == 0)
+    const uint64_t last_of_prev_lane = shfl_u64(v[R - 1], lane > 0 ? lane - 1 : 0);
+    bool keep[R];
+    int cnt = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint64_t before = r > 0 ? v[r - 1] : (lane > 0 ? last_of_prev_lane : kNoKey);
+        keep[r] = v[r] != kNoKey && v[r] != before;
+        cnt += keep[r] ? 1 : 0;
+    }
+    int kept;
+    int pos = wave_excl_scan(cnt, &kept);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (keep[r]) {
+            if (pos < k) {
+                oid[row * k + pos] = key_id(v[r]);
+                od[row * k + pos] = key_dist(v[r]);
+            }
+            ++pos;
+        }
+    }
+    for (int p = kept + lane; p < k; p += kWave) {
+        oid[row * k + p] = -1;
+        od[row * k + p] = __int_as_float(0x7f800000);
+    }
+}
+
+using MergeFn = void (*)(int64_t, int, int, int, const int32_t*, const float*, int32_t*, float*,
+                         int);
+
+MergeFn pick(int slots) {
+    if (slots <= 64) return k_merge<1>;
+    if (slots <= 128) return k_merge<2>;
+    if (slots <= 256) return k_merge<4>;
+    if (slots <= 512) return k_merge<8>;
+    return k_merge<16>;
+}
+
+}  // namespace
+
+int merge_run(const MergeArgs& a, int* launches, char* err, size_t errlen) {
+    const int k = a.k;
+    const int64_t blocks = (a.n + 3) / 4;
+    constexpr int kMaxSlots = 1024;
+    int t = 0;
+    bool prev = false;
+    while (t < a.n_trees) {
+        const int room = kMaxSlots - (prev ? k : 0);
+        int g = room / k;
+        if (g < 1) g = 1;
+        const int t1 = t + g < a.n_trees ? t + g : a.n_trees;
+        const int slots = (prev ? k : 0) + (t1 - t) * k;
+        if (slots > kMaxSlots) {
+            std::snprintf(err, errlen, "k=%d too large for the merge", k);
+            return kUnsupported;
+        }
+        pick(slots)<<<static_cast<unsigned>(blocks), 256, 0, a.stream>>>(
+            a.n, k, t, t1, a.cand_ids, a.cand_d, a.ids_out, a.dists_out, prev ? 1 : 0);
+        ++*launches;
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            std::snprintf(err, errlen, "merge launch failed: %s", hipGetErrorString(e));
+            return kHip;
+        }
+        prev = true;
+        t = t1;
+    }
+    return kOk;
+}
+
+}  // namespace knng

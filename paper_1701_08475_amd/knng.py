@@ -1,0 +1,201 @@
+"""Python binding of libknng.so (include/knng.h).  Argument marshalling only:
+every step of the build runs in the library's HIP kernels.  PyTorch provides
+device memory and the current stream.
+
+    ids, dists = knng.build(x, k=20, n_trees=8, leaf_max=100, seed=0)
+
+raises ``KnngError`` on a non-zero status and ``RuntimeError`` when the
+library has not been built (there is no fallback path).
+"""
+import ctypes
+import os
+import re
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+LIB_PATH = os.path.join(PKG, "libknng.so")
+HEADER = os.path.join(ROOT, "include", "knng.h")
+
+KNNG_OK = 0
+KNNG_ERR_INVALID_ARG = -1
+KNNG_ERR_UNSUPPORTED = -2
+KNNG_ERR_OOM = -3
+KNNG_ERR_HIP = -4
+KNNG_ERR_NONFINITE = -5
+PRECISION = {"fp32": 0, "bf16": 1, "fp16": 2, "fp8": 3, "fp8_e4m3": 3}
+
+
+class KnngOptions(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("rerank_factor", ctypes.c_int32), ("min_leaf", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("plain", ctypes.c_int32),
+                ("check_finite", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class KnngStats(ctypes.Structure):
+    _fields_ = [("assign_rows", ctypes.c_int64), ("ordered_pairs", ctypes.c_int64),
+                ("leaves", ctypes.c_int64), ("splits", ctypes.c_int64),
+                ("repairs", ctypes.c_int64), ("levels", ctypes.c_int32),
+                ("launches", ctypes.c_int32), ("ms_prep", ctypes.c_float),
+                ("ms_partition", ctypes.c_float), ("ms_leaf", ctypes.c_float),
+                ("ms_merge", ctypes.c_float), ("ms_total", ctypes.c_float)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class KnngError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("knng status %d: %s" % (status, msg))
+        self.status = status
+
+
+_lib = None
+
+
+def declared_functions():
+    """Names of the functions include/knng.h declares."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(knng_\w+)\s*\(", txt)))
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libknng.so is not built (run __graft_entry__.build() or "
+                           "python -m paper_1701_08475_amd.build_lib)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64
+    L.knng_build.restype = ctypes.c_int
+    L.knng_build.argtypes = [vp, i64, i32, i32, i32, i32, u64, vp, vp, vp]
+    L.knng_build_ex.restype = ctypes.c_int
+    L.knng_build_ex.argtypes = [vp, i64, i32, i32, i32, i32, u64, vp, vp,
+                                ctypes.POINTER(KnngOptions), ctypes.POINTER(KnngStats), vp]
+    L.knng_partition.restype = ctypes.c_int
+    L.knng_partition.argtypes = [vp, i64, i32, i32, i32, i32, u64, i32, vp, vp,
+                                 ctypes.POINTER(i32), vp, ctypes.POINTER(i32), vp]
+    L.knng_leaf_search.restype = ctypes.c_int
+    L.knng_leaf_search.argtypes = [vp, i64, i32, i32, i32, vp, vp, ctypes.POINTER(i32),
+                                   ctypes.POINTER(KnngOptions), vp, vp, vp]
+    L.knng_default_options.restype = None
+    L.knng_default_options.argtypes = [ctypes.POINTER(KnngOptions)]
+    L.knng_status_string.restype = ctypes.c_char_p
+    L.knng_status_string.argtypes = [ctypes.c_int]
+    L.knng_last_error.restype = ctypes.c_char_p
+    L.knng_last_error.argtypes = []
+    L.knng_version.restype = ctypes.c_int
+    L.knng_version.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != KNNG_OK:
+        raise KnngError(rc, lib().knng_last_error().decode(errors="replace"))
+
+
+def options(precision="fp32", rerank_factor=2, min_leaf=0, max_iter=0, plain=False,
+            check_finite=True):
+    o = KnngOptions()
+    lib().knng_default_options(ctypes.byref(o))
+    o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    o.rerank_factor = int(rerank_factor)
+    o.min_leaf = int(min_leaf)
+    o.max_iter = int(max_iter)
+    o.plain = 1 if plain else 0
+    o.check_finite = 1 if check_finite else 0
+    return o
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_f32(x):
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32
+            and x.dim() == 2 and x.is_contiguous()):
+        raise ValueError("x must be a contiguous 2-D float32 CUDA tensor")
+    return x
+
+
+def build(x, k, n_trees, leaf_max, seed=0, precision="fp32", rerank_factor=2, min_leaf=0,
+          max_iter=0, plain=False, stats=False, out=None, stream=None):
+    """kNN graph of the rows of x.  Returns (ids int32 [n,k], dists f32 [n,k])
+    and a stats dict when stats=True."""
+    import torch
+    x = _dev_f32(x)
+    n, D = x.shape
+    if out is None:
+        ids = torch.empty((n, k), dtype=torch.int32, device=x.device)
+        ds = torch.empty((n, k), dtype=torch.float32, device=x.device)
+    else:
+        ids, ds = out
+    o = options(precision, rerank_factor, min_leaf, max_iter, plain)
+    st = KnngStats() if stats else None
+    rc = lib().knng_build_ex(ctypes.c_void_p(x.data_ptr()), n, D, k, n_trees, leaf_max,
+                             ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF),
+                             ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(ds.data_ptr()),
+                             ctypes.byref(o), ctypes.byref(st) if st is not None else None,
+                             _stream(stream))
+    _check(rc)
+    return (ids, ds, st.as_dict()) if stats else (ids, ds)
+
+
+def build_plain_call(x, k, n_trees, leaf_max, seed, ids, ds, stream=None):
+    """knng_build (the options-free entry point) into given outputs."""
+    rc = lib().knng_build(ctypes.c_void_p(x.data_ptr()), x.shape[0], x.shape[1], k, n_trees,
+                          leaf_max, ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF),
+                          ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(ds.data_ptr()),
+                          _stream(stream))
+    _check(rc)
+
+
+def partition(x, leaf_max, min_leaf, seed, tree, max_iter=0, with_nodes=False, stream=None):
+    """One tree's clustering.  Returns dict(perm [n] int32, leaf_off [n_leaves+1]
+    int32, nodes [n_nodes, 4] int32 if with_nodes), all CUDA tensors."""
+    import torch
+    x = _dev_f32(x)
+    n, D = x.shape
+    perm = torch.empty(n, dtype=torch.int32, device=x.device)
+    loff = torch.empty(n + 1, dtype=torch.int32, device=x.device)
+    nodes = torch.empty((n, 4), dtype=torch.int32, device=x.device) if with_nodes else None
+    nl = ctypes.c_int32(0)
+    nn = ctypes.c_int32(0)
+    rc = lib().knng_partition(ctypes.c_void_p(x.data_ptr()), n, D, leaf_max, min_leaf, max_iter,
+                              ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), tree,
+                              ctypes.c_void_p(perm.data_ptr()), ctypes.c_void_p(loff.data_ptr()),
+                              ctypes.byref(nl),
+                              ctypes.c_void_p(nodes.data_ptr()) if with_nodes else None,
+                              ctypes.byref(nn), _stream(stream))
+    _check(rc)
+    out = dict(perm=perm, leaf_off=loff[: nl.value + 1])
+    if with_nodes:
+        out["nodes"] = nodes[: nn.value]
+    return out
+
+
+def leaf_search(x, k, perms, leaf_offs, precision="fp32", rerank_factor=2, stream=None):
+    """G from given clusters.  perms: int32 CUDA [T, n]; leaf_offs: list of T
+    int32 CUDA boundary tensors.  Returns (ids, dists)."""
+    import torch
+    x = _dev_f32(x)
+    n, D = x.shape
+    perms = perms.reshape(-1, n).contiguous()
+    T = perms.shape[0]
+    cat = torch.cat([o.to(torch.int32) for o in leaf_offs]).contiguous()
+    nl = (ctypes.c_int32 * T)(*[int(o.numel()) - 1 for o in leaf_offs])
+    ids = torch.empty((n, k), dtype=torch.int32, device=x.device)
+    ds = torch.empty((n, k), dtype=torch.float32, device=x.device)
+    o = options(precision, rerank_factor)
+    rc = lib().knng_leaf_search(ctypes.c_void_p(x.data_ptr()), n, D, k, T,
+                                ctypes.c_void_p(perms.data_ptr()), ctypes.c_void_p(cat.data_ptr()),
+                                nl, ctypes.byref(o), ctypes.c_void_p(ids.data_ptr()),
+                                ctypes.c_void_p(ds.data_ptr()), _stream(stream))
+    _check(rc)
+    return ids, ds

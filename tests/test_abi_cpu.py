@@ -1,0 +1,114 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/knng.h declares, and rejects invalid arguments on the host before any
+HIP call (so these calls are safe on a machine without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1701_08475_amd import knng
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(knng.LIB_PATH):
+        from paper_1701_08475_amd import build_lib
+        build_lib.build()
+    return knng.lib()
+
+
+def test_exports_every_declared_function(L):
+    names = knng.declared_functions()
+    assert set(names) >= {"knng_build", "knng_build_ex", "knng_partition", "knng_leaf_search",
+                          "knng_status_string", "knng_last_error", "knng_default_options",
+                          "knng_version"}
+    for nm in names:
+        assert hasattr(L, nm), nm
+
+
+def test_status_codes_match_header(L):
+    txt = open(os.path.join(ROOT, "include", "knng.h")).read()
+    codes = {m.group(1): int(m.group(2)) for m in
+             re.finditer(r"#define\s+(KNNG_(?:OK|ERR_\w+))\s+(-?\d+)", txt)}
+    for nm, v in codes.items():
+        assert getattr(knng, nm) == v
+        assert L.knng_status_string(v) not in (None, b"unknown status")
+    assert L.knng_status_string(12345) == b"unknown status"
+
+
+def test_options_struct_layout(L):
+    o = knng.KnngOptions()
+    L.knng_default_options(ctypes.byref(o))
+    assert o.struct_size == ctypes.sizeof(knng.KnngOptions) == 32
+    assert (o.precision, o.rerank_factor, o.min_leaf, o.max_iter, o.plain, o.check_finite) == \
+        (0, 2, 0, 10, 0, 1)
+    assert ctypes.sizeof(knng.KnngStats) == 8 * 5 + 4 * 2 + 4 * 5 + 4  # padded to 8
+
+
+FAKE = 0x10000  # aligned, never dereferenced: validation fails first
+
+
+def _build(L, data=FAKE, n=100, D=8, k=5, T=1, leaf=20, ids=FAKE, ds=FAKE, opt=None):
+    return L.knng_build_ex(ctypes.c_void_p(data), n, D, k, T, leaf, 0, ctypes.c_void_p(ids),
+                           ctypes.c_void_p(ds), opt, None, None)
+
+
+@pytest.mark.parametrize("kw,status,msg", [
+    (dict(data=0), knng.KNNG_ERR_INVALID_ARG, "null"),
+    (dict(ids=0), knng.KNNG_ERR_INVALID_ARG, "null"),
+    (dict(data=FAKE + 4), knng.KNNG_ERR_INVALID_ARG, "aligned"),
+    (dict(n=1), knng.KNNG_ERR_INVALID_ARG, "n="),
+    (dict(n=1 << 31), knng.KNNG_ERR_INVALID_ARG, "n="),
+    (dict(D=0), knng.KNNG_ERR_INVALID_ARG, "D="),
+    (dict(D=4100), knng.KNNG_ERR_UNSUPPORTED, "D="),
+    (dict(D=1027), knng.KNNG_ERR_UNSUPPORTED, "D="),
+    (dict(k=0), knng.KNNG_ERR_INVALID_ARG, "k="),
+    (dict(k=100), knng.KNNG_ERR_INVALID_ARG, "k="),
+    (dict(n=2000, k=600, leaf=1500), knng.KNNG_ERR_UNSUPPORTED, "k="),
+    (dict(T=0), knng.KNNG_ERR_INVALID_ARG, "n_trees"),
+    (dict(leaf=10), knng.KNNG_ERR_INVALID_ARG, "leaf_max"),   # needs >= 2*(k+1)-1 = 11
+    (dict(n=5000, leaf=513), knng.KNNG_ERR_UNSUPPORTED, "leaf_max"),
+])
+def test_build_rejects_invalid_arguments(L, kw, status, msg):
+    assert _build(L, **kw) == status
+    assert msg in L.knng_last_error().decode()
+
+
+def test_build_rejects_bad_options(L):
+    o = knng.KnngOptions()
+    L.knng_default_options(ctypes.byref(o))
+    o.struct_size = 8
+    assert _build(L, opt=ctypes.byref(o)) == knng.KNNG_ERR_INVALID_ARG
+    L.knng_default_options(ctypes.byref(o))
+    o.precision = 9
+    assert _build(L, opt=ctypes.byref(o)) == knng.KNNG_ERR_INVALID_ARG
+    L.knng_default_options(ctypes.byref(o))
+    o.min_leaf = -1
+    assert _build(L, opt=ctypes.byref(o)) == knng.KNNG_ERR_INVALID_ARG
+    L.knng_default_options(ctypes.byref(o))
+    o.min_leaf = 15  # leaf_max 20 < 2*15-1
+    assert _build(L, opt=ctypes.byref(o)) == knng.KNNG_ERR_INVALID_ARG
+
+
+def test_partition_and_leaf_search_reject_invalid_arguments(L):
+    nl = ctypes.c_int32(0)
+    f = ctypes.c_void_p(FAKE)
+    assert L.knng_partition(None, 100, 8, 20, 1, 10, 0, 0, f, f, ctypes.byref(nl), None, None,
+                            None) == knng.KNNG_ERR_INVALID_ARG
+    assert L.knng_partition(f, 100, 8, 20, 11, 10, 0, 0, f, f, ctypes.byref(nl), None, None,
+                            None) == knng.KNNG_ERR_INVALID_ARG  # 20 < 2*11-1
+    assert L.knng_partition(f, 100, 8, 20, 1, 10, 0, -1, f, f, ctypes.byref(nl), None, None,
+                            None) == knng.KNNG_ERR_INVALID_ARG
+    nls = (ctypes.c_int32 * 1)(0)
+    assert L.knng_leaf_search(f, 100, 8, 5, 1, f, f, nls, None, f, f, None) == \
+        knng.KNNG_ERR_INVALID_ARG  # zero leaves
+    nls = (ctypes.c_int32 * 1)(3)
+    assert L.knng_leaf_search(f, 100, 8, 5, 1, None, f, nls, None, f, f, None) == \
+        knng.KNNG_ERR_INVALID_ARG
+
+
+def test_version(L):
+    assert L.knng_version() >= 100

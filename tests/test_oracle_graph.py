@@ -114,3 +114,16 @@ def test_recall_pins(orc):
     # recall of the graph grows with the number of rounds (C1-shaped data)
     r = [orc.recall(X, rows, orc.graph(X, 10, T, 50, 1)[0][rows], E, Ed) for T in (1, 4)]
     assert 0.2 < r[0] < r[1] <= 1.0
+
+
+def test_rows_from_leaves_matches_full_graph(orc):
+    X = datagen.make("c1", n=2000)
+    perms, offs = [], []
+    for t in range(3):
+        tr = orc.tree(X, 50, 11, 10, 2, t)
+        perms.append(tr["perm"])
+        offs.append(tr["leaf_off"])
+    ids, ds = orc.graph_from_leaves(X, 10, np.stack(perms), offs)
+    rows = datagen.sample_rows(2000, 300, seed=3)
+    r_ids, r_ds = orc.rows_from_leaves(X, 10, np.stack(perms), offs, rows)
+    assert np.array_equal(r_ids, ids[rows]) and np.array_equal(r_ds, ds[rows])
