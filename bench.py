@@ -1,0 +1,221 @@
+#!/usr/bin/env python3
+"""kNN-graph build throughput on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
+
+One step = one full build (knng_build_ex: partition of every tree, leaf
+search, merge) of the resident synthetic input.  Prints one JSON line with
+points/s, the roofline position of the dominant kernel (the two-means
+assignment pass, HBM-bound), recall@k on sampled rows against exact FP64
+brute force, and the CPU oracle timed on a bounded sample on the host.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "kNN-graph build points/sec at recall@k≥target; leaf MFMA util vs plain FP32"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+PROFILES = os.path.join(ROOT, "profiles")
+PARTITION_SRC = os.path.join(ROOT, "paper_1701_08475_amd", "csrc", "partition.hip")
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def source_sha(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def stored_traffic(config):
+    """HBM bytes per assignment launch from the committed rocprofv3 counter
+    summary, or None when it is missing or the kernel source changed since."""
+    path = os.path.join(PROFILES, "k_assign_%s_hbm_counters.md" % config)
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"traffic_bytes_per_launch\s*=\s*([0-9.eE+]+)", txt)
+    s = re.search(r"partition_hip_sha256_16\s*=\s*([0-9a-f]+)", txt)
+    if not m or not s or s.group(1) != source_sha(PARTITION_SRC):
+        return None
+    return float(m.group(1))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--precision", default=None, help="override the config's leaf precision")
+    ap.add_argument("--recall-rows", type=int, default=500)
+    ap.add_argument("--cpu-sample", type=int, default=250_000)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip timing the plain schedule")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a 1 GiB elementwise copy first (HBM counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU; multi-GPU sharding by tree is a design "
+              "note only (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1701_08475_amd import datagen, knng
+
+    c = dict(datagen.CONFIGS[args.config])
+    if args.precision:
+        c["precision"] = args.precision
+    n, D, k, T, L = c["n"], c["D"], c["k"], c["n_trees"], c["leaf_max"]
+    seed = c["seed"]
+    log("config %s: n=%d D=%d k=%d trees=%d leaf_max=%d precision=%s" %
+        (args.config, n, D, k, T, L, c["precision"]))
+    t = time.perf_counter()
+    X = datagen.make(args.config)
+    log("data generated in %.1fs" % (time.perf_counter() - t))
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    xd = torch.from_numpy(X).to(dev)
+    ids = torch.empty((n, k), dtype=torch.int32, device=dev)
+    ds = torch.empty((n, k), dtype=torch.float32, device=dev)
+    knng.lib()
+
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
+        log("copy calibration kernel: 1 GiB read + 1 GiB write")
+
+    def step(stats=True):
+        return knng.build(xd, k, T, L, seed=seed, precision=c["precision"], stats=stats,
+                          time_kernels=stats, out=(ids, ds))
+
+    for w in range(args.warmup):
+        step()
+        log("warmup %d done" % w)
+    torch.cuda.synchronize()
+    sts = []
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        sts.append(step()[2])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = n / (ms_per_step / 1e3)
+    log("timed %d steps: %.2f ms/step, %.3e points/s" % (args.steps, ms_per_step, value))
+
+    # dominant kernel: two-means assignment pass, bound by HBM
+    a_bytes = sum(s["assign_rows"] for s in sts) * D * 4.0
+    a_ms = sum(s["ms_k_assign"] for s in sts)
+    a_launches = sum(s["n_k_assign"] for s in sts)
+    achieved = a_bytes / (a_ms / 1e3) / 1e9
+    traffic = stored_traffic(args.config)
+    roofline = {
+        "bound": "hbm", "kernel": "k_assign (two-means assignment pass)",
+        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "bytes_per_launch": a_bytes / a_launches, "avg_launch_ms": a_ms / a_launches,
+        "launches_per_step": a_launches / args.steps,
+    }
+    st = sts[-1]
+    pairs = st["ordered_pairs"]
+    leaf_ms = sum(s["ms_k_leaf"] for s in sts) / args.steps
+    merge_ms = sum(s["ms_k_merge"] for s in sts) / args.steps
+    leaf_flops = 2.0 * D * pairs  # one D-long dot product per ordered pair
+    merge_bytes = (T * n * k * 8.0 + n * k * 8.0) if T > 1 else 0.0
+    phases = {
+        "ms_partition": round(sum(s["ms_partition"] for s in sts) / args.steps, 3),
+        "ms_leaf": round(sum(s["ms_leaf"] for s in sts) / args.steps, 3),
+        "ms_merge": round(sum(s["ms_merge"] for s in sts) / args.steps, 3),
+        "leaf_kernel": {"ms": round(leaf_ms, 3), "tflops": round(leaf_flops / leaf_ms / 1e9, 2),
+                        "peak_tflops": FP32_PEAK_TFLOPS,
+                        "frac": round(leaf_flops / leaf_ms / 1e9 / FP32_PEAK_TFLOPS, 4),
+                        "precision": c["precision"]},
+        "merge_kernel": {"ms": round(merge_ms, 3),
+                         "gbs": round(merge_bytes / merge_ms / 1e6, 1) if merge_ms > 0 else None},
+        "pairs_per_s": pairs / (ms_per_step / 1e3),
+        "assign_passes_per_point_per_tree": st["assign_rows"] / float(n * T),
+        "leaves": st["leaves"], "levels": st["levels"], "repairs": st["repairs"],
+        "launches": st["launches"],
+    }
+
+    plain = None
+    if not args.no_plain:
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        reps = 2
+        for _ in range(reps):
+            knng.build(xd, k, T, L, seed=seed, precision="fp32", plain=True, out=(ids, ds))
+        torch.cuda.synchronize()
+        plain_ms = (time.perf_counter() - tp) * 1e3 / reps
+        plain = {"ms_per_step": round(plain_ms, 2), "speedup_of_batched": round(plain_ms / ms_per_step, 3)}
+        log("plain schedule: %.2f ms/step" % plain_ms)
+        step(stats=False)  # leave the batched graph in (ids, ds)
+        torch.cuda.synchronize()
+
+    recall = None
+    cpu = None
+    if not (args.no_recall and args.no_cpu):
+        from oracle import oracle
+        oracle.build()
+    if not args.no_recall:
+        rows = datagen.sample_rows(n, args.recall_rows)
+        tr = time.perf_counter()
+        E, Ed = oracle.exact_knn(X, k, rows)
+        g = ids.cpu().numpy()[rows]
+        recall = {"recall_at_k": round(oracle.recall(X, rows, g, E, Ed), 5), "rows": len(rows),
+                  "k": k, "ground_truth": "FP64 brute force (oracle), tie-tolerant"}
+        log("recall@%d = %.4f on %d rows (%.1fs)" % (k, recall["recall_at_k"], len(rows),
+                                                     time.perf_counter() - tr))
+    if not args.no_cpu:
+        ns = min(args.cpu_sample, n)
+        Xs = np.ascontiguousarray(X[:ns])
+        threads = oracle.num_threads()
+        tc = time.perf_counter()
+        oracle.graph(Xs, k, T, L, seed)
+        el = time.perf_counter() - tc
+        cpu = {"value": round(ns / el, 1), "unit": "points/s", "cores": threads, "kind": "oracle",
+               "seconds": round(el, 2),
+               "sample": "first %d of the %d rows, all %d trees, k=%d, leaf_max=%d, FP64 "
+                         "(per-point cost grows with log n, so the full-size rate is somewhat "
+                         "lower)" % (ns, n, T, k, L)}
+        log("cpu oracle: %d points in %.1fs on %d threads" % (ns, el, threads))
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 partition / %s leaf" % c["precision"],
+        "data": "synthetic (seeded Gaussian mixture shaped like the paper's workloads)",
+        "config": {"workload": "%s: n=%d D=%d k=%d trees=%d leaf_max=%d %s leaves, batched"
+                               % (args.config, n, D, k, T, L, c["precision"]),
+                   "n": n, "D": D, "k": k, "n_trees": T, "leaf_max": L, "seed": seed,
+                   "precision": c["precision"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "recall": recall,
+        "plain_schedule": plain,
+        "phases": phases,
+        "gpu": torch.cuda.get_device_name(0),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

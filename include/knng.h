@@ -63,7 +63,9 @@ typedef struct {
     int32_t plain;          /* 1: unbatched schedule (trees one after another, one
                                leaf launch per tree); 0: batched (default) */
     int32_t check_finite;   /* 1 (default): reject NaN/Inf input */
-    int32_t reserved;
+    int32_t time_kernels;   /* 1: bracket every launch of the assignment, leaf and
+                               merge kernels with HIP events and report the summed
+                               time in knng_stats (0 default: no events) */
 } knng_options;
 
 typedef struct {
@@ -75,6 +77,14 @@ typedef struct {
     int32_t levels;         /* deepest level + 1 */
     int32_t launches;       /* kernel launches issued */
     float ms_prep, ms_partition, ms_leaf, ms_merge, ms_total;  /* stream time */
+    /* with time_kernels = 1: summed event time and launch count per kernel
+       class (two-means assignment pass, leaf search, merge); else 0 */
+    float ms_k_assign;
+    int32_t n_k_assign;
+    float ms_k_leaf;
+    int32_t n_k_leaf;
+    float ms_k_merge;
+    int32_t n_k_merge;
 } knng_stats;
 
 /* Fill *opt with the defaults listed above. */

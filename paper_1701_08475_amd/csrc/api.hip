@@ -31,6 +31,7 @@ struct Resolved {
     int max_iter = 10;
     int plain = 0;
     int check_finite = 1;
+    int time_kernels = 0;
 };
 
 int resolve(const knng_options* opt, int k, Resolved* r) {
@@ -44,6 +45,7 @@ int resolve(const knng_options* opt, int k, Resolved* r) {
         r->max_iter = opt->max_iter;
         r->plain = opt->plain;
         r->check_finite = opt->check_finite;
+        r->time_kernels = opt->time_kernels;
     }
     if (r->min_leaf == 0) r->min_leaf = k + 1;
     if (r->max_iter == 0) r->max_iter = 10;
@@ -132,6 +134,7 @@ void knng_default_options(knng_options* o) {
     o->max_iter = 10;
     o->plain = 0;
     o->check_finite = 1;
+    o->time_kernels = 0;
 }
 
 const char* knng_status_string(int status) {
@@ -169,6 +172,7 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
 
     hipStream_t s = stream;
     Events ev(stats_out != nullptr);
+    knng::KernelTimer timer(o.time_kernels != 0 && stats_out != nullptr);
     ev.record(0, s);
     if (o.check_finite) {
         rc = check_finite(data, n * static_cast<int64_t>(D), s);
@@ -190,7 +194,8 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
     int64_t pairs = 0;
     int64_t n_leaves_total = 0;
     hipError_t e;
-    std::vector<knng::LeafRec> hl;
+    unsigned long long* dpairs = nullptr;
+    unsigned long long hpairs = 0;
 
     e = hipMallocAsync(reinterpret_cast<void**>(&perm), sizeof(int32_t) * slots * n, s);
     if (e == hipSuccess)
@@ -199,6 +204,9 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
         e = hipMallocAsync(reinterpret_cast<void**>(&cand_ids), sizeof(int32_t) * T * n * k, s);
     if (e == hipSuccess && !direct)
         e = hipMallocAsync(reinterpret_cast<void**>(&cand_d), sizeof(float) * T * n * k, s);
+    if (e == hipSuccess)
+        e = hipMallocAsync(reinterpret_cast<void**>(&dpairs), sizeof(unsigned long long), s);
+    if (e == hipSuccess) e = hipMemsetAsync(dpairs, 0, sizeof(unsigned long long), s);
     if (e != hipSuccess) {
         rc = hip_fail(e, "workspace allocation");
         goto done;
@@ -224,6 +232,7 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
         pa.leaves_cap = lcap;
         pa.node_log = nullptr;
         pa.node_log_cap = 0;
+        pa.timer = &timer;
         pa.stream = s;
         knng::PartitionResult r;
         rc = knng::partition_run(pa, &r, err, sizeof(err));
@@ -237,18 +246,6 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
         pres.levels = r.levels > pres.levels ? r.levels : pres.levels;
         launches += r.launches;
         n_leaves_total += r.n_leaves;
-        // ordered pairs (stats) need the leaf sizes
-        if (stats_out != nullptr) {
-            hl.resize(static_cast<size_t>(r.n_leaves));
-            e = hipMemcpyAsync(hl.data(), leaves, sizeof(knng::LeafRec) * r.n_leaves,
-                               hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
-            if (e != hipSuccess) {
-                rc = hip_fail(e, "leaf readback");
-                goto done;
-            }
-            for (const auto& L : hl) pairs += static_cast<int64_t>(L.size) * (L.size - 1);
-        }
         if (t0 == 0) ev.record(2, s);
         knng::LeafArgs la{};
         la.X = data;
@@ -264,6 +261,8 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
         la.rerank = o.rerank * k;
         la.cand_ids = cand_ids + static_cast<size_t>(t0) * n * k;
         la.cand_d = cand_d + static_cast<size_t>(t0) * n * k;
+        la.pairs = dpairs;
+        la.timer = &timer;
         la.stream = s;
         rc = knng::leaf_run(la, &launches, err, sizeof(err));
         if (rc != KNNG_OK) {
@@ -281,6 +280,7 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
         ma.cand_d = cand_d;
         ma.ids_out = ids_out;
         ma.dists_out = dists_out;
+        ma.timer = &timer;
         ma.stream = s;
         rc = knng::merge_run(ma, &launches, err, sizeof(err));
         if (rc != KNNG_OK) {
@@ -289,12 +289,15 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
         }
     }
     ev.record(4, s);
-    e = hipStreamSynchronize(s);
+    e = hipMemcpyAsync(&hpairs, dpairs, sizeof(hpairs), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) rc = hip_fail(e, "build");
+    pairs = static_cast<int64_t>(hpairs);
 
 done:
     if (perm) hipFreeAsync(perm, s);
     if (leaves) hipFreeAsync(leaves, s);
+    if (dpairs) hipFreeAsync(dpairs, s);
     if (!direct) {
         if (cand_ids) hipFreeAsync(cand_ids, s);
         if (cand_d) hipFreeAsync(cand_d, s);
@@ -320,6 +323,15 @@ done:
         }
         stats_out->ms_merge = ev.ms(3, 4);
         stats_out->ms_total = ev.ms(0, 4);
+        float kms[knng::kKClasses];
+        int kn[knng::kKClasses];
+        timer.collect(kms, kn);
+        stats_out->ms_k_assign = kms[knng::kKAssign];
+        stats_out->n_k_assign = kn[knng::kKAssign];
+        stats_out->ms_k_leaf = kms[knng::kKLeaf];
+        stats_out->n_k_leaf = kn[knng::kKLeaf];
+        stats_out->ms_k_merge = kms[knng::kKMerge];
+        stats_out->n_k_merge = kn[knng::kKMerge];
     }
     return rc;
 }
@@ -382,6 +394,7 @@ int knng_partition(const float* data, int64_t n, int32_t D, int32_t leaf_max, in
         pa.leaves_cap = lcap;
         pa.node_log = nodes_out;
         pa.node_log_cap = nodes_out ? n : 0;
+        pa.timer = nullptr;
         pa.stream = s;
         rc = knng::partition_run(pa, &r, err, sizeof(err));
         if (rc != KNNG_OK) {
@@ -535,6 +548,8 @@ extern "C" int knng_leaf_search(const float* data, int64_t n, int32_t D, int32_t
         la.rerank = o.rerank * k;
         la.cand_ids = cand_ids;
         la.cand_d = cand_d;
+        la.pairs = nullptr;
+        la.timer = nullptr;
         la.stream = s;
         rc = knng::leaf_run(la, &launches, err, sizeof(err));
         if (rc != KNNG_OK) {
@@ -551,6 +566,7 @@ extern "C" int knng_leaf_search(const float* data, int64_t n, int32_t D, int32_t
         ma.cand_d = cand_d;
         ma.ids_out = ids_out;
         ma.dists_out = dists_out;
+        ma.timer = nullptr;
         ma.stream = s;
         rc = knng::merge_run(ma, &launches, err, sizeof(err));
         if (rc != KNNG_OK) {

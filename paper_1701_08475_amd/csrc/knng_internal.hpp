@@ -49,6 +49,29 @@ enum Status : int {
     kNonFinite = -5,
 };
 
+// Optional HIP-event timing of every launch of a few kernel classes.
+enum KernelClass { kKAssign = 0, kKLeaf = 1, kKMerge = 2, kKClasses = 3 };
+
+class KernelTimer {
+  public:
+    explicit KernelTimer(bool on) : on_(on) {}
+    ~KernelTimer();
+    KernelTimer(const KernelTimer&) = delete;
+    KernelTimer& operator=(const KernelTimer&) = delete;
+    bool on() const { return on_; }
+    void begin(KernelClass c, hipStream_t s);
+    void end(KernelClass c, hipStream_t s);
+    // Sum of elapsed times per class (call after the stream completed).
+    void collect(float ms[kKClasses], int count[kKClasses]);
+
+  private:
+    struct Pair { hipEvent_t a, b; int cls; };
+    bool on_;
+    Pair* pairs_ = nullptr;
+    int n_ = 0, cap_ = 0;
+    int open_ = -1;
+};
+
 // ---------------------------------------------------------------- partition
 struct PartitionArgs {
     const float* X;
@@ -65,6 +88,7 @@ struct PartitionArgs {
     int64_t leaves_cap;
     int32_t* node_log;      // device nullable, [node_log_cap][4]
     int64_t node_log_cap;
+    KernelTimer* timer;     // nullable
     hipStream_t stream;
 };
 
@@ -101,6 +125,8 @@ struct LeafArgs {
     int rerank;              // candidates per row for reduced precision
     int32_t* cand_ids;       // device [n_trees][n][k]
     float* cand_d;           // device [n_trees][n][k]
+    unsigned long long* pairs;  // device nullable: += m*(m-1) per leaf
+    KernelTimer* timer;      // nullable
     hipStream_t stream;
 };
 int leaf_run(const LeafArgs& a, int* launches, char* err, size_t errlen);
@@ -114,6 +140,7 @@ struct MergeArgs {
     const float* cand_d;
     int32_t* ids_out;         // [n][k]
     float* dists_out;
+    KernelTimer* timer;       // nullable
     hipStream_t stream;
 };
 int merge_run(const MergeArgs& a, int* launches, char* err, size_t errlen);

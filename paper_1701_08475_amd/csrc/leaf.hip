@@ -26,7 +26,8 @@ __global__ __launch_bounds__(256) void k_leaf_fp32(const float* __restrict__ X, 
                                                    int k, const int32_t* __restrict__ perm,
                                                    const LeafRec* __restrict__ leaves,
                                                    int32_t* __restrict__ cand_ids,
-                                                   float* __restrict__ cand_d) {
+                                                   float* __restrict__ cand_d,
+                                                   unsigned long long* __restrict__ pairs) {
     constexpr int MP = 8 * MC;
     constexpr int R = MP >= kWave ? MP / kWave : 1;  // sort slots per lane
     __shared__ float colT[kDimTile][MP + 1];
@@ -39,6 +40,8 @@ __global__ __launch_bounds__(256) void k_leaf_fp32(const float* __restrict__ X, 
     const size_t base = static_cast<size_t>(lf.tree) * n + lf.start;
     const int tid = threadIdx.x;
     for (int j = tid; j < m; j += 256) ids[j] = perm[base + j];
+    if (tid == 0 && pairs != nullptr)
+        atomicAdd(pairs, static_cast<unsigned long long>(m) * static_cast<unsigned long long>(m - 1));
     __syncthreads();
 
     const int ri = tid & (kPanel - 1);
@@ -136,8 +139,10 @@ int leaf_run(const LeafArgs& a, int* launches, char* err, size_t errlen) {
     const int lm = a.leaf_max;
     // slots = sort width of the kernel: columns e >= slots are never written
     auto launch = [&](auto kern, int slots) -> int {
+        if (a.timer) a.timer->begin(kKLeaf, a.stream);
         kern<<<static_cast<unsigned>(a.n_leaves), 256, 0, a.stream>>>(
-            a.X, a.n, a.D, a.k, a.perm, a.leaves, a.cand_ids, a.cand_d);
+            a.X, a.n, a.D, a.k, a.perm, a.leaves, a.cand_ids, a.cand_d, a.pairs);
+        if (a.timer) a.timer->end(kKLeaf, a.stream);
         ++*launches;
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) {

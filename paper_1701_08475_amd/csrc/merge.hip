@@ -103,8 +103,10 @@ int merge_run(const MergeArgs& a, int* launches, char* err, size_t errlen) {
             std::snprintf(err, errlen, "k=%d too large for the merge", k);
             return kUnsupported;
         }
+        if (a.timer) a.timer->begin(kKMerge, a.stream);
         pick(slots)<<<static_cast<unsigned>(blocks), 256, 0, a.stream>>>(
             a.n, k, t, t1, a.cand_ids, a.cand_d, a.ids_out, a.dists_out, prev ? 1 : 0);
+        if (a.timer) a.timer->end(kKMerge, a.stream);
         ++*launches;
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) {

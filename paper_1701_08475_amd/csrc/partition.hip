@@ -722,8 +722,10 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
         k_init_nodes<<<na, 64, 0, s>>>(nodes[cur], a.perm, a.X, n, D, a.seed, a.tree0, W, H, status);
         KNNG_LAUNCH();
         for (int pass = 0; pass < a.max_iter; ++pass) {
+            if (a.timer) a.timer->begin(kKAssign, s);
             assign<<<cblocks, 256, 0, s>>>(a.X, n, D, a.perm, nodes[cur], chunk_node, nc, W, H,
                                            status, labels, dots, P, cnt, pass);
+            if (a.timer) a.timer->end(kKAssign, s);
             KNNG_LAUNCH();
             k_update<<<na, 256, 0, s>>>(nodes[cur], D, P, cnt, W, H, status, n0f, pass,
                                         a.max_iter, dstats);

@@ -135,3 +135,56 @@ int leaves_to_offsets(const LeafRec* leaves, int64_t n_leaves, int64_t n, int tr
 }
 
 }  // namespace knng
+
+namespace knng {
+
+KernelTimer::~KernelTimer() {
+    for (int i = 0; i < n_; ++i) {
+        hipEventDestroy(pairs_[i].a);
+        hipEventDestroy(pairs_[i].b);
+    }
+    delete[] pairs_;
+}
+
+void KernelTimer::begin(KernelClass c, hipStream_t s) {
+    if (!on_) return;
+    if (n_ == cap_) {
+        const int nc = cap_ ? 2 * cap_ : 256;
+        Pair* p = new Pair[nc];
+        for (int i = 0; i < n_; ++i) p[i] = pairs_[i];
+        delete[] pairs_;
+        pairs_ = p;
+        cap_ = nc;
+    }
+    Pair& q = pairs_[n_];
+    if (hipEventCreate(&q.a) != hipSuccess || hipEventCreate(&q.b) != hipSuccess) {
+        on_ = false;  // timing is best effort; the build goes on
+        return;
+    }
+    q.cls = c;
+    hipEventRecord(q.a, s);
+    open_ = n_++;
+}
+
+void KernelTimer::end(KernelClass c, hipStream_t s) {
+    if (!on_ || open_ < 0) return;
+    (void)c;
+    hipEventRecord(pairs_[open_].b, s);
+    open_ = -1;
+}
+
+void KernelTimer::collect(float ms[kKClasses], int count[kKClasses]) {
+    for (int c = 0; c < kKClasses; ++c) {
+        ms[c] = 0.f;
+        count[c] = 0;
+    }
+    for (int i = 0; i < n_; ++i) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, pairs_[i].a, pairs_[i].b) == hipSuccess) {
+            ms[pairs_[i].cls] += t;
+            count[pairs_[i].cls] += 1;
+        }
+    }
+}
+
+}  // namespace knng

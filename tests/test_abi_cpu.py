@@ -43,9 +43,11 @@ def test_options_struct_layout(L):
     o = knng.KnngOptions()
     L.knng_default_options(ctypes.byref(o))
     assert o.struct_size == ctypes.sizeof(knng.KnngOptions) == 32
-    assert (o.precision, o.rerank_factor, o.min_leaf, o.max_iter, o.plain, o.check_finite) == \
-        (0, 2, 0, 10, 0, 1)
-    assert ctypes.sizeof(knng.KnngStats) == 8 * 5 + 4 * 2 + 4 * 5 + 4  # padded to 8
+    assert (o.precision, o.rerank_factor, o.min_leaf, o.max_iter, o.plain, o.check_finite,
+            o.time_kernels) == \
+        (0, 2, 0, 10, 0, 1, 0)
+    # 5 int64, 2 int32, 5 float, 3 (float, int32) pairs = 92 bytes, padded to 8
+    assert ctypes.sizeof(knng.KnngStats) == 96
 
 
 FAKE = 0x10000  # aligned, never dereferenced: validation fails first
