@@ -62,6 +62,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-recall", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain schedule")
+    ap.add_argument("--no-compact", action="store_true",
+                    help="stream FP32 rows in the partition even for integer data")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 1 GiB elementwise copy first (HBM counter calibration)")
     args = ap.parse_args()
@@ -103,7 +105,7 @@ def main():
 
     def step(stats=True):
         return knng.build(xd, k, T, L, seed=seed, precision=c["precision"], stats=stats,
-                          time_kernels=stats, out=(ids, ds))
+                          time_kernels=stats, compact=not args.no_compact, out=(ids, ds))
 
     for w in range(args.warmup):
         step()
@@ -120,7 +122,9 @@ def main():
     log("timed %d steps: %.2f ms/step, %.3e points/s" % (args.steps, ms_per_step, value))
 
     # dominant kernel: two-means assignment pass, bound by HBM
-    a_bytes = sum(s["assign_rows"] for s in sts) * D * 4.0
+    st_last = sts[-1]
+    elem_bytes = 1.0 if st_last["compact_used"] else 4.0  # uint8 copy or FP32 rows
+    a_bytes = sum(s["assign_rows"] for s in sts) * D * elem_bytes
     a_ms = sum(s["ms_k_assign"] for s in sts)
     a_launches = sum(s["n_k_assign"] for s in sts)
     achieved = a_bytes / (a_ms / 1e3) / 1e9
@@ -131,6 +135,7 @@ def main():
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": traffic,
         "bytes_per_launch": a_bytes / a_launches, "avg_launch_ms": a_ms / a_launches,
+        "row_storage": "uint8 (lossless: integer data)" if st_last["compact_used"] else "fp32",
         "launches_per_step": a_launches / args.steps,
     }
     st = sts[-1]

@@ -66,6 +66,10 @@ typedef struct {
     int32_t time_kernels;   /* 1: bracket every launch of the assignment, leaf and
                                merge kernels with HIP events and report the summed
                                time in knng_stats (0 default: no events) */
+    int32_t compact;        /* 1 (default): when every input value is an integer in
+                               [0, 255] and D % 16 == 0, the partition streams a
+                               uint8 copy of X (same values, same results); 0: FP32 */
+    int32_t reserved;
 } knng_options;
 
 typedef struct {
@@ -85,6 +89,8 @@ typedef struct {
     int32_t n_k_leaf;
     float ms_k_merge;
     int32_t n_k_merge;
+    int32_t compact_used;   /* 1 if the partition streamed the uint8 copy */
+    int32_t reserved;
 } knng_stats;
 
 /* Fill *opt with the defaults listed above. */
@@ -120,7 +126,8 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
  * knng_partition -- one round's clustering (Sec. 3.1: bisect repeatedly with
  * two-means until no cluster exceeds leaf_max; Alg. 1 "apply two means
  * clustering" and "collect clusters set S") for tree index `tree`, exactly as
- * knng_build runs it.
+ * knng_build runs it with default options (including the uint8 storage of
+ * integer-valued input).
  *   perm_out          device, int32[n]: the points in depth-first leaf order
  *                     (left child first); every cluster is a contiguous run
  *                     and lists its ids in ascending order

@@ -32,6 +32,7 @@ struct Resolved {
     int plain = 0;
     int check_finite = 1;
     int time_kernels = 0;
+    int compact = 1;
 };
 
 int resolve(const knng_options* opt, int k, Resolved* r) {
@@ -46,6 +47,7 @@ int resolve(const knng_options* opt, int k, Resolved* r) {
         r->plain = opt->plain;
         r->check_finite = opt->check_finite;
         r->time_kernels = opt->time_kernels;
+        r->compact = opt->compact;
     }
     if (r->min_leaf == 0) r->min_leaf = k + 1;
     if (r->max_iter == 0) r->max_iter = 10;
@@ -102,22 +104,29 @@ int hip_fail(hipError_t e, const char* what) {
                    hipGetErrorString(e));
 }
 
-int check_finite(const float* data, int64_t count, hipStream_t s) {
-    int32_t* flag = nullptr;
-    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&flag), sizeof(int32_t), s);
+// One pass over the input: *u8 (nullable) <- all values are integers in
+// [0, 255].  Returns KNNG_ERR_NONFINITE for NaN/Inf input.
+int scan_input(const float* data, int64_t count, bool want_finite, int* u8, hipStream_t s) {
+    int32_t* flags = nullptr;
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&flags), 2 * sizeof(int32_t), s);
     if (e != hipSuccess) return hip_fail(e, "hipMallocAsync");
-    int rc = knng::prep_check_finite(data, count, flag, s);
-    int32_t h = 0;
+    int rc = knng::prep_scan(data, count, flags, s);
+    int32_t h[2] = {0, 0};
     if (rc == KNNG_OK) {
-        e = hipMemcpyAsync(&h, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        e = hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) rc = hip_fail(e, "finite check");
+        if (e != hipSuccess) rc = hip_fail(e, "input scan");
     } else {
-        rc = set_err(KNNG_ERR_HIP, "finite-check launch failed");
+        rc = set_err(KNNG_ERR_HIP, "input-scan launch failed");
     }
-    hipFreeAsync(flag, s);
-    if (rc == KNNG_OK && h) rc = set_err(KNNG_ERR_NONFINITE, "input holds NaN or Inf");
+    hipFreeAsync(flags, s);
+    if (rc == KNNG_OK && want_finite && h[0]) rc = set_err(KNNG_ERR_NONFINITE, "input holds NaN or Inf");
+    if (u8) *u8 = (h[1] == 0 && h[0] == 0) ? 1 : 0;
     return rc;
+}
+
+int check_finite(const float* data, int64_t count, hipStream_t s) {
+    return scan_input(data, count, true, nullptr, s);
 }
 
 }  // namespace
@@ -135,6 +144,8 @@ void knng_default_options(knng_options* o) {
     o->plain = 0;
     o->check_finite = 1;
     o->time_kernels = 0;
+    o->compact = 1;
+    o->reserved = 0;
 }
 
 const char* knng_status_string(int status) {
@@ -174,11 +185,12 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
     Events ev(stats_out != nullptr);
     knng::KernelTimer timer(o.time_kernels != 0 && stats_out != nullptr);
     ev.record(0, s);
-    if (o.check_finite) {
-        rc = check_finite(data, n * static_cast<int64_t>(D), s);
+    int all_u8 = 0;
+    if (o.check_finite || (o.compact && D % 16 == 0)) {
+        rc = scan_input(data, n * static_cast<int64_t>(D), o.check_finite != 0, &all_u8, s);
         if (rc != KNNG_OK) return rc;
     }
-    ev.record(1, s);
+    const bool use_u8 = o.compact && D % 16 == 0 && all_u8;
 
     const int T = n_trees;
     const int slots = o.plain ? 1 : T;  // trees partitioned per call
@@ -196,6 +208,7 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
     hipError_t e;
     unsigned long long* dpairs = nullptr;
     unsigned long long hpairs = 0;
+    uint8_t* x8 = nullptr;
 
     e = hipMallocAsync(reinterpret_cast<void**>(&perm), sizeof(int32_t) * slots * n, s);
     if (e == hipSuccess)
@@ -207,10 +220,17 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
     if (e == hipSuccess)
         e = hipMallocAsync(reinterpret_cast<void**>(&dpairs), sizeof(unsigned long long), s);
     if (e == hipSuccess) e = hipMemsetAsync(dpairs, 0, sizeof(unsigned long long), s);
+    if (e == hipSuccess && use_u8)
+        e = hipMallocAsync(reinterpret_cast<void**>(&x8), static_cast<size_t>(n) * D, s);
     if (e != hipSuccess) {
         rc = hip_fail(e, "workspace allocation");
         goto done;
     }
+    if (use_u8 && knng::prep_to_u8(data, n * static_cast<int64_t>(D), x8, s) != KNNG_OK) {
+        rc = set_err(KNNG_ERR_HIP, "uint8 copy launch failed");
+        goto done;
+    }
+    ev.record(1, s);
     if (direct) {
         cand_ids = ids_out;
         cand_d = dists_out;
@@ -219,6 +239,7 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
     for (int t0 = 0; t0 < T; t0 += slots) {
         knng::PartitionArgs pa{};
         pa.X = data;
+        pa.X8 = x8;
         pa.n = n;
         pa.D = D;
         pa.n_trees = slots;
@@ -298,6 +319,7 @@ done:
     if (perm) hipFreeAsync(perm, s);
     if (leaves) hipFreeAsync(leaves, s);
     if (dpairs) hipFreeAsync(dpairs, s);
+    if (x8) hipFreeAsync(x8, s);
     if (!direct) {
         if (cand_ids) hipFreeAsync(cand_ids, s);
         if (cand_d) hipFreeAsync(cand_d, s);
@@ -332,6 +354,7 @@ done:
         stats_out->n_k_leaf = kn[knng::kKLeaf];
         stats_out->ms_k_merge = kms[knng::kKMerge];
         stats_out->n_k_merge = kn[knng::kKMerge];
+        stats_out->compact_used = use_u8 ? 1 : 0;
     }
     return rc;
 }
@@ -364,23 +387,33 @@ int knng_partition(const float* data, int64_t n, int32_t D, int32_t leaf_max, in
         return set_err(KNNG_ERR_INVALID_ARG, "leaf_max < 2*min_leaf-1");
 
     hipStream_t s = stream;
-    int rc = check_finite(data, n * static_cast<int64_t>(D), s);
+    int all_u8 = 0;
+    int rc = scan_input(data, n * static_cast<int64_t>(D), true, &all_u8, s);
     if (rc != KNNG_OK) return rc;
+    const bool use_u8 = D % 16 == 0 && all_u8;  // same storage choice as knng_build
     const int64_t lcap = knng::max_leaves_per_tree(n, min_leaf);
     knng::LeafRec* leaves = nullptr;
+    uint8_t* x8 = nullptr;
     int32_t* dcount = nullptr;
     int32_t hcount = 0;
     char err[400] = "";
     knng::PartitionResult r;
     hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&leaves), sizeof(knng::LeafRec) * lcap, s);
     if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&dcount), sizeof(int32_t), s);
+    if (e == hipSuccess && use_u8)
+        e = hipMallocAsync(reinterpret_cast<void**>(&x8), static_cast<size_t>(n) * D, s);
     if (e != hipSuccess) {
         rc = hip_fail(e, "workspace allocation");
+        goto done;
+    }
+    if (use_u8 && knng::prep_to_u8(data, n * static_cast<int64_t>(D), x8, s) != KNNG_OK) {
+        rc = set_err(KNNG_ERR_HIP, "uint8 copy launch failed");
         goto done;
     }
     {
         knng::PartitionArgs pa{};
         pa.X = data;
+        pa.X8 = x8;
         pa.n = n;
         pa.D = D;
         pa.n_trees = 1;
@@ -418,6 +451,7 @@ int knng_partition(const float* data, int64_t n, int32_t D, int32_t leaf_max, in
 
 done:
     if (leaves) hipFreeAsync(leaves, s);
+    if (x8) hipFreeAsync(x8, s);
     if (dcount) hipFreeAsync(dcount, s);
     e = hipStreamSynchronize(s);
     if (rc == KNNG_OK && e != hipSuccess) rc = hip_fail(e, "partition");

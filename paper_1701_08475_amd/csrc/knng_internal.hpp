@@ -35,8 +35,10 @@ struct LeafRec {
 struct LevelCounters {
     int32_t n_next;     // active nodes of the next level
     int32_t nc_next;    // assignment chunks of the next level
+    int32_t n_big;      // next-level nodes spanning more than one chunk
     int32_t n_leaves;   // leaves so far
     int32_t n_log;      // bisected nodes logged so far
+    int32_t pad;
 };
 
 // Status codes (mirror include/knng.h).
@@ -75,6 +77,7 @@ class KernelTimer {
 // ---------------------------------------------------------------- partition
 struct PartitionArgs {
     const float* X;
+    const uint8_t* X8;      // nullable: the same values stored as uint8 (all integers 0..255)
     int64_t n;
     int D;
     int n_trees;      // trees tree0 .. tree0+n_trees-1 go to slots 0..n_trees-1
@@ -146,8 +149,11 @@ struct MergeArgs {
 int merge_run(const MergeArgs& a, int* launches, char* err, size_t errlen);
 
 // ---------------------------------------------------------------- prep
-// Sets *flag (device int) to 1 if X holds a NaN or Inf.
-int prep_check_finite(const float* X, int64_t count, int32_t* flag, hipStream_t s);
+// flags[0] <- 1 if X holds a NaN or Inf; flags[1] <- 1 if some value is not
+// an integer in [0, 255] (flags: device int[2]).
+int prep_scan(const float* X, int64_t count, int32_t* flags, hipStream_t s);
+// X8[i] = X[i] for data whose values are all integers in [0, 255].
+int prep_to_u8(const float* X, int64_t count, uint8_t* X8, hipStream_t s);
 
 // Converts per-tree leaf lists into sorted run boundaries (knng_partition).
 int leaves_to_offsets(const LeafRec* leaves, int64_t n_leaves, int64_t n, int tree,

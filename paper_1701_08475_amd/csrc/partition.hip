@@ -1,7 +1,7 @@
-// Level-synchronous two-means bisection of all trees at once (Sec. 3.1:
-// "bisecting the reference set repeatedly with two means clustering" until no
-// cluster exceeds the threshold; Alg. 1 "apply two means clustering",
-// "collect clusters set S").
+// Level-synchronous two-means bisection of all trees at once (Sec. 3.1: the
+// reference set is split in two by two-means clustering, again and again,
+// until no cluster holds more points than the threshold; Alg. 1, clustering
+// step and collection of the cluster set S).
 //
 // Every node of a level, in every tree, advances one Lloyd pass per launch.
 // A node is a contiguous run of perm[tree]; members keep ascending ids because
@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 namespace knng {
@@ -52,22 +53,26 @@ __device__ __forceinline__ uint64_t ordered_key(double v) {
     return (u >> 63) ? ~u : (u | (1ull << 63));
 }
 
-// ------------------------------------------------------------- kernels
+__device__ __forceinline__ int chunks_of(int size) { return (size + kChunkRows - 1) / kChunkRows; }
+
+// ------------------------------------------------------------- level setup
 // Root nodes (or root leaves when n <= leaf_max) of every tree slot.
-__global__ void k_roots(int T, int64_t n, int leaf_max, NodeRec* nodes, LeafRec* leaves,
-                        LevelCounters* ctr) {
+__global__ void k_roots(int T, int64_t n, int leaf_max, NodeRec* nodes, int32_t* big,
+                        LeafRec* leaves, LevelCounters* ctr) {
     const int nch = static_cast<int>((n + kChunkRows - 1) / kChunkRows);
+    const bool split = n > leaf_max;
     for (int t = threadIdx.x; t < T; t += blockDim.x) {
-        if (n > leaf_max) {
+        if (split) {
             nodes[t] = NodeRec{t, 0, static_cast<int32_t>(n), t * nch};
+            big[t] = t;
         } else {
             leaves[t] = LeafRec{t, 0, static_cast<int32_t>(n), 0};
         }
     }
     if (threadIdx.x == 0) {
-        const bool split = n > leaf_max;
         ctr->n_next = split ? T : 0;
         ctr->nc_next = split ? T * nch : 0;
+        ctr->n_big = (split && nch > 1) ? T : 0;
         ctr->n_leaves = split ? 0 : T;
         ctr->n_log = 0;
     }
@@ -80,63 +85,115 @@ __global__ void k_iota(int32_t* perm, int64_t n, int T) {
         perm[i] = static_cast<int32_t>(i % n);
 }
 
+__global__ void k_fill_u8(uint8_t* p, int64_t count) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < count;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[i] = 0;
+}
+
+__global__ void k_zero_small(unsigned long long* stats, int* flag) {
+    if (threadIdx.x < 2) stats[threadIdx.x] = 0ull;
+    if (threadIdx.x == 0) *flag = 0;
+}
+
 // chunk -> node map of a level.
 __global__ void k_chunk_map(const NodeRec* nodes, int32_t* chunk_node) {
     const NodeRec r = nodes[blockIdx.x];
-    const int nch = (r.size + kChunkRows - 1) / kChunkRows;
+    const int nch = chunks_of(r.size);
     for (int c = threadIdx.x; c < nch; c += blockDim.x) chunk_node[r.chunk0 + c] = blockIdx.x;
 }
 
 // Starting centres c0 = x[S[a]], c1 = x[S[b]] of every node; one wave each.
+// C holds per node c0[D] then c1[D] (FP64).
 __global__ __launch_bounds__(64) void k_init_nodes(const NodeRec* __restrict__ nodes,
                                                    const int32_t* __restrict__ perm,
                                                    const float* __restrict__ X, int64_t n, int D,
-                                                   uint64_t seed, int tree0, double* __restrict__ W,
-                                                   double* __restrict__ H,
+                                                   uint64_t seed, int tree0,
+                                                   double* __restrict__ C,
                                                    int32_t* __restrict__ status) {
     const int node = blockIdx.x;
-    const int lane = threadIdx.x;
     const NodeRec r = nodes[node];
     const size_t base = static_cast<size_t>(r.tree) * n + r.start;
     const uint64_t m = static_cast<uint64_t>(r.size);
     const uint64_t min_id = static_cast<uint64_t>(static_cast<uint32_t>(perm[base]));
     const uint64_t tg = static_cast<uint64_t>(tree0 + r.tree);
-    const uint64_t u0 = pair_hash(seed, tg, min_id, m, 0);
-    const uint64_t u1 = pair_hash(seed, tg, min_id, m, 1);
-    const uint64_t a = u0 % m;
-    uint64_t b = u1 % (m - 1);
+    const uint64_t a = pair_hash(seed, tg, min_id, m, 0) % m;
+    uint64_t b = pair_hash(seed, tg, min_id, m, 1) % (m - 1);
     if (b >= a) ++b;
-    const float* c0 = X + static_cast<size_t>(perm[base + a]) * D;
-    const float* c1 = X + static_cast<size_t>(perm[base + b]) * D;
-    double q0 = 0.0, q1 = 0.0;
-    double* w = W + static_cast<size_t>(node) * D;
-    for (int d = lane; d < D; d += kWave) {
-        const double x0 = c0[d], x1 = c1[d];
-        w[d] = x0 - x1;
-        q0 = fma(x0, x0, q0);
-        q1 = fma(x1, x1, q1);
+    const float* x0 = X + static_cast<size_t>(perm[base + a]) * D;
+    const float* x1 = X + static_cast<size_t>(perm[base + b]) * D;
+    double* c = C + static_cast<size_t>(node) * 2 * D;
+    for (int d = threadIdx.x; d < D; d += kWave) {
+        c[d] = static_cast<double>(x0[d]);
+        c[D + d] = static_cast<double>(x1[d]);
     }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        q0 += shfl_xor_f64(q0, o);
-        q1 += shfl_xor_f64(q1, o);
-    }
-    if (lane == 0) {
-        H[node] = 0.5 * (q0 - q1);
-        status[node] = 0;
-    }
+    if (threadIdx.x == 0) status[node] = 0;
 }
 
-// One Lloyd assignment pass over every chunk of every unfinished node.
-// G lanes share one row; each lane holds NF groups of VEC consecutive
-// elements (element e = (lane_in_group + G*j)*VEC + v).
-template <int G, int NF, int VEC>
+// ------------------------------------------------------------- Lloyd pass
+// Element storage of the reference set for the assignment passes: FP32 as
+// given, or a lossless uint8 copy when every value is an integer in [0, 255]
+// (each stored value is the same number, so every result is unchanged).
+template <typename TX, int VEC>
+struct RowVec;
+template <>
+struct RowVec<float, 1> {  // one float per load (rows not 16-byte aligned)
+    static constexpr int kVec = 1;
+    using Acc = double;
+    __device__ static void load(const float* row, int e, int D, bool ok, float (&x)[1]) {
+        x[0] = (ok && e < D) ? row[e] : 0.f;
+    }
+};
+template <>
+struct RowVec<float, 4> {  // 4 floats per 16-byte load
+    static constexpr int kVec = 4;
+    using Acc = double;
+    __device__ static void load(const float* row, int e, int D, bool ok, float (&x)[4]) {
+        float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (ok && e < D) q = *reinterpret_cast<const float4*>(row + e);
+        x[0] = q.x;
+        x[1] = q.y;
+        x[2] = q.z;
+        x[3] = q.w;
+    }
+};
+template <>
+struct RowVec<uint8_t, 16> {  // 16 bytes per 16-byte load; exact integer sums
+    static constexpr int kVec = 16;
+    using Acc = uint32_t;
+    __device__ static void load(const uint8_t* row, int e, int D, bool ok, float (&x)[16]) {
+        uint4 q = make_uint4(0u, 0u, 0u, 0u);
+        if (ok && e < D) q = *reinterpret_cast<const uint4*>(row + e);
+        const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) x[4 * i + b] = static_cast<float>((w4[i] >> (8 * b)) & 255u);
+    }
+};
+
+// One assignment pass over every chunk of every unfinished node.
+// G lanes share one row; each lane holds NF vectors of VEC consecutive
+// elements (element e = (lane_in_group + G*j)*VEC + v).  Each lane group
+// takes U rows per step (row = row0 + (step*U + u)*RPW + group).  Loads are
+// software-pipelined: the rows of step s+1 are in flight while step s is
+// computed, and the row ids of step s+2 are fetched meanwhile.
+//
+// w and h are derived by every wave from the node's centres with the same
+// lane layout, so all waves of a node use bit-identical values.  A node of
+// one chunk moves its centres at the end of the pass from the wave's own
+// sums; larger nodes publish per-chunk sums for k_update_big.  A node stops
+// when no label changed, a side is empty, or the pass budget is spent; its
+// centres are then the ones that produced its final labels.
+template <typename TX, int VEC, int G, int NF, int U>
 __global__ __launch_bounds__(256) void k_assign(
-    const float* __restrict__ X, int64_t n, int D, const int32_t* __restrict__ perm,
+    const TX* __restrict__ X, int64_t n, int D, const int32_t* __restrict__ perm,
     const NodeRec* __restrict__ nodes, const int32_t* __restrict__ chunk_node, int nc,
-    const double* __restrict__ W, const double* __restrict__ H,
-    const int32_t* __restrict__ status, uint8_t* __restrict__ labels,
-    double* __restrict__ dots, double* __restrict__ P, int32_t* __restrict__ cnt, int pass) {
+    double* __restrict__ C, int32_t* __restrict__ status, int32_t* __restrict__ n0f,
+    uint8_t* __restrict__ labels, double* __restrict__ dots, double* __restrict__ P,
+    int32_t* __restrict__ cnt, int pass, int max_iter, unsigned long long* __restrict__ assigned) {
+    using RV = RowVec<TX, VEC>;
+    using Acc = typename RV::Acc;
     constexpr int RPW = kWave / G;  // rows per wave step
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (wave >= nc) return;
@@ -145,78 +202,102 @@ __global__ __launch_bounds__(256) void k_assign(
     const NodeRec r = nodes[node];
     const int lane = threadIdx.x & 63;
     const int g = lane / G, l = lane % G;
+    const int nch = chunks_of(r.size);
     const int row0 = (wave - r.chunk0) * kChunkRows;
     const int row1 = min(r.size, row0 + kChunkRows);
     const size_t base = static_cast<size_t>(r.tree) * n + r.start;
 
+    double* cn = C + static_cast<size_t>(node) * 2 * D;
     double w[NF][VEC];
-    double a0[NF][VEC], a1[NF][VEC];
-    const double* wn = W + static_cast<size_t>(node) * D;
+    Acc a0[NF][VEC], a1[NF][VEC];
+    double q0 = 0.0, q1 = 0.0;
 #pragma unroll
     for (int j = 0; j < NF; ++j)
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
             const int e = (l + G * j) * VEC + v;
-            w[j][v] = e < D ? wn[e] : 0.0;
-            a0[j][v] = 0.0;
-            a1[j][v] = 0.0;
+            const double c0 = e < D ? cn[e] : 0.0;
+            const double c1 = e < D ? cn[D + e] : 0.0;
+            w[j][v] = c0 - c1;
+            q0 = fma(c0, c0, q0);
+            q1 = fma(c1, c1, q1);
+            a0[j][v] = Acc(0);
+            a1[j][v] = Acc(0);
         }
-    const double h = H[node];
+#pragma unroll
+    for (int o = G / 2; o >= 1; o >>= 1) {
+        q0 += shfl_xor_f64(q0, o);
+        q1 += shfl_xor_f64(q1, o);
+    }
+    const double h = 0.5 * (q0 - q1);
     int n1 = 0, changed = 0;
 
-    const int iters = (row1 - row0 + RPW - 1) / RPW;
-    for (int it = 0; it < iters; ++it) {
-        const int row = row0 + it * RPW + g;
-        const bool valid = row < row1;
-        float x[NF][VEC];
-        if (valid) {
-            const float* xr = X + static_cast<size_t>(perm[base + row]) * D;
+    const int steps = (row1 - row0 + RPW * U - 1) / (RPW * U);
+    auto row_id = [&](int st, int u) -> int {
+        const int row = row0 + (st * U + u) * RPW + g;
+        return row < row1 ? perm[base + row] : -1;
+    };
+    auto load_rows = [&](const int (&id)[U], float (&x)[U][NF][VEC]) {
 #pragma unroll
-            for (int j = 0; j < NF; ++j) {
-                const int e = (l + G * j) * VEC;
-                if constexpr (VEC == 4) {
-                    float4 q = e < D ? *reinterpret_cast<const float4*>(xr + e)
-                                     : make_float4(0.f, 0.f, 0.f, 0.f);
-                    x[j][0] = q.x;
-                    x[j][VEC > 1 ? 1 : 0] = q.y;
-                    x[j][VEC > 2 ? 2 : 0] = q.z;
-                    x[j][VEC > 3 ? 3 : 0] = q.w;
-                } else {
+        for (int u = 0; u < U; ++u) {
+            const TX* xr = X + static_cast<size_t>(id[u] < 0 ? 0 : id[u]) * D;
 #pragma unroll
-                    for (int v = 0; v < VEC; ++v) x[j][v] = (e + v) < D ? xr[e + v] : 0.f;
-                }
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < NF; ++j)
-#pragma unroll
-                for (int v = 0; v < VEC; ++v) x[j][v] = 0.f;
+            for (int j = 0; j < NF; ++j) RV::load(xr, (l + G * j) * VEC, D, id[u] >= 0, x[u][j]);
         }
-        double dot = 0.0;
+    };
+    int idc[U], idn[U];
+    float xc[U][NF][VEC];
 #pragma unroll
-        for (int j = 0; j < NF; ++j)
+    for (int u = 0; u < U; ++u) {
+        idc[u] = row_id(0, u);
+        idn[u] = row_id(1, u);
+    }
+    load_rows(idc, xc);
+    for (int st = 0; st < steps; ++st) {
+        float xn[U][NF][VEC];
+        load_rows(idn, xn);  // rows of step st+1 (ids -1 past the end)
+        int idnn[U];
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) dot = fma(static_cast<double>(x[j][v]), w[j][v], dot);
+        for (int u = 0; u < U; ++u) idnn[u] = row_id(st + 2, u);
 #pragma unroll
-        for (int o = G / 2; o >= 1; o >>= 1) dot += shfl_xor_f64(dot, o);
-        const bool lab = dot < h;
-        if (valid) {
-            if (l == 0) {
-                const size_t p = base + row;
-                const uint8_t old = labels[p];
-                labels[p] = lab ? 1 : 0;
-                dots[p] = dot;
-                changed += (pass > 0 && old != (lab ? 1 : 0)) ? 1 : 0;
-                n1 += lab ? 1 : 0;
-            }
+        for (int u = 0; u < U; ++u) {
+            const int row = row0 + (st * U + u) * RPW + g;
+            double dot = 0.0;
 #pragma unroll
             for (int j = 0; j < NF; ++j)
 #pragma unroll
-                for (int v = 0; v < VEC; ++v) {
-                    const double xv = static_cast<double>(x[j][v]);
-                    a0[j][v] += lab ? 0.0 : xv;
-                    a1[j][v] += lab ? xv : 0.0;
+                for (int v = 0; v < VEC; ++v)
+                    dot = fma(static_cast<double>(xc[u][j][v]), w[j][v], dot);
+#pragma unroll
+            for (int o = G / 2; o >= 1; o >>= 1) dot += shfl_xor_f64(dot, o);
+            const bool lab = dot < h;
+            if (idc[u] >= 0) {
+                if (l == 0) {
+                    const size_t p = base + row;
+                    const uint8_t old = labels[p];
+                    labels[p] = lab ? 1 : 0;
+                    dots[p] = dot;
+                    changed += (pass > 0 && old != (lab ? 1 : 0)) ? 1 : 0;
+                    n1 += lab ? 1 : 0;
                 }
+#pragma unroll
+                for (int j = 0; j < NF; ++j)
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) {
+                        const Acc xv = static_cast<Acc>(xc[u][j][v]);
+                        a0[j][v] += lab ? Acc(0) : xv;
+                        a1[j][v] += lab ? xv : Acc(0);
+                    }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            idc[u] = idn[u];
+            idn[u] = idnn[u];
+#pragma unroll
+            for (int j = 0; j < NF; ++j)
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) xc[u][j][v] = xn[u][j][v];
         }
     }
     // combine the RPW row groups of the wave (fixed butterfly order)
@@ -226,96 +307,148 @@ __global__ __launch_bounds__(256) void k_assign(
         for (int j = 0; j < NF; ++j)
 #pragma unroll
             for (int v = 0; v < VEC; ++v) {
-                a0[j][v] += shfl_xor_f64(a0[j][v], o);
-                a1[j][v] += shfl_xor_f64(a1[j][v], o);
+                if constexpr (sizeof(Acc) == 8) {
+                    a0[j][v] += shfl_xor_f64(a0[j][v], o);
+                    a1[j][v] += shfl_xor_f64(a1[j][v], o);
+                } else {
+                    a0[j][v] += __shfl_xor(a0[j][v], o, kWave);
+                    a1[j][v] += __shfl_xor(a1[j][v], o, kWave);
+                }
             }
     n1 = wave_sum_i32(n1);
     changed = wave_sum_i32(changed);
-    if (g == 0) {
+    if (lane == 0) {
+        cnt[2 * wave] = n1;  // ones of this chunk (also read by the scatter)
+        cnt[2 * wave + 1] = changed;
+        atomicAdd(assigned, static_cast<unsigned long long>(row1 - row0));
+    }
+
+    if (nch == 1) {  // the wave holds the whole node
+        const int n0 = r.size - n1;
+        const bool stop =
+            n1 == 0 || n0 == 0 || (pass >= 1 && changed == 0) || pass + 1 >= max_iter;
+        if (stop) {
+            if (lane == 0) {
+                status[node] = 1;
+                n0f[node] = n0;
+            }
+            return;
+        }
+        if (g == 0) {
+            const double dn0 = static_cast<double>(n0), dn1 = static_cast<double>(n1);
+#pragma unroll
+            for (int j = 0; j < NF; ++j)
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    const int e = (l + G * j) * VEC + v;
+                    if (e < D) {
+                        cn[e] = static_cast<double>(a0[j][v]) / dn0;
+                        cn[D + e] = static_cast<double>(a1[j][v]) / dn1;
+                    }
+                }
+        }
+        return;
+    }
+    if (g == 0) {  // publish this chunk's sums
         double* p0 = P + static_cast<size_t>(wave) * 2 * D;
-        double* p1 = p0 + D;
 #pragma unroll
         for (int j = 0; j < NF; ++j)
 #pragma unroll
             for (int v = 0; v < VEC; ++v) {
                 const int e = (l + G * j) * VEC + v;
                 if (e < D) {
-                    p0[e] = a0[j][v];
-                    p1[e] = a1[j][v];
+                    p0[e] = static_cast<double>(a0[j][v]);
+                    p0[D + e] = static_cast<double>(a1[j][v]);
                 }
             }
     }
-    if (lane == 0) {
-        cnt[2 * wave] = n1;
-        cnt[2 * wave + 1] = changed;
-    }
 }
 
-// After a pass: stop the node (nothing changed, a side empty, or the pass
-// budget spent) or move its centres to the means of the two sides.
-__global__ __launch_bounds__(256) void k_update(const NodeRec* __restrict__ nodes, int D,
-                                                const double* __restrict__ P,
-                                                const int32_t* __restrict__ cnt,
-                                                double* __restrict__ W, double* __restrict__ H,
-                                                int32_t* __restrict__ status,
-                                                int32_t* __restrict__ n0f, int pass, int max_iter,
-                                                unsigned long long* __restrict__ assigned) {
-    const int node = blockIdx.x;
+// Centre update of the nodes spanning several chunks.  One block per (node,
+// slice of 8 dimensions): 16 values (8 dims x 2 sides) x 16 chunk lanes; lane
+// c sums chunks c, c+16, ... in order, then the 16 lane sums are added in
+// lane order.  Every block of a node derives the same stop decision.
+constexpr int kUpdDims = 8;
+constexpr int kUpdLanes = 16;
+
+__global__ __launch_bounds__(256) void k_update_big(const NodeRec* __restrict__ nodes,
+                                                    const int32_t* __restrict__ big, int D,
+                                                    const double* __restrict__ P,
+                                                    const int32_t* __restrict__ cnt,
+                                                    double* __restrict__ C,
+                                                    int32_t* __restrict__ status,
+                                                    int32_t* __restrict__ n0f, int pass,
+                                                    int max_iter) {
+    const int slices = (D + kUpdDims - 1) / kUpdDims;
+    const int node = big[blockIdx.x / slices];
+    const int slice = blockIdx.x % slices;
     if (status[node]) return;
-    __shared__ int s_n1, s_changed;
-    __shared__ double red[2][256];
     const NodeRec r = nodes[node];
-    const int nch = (r.size + kChunkRows - 1) / kChunkRows;
-    const int c0 = r.chunk0;
-    if (threadIdx.x == 0) {
-        int a = 0, b = 0;
-        for (int c = 0; c < nch; ++c) {
-            a += cnt[2 * (c0 + c)];
-            b += cnt[2 * (c0 + c) + 1];
-        }
-        s_n1 = a;
-        s_changed = b;
-        atomicAdd(assigned, static_cast<unsigned long long>(r.size));
+    const int nch = chunks_of(r.size);
+    __shared__ int s_cnt[2][256];
+    __shared__ double s_sum[kUpdLanes][2 * kUpdDims];
+    const int tid = threadIdx.x;
+    int a = 0, b = 0;
+    for (int c = tid; c < nch; c += 256) {
+        a += cnt[2 * (r.chunk0 + c)];
+        b += cnt[2 * (r.chunk0 + c) + 1];
     }
+    s_cnt[0][tid] = a;
+    s_cnt[1][tid] = b;
     __syncthreads();
-    const int n1 = s_n1, n0 = r.size - n1;
-    const bool stop = n1 == 0 || n0 == 0 || (pass >= 1 && s_changed == 0) || pass + 1 >= max_iter;
+    for (int s = 128; s >= 1; s >>= 1) {
+        if (tid < s) {
+            s_cnt[0][tid] += s_cnt[0][tid + s];
+            s_cnt[1][tid] += s_cnt[1][tid + s];
+        }
+        __syncthreads();
+    }
+    const int n1 = s_cnt[0][0], changed = s_cnt[1][0];
+    const int n0 = r.size - n1;
+    const bool stop = n1 == 0 || n0 == 0 || (pass >= 1 && changed == 0) || pass + 1 >= max_iter;
     if (stop) {
-        if (threadIdx.x == 0) {
+        if (slice == 0 && tid == 0) {
             status[node] = 1;
             n0f[node] = n0;
         }
         return;
     }
-    double q0 = 0.0, q1 = 0.0;
-    double* w = W + static_cast<size_t>(node) * D;
-    const double dn0 = static_cast<double>(n0), dn1 = static_cast<double>(n1);
-    for (int d = threadIdx.x; d < D; d += 256) {
-        double s0 = 0.0, s1 = 0.0;
-        const double* p = P + static_cast<size_t>(c0) * 2 * D + d;
-        for (int c = 0; c < nch; ++c) {
-            s0 += p[0];
-            s1 += p[D];
-            p += 2 * static_cast<size_t>(D);
+    // value v: side = v / kUpdDims, dim = slice*kUpdDims + v % kUpdDims
+    const int v = tid % (2 * kUpdDims), cl = tid / (2 * kUpdDims);
+    const int side = v / kUpdDims, d = slice * kUpdDims + v % kUpdDims;
+    double sum = 0.0;
+    if (d < D) {
+        const size_t sD = static_cast<size_t>(D);
+        const size_t step = static_cast<size_t>(kUpdLanes) * 2 * sD;
+        const double* q = P + (static_cast<size_t>(r.chunk0) + cl) * 2 * sD + side * sD + d;
+        int c = cl;
+        for (; c + 3 * kUpdLanes < nch; c += 4 * kUpdLanes) {  // loads in flight, adds in order
+            const double x0 = q[0];
+            const double x1 = q[step];
+            const double x2 = q[2 * step];
+            const double x3 = q[3 * step];
+            sum += x0;
+            sum += x1;
+            sum += x2;
+            sum += x3;
+            q += 4 * step;
         }
-        const double m0 = s0 / dn0, m1 = s1 / dn1;
-        w[d] = m0 - m1;
-        q0 = fma(m0, m0, q0);
-        q1 = fma(m1, m1, q1);
+        for (; c < nch; c += kUpdLanes) {
+            sum += q[0];
+            q += step;
+        }
     }
-    red[0][threadIdx.x] = q0;
-    red[1][threadIdx.x] = q1;
+    s_sum[cl][v] = sum;
     __syncthreads();
-    for (int s = 128; s >= 1; s >>= 1) {
-        if (threadIdx.x < s) {
-            red[0][threadIdx.x] += red[0][threadIdx.x + s];
-            red[1][threadIdx.x] += red[1][threadIdx.x + s];
-        }
-        __syncthreads();
+    if (tid < 2 * kUpdDims && d < D) {
+        double t = 0.0;
+        for (int k = 0; k < kUpdLanes; ++k) t += s_sum[k][tid];
+        const double cnt_side = side ? static_cast<double>(n1) : static_cast<double>(n0);
+        C[static_cast<size_t>(node) * 2 * D + side * static_cast<size_t>(D) + d] = t / cnt_side;
     }
-    if (threadIdx.x == 0) H[node] = 0.5 * (red[0][0] - red[1][0]);
 }
 
+// ------------------------------------------------------------- repair
 // Block-wide exclusive scan of one flag per thread (256 threads).
 __device__ __forceinline__ int block_excl_scan_flag(bool f, int* warp_tot, int* total) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -334,15 +467,16 @@ __device__ __forceinline__ int block_excl_scan_flag(bool f, int* warp_tot, int* 
 }
 
 // Margin-rank repair of nodes with a side smaller than min_leaf: order the
-// members by (mu, id), mu = |x-c0|^2 - |x-c1|^2 = 2 (h - dot), and put the
-// first s on the left, s = clamp(n0, min_leaf, m - min_leaf), or floor(m/2)
-// when every margin is equal.  Exact rank s is found by radix selection on
-// the 64-bit key of (h - dot); equal keys go by position (= id order).
+// members by (mu, id), mu = |x-c0|^2 - |x-c1|^2 = 2 (h - dot), i.e. by
+// descending dot, and put the first s on the left, s = clamp(n0, min_leaf,
+// m - min_leaf), or floor(m/2) when every margin is equal.  Rank s is found
+// exactly by radix selection on the 64-bit key of -dot; equal keys go by
+// position (= id order).  Per-chunk ones counts are rewritten.
 __global__ __launch_bounds__(256) void k_repair(const NodeRec* __restrict__ nodes, int64_t n,
-                                                const double* __restrict__ H,
                                                 const double* __restrict__ dots,
                                                 uint8_t* __restrict__ labels,
                                                 int32_t* __restrict__ n0f, int min_leaf,
+                                                int32_t* __restrict__ cnt,
                                                 unsigned long long* __restrict__ repairs) {
     const int node = blockIdx.x;
     const NodeRec r = nodes[node];
@@ -350,7 +484,6 @@ __global__ __launch_bounds__(256) void k_repair(const NodeRec* __restrict__ node
     const int n0 = n0f[node];
     if (n0 >= min_leaf && m - n0 >= min_leaf) return;
     const size_t base = static_cast<size_t>(r.tree) * n + r.start;
-    const double h = H[node];
     __shared__ unsigned int hist[256];
     __shared__ unsigned long long s_min[256], s_max[256];
     __shared__ unsigned long long s_prefix;
@@ -360,7 +493,7 @@ __global__ __launch_bounds__(256) void k_repair(const NodeRec* __restrict__ node
 
     unsigned long long kmin = ~0ull, kmax = 0ull;
     for (int p = tid; p < m; p += 256) {
-        const unsigned long long key = ordered_key(h - dots[base + p]);
+        const unsigned long long key = ordered_key(-dots[base + p]);
         kmin = key < kmin ? key : kmin;
         kmax = key > kmax ? key : kmax;
     }
@@ -391,7 +524,7 @@ __global__ __launch_bounds__(256) void k_repair(const NodeRec* __restrict__ node
         __syncthreads();
         const unsigned long long hi = shift == 56 ? 0ull : (~0ull << (shift + 8));
         for (int p = tid; p < m; p += 256) {
-            const unsigned long long key = ordered_key(h - dots[base + p]);
+            const unsigned long long key = ordered_key(-dots[base + p]);
             if ((key & hi) == (prefix & hi)) atomicAdd(&hist[(key >> shift) & 255ull], 1u);
         }
         __syncthreads();
@@ -413,20 +546,26 @@ __global__ __launch_bounds__(256) void k_repair(const NodeRec* __restrict__ node
         __syncthreads();
     }
     // relabel: keys below the selected key go left, above go right, equal
-    // keys go left while their running count (in position order) < rem
-    int run = 0;
+    // keys go left while their running count (in position order) < rem.
+    // kChunkRows is a multiple of 256, so each step lies in one chunk.
+    int run = 0, ones = 0;
     for (int p0 = 0; p0 < m; p0 += 256) {
         const int p = p0 + tid;
         const bool valid = p < m;
-        const unsigned long long key = valid ? ordered_key(h - dots[base + p]) : 0ull;
+        const unsigned long long key = valid ? ordered_key(-dots[base + p]) : 0ull;
         const bool eq = valid && key == prefix;
         int tot;
         const int rank = run + block_excl_scan_flag(eq, warp_tot, &tot);
-        if (valid) {
-            const bool right = key > prefix || (eq && rank >= rem);
-            labels[base + p] = right ? 1 : 0;
-        }
+        const bool right = valid && (key > prefix || (eq && rank >= rem));
+        if (valid) labels[base + p] = right ? 1 : 0;
         run += tot;
+        int tot1;
+        block_excl_scan_flag(right, warp_tot, &tot1);
+        ones += tot1;
+        if (p0 + 256 >= m || ((p0 + 256) % kChunkRows) == 0) {
+            if (tid == 0) cnt[2 * (r.chunk0 + p0 / kChunkRows)] = ones;
+            ones = 0;
+        }
     }
     if (tid == 0) {
         n0f[node] = s;
@@ -434,30 +573,13 @@ __global__ __launch_bounds__(256) void k_repair(const NodeRec* __restrict__ node
     }
 }
 
-// Ones per chunk after the (possibly repaired) final labels.
-__global__ __launch_bounds__(256) void k_count(int64_t n, const NodeRec* __restrict__ nodes,
-                                               const int32_t* __restrict__ chunk_node, int nc,
-                                               const uint8_t* __restrict__ labels,
-                                               int32_t* __restrict__ cnt1) {
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (wave >= nc) return;
-    const int lane = threadIdx.x & 63;
-    const NodeRec r = nodes[chunk_node[wave]];
-    const int row0 = (wave - r.chunk0) * kChunkRows;
-    const int row1 = min(r.size, row0 + kChunkRows);
-    const size_t base = static_cast<size_t>(r.tree) * n + r.start;
-    int c = 0;
-    for (int row = row0 + lane; row < row1; row += kWave) c += labels[base + row];
-    c = wave_sum_i32(c);
-    if (lane == 0) cnt1[wave] = c;
-}
-
+// ------------------------------------------------------------- split
 // Stable partition of every node: label-0 members first, then label-1, each
 // in their previous (ascending id) order.  Writes into perm_tmp.
 __global__ __launch_bounds__(256) void k_scatter(int64_t n, const NodeRec* __restrict__ nodes,
                                                  const int32_t* __restrict__ chunk_node, int nc,
                                                  const uint8_t* __restrict__ labels,
-                                                 const int32_t* __restrict__ cnt1,
+                                                 const int32_t* __restrict__ cnt,
                                                  const int32_t* __restrict__ n0f,
                                                  const int32_t* __restrict__ perm,
                                                  int32_t* __restrict__ perm_tmp) {
@@ -470,7 +592,7 @@ __global__ __launch_bounds__(256) void k_scatter(int64_t n, const NodeRec* __res
     const int row1 = min(r.size, row0 + kChunkRows);
     const size_t base = static_cast<size_t>(r.tree) * n + r.start;
     int pre = 0;
-    for (int c = r.chunk0 + lane; c < wave; c += kWave) pre += cnt1[c];
+    for (int c = r.chunk0 + lane; c < wave; c += kWave) pre += cnt[2 * c];
     pre = wave_sum_i32(pre);
     const int n0 = n0f[node];
     int run = 0;
@@ -503,26 +625,29 @@ __global__ __launch_bounds__(256) void k_copyback(int64_t n, const NodeRec* __re
 }
 
 // Children of every node of the level: runs of size > leaf_max become the
-// next level's nodes (in parent order, left first), the others become
-// leaves.  One block; deterministic order.
+// next level's nodes (in parent order, left first), the others leaves; next
+// nodes of several chunks are also listed in `big`.  One block; the order is
+// deterministic.
 __global__ __launch_bounds__(1024) void k_next_level(
     const NodeRec* __restrict__ cur, int n_cur, const int32_t* __restrict__ n0f, int leaf_max,
-    int depth, NodeRec* __restrict__ next, LeafRec* __restrict__ leaves, int64_t leaves_cap,
-    int32_t* __restrict__ node_log, int64_t node_log_cap, LevelCounters* __restrict__ ctr,
-    int* __restrict__ overflow) {
-    __shared__ int s_int[1024], s_leaf[1024], s_ch[1024];
+    int depth, NodeRec* __restrict__ next, int32_t* __restrict__ big, LeafRec* __restrict__ leaves,
+    int64_t leaves_cap, int32_t* __restrict__ node_log, int64_t node_log_cap,
+    LevelCounters* __restrict__ ctr, int* __restrict__ overflow) {
+    __shared__ int s_int[1024], s_leaf[1024], s_ch[1024], s_big[1024];
     __shared__ int s_base_leaf, s_base_log;
     const int tid = threadIdx.x;
     const int per = (n_cur + 1023) / 1024;
     const int i0 = min(n_cur, tid * per), i1 = min(n_cur, i0 + per);
-    int ci = 0, cl = 0, cc = 0;
+    int ci = 0, cl = 0, cc = 0, cb = 0;
     for (int i = i0; i < i1; ++i) {
         const NodeRec r = cur[i];
         const int sz[2] = {n0f[i], r.size - n0f[i]};
         for (int s = 0; s < 2; ++s) {
             if (sz[s] > leaf_max) {
                 ++ci;
-                cc += (sz[s] + kChunkRows - 1) / kChunkRows;
+                const int ch = (sz[s] + kChunkRows - 1) / kChunkRows;
+                cc += ch;
+                cb += ch > 1 ? 1 : 0;
             } else {
                 ++cl;
             }
@@ -531,26 +656,29 @@ __global__ __launch_bounds__(1024) void k_next_level(
     s_int[tid] = ci;
     s_leaf[tid] = cl;
     s_ch[tid] = cc;
+    s_big[tid] = cb;
     if (tid == 0) {
         s_base_leaf = ctr->n_leaves;
         s_base_log = ctr->n_log;
     }
     __syncthreads();
-    // inclusive Hillis-Steele scans
-    for (int o = 1; o < 1024; o <<= 1) {
-        int a = 0, b = 0, c = 0;
+    for (int o = 1; o < 1024; o <<= 1) {  // inclusive Hillis-Steele scans
+        int a = 0, b = 0, c = 0, e = 0;
         if (tid >= o) {
             a = s_int[tid - o];
             b = s_leaf[tid - o];
             c = s_ch[tid - o];
+            e = s_big[tid - o];
         }
         __syncthreads();
         s_int[tid] += a;
         s_leaf[tid] += b;
         s_ch[tid] += c;
+        s_big[tid] += e;
         __syncthreads();
     }
-    int oi = s_int[tid] - ci, ol = s_base_leaf + s_leaf[tid] - cl, oc = s_ch[tid] - cc;
+    int oi = s_int[tid] - ci, ol = s_base_leaf + s_leaf[tid] - cl, oc = s_ch[tid] - cc,
+        ob = s_big[tid] - cb;
     for (int i = i0; i < i1; ++i) {
         const NodeRec r = cur[i];
         const int n0 = n0f[i];
@@ -567,8 +695,10 @@ __global__ __launch_bounds__(1024) void k_next_level(
         const int sz[2] = {n0, r.size - n0};
         for (int s = 0; s < 2; ++s) {
             if (sz[s] > leaf_max) {
+                const int ch = (sz[s] + kChunkRows - 1) / kChunkRows;
+                if (ch > 1) big[ob++] = oi;
                 next[oi++] = NodeRec{r.tree, st[s], sz[s], oc};
-                oc += (sz[s] + kChunkRows - 1) / kChunkRows;
+                oc += ch;
             } else {
                 if (ol < leaves_cap)
                     leaves[ol] = LeafRec{r.tree, st[s], sz[s], 0};
@@ -582,44 +712,79 @@ __global__ __launch_bounds__(1024) void k_next_level(
     if (tid == 1023) {
         ctr->n_next = s_int[1023];
         ctr->nc_next = s_ch[1023];
+        ctr->n_big = s_big[1023];
         ctr->n_leaves = s_base_leaf + s_leaf[1023];
         ctr->n_log = s_base_log + n_cur;
     }
 }
 
 // ------------------------------------------------------------- dispatch
-using AssignFn = void (*)(const float*, int64_t, int, const int32_t*, const NodeRec*,
-                          const int32_t*, int, const double*, const double*, const int32_t*,
-                          uint8_t*, double*, double*, int32_t*, int);
+template <typename TX>
+using AssignFn = void (*)(const TX*, int64_t, int, const int32_t*, const NodeRec*, const int32_t*,
+                          int, double*, int32_t*, int32_t*, uint8_t*, double*, double*, int32_t*,
+                          int, int, unsigned long long*);
 
-template <int VEC>
-AssignFn pick_assign_vec(int D) {
-    const int E = D / VEC;
-    int G = 1;
-    while (G < 64 && G * 4 < E) G <<= 1;
-    if (G < 64) {
-        switch (G) {
-            case 1: return k_assign<1, 4, VEC>;
-            case 2: return k_assign<2, 4, VEC>;
-            case 4: return k_assign<4, 4, VEC>;
-            case 8: return k_assign<8, 4, VEC>;
-            case 16: return k_assign<16, 4, VEC>;
-            default: return k_assign<32, 4, VEC>;
-        }
+// Rows per lane group and step; more rows keep more loads in flight.
+template <typename TX, int VEC, int G, int NF>
+AssignFn<TX> pick_unroll(int u) {
+    switch (u) {
+        case 1: return k_assign<TX, VEC, G, NF, 1>;
+        case 4: return k_assign<TX, VEC, G, NF, 4>;
+        default: return k_assign<TX, VEC, G, NF, 2>;
     }
-    if (E <= 64 * 4) return k_assign<64, 4, VEC>;
-    if (E <= 64 * 8) return k_assign<64, 8, VEC>;
-    if (E <= 64 * 16) return k_assign<64, 16, VEC>;
+}
+
+// Smallest lane group G (<= 32) with G*NF vectors covering a row of E vectors.
+template <typename TX, int VEC, int NF>
+AssignFn<TX> pick_groups(int E, int u) {
+    int G = 1;
+    while (G < 32 && G * NF < E) G <<= 1;
+    switch (G) {
+        case 1: return pick_unroll<TX, VEC, 1, NF>(u);
+        case 2: return pick_unroll<TX, VEC, 2, NF>(u);
+        case 4: return pick_unroll<TX, VEC, 4, NF>(u);
+        case 8: return pick_unroll<TX, VEC, 8, NF>(u);
+        case 16: return pick_unroll<TX, VEC, 16, NF>(u);
+        default: return pick_unroll<TX, VEC, 32, NF>(u);
+    }
+}
+
+// FP32 rows.  epl: elements per lane (4, 8 or 16) for rows that fit 32
+// lanes; wider rows use all 64 lanes.
+AssignFn<float> pick_assign_f32(int D, int epl, int u) {
+    if (D % 4 == 0) {
+        const int E = D / 4;
+        if (E <= 32 * (epl / 4)) {
+            if (epl == 4) return pick_groups<float, 4, 1>(E, u);
+            if (epl == 8) return pick_groups<float, 4, 2>(E, u);
+            return pick_groups<float, 4, 4>(E, u);
+        }
+        if (E <= 64 * 4) return pick_unroll<float, 4, 64, 4>(u);
+        if (E <= 64 * 8) return k_assign<float, 4, 64, 8, 1>;
+        if (E <= 64 * 16) return k_assign<float, 4, 64, 16, 1>;
+        return nullptr;
+    }
+    if (D <= 32 * 4) return pick_groups<float, 1, 4>(D, 2);
+    if (D <= 64 * 4) return k_assign<float, 1, 64, 4, 2>;
+    if (D <= 64 * 8) return k_assign<float, 1, 64, 8, 1>;
+    if (D <= 64 * 16) return k_assign<float, 1, 64, 16, 1>;
     return nullptr;
 }
 
-AssignFn pick_assign(int D) {
-    return (D % 4 == 0) ? pick_assign_vec<4>(D) : pick_assign_vec<1>(D);
+// uint8 rows (D % 16 == 0): 16 elements per lane.
+AssignFn<uint8_t> pick_assign_u8(int D, int u) {
+    const int E = D / 16;
+    if (E <= 32) return pick_groups<uint8_t, 16, 1>(E, u);
+    if (E <= 64) return pick_unroll<uint8_t, 16, 64, 1>(u);
+    if (E <= 128) return k_assign<uint8_t, 16, 64, 2, 1>;
+    if (E <= 256) return k_assign<uint8_t, 16, 64, 4, 1>;
+    return nullptr;
 }
 
-struct DevBuf {
-    void* p = nullptr;
-};
+int env_int(const char* name, int dflt) {
+    const char* e = std::getenv(name);
+    return e ? std::atoi(e) : dflt;
+}
 
 }  // namespace
 
@@ -652,20 +817,32 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     const int T = a.n_trees;
     const int L = a.leaf_max;
     hipStream_t s = a.stream;
-    AssignFn assign = pick_assign(D);
-    if (assign == nullptr) {
+    // Tuned on MI355X (1M x 128 rows): FP32 rows 8 elements per lane, one row
+    // per lane group and step; uint8 rows four.  The environment may override
+    // both for tuning runs.
+    const bool use_u8 = a.X8 != nullptr && D % 16 == 0;
+    int epl = env_int("KNNG_ASSIGN_EPL", 8);
+    int unroll = env_int("KNNG_ASSIGN_UNROLL", use_u8 ? 4 : 1);
+    if (epl != 4 && epl != 8 && epl != 16) epl = 8;
+    if (unroll != 1 && unroll != 2 && unroll != 4) unroll = use_u8 ? 4 : 1;
+    AssignFn<float> assign = use_u8 ? nullptr : pick_assign_f32(D, epl, unroll);
+    AssignFn<uint8_t> assign8 = use_u8 ? pick_assign_u8(D, unroll) : nullptr;
+    if (assign == nullptr && assign8 == nullptr) {
         std::snprintf(err, errlen, "dimension %d not supported by the partition kernels", D);
         return kUnsupported;
     }
     // capacities: active nodes of a level are disjoint runs of > L points
     const int64_t nmax = std::max<int64_t>(1, static_cast<int64_t>(T) * (n / (L + 1) + 1));
-    const int64_t cmax = static_cast<int64_t>(T) * ((n + kChunkRows - 1) / kChunkRows + n / (L + 1) + 1);
+    const int64_t cmax =
+        static_cast<int64_t>(T) * ((n + kChunkRows - 1) / kChunkRows + n / (L + 1) + 1);
     const size_t tn = static_cast<size_t>(T) * n;
+    const int slices = (D + kUpdDims - 1) / kUpdDims;
 
     NodeRec* nodes[2] = {nullptr, nullptr};
+    int32_t* big[2] = {nullptr, nullptr};
     int32_t *chunk_node = nullptr, *status = nullptr, *n0f = nullptr, *cnt = nullptr,
-            *cnt1 = nullptr, *perm_tmp = nullptr, *overflow = nullptr;
-    double *W = nullptr, *H = nullptr, *P = nullptr, *dots = nullptr;
+            *perm_tmp = nullptr, *overflow = nullptr;
+    double *C = nullptr, *P = nullptr, *dots = nullptr;
     uint8_t* labels = nullptr;
     LevelCounters* ctr = nullptr;
     unsigned long long* dstats = nullptr;
@@ -676,34 +853,35 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     int depth = 0;
     int64_t splits = 0;
 
-    KNNG_HIP(hipHostMalloc(reinterpret_cast<void**>(&hctr), sizeof(LevelCounters), hipHostMallocDefault));
+    KNNG_HIP(hipHostMalloc(reinterpret_cast<void**>(&hctr), sizeof(LevelCounters),
+                           hipHostMallocDefault));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&nodes[0]), sizeof(NodeRec) * nmax, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&nodes[1]), sizeof(NodeRec) * nmax, s));
+    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&big[0]), sizeof(int32_t) * nmax, s));
+    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&big[1]), sizeof(int32_t) * nmax, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&chunk_node), sizeof(int32_t) * cmax, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&status), sizeof(int32_t) * nmax, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&n0f), sizeof(int32_t) * nmax, s));
-    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&W), sizeof(double) * nmax * D, s));
-    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&H), sizeof(double) * nmax, s));
+    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&C), sizeof(double) * nmax * 2 * D, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&P), sizeof(double) * cmax * 2 * D, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&cnt), sizeof(int32_t) * cmax * 2, s));
-    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&cnt1), sizeof(int32_t) * cmax, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&labels), tn, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&dots), sizeof(double) * tn, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&perm_tmp), sizeof(int32_t) * tn, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&ctr), sizeof(LevelCounters), s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&dstats), sizeof(unsigned long long) * 2, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&overflow), sizeof(int), s));
-    KNNG_HIP(hipMemsetAsync(dstats, 0, sizeof(unsigned long long) * 2, s));
-    KNNG_HIP(hipMemsetAsync(overflow, 0, sizeof(int), s));
-    KNNG_HIP(hipMemsetAsync(labels, 0, tn, s));
-
+    k_zero_small<<<1, 64, 0, s>>>(dstats, overflow);
+    KNNG_LAUNCH();
     {
         const int64_t want = (static_cast<int64_t>(tn) + 255) / 256;
         const int blocks = static_cast<int>(std::min<int64_t>(want, 65536));
+        k_fill_u8<<<blocks, 256, 0, s>>>(labels, static_cast<int64_t>(tn));
+        KNNG_LAUNCH();
         k_iota<<<blocks, 256, 0, s>>>(a.perm, n, T);
         KNNG_LAUNCH();
     }
-    k_roots<<<1, 64, 0, s>>>(T, n, L, nodes[0], a.leaves, ctr);
+    k_roots<<<1, 64, 0, s>>>(T, n, L, nodes[0], big[0], a.leaves, ctr);
     KNNG_LAUNCH();
     KNNG_HIP(hipMemcpyAsync(hctr, ctr, sizeof(LevelCounters), hipMemcpyDeviceToHost, s));
     KNNG_HIP(hipStreamSynchronize(s));
@@ -716,32 +894,40 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
         }
         const int na = hctr->n_next;
         const int nc = hctr->nc_next;
+        const int nb = hctr->n_big;
         const int cblocks = (nc + 3) / 4;
         k_chunk_map<<<na, 64, 0, s>>>(nodes[cur], chunk_node);
         KNNG_LAUNCH();
-        k_init_nodes<<<na, 64, 0, s>>>(nodes[cur], a.perm, a.X, n, D, a.seed, a.tree0, W, H, status);
+        k_init_nodes<<<na, 64, 0, s>>>(nodes[cur], a.perm, a.X, n, D, a.seed, a.tree0, C, status);
         KNNG_LAUNCH();
         for (int pass = 0; pass < a.max_iter; ++pass) {
             if (a.timer) a.timer->begin(kKAssign, s);
-            assign<<<cblocks, 256, 0, s>>>(a.X, n, D, a.perm, nodes[cur], chunk_node, nc, W, H,
-                                           status, labels, dots, P, cnt, pass);
+            if (use_u8)
+                assign8<<<cblocks, 256, 0, s>>>(a.X8, n, D, a.perm, nodes[cur], chunk_node, nc, C,
+                                                status, n0f, labels, dots, P, cnt, pass,
+                                                a.max_iter, dstats);
+            else
+                assign<<<cblocks, 256, 0, s>>>(a.X, n, D, a.perm, nodes[cur], chunk_node, nc, C,
+                                               status, n0f, labels, dots, P, cnt, pass,
+                                               a.max_iter, dstats);
             if (a.timer) a.timer->end(kKAssign, s);
             KNNG_LAUNCH();
-            k_update<<<na, 256, 0, s>>>(nodes[cur], D, P, cnt, W, H, status, n0f, pass,
-                                        a.max_iter, dstats);
-            KNNG_LAUNCH();
+            if (nb > 0) {
+                k_update_big<<<nb * slices, 256, 0, s>>>(nodes[cur], big[cur], D, P, cnt, C,
+                                                         status, n0f, pass, a.max_iter);
+                KNNG_LAUNCH();
+            }
         }
-        k_repair<<<na, 256, 0, s>>>(nodes[cur], n, H, dots, labels, n0f, a.min_leaf, dstats + 1);
+        k_repair<<<na, 256, 0, s>>>(nodes[cur], n, dots, labels, n0f, a.min_leaf, cnt, dstats + 1);
         KNNG_LAUNCH();
-        k_count<<<cblocks, 256, 0, s>>>(n, nodes[cur], chunk_node, nc, labels, cnt1);
-        KNNG_LAUNCH();
-        k_scatter<<<cblocks, 256, 0, s>>>(n, nodes[cur], chunk_node, nc, labels, cnt1, n0f,
-                                          a.perm, perm_tmp);
+        k_scatter<<<cblocks, 256, 0, s>>>(n, nodes[cur], chunk_node, nc, labels, cnt, n0f, a.perm,
+                                          perm_tmp);
         KNNG_LAUNCH();
         k_copyback<<<cblocks, 256, 0, s>>>(n, nodes[cur], chunk_node, nc, perm_tmp, a.perm);
         KNNG_LAUNCH();
-        k_next_level<<<1, 1024, 0, s>>>(nodes[cur], na, n0f, L, depth, nodes[cur ^ 1], a.leaves,
-                                        a.leaves_cap, a.node_log, a.node_log_cap, ctr, overflow);
+        k_next_level<<<1, 1024, 0, s>>>(nodes[cur], na, n0f, L, depth, nodes[cur ^ 1], big[cur ^ 1],
+                                        a.leaves, a.leaves_cap, a.node_log, a.node_log_cap, ctr,
+                                        overflow);
         KNNG_LAUNCH();
         KNNG_HIP(hipMemcpyAsync(hctr, ctr, sizeof(LevelCounters), hipMemcpyDeviceToHost, s));
         KNNG_HIP(hipStreamSynchronize(s));
@@ -766,22 +952,22 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     res->levels = depth + 1;
 
 done:
-    hipFreeAsync(nodes[0], s);
-    hipFreeAsync(nodes[1], s);
-    hipFreeAsync(chunk_node, s);
-    hipFreeAsync(status, s);
-    hipFreeAsync(n0f, s);
-    hipFreeAsync(W, s);
-    hipFreeAsync(H, s);
-    hipFreeAsync(P, s);
-    hipFreeAsync(cnt, s);
-    hipFreeAsync(cnt1, s);
-    hipFreeAsync(labels, s);
-    hipFreeAsync(dots, s);
-    hipFreeAsync(perm_tmp, s);
-    hipFreeAsync(ctr, s);
-    hipFreeAsync(dstats, s);
-    hipFreeAsync(overflow, s);
+    if (nodes[0]) hipFreeAsync(nodes[0], s);
+    if (nodes[1]) hipFreeAsync(nodes[1], s);
+    if (big[0]) hipFreeAsync(big[0], s);
+    if (big[1]) hipFreeAsync(big[1], s);
+    if (chunk_node) hipFreeAsync(chunk_node, s);
+    if (status) hipFreeAsync(status, s);
+    if (n0f) hipFreeAsync(n0f, s);
+    if (C) hipFreeAsync(C, s);
+    if (P) hipFreeAsync(P, s);
+    if (cnt) hipFreeAsync(cnt, s);
+    if (labels) hipFreeAsync(labels, s);
+    if (dots) hipFreeAsync(dots, s);
+    if (perm_tmp) hipFreeAsync(perm_tmp, s);
+    if (ctr) hipFreeAsync(ctr, s);
+    if (dstats) hipFreeAsync(dstats, s);
+    if (overflow) hipFreeAsync(overflow, s);
     hipStreamSynchronize(s);
     if (hctr) hipHostFree(hctr);
     res->launches += launches;

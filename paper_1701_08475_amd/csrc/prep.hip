@@ -5,17 +5,33 @@
 namespace knng {
 namespace {
 
-// flag <- 1 if any element is NaN or +-Inf (exponent bits all ones).
-__global__ __launch_bounds__(256) void k_check_finite(const float* __restrict__ X, int64_t count,
-                                                      int32_t* __restrict__ flag) {
-    int bad = 0;
+// flags[0] <- 1 if any element is NaN or +-Inf (exponent bits all ones);
+// flags[1] <- 1 if any element is not an integer in [0, 255].
+__global__ __launch_bounds__(256) void k_scan(const float* __restrict__ X, int64_t count,
+                                              int32_t* __restrict__ flags) {
+    int bad = 0, not_u8 = 0;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < count;
          i += stride) {
-        const uint32_t u = __float_as_uint(X[i]);
+        const float v = X[i];
+        const uint32_t u = __float_as_uint(v);
         bad |= ((u & 0x7f800000u) == 0x7f800000u) ? 1 : 0;
+        not_u8 |= (v >= 0.f && v <= 255.f && v == rintf(v)) ? 0 : 1;
     }
-    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+    // wave votes in converged code, then one lane per wave publishes
+    const bool any_bad = __any(bad), any_not_u8 = __any(not_u8);
+    if ((threadIdx.x & 63) == 0) {
+        if (any_bad) atomicOr(flags, 1);
+        if (any_not_u8) atomicOr(flags + 1, 1);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_to_u8(const float* __restrict__ X, int64_t count,
+                                               uint8_t* __restrict__ X8) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < count;
+         i += stride)
+        X8[i] = static_cast<uint8_t>(X[i]);
 }
 
 __global__ void k_fill_i32(int32_t* p, int64_t count, int32_t v) {
@@ -103,11 +119,18 @@ __global__ void k_set_last(int32_t* offsets, const int32_t* total, int32_t n) {
 
 }  // namespace
 
-int prep_check_finite(const float* X, int64_t count, int32_t* flag, hipStream_t s) {
-    k_fill_i32<<<1, 64, 0, s>>>(flag, 1, 0);
+int prep_scan(const float* X, int64_t count, int32_t* flags, hipStream_t s) {
+    k_fill_i32<<<1, 64, 0, s>>>(flags, 2, 0);
     const int64_t want = (count + 255) / 256;
     const int blocks = static_cast<int>(want < 4096 ? (want > 0 ? want : 1) : 4096);
-    k_check_finite<<<blocks, 256, 0, s>>>(X, count, flag);
+    k_scan<<<blocks, 256, 0, s>>>(X, count, flags);
+    return hipGetLastError() == hipSuccess ? kOk : kHip;
+}
+
+int prep_to_u8(const float* X, int64_t count, uint8_t* X8, hipStream_t s) {
+    const int64_t want = (count + 255) / 256;
+    const int blocks = static_cast<int>(want < 8192 ? (want > 0 ? want : 1) : 8192);
+    k_to_u8<<<blocks, 256, 0, s>>>(X, count, X8);
     return hipGetLastError() == hipSuccess ? kOk : kHip;
 }
 

@@ -29,7 +29,8 @@ class KnngOptions(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("rerank_factor", ctypes.c_int32), ("min_leaf", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("plain", ctypes.c_int32),
-                ("check_finite", ctypes.c_int32), ("time_kernels", ctypes.c_int32)]
+                ("check_finite", ctypes.c_int32), ("time_kernels", ctypes.c_int32),
+                ("compact", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class KnngStats(ctypes.Structure):
@@ -41,7 +42,8 @@ class KnngStats(ctypes.Structure):
                 ("ms_merge", ctypes.c_float), ("ms_total", ctypes.c_float),
                 ("ms_k_assign", ctypes.c_float), ("n_k_assign", ctypes.c_int32),
                 ("ms_k_leaf", ctypes.c_float), ("n_k_leaf", ctypes.c_int32),
-                ("ms_k_merge", ctypes.c_float), ("n_k_merge", ctypes.c_int32)]
+                ("ms_k_merge", ctypes.c_float), ("n_k_merge", ctypes.c_int32),
+                ("compact_used", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -101,7 +103,7 @@ def _check(rc):
 
 
 def options(precision="fp32", rerank_factor=2, min_leaf=0, max_iter=0, plain=False,
-            check_finite=True, time_kernels=False):
+            check_finite=True, time_kernels=False, compact=True):
     o = KnngOptions()
     lib().knng_default_options(ctypes.byref(o))
     o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
@@ -111,6 +113,7 @@ def options(precision="fp32", rerank_factor=2, min_leaf=0, max_iter=0, plain=Fal
     o.plain = 1 if plain else 0
     o.check_finite = 1 if check_finite else 0
     o.time_kernels = 1 if time_kernels else 0
+    o.compact = 1 if compact else 0
     return o
 
 
@@ -129,7 +132,8 @@ def _dev_f32(x):
 
 
 def build(x, k, n_trees, leaf_max, seed=0, precision="fp32", rerank_factor=2, min_leaf=0,
-          max_iter=0, plain=False, stats=False, time_kernels=False, out=None, stream=None):
+          max_iter=0, plain=False, stats=False, time_kernels=False, compact=True, out=None,
+          stream=None):
     """kNN graph of the rows of x.  Returns (ids int32 [n,k], dists f32 [n,k])
     and a stats dict when stats=True."""
     import torch
@@ -141,7 +145,7 @@ def build(x, k, n_trees, leaf_max, seed=0, precision="fp32", rerank_factor=2, mi
     else:
         ids, ds = out
     o = options(precision, rerank_factor, min_leaf, max_iter, plain,
-                time_kernels=time_kernels)
+                time_kernels=time_kernels, compact=compact)
     st = KnngStats() if stats else None
     rc = lib().knng_build_ex(ctypes.c_void_p(x.data_ptr()), n, D, k, n_trees, leaf_max,
                              ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF),

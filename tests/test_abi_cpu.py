@@ -42,12 +42,12 @@ def test_status_codes_match_header(L):
 def test_options_struct_layout(L):
     o = knng.KnngOptions()
     L.knng_default_options(ctypes.byref(o))
-    assert o.struct_size == ctypes.sizeof(knng.KnngOptions) == 32
+    assert o.struct_size == ctypes.sizeof(knng.KnngOptions) == 40
     assert (o.precision, o.rerank_factor, o.min_leaf, o.max_iter, o.plain, o.check_finite,
-            o.time_kernels) == \
-        (0, 2, 0, 10, 0, 1, 0)
-    # 5 int64, 2 int32, 5 float, 3 (float, int32) pairs = 92 bytes, padded to 8
-    assert ctypes.sizeof(knng.KnngStats) == 96
+            o.time_kernels, o.compact) == (0, 2, 0, 10, 0, 1, 0, 1)
+    # 5 int64, 2 int32, 5 float, 3 (float, int32) pairs, 2 int32 = 100 bytes,
+    # padded to a multiple of 8
+    assert ctypes.sizeof(knng.KnngStats) == 104
 
 
 FAKE = 0x10000  # aligned, never dereferenced: validation fails first

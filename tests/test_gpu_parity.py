@@ -221,3 +221,20 @@ def test_stats(K):
     assert st["leaves"] > 2 * 10_000 // 50 - 10
     assert st["ordered_pairs"] > 0 and st["assign_rows"] >= 2 * 10_000
     assert st["ms_total"] > 0
+
+
+def test_compact_storage_is_lossless(K, orc):
+    """Integer data in [0, 255]: the uint8 copy the partition streams holds the
+    same values, so the graph is bit-identical to the FP32-storage build."""
+    X = datagen.make("c2", n=30_000)
+    Xd = to_dev(X)
+    a_ids, a_d, a_st = K.build(Xd, 20, 3, 100, seed=7, stats=True)
+    b_ids, b_d, b_st = K.build(Xd, 20, 3, 100, seed=7, stats=True, compact=False)
+    assert a_st["compact_used"] == 1 and b_st["compact_used"] == 0
+    assert np.array_equal(_np(a_ids), _np(b_ids))
+    assert np.array_equal(_np(a_d).view(np.int32), _np(b_d).view(np.int32))
+    # and a value outside [0, 255] (or a fraction) disables it
+    Y = X.copy()
+    Y[5, 5] = 255.5
+    _, _, c_st = K.build(to_dev(Y), 20, 1, 100, seed=7, stats=True)
+    assert c_st["compact_used"] == 0
