@@ -511,3 +511,125 @@ int orc_rows_from_leaves(const float *X, int64_t n, int D, int k, int n_trees,
     free(offs);
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Reduced-precision first pass (the leaf distances of the reduced     */
+/* path), emulated: reading R9.                                        */
+/*   R9  x~_i = rnd(sigma_i x_i) in the format (round to nearest, ties */
+/*       to even, with the format's subnormals); sigma_i = 1 for BF16, */
+/*       else 2^(E - floor(log2 max_d |x_id|) - 1), E = 15 (FP16) or 8 */
+/*       (FP8-e4m3), so |sigma x| < 2^E.  d~(i,j) = |x~_i/s_i - x~_j/s_j|^2  */
+/*       computed as n~_i + n~_j - 2 <x~_i/s_i, x~_j/s_j> in FP64.  Per */
+/*       row and leaf the c smallest (d~, j) are re-ranked by d64 and the */
+/*       k smallest (d64, j) kept; rows are then merged as in R7.       */
+/* ------------------------------------------------------------------ */
+enum { ORC_BF16 = 1, ORC_FP16 = 2, ORC_FP8 = 3 };
+
+/* Nearest value with `mant` fraction bits and smallest normal exponent
+ * emin (evenly spaced subnormals below it); ties to even.  Every step is
+ * exact in double for mant <= 10. */
+double orc_round_fmt(double x, int mant, int emin)
+{
+    if (x == 0.0) return x;
+    int e;
+    frexp(x, &e);
+    e -= 1; /* |x| in [2^e, 2^(e+1)) */
+    if (e < emin) e = emin;
+    double ulp = ldexp(1.0, e - mant);
+    return nearbyint(x / ulp) * ulp; /* default rounding mode: ties to even */
+}
+
+double orc_quantize(int fmt, double x)
+{
+    switch (fmt) {
+    case ORC_BF16: return orc_round_fmt(x, 7, -126);
+    case ORC_FP16: return orc_round_fmt(x, 10, -14);
+    case ORC_FP8: return orc_round_fmt(x, 3, -6);
+    default: return x;
+    }
+}
+
+/* Power-of-two scale sigma of one row (R9). */
+double orc_row_scale(int fmt, const float *x, int D)
+{
+    if (fmt == ORC_BF16) return 1.0;
+    double mx = 0.0;
+    for (int d = 0; d < D; ++d) {
+        double a = fabs((double)x[d]);
+        if (a > mx) mx = a;
+    }
+    if (mx == 0.0) return 1.0;
+    int e;
+    frexp(mx, &e); /* mx in [2^(e-1), 2^e): floor(log2 mx) = e-1 */
+    int E = (fmt == ORC_FP16) ? 15 : 8;
+    return ldexp(1.0, E - (e - 1) - 1);
+}
+
+/* Dequantised reduced row x~/sigma. */
+static void reduced_row(int fmt, const float *x, int D, double *out)
+{
+    double s = orc_row_scale(fmt, x, D);
+    for (int d = 0; d < D; ++d) out[d] = orc_quantize(fmt, (double)x[d] * s) / s;
+}
+
+typedef struct { double d; int32_t j; } dj_rec;
+
+static int dj_cmp(const void *a, const void *b)
+{
+    const dj_rec *x = (const dj_rec *)a, *y = (const dj_rec *)b;
+    if (x->d < y->d) return -1;
+    if (x->d > y->d) return 1;
+    return (x->j > y->j) - (x->j < y->j);
+}
+
+/* Graph from given leaves with the reduced first pass (R9); arguments as
+ * orc_graph_from_leaves plus the format and c candidates per row and leaf. */
+int orc_graph_from_leaves_reduced(const float *X, int64_t n, int D, int k, int n_trees,
+                                  const int32_t *perm, const int32_t *leaf_off,
+                                  const int64_t *n_leaves, int fmt, int c,
+                                  int32_t *ids, double *ds)
+{
+    int *cnt = (int *)malloc(sizeof(int) * (size_t)n);
+    if (!cnt) return -1;
+    graph_init(ids, ds, cnt, n, k);
+    int64_t off = 0;
+    for (int t = 0; t < n_trees; ++t) {
+        const int32_t *pm = perm + (size_t)t * n;
+        const int32_t *lo = leaf_off + off;
+#pragma omp parallel for schedule(dynamic, 8)
+        for (int64_t l = 0; l < n_leaves[t]; ++l) {
+            int64_t s = lo[l], m = lo[l + 1] - lo[l];
+            double *q = (double *)malloc(sizeof(double) * (size_t)(m * D));
+            double *nq = (double *)malloc(sizeof(double) * (size_t)m);
+            dj_rec *r = (dj_rec *)malloc(sizeof(dj_rec) * (size_t)m);
+            for (int64_t a = 0; a < m; ++a) {
+                reduced_row(fmt, X + (size_t)pm[s + a] * D, D, q + a * D);
+                double acc = 0.0;
+                for (int d = 0; d < D; ++d) acc += q[a * D + d] * q[a * D + d];
+                nq[a] = acc;
+            }
+            for (int64_t a = 0; a < m; ++a) {
+                int nr = 0;
+                for (int64_t b = 0; b < m; ++b) {
+                    if (b == a) continue;
+                    double g = 0.0;
+                    for (int d = 0; d < D; ++d) g += q[a * D + d] * q[b * D + d];
+                    r[nr].d = nq[a] + nq[b] - 2.0 * g;
+                    r[nr].j = pm[s + b];
+                    ++nr;
+                }
+                qsort(r, (size_t)nr, sizeof(dj_rec), dj_cmp);
+                int cc = nr < c ? nr : c;
+                for (int p = 0; p < cc; ++p) r[p].d = orc_d64(X, D, pm[s + a], r[p].j);
+                qsort(r, (size_t)cc, sizeof(dj_rec), dj_cmp);
+                int i = pm[s + a];
+                for (int p = 0; p < cc && p < k; ++p)
+                    row_insert(ids + (size_t)i * k, ds + (size_t)i * k, cnt + i, k, r[p].j, r[p].d);
+            }
+            free(q); free(nq); free(r);
+        }
+        off += n_leaves[t] + 1;
+    }
+    free(cnt);
+    return 0;
+}

@@ -58,6 +58,15 @@ def lib():
         L.orc_graph_from_leaves.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp, vp, vp]
         L.orc_rows_from_leaves.restype = i32
         L.orc_rows_from_leaves.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp, vp, i64, vp, vp]
+        L.orc_round_fmt.restype = ctypes.c_double
+        L.orc_round_fmt.argtypes = [ctypes.c_double, i32, i32]
+        L.orc_quantize.restype = ctypes.c_double
+        L.orc_quantize.argtypes = [i32, ctypes.c_double]
+        L.orc_row_scale.restype = ctypes.c_double
+        L.orc_row_scale.argtypes = [i32, vp, i32]
+        L.orc_graph_from_leaves_reduced.restype = i32
+        L.orc_graph_from_leaves_reduced.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp, i32, i32,
+                                                    vp, vp]
         L.orc_graph.restype = i32
         L.orc_graph.argtypes = [vp, i64, i32, i32, i32, i32, i32, i32, u64, vp, vp, vp]
         L.orc_num_threads.restype = i32
@@ -196,6 +205,35 @@ def rows_from_leaves(X, k, perms, leaf_offs, rows):
     ds = np.empty((len(rows), k), np.float64)
     rc = lib().orc_rows_from_leaves(_p(X), n, D, k, T, _p(perms), _p(cat), _p(nl), _p(rows),
                                     len(rows), _p(ids), _p(ds))
+    assert rc == 0
+    return ids, ds
+
+
+FORMATS = {"bf16": 1, "fp16": 2, "fp8": 3}
+
+
+def quantize(fmt, x):
+    """Round x (float) to the format, ties to even (reading R9)."""
+    return lib().orc_quantize(FORMATS[fmt], float(x))
+
+
+def row_scale(fmt, row):
+    row = np.ascontiguousarray(row, np.float32)
+    return lib().orc_row_scale(FORMATS[fmt], _p(row), len(row))
+
+
+def graph_from_leaves_reduced(X, k, perms, leaf_offs, fmt, c):
+    """G from given leaves with the reduced-precision first pass (R9)."""
+    X = _f32(X)
+    n, D = X.shape
+    perms = np.ascontiguousarray(perms, np.int32).reshape(-1, n)
+    T = perms.shape[0]
+    cat = np.ascontiguousarray(np.concatenate([np.asarray(o, np.int32) for o in leaf_offs]))
+    nl = np.array([len(o) - 1 for o in leaf_offs], np.int64)
+    ids = np.empty((n, k), np.int32)
+    ds = np.empty((n, k), np.float64)
+    rc = lib().orc_graph_from_leaves_reduced(_p(X), n, D, k, T, _p(perms), _p(cat), _p(nl),
+                                             FORMATS[fmt], c, _p(ids), _p(ds))
     assert rc == 0
     return ids, ds
 

@@ -13,7 +13,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libknng.so")
-SOURCES = ["api.hip", "partition.hip", "leaf.hip", "merge.hip", "prep.hip"]
+SOURCES = ["api.hip", "partition.hip", "leaf.hip", "leaf_mfma.hip", "merge.hip", "prep.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [

@@ -178,8 +178,8 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
                        2 * o.min_leaf - 1);
     if (leaf_max > knng::kMaxLeaf)
         return set_err(KNNG_ERR_UNSUPPORTED, "leaf_max=%d exceeds %d", leaf_max, knng::kMaxLeaf);
-    if (o.precision != KNNG_FP32)
-        return set_err(KNNG_ERR_UNSUPPORTED, "precision %d not available in this build", o.precision);
+    if (o.precision != KNNG_FP32 && o.rerank * k > 128)
+        return set_err(KNNG_ERR_UNSUPPORTED, "rerank_factor*k = %d exceeds 128", o.rerank * k);
 
     hipStream_t s = stream;
     Events ev(stats_out != nullptr);
@@ -209,6 +209,10 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
     unsigned long long* dpairs = nullptr;
     unsigned long long hpairs = 0;
     uint8_t* x8 = nullptr;
+    // BF16 holds integers 0..255 exactly; with D <= 258 every product and
+    // partial sum of the first pass stays below 2^24, so it is exact.
+    knng::ReducedRows rr{nullptr, nullptr, nullptr, knng::reduced_rows_dp(D),
+                         o.precision == KNNG_BF16 && all_u8 != 0 && D <= 258};
 
     e = hipMallocAsync(reinterpret_cast<void**>(&perm), sizeof(int32_t) * slots * n, s);
     if (e == hipSuccess)
@@ -222,12 +226,23 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
     if (e == hipSuccess) e = hipMemsetAsync(dpairs, 0, sizeof(unsigned long long), s);
     if (e == hipSuccess && use_u8)
         e = hipMallocAsync(reinterpret_cast<void**>(&x8), static_cast<size_t>(n) * D, s);
+    if (e == hipSuccess && o.precision != KNNG_FP32)
+        e = hipMallocAsync(reinterpret_cast<void**>(&rr.Xr),
+                           knng::reduced_rows_bytes(o.precision, n, D), s);
+    if (e == hipSuccess && o.precision != KNNG_FP32)
+        e = hipMallocAsync(reinterpret_cast<void**>(&rr.nrm), sizeof(float) * n, s);
+    if (e == hipSuccess && o.precision != KNNG_FP32)
+        e = hipMallocAsync(reinterpret_cast<void**>(&rr.sinv), sizeof(float) * n, s);
     if (e != hipSuccess) {
         rc = hip_fail(e, "workspace allocation");
         goto done;
     }
     if (use_u8 && knng::prep_to_u8(data, n * static_cast<int64_t>(D), x8, s) != KNNG_OK) {
         rc = set_err(KNNG_ERR_HIP, "uint8 copy launch failed");
+        goto done;
+    }
+    if (o.precision != KNNG_FP32 && knng::prep_reduced(o.precision, data, n, D, &rr, s) != KNNG_OK) {
+        rc = set_err(KNNG_ERR_HIP, "reduced-copy launch failed");
         goto done;
     }
     ev.record(1, s);
@@ -285,7 +300,8 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
         la.pairs = dpairs;
         la.timer = &timer;
         la.stream = s;
-        rc = knng::leaf_run(la, &launches, err, sizeof(err));
+        rc = o.precision == KNNG_FP32 ? knng::leaf_run(la, &launches, err, sizeof(err))
+                                      : knng::leaf_run_mfma(la, rr, &launches, err, sizeof(err));
         if (rc != KNNG_OK) {
             set_err(rc, "leaf search: %s", err);
             goto done;
@@ -320,6 +336,9 @@ done:
     if (leaves) hipFreeAsync(leaves, s);
     if (dpairs) hipFreeAsync(dpairs, s);
     if (x8) hipFreeAsync(x8, s);
+    if (rr.Xr) hipFreeAsync(rr.Xr, s);
+    if (rr.nrm) hipFreeAsync(rr.nrm, s);
+    if (rr.sinv) hipFreeAsync(rr.sinv, s);
     if (!direct) {
         if (cand_ids) hipFreeAsync(cand_ids, s);
         if (cand_d) hipFreeAsync(cand_d, s);
@@ -501,8 +520,8 @@ extern "C" int knng_leaf_search(const float* data, int64_t n, int32_t D, int32_t
     Resolved o;
     rc = resolve(opt, k, &o);
     if (rc != KNNG_OK) return rc;
-    if (o.precision != KNNG_FP32)
-        return set_err(KNNG_ERR_UNSUPPORTED, "precision %d not available in this build", o.precision);
+    if (o.precision != KNNG_FP32 && o.rerank * k > 128)
+        return set_err(KNNG_ERR_UNSUPPORTED, "rerank_factor*k = %d exceeds 128", o.rerank * k);
     int64_t total = 0;
     for (int t = 0; t < n_trees; ++t) {
         if (n_leaves[t] < 1 || n_leaves[t] > n)
@@ -518,6 +537,7 @@ extern "C" int knng_leaf_search(const float* data, int64_t n, int32_t D, int32_t
     const bool direct = (n_trees == 1);
     char err[400] = "";
     int launches = 0;
+    knng::ReducedRows rr{nullptr, nullptr, nullptr, knng::reduced_rows_dp(D), false};
     hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&leaves), sizeof(knng::LeafRec) * total, s);
     if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&flags), sizeof(int32_t) * 2, s);
     if (e != hipSuccess) {
@@ -567,6 +587,20 @@ extern "C" int knng_leaf_search(const float* data, int64_t n, int32_t D, int32_t
             goto done;
         }
     }
+    if (o.precision != KNNG_FP32) {
+        e = hipMallocAsync(reinterpret_cast<void**>(&rr.Xr),
+                           knng::reduced_rows_bytes(o.precision, n, D), s);
+        if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&rr.nrm), sizeof(float) * n, s);
+        if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&rr.sinv), sizeof(float) * n, s);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "workspace allocation");
+            goto done;
+        }
+        if (knng::prep_reduced(o.precision, data, n, D, &rr, s) != KNNG_OK) {
+            rc = set_err(KNNG_ERR_HIP, "reduced-copy launch failed");
+            goto done;
+        }
+    }
     {
         knng::LeafArgs la{};
         la.X = data;
@@ -585,7 +619,8 @@ extern "C" int knng_leaf_search(const float* data, int64_t n, int32_t D, int32_t
         la.pairs = nullptr;
         la.timer = nullptr;
         la.stream = s;
-        rc = knng::leaf_run(la, &launches, err, sizeof(err));
+        rc = o.precision == KNNG_FP32 ? knng::leaf_run(la, &launches, err, sizeof(err))
+                                      : knng::leaf_run_mfma(la, rr, &launches, err, sizeof(err));
         if (rc != KNNG_OK) {
             set_err(rc, "leaf search: %s", err);
             goto done;
@@ -613,6 +648,9 @@ extern "C" int knng_leaf_search(const float* data, int64_t n, int32_t D, int32_t
 done:
     if (leaves) hipFreeAsync(leaves, s);
     if (flags) hipFreeAsync(flags, s);
+    if (rr.Xr) hipFreeAsync(rr.Xr, s);
+    if (rr.nrm) hipFreeAsync(rr.nrm, s);
+    if (rr.sinv) hipFreeAsync(rr.sinv, s);
     if (!direct) {
         if (cand_ids) hipFreeAsync(cand_ids, s);
         if (cand_d) hipFreeAsync(cand_d, s);

@@ -134,6 +134,20 @@ struct LeafArgs {
 };
 int leaf_run(const LeafArgs& a, int* launches, char* err, size_t errlen);
 
+// Reduced-precision copy of the rows for the MFMA first pass.
+struct ReducedRows {
+    uint8_t* Xr;   // [n][Dp] elements of the format (2 bytes BF16/FP16, 1 byte FP8)
+    float* nrm;    // [n] squared norm of the dequantised reduced row
+    float* sinv;   // [n] 1/sigma (power of two)
+    int Dp;        // D rounded up to 32
+    bool exact;    // first pass exact (d~ == d32): skip the re-rank
+};
+int reduced_rows_dp(int D);
+size_t reduced_rows_bytes(int precision, int64_t n, int D);
+int prep_reduced(int precision, const float* X, int64_t n, int D, ReducedRows* rr, hipStream_t s);
+int leaf_run_mfma(const LeafArgs& a, const ReducedRows& rr, int* launches, char* err,
+                  size_t errlen);
+
 // ---------------------------------------------------------------- merge
 struct MergeArgs {
     int64_t n;

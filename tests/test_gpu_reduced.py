@@ -1,0 +1,128 @@
+"""Reduced-precision leaf search on MFMA (BF16 / FP16 / FP8-e4m3 first pass,
+FP32 re-rank) against the oracle's emulation (reading R9) and the FP32 path.
+
+Exact cases are compared bit for bit: integer data is exact in BF16 (so the
+first pass is exact), and a candidate budget covering the whole leaf makes
+the first pass irrelevant.  Otherwise the first pass rounds differently on
+the GPU (FP32 accumulation in the matrix cores) than in the FP64 emulation,
+so the comparison is: every GPU row is valid (distinct co-leaf ids, d32
+within 1e-5 of d64, sorted) and agrees with the emulation on nearly all
+positions."""
+import numpy as np
+import pytest
+
+from paper_1701_08475_amd import datagen
+from tests.gpu_helpers import TAU, graph_parity, log, rows_sorted, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1701_08475_amd import knng
+    knng.lib()
+    return knng
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _oracle_leaves(orc, X, T, L, ml, seed):
+    perms, offs = [], []
+    for t in range(T):
+        tr = orc.tree(X, L, ml, 10, seed, t)
+        perms.append(tr["perm"])
+        offs.append(tr["leaf_off"])
+    return np.stack(perms), offs
+
+
+def _gpu_leaf_search(K, X, k, perms, offs, precision, rerank=2):
+    import torch
+    return K.leaf_search(to_dev(X), k, torch.from_numpy(perms).cuda(),
+                         [torch.from_numpy(o).cuda() for o in offs], precision=precision,
+                         rerank_factor=rerank)
+
+
+def _co_leaf_sets(perms, offs, n):
+    sets = [set() for _ in range(n)]
+    for perm, lo in zip(perms, offs):
+        for s, e in zip(lo[:-1], lo[1:]):
+            leaf = perm[s:e].tolist()
+            for i in leaf:
+                sets[i].update(leaf)
+    return sets
+
+
+def _valid_rows(orc, X, ids, ds, co, k):
+    n = len(X)
+    d64 = orc.pair_d64(X, np.arange(n), np.where(ids >= 0, ids, 0))
+    for i in range(n):
+        r = ids[i][ids[i] >= 0]
+        assert len(set(r.tolist())) == len(r) and i not in r
+        assert set(r.tolist()) <= co[i]
+        dv = ds[i][: len(r)].astype(np.float64)
+        assert np.all(np.abs(dv - d64[i][: len(r)]) <= TAU * d64[i][: len(r)])
+    assert rows_sorted(ids, ds)
+
+
+def test_bf16_integer_data_bit_identical_to_fp32(K, orc):
+    X = datagen.make("c2", n=20_000)
+    Xd = to_dev(X)
+    log("bf16 build on integer data")
+    a = K.build(Xd, 20, 3, 100, seed=2)
+    b = K.build(Xd, 20, 3, 100, seed=2, precision="bf16")
+    assert np.array_equal(_np(a[0]), _np(b[0]))
+    assert np.array_equal(_np(a[1]).view(np.int32), _np(b[1]).view(np.int32))
+    o_ids, o_d, _ = orc.graph(X, 20, 3, 100, 2)
+    graph_parity(orc, X, np.arange(len(X)), _np(b[0]), _np(b[1]), o_ids, o_d, strict=True)
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp16", "fp8"])
+def test_full_candidate_budget_equals_fp32(K, orc, precision):
+    """rerank * k >= leaf size - 1: every co-leaf member is re-ranked with
+    d32, so the result is the FP32 path's, bit for bit."""
+    X = datagen.make("c1", n=5000)
+    perms, offs = _oracle_leaves(orc, X, 2, 50, 11, 4)
+    a = _gpu_leaf_search(K, X, 10, perms, offs, "fp32")
+    b = _gpu_leaf_search(K, X, 10, perms, offs, precision, rerank=5)
+    assert np.array_equal(_np(a[0]), _np(b[0]))
+    assert np.array_equal(_np(a[1]).view(np.int32), _np(b[1]).view(np.int32))
+
+
+@pytest.mark.parametrize("precision,n,D,k,T,L,kind", [
+    ("bf16", 6000, 32, 10, 2, 50, "c1"),
+    ("fp16", 3000, 960, 20, 2, 200, "unit960"),
+    ("fp8", 6000, 96, 32, 2, 500, "unit96"),
+    ("fp8", 4000, 32, 10, 2, 100, "c1"),
+    ("fp16", 2000, 40, 6, 1, 30, "c1"),      # D not a multiple of 32
+])
+def test_reduced_matches_emulation(K, orc, precision, n, D, k, T, L, kind):
+    if kind == "c1":
+        X = datagen.gmm_uniform(n, D, 20, -10, 10, 1.0, 11)
+    else:
+        X = datagen.gmm_unit(n, D, 16, 0.35, 12)
+    perms, offs = _oracle_leaves(orc, X, T, L, k + 1, 5)
+    log("reduced %s n=%d D=%d L=%d" % (precision, n, D, L))
+    ids, ds = _gpu_leaf_search(K, X, k, perms, offs, precision)
+    ids, ds = _np(ids), _np(ds)
+    _valid_rows(orc, X, ids, ds, _co_leaf_sets(perms, offs, n), k)
+    o_ids, o_d = orc.graph_from_leaves_reduced(X, k, perms, offs, precision, 2 * k)
+    same = np.mean(ids == o_ids)
+    log("  identical id fraction vs emulation %.5f" % same)
+    assert same > 0.99
+
+
+def test_reduced_build_end_to_end(K, orc):
+    X = datagen.make("c1")
+    ids, ds, st = K.build(to_dev(X), 10, 2, 50, seed=1, precision="fp8", stats=True)
+    assert st["leaves"] > 0
+    o_ids, o_d, _ = orc.graph(X, 10, 2, 50, 1)
+    rows = np.arange(len(X))
+    E, Ed = orc.exact_knn(X, 10, rows[::10])
+    r_fp8 = orc.recall(X, rows[::10], _np(ids)[::10], E, Ed)
+    r_exact_alg = orc.recall(X, rows[::10], o_ids[::10], E, Ed)
+    log("recall fp8 %.4f vs FP64 algorithm %.4f" % (r_fp8, r_exact_alg))
+    assert r_fp8 > r_exact_alg - 0.01
