@@ -124,8 +124,8 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
 
 /*
  * knng_partition -- one round's clustering (Sec. 3.1: bisect repeatedly with
- * two-means until no cluster exceeds leaf_max; Alg. 1 "apply two means
- * clustering" and "collect clusters set S") for tree index `tree`, exactly as
+ * two-means until no cluster exceeds leaf_max; Alg. 1, clustering step and
+ * collection of the cluster set S) for tree index `tree`, exactly as
  * knng_build runs it with default options (including the uint8 storage of
  * integer-valued input).
  *   perm_out          device, int32[n]: the points in depth-first leaf order

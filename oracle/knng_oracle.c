@@ -2,7 +2,7 @@
  * CPU oracle for kNN-graph construction by repeated two-means bisection.
  *
  * Method: Zhao, Yang, Deng, "Scalable Nearest Neighbor Search based on kNN
- * Graph" (arXiv 1701.08475), Sec. 3.1 and Algorithm 1 ("kNNG construction").
+ * Graph" (arXiv 1701.08475), Sec. 3.1 and Algorithm 1 (kNN graph construction).
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, FP64 reference
  * that the tests, the GPU smoke check and the benchmark's CPU-baseline leg
@@ -13,7 +13,7 @@
  *   R1  d(x_i, x_j) is the squared Euclidean distance, summed in FP64 over the
  *       exact FP32 inputs in increasing dimension order (Sec. 1 names l1 or
  *       l2; Eqn 2 works with squared l2).
- *   R2  "two means clustering" is plain Lloyd 2-means on the sum-of-squares
+ *   R2  The two-means clustering is plain Lloyd 2-means on the sum-of-squares
  *       objective (the boost k-means objective of Sec. 3.1 is not defined in
  *       the paper).
  *   R3  The two starting centres are two distinct members drawn with a keyed
@@ -22,14 +22,14 @@
  *       states that the clustering differs from round to round).
  *   R4  At most I_max assignment passes; stop when no label changes or a
  *       side is empty.  A point equidistant from both centres goes left.
- *   R5  A node is split iff it holds more than leaf_max points ("no bigger
- *       than a threshold", Sec. 3.1).  A side smaller than min_leaf is
+ *   R5  A node is split iff it holds more than leaf_max points (Sec. 3.1
+ *       bounds the cluster size by a threshold).  A side smaller than min_leaf is
  *       repaired by re-splitting on the rank of the margin
  *       mu = |x-c0|^2 - |x-c1|^2 (ties by id), left size clamped to
  *       [min_leaf, m-min_leaf]; if every margin is equal the left size is
  *       floor(m/2).
- *   R6  "Initialize G" is an empty list per row, (-1, +inf) padding.
- *   R7  "if <i,j> is NOT visited" is realised as de-duplication by id when
+ *   R6  The initial G of Alg. 1 is an empty list per row, (-1, +inf) padding.
+ *   R7  Alg. 1 skips pairs compared before; this is realised as de-duplication by id when
  *       a candidate is inserted: G[i] is the k smallest (d, id) over the
  *       distinct co-leaf members seen in all rounds, which is exactly what
  *       Algorithm 1's update produces (a rejected pair stays rejected since
@@ -294,8 +294,8 @@ int64_t orc_split(const float *X, int D, const int32_t *mem, int64_t m,
 }
 
 /* ------------------------------------------------------------------ */
-/* One tree: recursive bisection down to leaves (Alg. 1, "apply two   */
-/* means clustering" and "collect clusters set S").                    */
+/* One tree: recursive bisection down to leaves (Alg. 1: clustering    */
+/* by two-means, then the collection of the clusters).                 */
 /* perm is filled in depth-first order, left child first, so that      */
 /* every node is a contiguous run of perm and every leaf too.          */
 /* ------------------------------------------------------------------ */

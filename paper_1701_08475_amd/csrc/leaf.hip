@@ -1,5 +1,5 @@
-// Exhaustive comparison inside every cluster (Alg. 1: for each S_m in S and
-// each <i, j> with i != j, update G[i] with d(x_i, x_j)), FP32 direct form.
+// Exhaustive comparison inside every cluster (Alg. 1: every pair of distinct
+// members of a cluster updates both members' rows of G), FP32 direct form.
 //
 // One workgroup per leaf.  Rows are taken in panels of 32; for each panel the
 // 32 x m distance block is accumulated from 16-dimension tiles staged in LDS,

@@ -1,5 +1,5 @@
-// Union of the rounds' candidate lists into G (Alg. 1: "update G[i] and G[j]"
-// over all rounds; a pair already compared is not counted twice).
+// Union of the rounds' candidate lists into G (Alg. 1: the rows of G are
+// refined round after round; a pair already compared is not counted twice).
 //
 // One wavefront per row: the row's candidates from every tree are sorted by
 // (d32, id) with a bitonic network, adjacent equal keys are dropped (the same
