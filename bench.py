@@ -143,19 +143,24 @@ def main():
     leaf_ms = sum(s["ms_k_leaf"] for s in sts) / args.steps
     merge_ms = sum(s["ms_k_merge"] for s in sts) / args.steps
     leaf_flops = 2.0 * D * pairs  # one D-long dot product per ordered pair
+    mfma_leaf = c["precision"] != "fp32" or st["exact_first_pass"]
+    leaf_peak = {"bf16": 2500.0, "fp16": 2500.0, "fp8": 5000.0}.get(
+        "bf16" if st["exact_first_pass"] else c["precision"], FP32_PEAK_TFLOPS)
     merge_bytes = (T * n * k * 8.0 + n * k * 8.0) if T > 1 else 0.0
     phases = {
         "ms_partition": round(sum(s["ms_partition"] for s in sts) / args.steps, 3),
         "ms_leaf": round(sum(s["ms_leaf"] for s in sts) / args.steps, 3),
         "ms_merge": round(sum(s["ms_merge"] for s in sts) / args.steps, 3),
         "leaf_kernel": {"ms": round(leaf_ms, 3), "tflops": round(leaf_flops / leaf_ms / 1e9, 2),
-                        "peak_tflops": FP32_PEAK_TFLOPS,
-                        "frac": round(leaf_flops / leaf_ms / 1e9 / FP32_PEAK_TFLOPS, 4),
+                        "peak_tflops": leaf_peak, "on_mfma": bool(mfma_leaf),
+                        "frac": round(leaf_flops / leaf_ms / 1e9 / leaf_peak, 5),
                         "precision": c["precision"]},
         "merge_kernel": {"ms": round(merge_ms, 3),
                          "gbs": round(merge_bytes / merge_ms / 1e6, 1) if merge_ms > 0 else None},
         "pairs_per_s": pairs / (ms_per_step / 1e3),
         "assign_passes_per_point_per_tree": st["assign_rows"] / float(n * T),
+        "leaf_path": ("exact BF16 MFMA first pass (integer data; equals FP32 d32)"
+                      if st["exact_first_pass"] else c["precision"]),
         "leaves": st["leaves"], "levels": st["levels"], "repairs": st["repairs"],
         "launches": st["launches"],
     }

@@ -67,8 +67,11 @@ typedef struct {
                                merge kernels with HIP events and report the summed
                                time in knng_stats (0 default: no events) */
     int32_t compact;        /* 1 (default): when every input value is an integer in
-                               [0, 255] and D % 16 == 0, the partition streams a
-                               uint8 copy of X (same values, same results); 0: FP32 */
+                               [0, 255], the partition streams a uint8 copy of X
+                               (D % 16 == 0) and, for FP32/BF16 requests with
+                               D <= 129 outside the plain schedule, leaf distances
+                               come from the exact BF16 matrix-core pass; the
+                               values are unchanged, so are the results.  0: FP32 */
     int32_t reserved;
 } knng_options;
 
@@ -90,7 +93,9 @@ typedef struct {
     float ms_k_merge;
     int32_t n_k_merge;
     int32_t compact_used;   /* 1 if the partition streamed the uint8 copy */
-    int32_t reserved;
+    int32_t exact_first_pass; /* 1 if leaf distances came from the exact BF16
+                                 first pass (integer data 0..255, D <= 129; equal
+                                 to d32 bit for bit) */
 } knng_stats;
 
 /* Fill *opt with the defaults listed above. */

@@ -209,10 +209,15 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
     unsigned long long* dpairs = nullptr;
     unsigned long long hpairs = 0;
     uint8_t* x8 = nullptr;
-    // BF16 holds integers 0..255 exactly; with D <= 258 every product and
-    // partial sum of the first pass stays below 2^24, so it is exact.
-    knng::ReducedRows rr{nullptr, nullptr, nullptr, knng::reduced_rows_dp(D),
-                         o.precision == KNNG_BF16 && all_u8 != 0 && D <= 258};
+    // BF16 holds integers 0..255 exactly, and with 2 D 255^2 < 2^24 (D <= 129)
+    // every product, norm, sum of two norms and partial sum of the first pass
+    // is an exact FP32 integer, so its distances equal d32 bit for bit.  Such
+    // data takes that path for FP32 and BF16 requests alike (not in the plain
+    // schedule, nor with compact=0).
+    const bool exact_bf16 = all_u8 != 0 && D <= 129 && o.compact && !o.plain &&
+                            (o.precision == KNNG_FP32 || o.precision == KNNG_BF16);
+    const int leaf_prec = exact_bf16 ? KNNG_BF16 : o.precision;
+    knng::ReducedRows rr{nullptr, nullptr, nullptr, knng::reduced_rows_dp(D), exact_bf16};
 
     e = hipMallocAsync(reinterpret_cast<void**>(&perm), sizeof(int32_t) * slots * n, s);
     if (e == hipSuccess)
@@ -226,12 +231,12 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
     if (e == hipSuccess) e = hipMemsetAsync(dpairs, 0, sizeof(unsigned long long), s);
     if (e == hipSuccess && use_u8)
         e = hipMallocAsync(reinterpret_cast<void**>(&x8), static_cast<size_t>(n) * D, s);
-    if (e == hipSuccess && o.precision != KNNG_FP32)
+    if (e == hipSuccess && leaf_prec != KNNG_FP32)
         e = hipMallocAsync(reinterpret_cast<void**>(&rr.Xr),
-                           knng::reduced_rows_bytes(o.precision, n, D), s);
-    if (e == hipSuccess && o.precision != KNNG_FP32)
+                           knng::reduced_rows_bytes(leaf_prec, n, D), s);
+    if (e == hipSuccess && leaf_prec != KNNG_FP32)
         e = hipMallocAsync(reinterpret_cast<void**>(&rr.nrm), sizeof(float) * n, s);
-    if (e == hipSuccess && o.precision != KNNG_FP32)
+    if (e == hipSuccess && leaf_prec != KNNG_FP32)
         e = hipMallocAsync(reinterpret_cast<void**>(&rr.sinv), sizeof(float) * n, s);
     if (e != hipSuccess) {
         rc = hip_fail(e, "workspace allocation");
@@ -241,7 +246,7 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
         rc = set_err(KNNG_ERR_HIP, "uint8 copy launch failed");
         goto done;
     }
-    if (o.precision != KNNG_FP32 && knng::prep_reduced(o.precision, data, n, D, &rr, s) != KNNG_OK) {
+    if (leaf_prec != KNNG_FP32 && knng::prep_reduced(leaf_prec, data, n, D, &rr, s) != KNNG_OK) {
         rc = set_err(KNNG_ERR_HIP, "reduced-copy launch failed");
         goto done;
     }
@@ -293,15 +298,15 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
         la.leaves = leaves;
         la.n_leaves = r.n_leaves;
         la.leaf_max = leaf_max < n ? leaf_max : static_cast<int>(n);
-        la.precision = o.precision;
+        la.precision = leaf_prec;
         la.rerank = o.rerank * k;
         la.cand_ids = cand_ids + static_cast<size_t>(t0) * n * k;
         la.cand_d = cand_d + static_cast<size_t>(t0) * n * k;
         la.pairs = dpairs;
         la.timer = &timer;
         la.stream = s;
-        rc = o.precision == KNNG_FP32 ? knng::leaf_run(la, &launches, err, sizeof(err))
-                                      : knng::leaf_run_mfma(la, rr, &launches, err, sizeof(err));
+        rc = leaf_prec == KNNG_FP32 ? knng::leaf_run(la, &launches, err, sizeof(err))
+                                    : knng::leaf_run_mfma(la, rr, &launches, err, sizeof(err));
         if (rc != KNNG_OK) {
             set_err(rc, "leaf search: %s", err);
             goto done;
@@ -374,6 +379,7 @@ done:
         stats_out->ms_k_merge = kms[knng::kKMerge];
         stats_out->n_k_merge = kn[knng::kKMerge];
         stats_out->compact_used = use_u8 ? 1 : 0;
+        stats_out->exact_first_pass = exact_bf16 ? 1 : 0;
     }
     return rc;
 }

@@ -16,6 +16,8 @@
 #include "knng_internal.hpp"
 #include "wave.hpp"
 
+#include <type_traits>
+
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -131,9 +133,7 @@ __global__ __launch_bounds__(64) void k_init_nodes(const NodeRec* __restrict__ n
 }
 
 // ------------------------------------------------------------- Lloyd pass
-// Element storage of the reference set for the assignment passes: FP32 as
-// given, or a lossless uint8 copy when every value is an integer in [0, 255]
-// (each stored value is the same number, so every result is unchanged).
+// FP32 rows as given (the uint8 copy has its own pass, k_assign_u8).
 template <typename TX, int VEC>
 struct RowVec;
 template <>
@@ -157,20 +157,7 @@ struct RowVec<float, 4> {  // 4 floats per 16-byte load
         x[3] = q.w;
     }
 };
-template <>
-struct RowVec<uint8_t, 16> {  // 16 bytes per 16-byte load; exact integer sums
-    static constexpr int kVec = 16;
-    using Acc = uint32_t;
-    __device__ static void load(const uint8_t* row, int e, int D, bool ok, float (&x)[16]) {
-        uint4 q = make_uint4(0u, 0u, 0u, 0u);
-        if (ok && e < D) q = *reinterpret_cast<const uint4*>(row + e);
-        const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) x[4 * i + b] = static_cast<float>((w4[i] >> (8 * b)) & 255u);
-    }
-};
+
 
 // One assignment pass over every chunk of every unfinished node.
 // G lanes share one row; each lane holds NF vectors of VEC consecutive
@@ -245,7 +232,13 @@ __global__ __launch_bounds__(256) void k_assign(
             for (int j = 0; j < NF; ++j) RV::load(xr, (l + G * j) * VEC, D, id[u] >= 0, x[u][j]);
         }
     };
-    int idc[U], idn[U];
+    // the previous pass's label of a row, fetched a step ahead with its row
+    // (a load consumed in its own step would wait for every load before it)
+    auto old_label = [&](int st, int u, int id) -> int {
+        const int row = row0 + (st * U + u) * RPW + g;
+        return (pass > 0 && id >= 0 && l == 0) ? static_cast<int>(labels[base + row]) : 0;
+    };
+    int idc[U], idn[U], oc[U];
     float xc[U][NF][VEC];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -253,9 +246,14 @@ __global__ __launch_bounds__(256) void k_assign(
         idn[u] = row_id(1, u);
     }
     load_rows(idc, xc);
+#pragma unroll
+    for (int u = 0; u < U; ++u) oc[u] = old_label(0, u, idc[u]);
     for (int st = 0; st < steps; ++st) {
         float xn[U][NF][VEC];
+        int on[U];
         load_rows(idn, xn);  // rows of step st+1 (ids -1 past the end)
+#pragma unroll
+        for (int u = 0; u < U; ++u) on[u] = old_label(st + 1, u, idn[u]);
         int idnn[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) idnn[u] = row_id(st + 2, u);
@@ -274,10 +272,9 @@ __global__ __launch_bounds__(256) void k_assign(
             if (idc[u] >= 0) {
                 if (l == 0) {
                     const size_t p = base + row;
-                    const uint8_t old = labels[p];
                     labels[p] = lab ? 1 : 0;
                     dots[p] = dot;
-                    changed += (pass > 0 && old != (lab ? 1 : 0)) ? 1 : 0;
+                    changed += (pass > 0 && oc[u] != (lab ? 1 : 0)) ? 1 : 0;
                     n1 += lab ? 1 : 0;
                 }
 #pragma unroll
@@ -294,6 +291,7 @@ __global__ __launch_bounds__(256) void k_assign(
         for (int u = 0; u < U; ++u) {
             idc[u] = idn[u];
             idn[u] = idnn[u];
+            oc[u] = on[u];
 #pragma unroll
             for (int j = 0; j < NF; ++j)
 #pragma unroll
@@ -364,10 +362,233 @@ __global__ __launch_bounds__(256) void k_assign(
     }
 }
 
+// One assignment pass over uint8 rows (the lossless copy of integer data in
+// [0, 255], D % 16 == 0), with the labels and stop rule of k_assign.  G lanes
+// share a row, each holding NF vectors of EPL (8 or 16) elements; U rows per
+// lane group and step.  The side sums are exact integers, so only the side-1
+// sum is accumulated in every pass (a multiply-add by the 0/1 label); the
+// chunk's total is taken in the level's first pass (FIRST) and kept in
+// P[wave][0][.], and the side-0 sum is total - side 1, the same integer as a
+// direct sum.  P[wave][1][.] holds the chunk's side-1 sum of the pass.
+//
+// Memory pipeline: the chunk's row ids and previous labels go to LDS first
+// (all loads in flight at once); the rows of steps st+1 .. st+PD are in
+// flight while step st is computed, in PD+1 register buffers rotated by
+// unrolling (a register copy of a buffer still being loaded would wait for
+// the load).  Row loads are unconditional (row 0 stands in past the end), so
+// the loop's only global loads are rows, counted in issue order.
+template <int EPL, int G, int NF, int U, int PD, bool FIRST>
+__global__ __launch_bounds__(256) void k_assign_u8(
+    const uint8_t* __restrict__ X, int64_t n, int D, const int32_t* __restrict__ perm,
+    const NodeRec* __restrict__ nodes, const int32_t* __restrict__ chunk_node, int nc,
+    double* __restrict__ C, int32_t* __restrict__ status, int32_t* __restrict__ n0f,
+    uint8_t* __restrict__ labels, double* __restrict__ dots, double* __restrict__ P,
+    int32_t* __restrict__ cnt, int pass, int max_iter, unsigned long long* __restrict__ assigned) {
+    using V = typename std::conditional<EPL == 16, uint4, uint2>::type;
+    constexpr int kWords = EPL / 4;
+    constexpr int RPW = kWave / G;  // rows per wave step
+    constexpr int kFill = kChunkRows / kWave;
+    __shared__ int32_t s_ids[4][kChunkRows];
+    __shared__ uint8_t s_old[4][kChunkRows];
+
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wave >= nc) return;
+    const int node = chunk_node[wave];
+    if (status[node]) return;
+    const NodeRec r = nodes[node];
+    const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
+    const int g = lane / G, l = lane % G;
+    const int nch = chunks_of(r.size);
+    const int row0 = (wave - r.chunk0) * kChunkRows;
+    const int nrows = min(r.size - row0, kChunkRows);
+    const size_t base = static_cast<size_t>(r.tree) * n + r.start + row0;
+
+    {  // row ids and previous labels of the chunk into LDS
+        int32_t pid[kFill];
+        uint8_t pl[kFill];
+#pragma unroll
+        for (int q = 0; q < kFill; ++q) {
+            const int i = min(q * kWave + lane, nrows - 1);
+            pid[q] = perm[base + i];
+            pl[q] = FIRST ? 0 : labels[base + i];
+        }
+#pragma unroll
+        for (int q = 0; q < kFill; ++q) {
+            const int i = q * kWave + lane;
+            if (i < nrows) {
+                s_ids[wl][i] = pid[q];
+                s_old[wl][i] = pl[q];
+            }
+        }
+    }
+
+    double* cn = C + static_cast<size_t>(node) * 2 * D;
+    double w[NF][EPL];
+    uint32_t a1[NF][EPL], tot[NF][EPL];
+    bool ev[NF];  // vector j of this lane lies inside the row (else its
+                  // loads read the row's start: finite values with w = 0,
+                  // and its sums are never stored)
+    double q0 = 0.0, q1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+        ev[j] = (l + G * j) * EPL < D;
+#pragma unroll
+        for (int v = 0; v < EPL; ++v) {
+            const int e = (l + G * j) * EPL + v;
+            const double c0 = e < D ? cn[e] : 0.0;
+            const double c1 = e < D ? cn[D + e] : 0.0;
+            w[j][v] = c0 - c1;
+            q0 = fma(c0, c0, q0);
+            q1 = fma(c1, c1, q1);
+            a1[j][v] = 0u;
+            tot[j][v] = 0u;
+        }
+    }
+    q0 = group_sum_f64<G>(q0);
+    q1 = group_sum_f64<G>(q1);
+    const double h = 0.5 * (q0 - q1);
+    int n1 = 0, changed = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    const int steps = (nrows + RPW * U - 1) / (RPW * U);
+    auto load_rows = [&](int st, V (&x)[U][NF]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = (st * U + u) * RPW + g;
+            const int id = i < nrows ? s_ids[wl][i] : 0;
+            const uint8_t* xr = X + static_cast<size_t>(id) * D;
+#pragma unroll
+            for (int j = 0; j < NF; ++j)
+                x[u][j] = *reinterpret_cast<const V*>(xr + (ev[j] ? (l + G * j) * EPL : 0));
+        }
+    };
+    auto compute = [&](int st, const V (&x)[U][NF]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = (st * U + u) * RPW + g;
+            const bool valid = i < nrows;
+            const int old = (!FIRST && valid) ? static_cast<int>(s_old[wl][i]) : 0;
+            uint32_t xv[NF][EPL];
+#pragma unroll
+            for (int j = 0; j < NF; ++j) {
+                uint32_t wd[kWords];
+                __builtin_memcpy(wd, &x[u][j], sizeof(V));
+#pragma unroll
+                for (int k4 = 0; k4 < kWords; ++k4)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        xv[j][4 * k4 + b] = (wd[k4] >> (8 * b)) & 255u;
+            }
+            double dot = 0.0;
+#pragma unroll
+            for (int j = 0; j < NF; ++j)
+#pragma unroll
+                for (int v = 0; v < EPL; ++v) dot = fma(static_cast<double>(xv[j][v]), w[j][v], dot);
+            dot = group_sum_f64<G>(dot);
+            const bool lab = dot < h;
+            if (valid && l == 0) {
+                labels[base + i] = lab ? 1 : 0;
+                dots[base + i] = dot;
+                changed += (!FIRST && old != (lab ? 1 : 0)) ? 1 : 0;
+                n1 += lab ? 1 : 0;
+            }
+            const uint32_t one = (valid && lab) ? 1u : 0u;
+            const uint32_t in = valid ? 1u : 0u;
+#pragma unroll
+            for (int j = 0; j < NF; ++j)
+#pragma unroll
+                for (int v = 0; v < EPL; ++v) {
+                    a1[j][v] = __umul24(xv[j][v], one) + a1[j][v];
+                    if constexpr (FIRST) tot[j][v] = __umul24(xv[j][v], in) + tot[j][v];
+                }
+        }
+    };
+    V xb[PD + 1][U][NF];
+#pragma unroll
+    for (int q = 0; q < PD; ++q) load_rows(q, xb[q]);
+    for (int st0 = 0; st0 < steps; st0 += PD + 1) {
+#pragma unroll
+        for (int ph = 0; ph <= PD; ++ph) {
+            const int st = st0 + ph;
+            load_rows(st + PD, xb[(ph + PD) % (PD + 1)]);  // no branch: waits stay exact
+            if (st < steps) compute(st, xb[ph]);
+        }
+    }
+    // combine the RPW row groups of the wave (exact integer sums)
+#pragma unroll
+    for (int o = G; o < kWave; o <<= 1)
+#pragma unroll
+        for (int j = 0; j < NF; ++j)
+#pragma unroll
+            for (int v = 0; v < EPL; ++v) {
+                a1[j][v] += __shfl_xor(a1[j][v], o, kWave);
+                if constexpr (FIRST) tot[j][v] += __shfl_xor(tot[j][v], o, kWave);
+            }
+    n1 = wave_sum_i32(n1);
+    changed = wave_sum_i32(changed);
+    if (lane == 0) {
+        cnt[2 * wave] = n1;  // ones of this chunk (also read by the scatter)
+        cnt[2 * wave + 1] = changed;
+        atomicAdd(assigned, static_cast<unsigned long long>(nrows));
+    }
+
+    double* p0 = P + static_cast<size_t>(wave) * 2 * D;
+    if (nch == 1) {  // the wave holds the whole node
+        const int n0 = r.size - n1;
+        const bool stop =
+            n1 == 0 || n0 == 0 || (pass >= 1 && changed == 0) || pass + 1 >= max_iter;
+        if (stop) {
+            if (lane == 0) {
+                status[node] = 1;
+                n0f[node] = n0;
+            }
+            return;
+        }
+        if (g == 0) {
+            const double dn0 = static_cast<double>(n0), dn1 = static_cast<double>(n1);
+#pragma unroll
+            for (int j = 0; j < NF; ++j)
+#pragma unroll
+                for (int v = 0; v < EPL; ++v) {
+                    const int e = (l + G * j) * EPL + v;
+                    if (e < D) {
+                        double t;
+                        if constexpr (FIRST) {
+                            t = static_cast<double>(tot[j][v]);
+                            p0[e] = t;
+                        } else {
+                            t = p0[e];
+                        }
+                        const double s1 = static_cast<double>(a1[j][v]);
+                        cn[e] = (t - s1) / dn0;
+                        cn[D + e] = s1 / dn1;
+                    }
+                }
+        }
+        return;
+    }
+    if (g == 0) {  // publish this chunk's sums
+#pragma unroll
+        for (int j = 0; j < NF; ++j)
+#pragma unroll
+            for (int v = 0; v < EPL; ++v) {
+                const int e = (l + G * j) * EPL + v;
+                if (e < D) {
+                    if constexpr (FIRST) p0[e] = static_cast<double>(tot[j][v]);
+                    p0[D + e] = static_cast<double>(a1[j][v]);
+                }
+            }
+    }
+}
+
 // Centre update of the nodes spanning several chunks.  One block per (node,
 // slice of 8 dimensions): 16 values (8 dims x 2 sides) x 16 chunk lanes; lane
 // c sums chunks c, c+16, ... in order, then the 16 lane sums are added in
 // lane order.  Every block of a node derives the same stop decision.
+// totals: side 0 of P holds chunk totals (uint8 rows), so the side-0 sum is
+// total - side 1.
 constexpr int kUpdDims = 8;
 constexpr int kUpdLanes = 16;
 
@@ -378,7 +599,7 @@ __global__ __launch_bounds__(256) void k_update_big(const NodeRec* __restrict__ 
                                                     double* __restrict__ C,
                                                     int32_t* __restrict__ status,
                                                     int32_t* __restrict__ n0f, int pass,
-                                                    int max_iter) {
+                                                    int max_iter, int totals) {
     const int slices = (D + kUpdDims - 1) / kUpdDims;
     const int node = big[blockIdx.x / slices];
     const int slice = blockIdx.x % slices;
@@ -443,6 +664,11 @@ __global__ __launch_bounds__(256) void k_update_big(const NodeRec* __restrict__ 
     if (tid < 2 * kUpdDims && d < D) {
         double t = 0.0;
         for (int k = 0; k < kUpdLanes; ++k) t += s_sum[k][tid];
+        if (totals && side == 0) {  // P holds totals and side-1 sums (exact integers)
+            double t1 = 0.0;
+            for (int k = 0; k < kUpdLanes; ++k) t1 += s_sum[k][tid + kUpdDims];
+            t -= t1;
+        }
         const double cnt_side = side ? static_cast<double>(n1) : static_cast<double>(n0);
         C[static_cast<size_t>(node) * 2 * D + side * static_cast<size_t>(D) + d] = t / cnt_side;
     }
@@ -771,14 +997,52 @@ AssignFn<float> pick_assign_f32(int D, int epl, int u) {
     return nullptr;
 }
 
-// uint8 rows (D % 16 == 0): 16 elements per lane.
-AssignFn<uint8_t> pick_assign_u8(int D, int u) {
-    const int E = D / 16;
-    if (E <= 32) return pick_groups<uint8_t, 16, 1>(E, u);
-    if (E <= 64) return pick_unroll<uint8_t, 16, 64, 1>(u);
-    if (E <= 128) return k_assign<uint8_t, 16, 64, 2, 1>;
-    if (E <= 256) return k_assign<uint8_t, 16, 64, 4, 1>;
-    return nullptr;
+// uint8 rows (D % 16 == 0): EPL (8 or 16) elements per lane; f[0] for a
+// level's first pass, f[1] for the later ones.
+template <int EPL, int G, int NF, int U>
+void pick_u8_depth(int pd, AssignFn<uint8_t>* f) {
+    if (pd == 2) {
+        f[0] = k_assign_u8<EPL, G, NF, U, 2, true>;
+        f[1] = k_assign_u8<EPL, G, NF, U, 2, false>;
+    } else {
+        f[0] = k_assign_u8<EPL, G, NF, U, 1, true>;
+        f[1] = k_assign_u8<EPL, G, NF, U, 1, false>;
+    }
+}
+
+template <int EPL, int G, int NF>
+void pick_u8_unroll(int u, int pd, AssignFn<uint8_t>* f) {
+    switch (u) {
+        case 1: pick_u8_depth<EPL, G, NF, 1>(pd, f); break;
+        case 2: pick_u8_depth<EPL, G, NF, 2>(pd, f); break;
+        default: pick_u8_depth<EPL, G, NF, 4>(pd, f); break;
+    }
+}
+
+template <int EPL>
+bool pick_u8_epl(int D, int u, int pd, AssignFn<uint8_t>* f) {
+    const int E = D / EPL;
+    int G = 1;
+    while (G < 64 && G < E) G <<= 1;
+    f[0] = f[1] = nullptr;
+    switch (G) {
+        case 1: pick_u8_unroll<EPL, 1, 1>(u, pd, f); break;
+        case 2: pick_u8_unroll<EPL, 2, 1>(u, pd, f); break;
+        case 4: pick_u8_unroll<EPL, 4, 1>(u, pd, f); break;
+        case 8: pick_u8_unroll<EPL, 8, 1>(u, pd, f); break;
+        case 16: pick_u8_unroll<EPL, 16, 1>(u, pd, f); break;
+        case 32: pick_u8_unroll<EPL, 32, 1>(u, pd, f); break;
+        default:
+            if (E <= 64) pick_u8_unroll<EPL, 64, 1>(u, pd, f);
+            else if (E <= 128) pick_u8_depth<EPL, 64, 2, 1>(pd, f);
+            else if (E <= 256) pick_u8_depth<EPL, 64, 4, 1>(pd, f);
+            break;
+    }
+    return f[0] != nullptr;
+}
+
+bool pick_assign_u8(int D, int epl, int u, int pd, AssignFn<uint8_t>* f) {
+    return epl == 8 ? pick_u8_epl<8>(D, u, pd, f) : pick_u8_epl<16>(D, u, pd, f);
 }
 
 int env_int(const char* name, int dflt) {
@@ -818,16 +1082,20 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     const int L = a.leaf_max;
     hipStream_t s = a.stream;
     // Tuned on MI355X (1M x 128 rows): FP32 rows 8 elements per lane, one row
-    // per lane group and step; uint8 rows four.  The environment may override
+    // per lane group and step; uint8 rows 16 elements per lane, two rows per
+    // step, one step of loads ahead.  The environment may override
     // both for tuning runs.
     const bool use_u8 = a.X8 != nullptr && D % 16 == 0;
     int epl = env_int("KNNG_ASSIGN_EPL", 8);
-    int unroll = env_int("KNNG_ASSIGN_UNROLL", use_u8 ? 4 : 1);
+    int unroll = env_int("KNNG_ASSIGN_UNROLL", use_u8 ? 2 : 1);
     if (epl != 4 && epl != 8 && epl != 16) epl = 8;
-    if (unroll != 1 && unroll != 2 && unroll != 4) unroll = use_u8 ? 4 : 1;
+    if (unroll != 1 && unroll != 2 && unroll != 4) unroll = use_u8 ? 2 : 1;
     AssignFn<float> assign = use_u8 ? nullptr : pick_assign_f32(D, epl, unroll);
-    AssignFn<uint8_t> assign8 = use_u8 ? pick_assign_u8(D, unroll) : nullptr;
-    if (assign == nullptr && assign8 == nullptr) {
+    AssignFn<uint8_t> assign8[2] = {nullptr, nullptr};
+    const int epl8 = env_int("KNNG_ASSIGN_U8_EPL", 16) == 8 ? 8 : 16;
+    const int depth8 = env_int("KNNG_ASSIGN_U8_DEPTH", 1) == 2 ? 2 : 1;
+    if (use_u8) pick_assign_u8(D, epl8, unroll, depth8, assign8);
+    if (assign == nullptr && assign8[0] == nullptr) {
         std::snprintf(err, errlen, "dimension %d not supported by the partition kernels", D);
         return kUnsupported;
     }
@@ -903,9 +1171,9 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
         for (int pass = 0; pass < a.max_iter; ++pass) {
             if (a.timer) a.timer->begin(kKAssign, s);
             if (use_u8)
-                assign8<<<cblocks, 256, 0, s>>>(a.X8, n, D, a.perm, nodes[cur], chunk_node, nc, C,
-                                                status, n0f, labels, dots, P, cnt, pass,
-                                                a.max_iter, dstats);
+                assign8[pass == 0 ? 0 : 1]<<<cblocks, 256, 0, s>>>(
+                    a.X8, n, D, a.perm, nodes[cur], chunk_node, nc, C, status, n0f, labels, dots,
+                    P, cnt, pass, a.max_iter, dstats);
             else
                 assign<<<cblocks, 256, 0, s>>>(a.X, n, D, a.perm, nodes[cur], chunk_node, nc, C,
                                                status, n0f, labels, dots, P, cnt, pass,
@@ -914,7 +1182,8 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
             KNNG_LAUNCH();
             if (nb > 0) {
                 k_update_big<<<nb * slices, 256, 0, s>>>(nodes[cur], big[cur], D, P, cnt, C,
-                                                         status, n0f, pass, a.max_iter);
+                                                         status, n0f, pass, a.max_iter,
+                                                         use_u8 ? 1 : 0);
                 KNNG_LAUNCH();
             }
         }

@@ -29,6 +29,35 @@ __device__ __forceinline__ double shfl_xor_f64(double v, int mask) {
         shfl_xor_u64(static_cast<uint64_t>(__double_as_longlong(v)), mask)));
 }
 
+// DPP exchange of a double between lanes of a 16-lane row (every lane active).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t u = static_cast<uint64_t>(__double_as_longlong(v));
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<uint32_t>(u)), CTRL,
+                                               0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<uint32_t>(u >> 32)),
+                                               CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(static_cast<long long>(
+        (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo)));
+}
+
+// Sum of v over each aligned group of G lanes (G a power of two <= 64), the
+// same value in every lane of the group.  Each stage adds the value of a
+// partner lane from the complementary half of the block (partners are
+// mutual and a + b == b + a, so both hold the same sum): lane xor 1, xor 2
+// (quad permutes), mirror within 8 and within 16 lanes (DPP), then xor 16
+// and xor 32 (permute through LDS).
+template <int G>
+__device__ __forceinline__ double group_sum_f64(double v) {
+    if constexpr (G >= 2) v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+    if constexpr (G >= 4) v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+    if constexpr (G >= 8) v += dpp_f64<0x141>(v);  // row_half_mirror
+    if constexpr (G >= 16) v += dpp_f64<0x140>(v); // row_mirror
+    if constexpr (G >= 32) v += shfl_xor_f64(v, 16);
+    if constexpr (G >= 64) v += shfl_xor_f64(v, 32);
+    return v;
+}
+
 // Sum over all 64 lanes of an integer (order irrelevant).
 __device__ __forceinline__ int wave_sum_i32(int v) {
 #pragma unroll

@@ -69,31 +69,43 @@ def _valid_rows(orc, X, ids, ds, co, k):
 
 
 def test_bf16_integer_data_bit_identical_to_fp32(K, orc):
+    """Integers 0..255, D=128: the BF16 first pass is exact, so the exact
+    matrix-core path (taken for FP32 and BF16 requests) gives the FP32 direct
+    path's graph bit for bit."""
     X = datagen.make("c2", n=20_000)
     Xd = to_dev(X)
     log("bf16 build on integer data")
-    a = K.build(Xd, 20, 3, 100, seed=2)
-    b = K.build(Xd, 20, 3, 100, seed=2, precision="bf16")
-    assert np.array_equal(_np(a[0]), _np(b[0]))
-    assert np.array_equal(_np(a[1]).view(np.int32), _np(b[1]).view(np.int32))
+    a = K.build(Xd, 20, 3, 100, seed=2, compact=False, stats=True)   # FP32 rows, FP32 leaves
+    b = K.build(Xd, 20, 3, 100, seed=2, precision="bf16", stats=True)
+    f = K.build(Xd, 20, 3, 100, seed=2, stats=True)                  # FP32 request
+    assert a[2]["exact_first_pass"] == 0 and b[2]["exact_first_pass"] == 1
+    assert f[2]["exact_first_pass"] == 1
+    for r in (b, f):
+        assert np.array_equal(_np(a[0]), _np(r[0]))
+        assert np.array_equal(_np(a[1]).view(np.int32), _np(r[1]).view(np.int32))
     o_ids, o_d, _ = orc.graph(X, 20, 3, 100, 2)
     graph_parity(orc, X, np.arange(len(X)), _np(b[0]), _np(b[1]), o_ids, o_d, strict=True)
 
 
-@pytest.mark.parametrize("precision", ["bf16", "fp16", "fp8"])
-def test_full_candidate_budget_equals_fp32(K, orc, precision):
+@pytest.mark.parametrize("precision,L,rerank", [
+    ("bf16", 50, 5), ("fp16", 50, 5), ("fp8", 50, 5),       # wave-per-row kernel (c = 50)
+    ("bf16", 30, 3), ("fp16", 30, 3), ("fp8", 30, 3),       # thread-per-row kernel (c = 30)
+])
+def test_full_candidate_budget_equals_fp32(K, orc, precision, L, rerank):
     """rerank * k >= leaf size - 1: every co-leaf member is re-ranked with
     d32, so the result is the FP32 path's, bit for bit."""
     X = datagen.make("c1", n=5000)
-    perms, offs = _oracle_leaves(orc, X, 2, 50, 11, 4)
+    perms, offs = _oracle_leaves(orc, X, 2, L, 11, 4)
     a = _gpu_leaf_search(K, X, 10, perms, offs, "fp32")
-    b = _gpu_leaf_search(K, X, 10, perms, offs, precision, rerank=5)
+    b = _gpu_leaf_search(K, X, 10, perms, offs, precision, rerank=rerank)
     assert np.array_equal(_np(a[0]), _np(b[0]))
     assert np.array_equal(_np(a[1]).view(np.int32), _np(b[1]).view(np.int32))
 
 
 @pytest.mark.parametrize("precision,n,D,k,T,L,kind", [
-    ("bf16", 6000, 32, 10, 2, 50, "c1"),
+    ("bf16", 6000, 32, 10, 2, 50, "c1"),      # thread-per-row kernel (c = 20)
+    ("fp16", 6000, 128, 16, 2, 100, "unit960"),  # thread-per-row, 112-point tiles (c = 32)
+    ("fp8", 5000, 64, 12, 2, 128, "c1"),      # thread-per-row, 128-point tiles (c = 24)
     ("fp16", 3000, 960, 20, 2, 200, "unit960"),
     ("fp8", 6000, 96, 32, 2, 500, "unit96"),
     ("fp8", 4000, 32, 10, 2, 100, "c1"),
@@ -102,6 +114,8 @@ def test_full_candidate_budget_equals_fp32(K, orc, precision):
 def test_reduced_matches_emulation(K, orc, precision, n, D, k, T, L, kind):
     if kind == "c1":
         X = datagen.gmm_uniform(n, D, 20, -10, 10, 1.0, 11)
+    elif kind == "unit960" and D != 960:
+        X = datagen.gmm_unit(n, D, 16, 0.35, 13)
     else:
         X = datagen.gmm_unit(n, D, 16, 0.35, 12)
     perms, offs = _oracle_leaves(orc, X, T, L, k + 1, 5)
@@ -126,3 +140,27 @@ def test_reduced_build_end_to_end(K, orc):
     r_exact_alg = orc.recall(X, rows[::10], o_ids[::10], E, Ed)
     log("recall fp8 %.4f vs FP64 algorithm %.4f" % (r_fp8, r_exact_alg))
     assert r_fp8 > r_exact_alg - 0.01
+
+
+@pytest.mark.parametrize("precision,L", [
+    ("fp32", 50), ("fp32", 200),                  # FP32 direct kernel
+    ("bf16", 50), ("fp16", 50), ("fp8", 50),      # thread-per-row kernel (c = 20)
+    ("bf16", 200), ("fp8", 200),                  # wave-per-row kernel
+])
+def test_ties_fall_to_smaller_id_on_shuffled_leaves(K, orc, precision, L):
+    """Integers 0..3 (many equal distances; exact in every first-pass format,
+    so d~ = d32 = d64) with each leaf's ids shuffled: the c = 2k pre-selection
+    and the final list must break distance ties by id, not by position, so the
+    result equals the oracle's (d, id)-ordered graph bit for bit."""
+    X = datagen.random_points(3000, 16, 21, "small_int")
+    perms, offs = _oracle_leaves(orc, X, 2, L, 11, 6)
+    rng = np.random.default_rng(5)
+    sh = perms.copy()
+    for t in range(len(offs)):
+        for s, e in zip(offs[t][:-1], offs[t][1:]):
+            sh[t, s:e] = rng.permutation(sh[t, s:e])
+    log("shuffled leaves %s L=%d" % (precision, L))
+    ids, ds = _gpu_leaf_search(K, X, 10, sh, offs, precision)
+    o_ids, o_d = orc.graph_from_leaves(X, 10, perms, offs)
+    assert np.array_equal(_np(ids), o_ids)
+    assert np.array_equal(_np(ds).astype(np.float64), o_d)
