@@ -322,13 +322,16 @@ __global__ __launch_bounds__(256) void k_leaf_mfma(
 }
 
 // ------------------------------------------------------------- small leaves
-// Leaves of at most MP (64 or 128) points.  The Gram on MFMA fills the whole
-// leaf's d~ block in LDS; then thread t owns row t: it scans the row once,
-// keeping its CL smallest (d~, position) in a register list (insertion by
-// compare-exchange on the pair; positions ascend with ids); for
-// the re-rank it streams the leaf's FP32 rows through LDS in 32-dimension
-// blocks and accumulates d32 of its candidates, then keeps the k smallest
-// (d32, id).  EXACT (first pass exact): the list is the answer.
+// Leaves of at most MP (64, 112 or 128) points.  The Gram on MFMA fills the
+// whole leaf's block of keys in LDS; then thread t owns row t and scans it
+// once, keeping its CL smallest keys in a sorted register list.
+//
+// EXACT (first pass exact, so d~ is the integer d32 < 2^23): the 32-bit key
+// (d << 7) | position orders by (distance, position) = (distance, id), and
+// insertion is one min and one max per slot; the list is the answer.
+// Otherwise the key is the 64-bit (order key of d~) << 32 | position, the
+// list is re-ranked with d32 by streaming the leaf's FP32 rows through LDS
+// in 32-dimension blocks, and the k smallest (d32, id) are kept.
 template <int FMT, int MP, int CL, int KL, bool EXACT>
 __global__ __launch_bounds__(256) void k_leaf_small(
     const float* __restrict__ X, const uint8_t* __restrict__ Xr, int64_t n, int D, int Dp,
@@ -337,12 +340,13 @@ __global__ __launch_bounds__(256) void k_leaf_small(
     int32_t* __restrict__ cand_ids, float* __restrict__ cand_d,
     unsigned long long* __restrict__ pairs) {
     using F = Frag<FMT>;
+    static_assert(MP <= 128, "positions take 7 bits of the exact key");
     constexpr int NT = MP / 16;            // row and column tiles
     constexpr int RPW = (NT + 3) / 4;      // row tiles per wave (the last may be empty)
-    // LDS: the d~ block, later the 32-dim FP32 blocks of the re-rank
-    constexpr int kDistFloats = MP * (MP + 1);
+    // LDS: the key block, later the 32-dim FP32 blocks of the re-rank
+    constexpr int kKeyWords = MP * (MP + 1);
     constexpr int kRowFloats = MP * 33;
-    __shared__ float lds[kDistFloats > kRowFloats ? kDistFloats : kRowFloats];
+    __shared__ uint32_t lds[kKeyWords > kRowFloats ? kKeyWords : kRowFloats];
     __shared__ int32_t ids[MP];
     __shared__ float snrm[MP], ssinv[MP];
 
@@ -403,75 +407,89 @@ __global__ __launch_bounds__(256) void k_leaf_small(
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int row = (wv * RPW + q) * 16 + 4 * kg + i;
-                    float v = __int_as_float(0x7f800000);
-                    if (row < m && col < m && row != col)
-                        v = snrm[row] + snrm[col] - 2.f * acc[q][t][i] * (ssinv[row] * ssinv[col]);
-                    if (row < MP) lds[row * (MP + 1) + col] = v;
+                    uint32_t key = 0xffffffffu;  // diagonal, padding
+                    if (row < m && col < m && row != col) {
+                        const float v =
+                            snrm[row] + snrm[col] - 2.f * acc[q][t][i] * (ssinv[row] * ssinv[col]);
+                        if constexpr (EXACT)
+                            key = (static_cast<uint32_t>(v) << 7) | static_cast<uint32_t>(col);
+                        else
+                            key = fkey(v);
+                    }
+                    if (row < MP) lds[row * (MP + 1) + col] = key;
                 }
             }
     }
     __syncthreads();
 
-    // ---- thread t: the CL smallest (d~, position) of row t
     const int t = tid;
     const bool own = t < m;
-    float Ld[CL];
-    int Lp[CL];
-#pragma unroll
-    for (int i = 0; i < CL; ++i) {
-        Ld[i] = __int_as_float(0x7f800000);
-        Lp[i] = -1;
-    }
-    if (own) {
-        const float* drow = lds + t * (MP + 1);
-        for (int j = 0; j < m; ++j) {
-            float d = drow[j];  // +inf on the diagonal
-            int p = j;
-#pragma unroll
-            for (int i = 0; i < CL; ++i) {
-                // (d~, position) order; positions ascend with ids
-                const bool lt = d < Ld[i] || (d == Ld[i] && p < Lp[i]);
-                const float td = Ld[i];
-                const int tp = Lp[i];
-                Ld[i] = lt ? d : td;
-                Lp[i] = lt ? p : tp;
-                d = lt ? td : d;
-                p = lt ? tp : p;
-            }
-        }
-    }
     const int ce = (c < m - 1 ? c : m - 1);
     if constexpr (EXACT) {
+        // ---- thread t: the CL smallest keys of row t (sorted insertion by min/max)
+        uint32_t L[CL];
+#pragma unroll
+        for (int i = 0; i < CL; ++i) L[i] = 0xffffffffu;
         if (own) {
+            const uint32_t* krow = lds + t * (MP + 1);
+            for (int j = 0; j < m; ++j) {
+                uint32_t x = krow[j];
+#pragma unroll
+                for (int i = 0; i < CL; ++i) {
+                    const uint32_t hi = max(L[i], x);
+                    L[i] = min(L[i], x);
+                    x = hi;
+                }
+            }
             const size_t out = (static_cast<size_t>(lf.tree) * n + ids[t]) * k;
 #pragma unroll
             for (int e = 0; e < CL; ++e)
                 if (e < k) {
-                    const bool ok = e < ce && Lp[e] >= 0;
-                    cand_ids[out + e] = ok ? ids[Lp[e]] : -1;
-                    cand_d[out + e] = ok ? Ld[e] : __int_as_float(0x7f800000);
+                    const bool ok = e < ce;
+                    cand_ids[out + e] = ok ? ids[L[e] & 127u] : -1;
+                    cand_d[out + e] = ok ? static_cast<float>(L[e] >> 7) : __int_as_float(0x7f800000);
                 }
         }
         return;
     } else {
+        // ---- thread t: the CL smallest (d~, position) of row t
+        uint64_t L[CL];
+#pragma unroll
+        for (int i = 0; i < CL; ++i) L[i] = ~0ull;
+        if (own) {
+            const uint32_t* krow = lds + t * (MP + 1);
+            for (int j = 0; j < m; ++j) {
+                const uint32_t kj = krow[j];
+                uint64_t x = kj == 0xffffffffu ? ~0ull
+                                               : (static_cast<uint64_t>(kj) << 32) | static_cast<uint32_t>(j);
+#pragma unroll
+                for (int i = 0; i < CL; ++i) {
+                    const bool lt = x < L[i];
+                    const uint64_t lo = lt ? x : L[i];
+                    x = lt ? L[i] : x;
+                    L[i] = lo;
+                }
+            }
+        }
         // ---- re-rank the ce candidates with d32, 32-dim blocks through LDS
         float tot[CL];
 #pragma unroll
         for (int i = 0; i < CL; ++i) tot[i] = 0.f;
-        __syncthreads();  // every thread is done reading the d~ block
+        float* rows = reinterpret_cast<float*>(lds);
+        __syncthreads();  // every thread is done reading the key block
         for (int d0 = 0; d0 < D; d0 += 32) {
             for (int idx = tid; idx < m * 32; idx += 256) {
                 const int j = idx >> 5, dd = idx & 31;
-                lds[j * 33 + dd] = d0 + dd < D ? X[static_cast<size_t>(ids[j]) * D + d0 + dd] : 0.f;
+                rows[j * 33 + dd] = d0 + dd < D ? X[static_cast<size_t>(ids[j]) * D + d0 + dd] : 0.f;
             }
             __syncthreads();
             if (own) {
                 const int dn = D - d0 < 32 ? D - d0 : 32;
-                const float* xr = lds + t * 33;
+                const float* xr = rows + t * 33;
 #pragma unroll
                 for (int i = 0; i < CL; ++i) {
                     if (i < ce) {
-                        const float* xc = lds + Lp[i] * 33;
+                        const float* xc = rows + static_cast<uint32_t>(L[i]) * 33;
                         float blk = 0.f;
                         for (int dd = 0; dd < dn; ++dd) {
                             const float df = xr[dd] - xc[dd];
@@ -484,28 +502,20 @@ __global__ __launch_bounds__(256) void k_leaf_small(
             __syncthreads();
         }
         if (own) {
-            // k smallest (d32, id), by insertion (KL >= k)
-            float Kd[KL];
-            int Ki[KL];
+            // k smallest (d32, id): 64-bit keys, d32 >= 0 (KL >= k)
+            uint64_t K[KL];
 #pragma unroll
-            for (int i = 0; i < KL; ++i) {
-                Kd[i] = __int_as_float(0x7f800000);
-                Ki[i] = 0x7fffffff;
-            }
+            for (int i = 0; i < KL; ++i) K[i] = kNoKey;
 #pragma unroll
             for (int s = 0; s < CL; ++s) {
                 if (s < ce) {
-                    float d = tot[s];
-                    int id = ids[Lp[s]];
+                    uint64_t x = cand_key(tot[s], ids[static_cast<uint32_t>(L[s])]);
 #pragma unroll
                     for (int i = 0; i < KL; ++i) {
-                        const bool lt = d < Kd[i] || (d == Kd[i] && id < Ki[i]);
-                        const float td = Kd[i];
-                        const int ti = Ki[i];
-                        Kd[i] = lt ? d : td;
-                        Ki[i] = lt ? id : ti;
-                        d = lt ? td : d;
-                        id = lt ? ti : id;
+                        const bool lt = x < K[i];
+                        const uint64_t lo = lt ? x : K[i];
+                        x = lt ? K[i] : x;
+                        K[i] = lo;
                     }
                 }
             }
@@ -514,8 +524,8 @@ __global__ __launch_bounds__(256) void k_leaf_small(
             for (int e = 0; e < KL; ++e)
                 if (e < k) {
                     const bool ok = e < ce;
-                    cand_ids[out + e] = ok ? Ki[e] : -1;
-                    cand_d[out + e] = ok ? Kd[e] : __int_as_float(0x7f800000);
+                    cand_ids[out + e] = ok ? key_id(K[e]) : -1;
+                    cand_d[out + e] = ok ? key_dist(K[e]) : __int_as_float(0x7f800000);
                 }
         }
     }
@@ -545,9 +555,16 @@ int launch_fmt(const LeafArgs& a, const ReducedRows& rr, int* launches, char* er
         // CL >= c candidates per row; KL >= k final list (re-rank only)
         auto small = [&](auto mp_tag) -> int {
             constexpr int MP = decltype(mp_tag)::value;
-            if constexpr (EXACT) {
-                if (c <= 16) return go(k_leaf_small<FMT, MP, 16, 16, true>);
-                return go(k_leaf_small<FMT, MP, 32, 32, true>);
+            if constexpr (EXACT) {  // list of exactly k rounded up to 4
+                switch ((c + 3) / 4) {
+                    case 1: case 2: return go(k_leaf_small<FMT, MP, 8, 8, true>);
+                    case 3: return go(k_leaf_small<FMT, MP, 12, 12, true>);
+                    case 4: return go(k_leaf_small<FMT, MP, 16, 16, true>);
+                    case 5: return go(k_leaf_small<FMT, MP, 20, 20, true>);
+                    case 6: return go(k_leaf_small<FMT, MP, 24, 24, true>);
+                    case 7: return go(k_leaf_small<FMT, MP, 28, 28, true>);
+                    default: return go(k_leaf_small<FMT, MP, 32, 32, true>);
+                }
             } else {
                 if (c <= 16) return go(k_leaf_small<FMT, MP, 16, 16, false>);
                 return a.k <= 16 ? go(k_leaf_small<FMT, MP, 32, 16, false>)
