@@ -38,7 +38,7 @@ struct LevelCounters {
     int32_t n_big;      // next-level nodes spanning more than one chunk
     int32_t n_leaves;   // leaves so far
     int32_t n_log;      // bisected nodes logged so far
-    int32_t pad;
+    int32_t n_sub;      // nodes handed to the subtree kernel so far
 };
 
 // Status codes (mirror include/knng.h).
@@ -73,6 +73,33 @@ class KernelTimer {
     int n_ = 0, cap_ = 0;
     int open_ = -1;
 };
+
+// ---------------------------------------------------------------- subtrees
+// Nodes of at most subtree_max_rows(D) rows (uint8 rows only) are split to
+// leaves by one workgroup each (subtree.hip); roots[i].chunk0 holds the
+// node's depth.
+struct SubtreeArgs {
+    const uint8_t* X8;
+    int64_t n;
+    int D;
+    const NodeRec* roots;
+    int n_roots;
+    int32_t* perm;
+    int leaf_max, min_leaf, max_iter;
+    uint64_t seed;
+    int tree0;
+    LeafRec* leaves;
+    int64_t leaves_cap;
+    int32_t* node_log;
+    int64_t node_log_cap;
+    LevelCounters* ctr;
+    unsigned long long* dstats;  // [assigned rows, repairs, splits, deepest split depth + 1]
+    int* overflow;               // bit 0: leaf list full, bit 1: subtree stack full
+    int row_budget;              // LDS bytes for rows per workgroup: 131072 or 65536
+    hipStream_t stream;
+};
+int subtree_max_rows(int D, int row_budget);  // 0: the subtree kernel does not take this D
+int subtree_launch(const SubtreeArgs& a);
 
 // ---------------------------------------------------------------- partition
 struct PartitionArgs {

@@ -14,6 +14,7 @@
 // order (lane butterflies, then chunks in index order), so results are
 // bit-reproducible.
 #include "knng_internal.hpp"
+#include "partition_dev.hpp"
 #include "wave.hpp"
 
 #include <type_traits>
@@ -22,49 +23,26 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <vector>
 
 namespace knng {
 namespace {
-
-// ------------------------------------------------------------- random pair
-// Keyed starting pair.  SplitMix64 output function (Steele, Lea, Flood,
-// OOPSLA 2014); each key word is absorbed as one SplitMix64 step taken from
-// state (h xor word).  Key: (seed, tree, smallest member id, node size, j).
-constexpr uint64_t kGolden = 0x9e3779b97f4a7c15ull;
-
-__device__ __forceinline__ uint64_t splitmix_out(uint64_t z) {
-    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-    return z ^ (z >> 31);
-}
-
-__device__ __forceinline__ uint64_t pair_hash(uint64_t seed, uint64_t tree, uint64_t min_id,
-                                              uint64_t size, uint64_t j) {
-    uint64_t h = seed;
-    h = splitmix_out((h ^ tree) + kGolden);
-    h = splitmix_out((h ^ min_id) + kGolden);
-    h = splitmix_out((h ^ size) + kGolden);
-    h = splitmix_out((h ^ j) + kGolden);
-    return h;
-}
-
-// Unsigned key with the order of a double (after turning -0 into +0).
-__device__ __forceinline__ uint64_t ordered_key(double v) {
-    v = v + 0.0;
-    const uint64_t u = static_cast<uint64_t>(__double_as_longlong(v));
-    return (u >> 63) ? ~u : (u | (1ull << 63));
-}
+using namespace pdev;
 
 __device__ __forceinline__ int chunks_of(int size) { return (size + kChunkRows - 1) / kChunkRows; }
 
 // ------------------------------------------------------------- level setup
-// Root nodes (or root leaves when n <= leaf_max) of every tree slot.
-__global__ void k_roots(int T, int64_t n, int leaf_max, NodeRec* nodes, int32_t* big,
-                        LeafRec* leaves, LevelCounters* ctr) {
+// Root nodes (or root leaves when n <= leaf_max) of every tree slot; roots
+// of at most small_max rows go straight to the subtree list (depth 0).
+__global__ void k_roots(int T, int64_t n, int leaf_max, int small_max, NodeRec* nodes,
+                        int32_t* big, NodeRec* sub, LeafRec* leaves, LevelCounters* ctr) {
     const int nch = static_cast<int>((n + kChunkRows - 1) / kChunkRows);
     const bool split = n > leaf_max;
+    const bool small = split && n <= small_max;
     for (int t = threadIdx.x; t < T; t += blockDim.x) {
-        if (split) {
+        if (small) {
+            sub[t] = NodeRec{t, 0, static_cast<int32_t>(n), 0};
+        } else if (split) {
             nodes[t] = NodeRec{t, 0, static_cast<int32_t>(n), t * nch};
             big[t] = t;
         } else {
@@ -72,11 +50,13 @@ __global__ void k_roots(int T, int64_t n, int leaf_max, NodeRec* nodes, int32_t*
         }
     }
     if (threadIdx.x == 0) {
-        ctr->n_next = split ? T : 0;
-        ctr->nc_next = split ? T * nch : 0;
-        ctr->n_big = (split && nch > 1) ? T : 0;
+        const bool level = split && !small;
+        ctr->n_next = level ? T : 0;
+        ctr->nc_next = level ? T * nch : 0;
+        ctr->n_big = (level && nch > 1) ? T : 0;
         ctr->n_leaves = split ? 0 : T;
         ctr->n_log = 0;
+        ctr->n_sub = small ? T : 0;
     }
 }
 
@@ -94,7 +74,7 @@ __global__ void k_fill_u8(uint8_t* p, int64_t count) {
 }
 
 __global__ void k_zero_small(unsigned long long* stats, int* flag) {
-    if (threadIdx.x < 2) stats[threadIdx.x] = 0ull;
+    if (threadIdx.x < 4) stats[threadIdx.x] = 0ull;
     if (threadIdx.x == 0) *flag = 0;
 }
 
@@ -423,6 +403,7 @@ __global__ __launch_bounds__(256) void k_assign_u8(
     }
 
     double* cn = C + static_cast<size_t>(node) * 2 * D;
+    double* p0 = P + static_cast<size_t>(wave) * 2 * D;
     double w[NF][EPL];
     uint32_t a1[NF][EPL], tot[NF][EPL];
     bool ev[NF];  // vector j of this lane lies inside the row (else its
@@ -440,7 +421,9 @@ __global__ __launch_bounds__(256) void k_assign_u8(
             w[j][v] = c0 - c1;
             q0 = fma(c0, c0, q0);
             q1 = fma(c1, c1, q1);
-            a1[j][v] = 0u;
+            // later passes start from the previous pass's side-1 sum (row
+            // group 0 only; the groups are added at the end)
+            a1[j][v] = (!FIRST && g == 0 && e < D) ? static_cast<uint32_t>(p0[D + e]) : 0u;
             tot[j][v] = 0u;
         }
     }
@@ -494,15 +477,28 @@ __global__ __launch_bounds__(256) void k_assign_u8(
                 changed += (!FIRST && old != (lab ? 1 : 0)) ? 1 : 0;
                 n1 += lab ? 1 : 0;
             }
-            const uint32_t one = (valid && lab) ? 1u : 0u;
-            const uint32_t in = valid ? 1u : 0u;
+            if constexpr (FIRST) {
+                const uint32_t one = (valid && lab) ? 1u : 0u;
+                const uint32_t in = valid ? 1u : 0u;
 #pragma unroll
-            for (int j = 0; j < NF; ++j)
+                for (int j = 0; j < NF; ++j)
 #pragma unroll
-                for (int v = 0; v < EPL; ++v) {
-                    a1[j][v] = __umul24(xv[j][v], one) + a1[j][v];
-                    if constexpr (FIRST) tot[j][v] = __umul24(xv[j][v], in) + tot[j][v];
+                    for (int v = 0; v < EPL; ++v) {
+                        a1[j][v] = __umul24(xv[j][v], one) + a1[j][v];
+                        tot[j][v] = __umul24(xv[j][v], in) + tot[j][v];
+                    }
+            } else {
+                // only rows that switched sides move the side-1 sum
+                const int df = valid ? (lab ? 1 : 0) - old : 0;
+                if (df != 0) {
+#pragma unroll
+                    for (int j = 0; j < NF; ++j)
+#pragma unroll
+                        for (int v = 0; v < EPL; ++v)
+                            a1[j][v] = static_cast<uint32_t>(
+                                __mul24(df, static_cast<int>(xv[j][v])) + static_cast<int>(a1[j][v]));
                 }
+            }
         }
     };
     V xb[PD + 1][U][NF];
@@ -534,7 +530,6 @@ __global__ __launch_bounds__(256) void k_assign_u8(
         atomicAdd(assigned, static_cast<unsigned long long>(nrows));
     }
 
-    double* p0 = P + static_cast<size_t>(wave) * 2 * D;
     if (nch == 1) {  // the wave holds the whole node
         const int n0 = r.size - n1;
         const bool stop =
@@ -562,6 +557,7 @@ __global__ __launch_bounds__(256) void k_assign_u8(
                             t = p0[e];
                         }
                         const double s1 = static_cast<double>(a1[j][v]);
+                        p0[D + e] = s1;
                         cn[e] = (t - s1) / dn0;
                         cn[D + e] = s1 / dn1;
                     }
@@ -675,23 +671,6 @@ __global__ __launch_bounds__(256) void k_update_big(const NodeRec* __restrict__ 
 }
 
 // ------------------------------------------------------------- repair
-// Block-wide exclusive scan of one flag per thread (256 threads).
-__device__ __forceinline__ int block_excl_scan_flag(bool f, int* warp_tot, int* total) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const unsigned long long b = __ballot(f);
-    const int below = __popcll(b & ((1ull << lane) - 1ull));
-    if (lane == 0) warp_tot[wv] = __popcll(b);
-    __syncthreads();
-    int off = 0, tot = 0;
-    for (int i = 0; i < 4; ++i) {
-        if (i < wv) off += warp_tot[i];
-        tot += warp_tot[i];
-    }
-    __syncthreads();
-    *total = tot;
-    return off + below;
-}
-
 // Margin-rank repair of nodes with a side smaller than min_leaf: order the
 // members by (mu, id), mu = |x-c0|^2 - |x-c1|^2 = 2 (h - dot), i.e. by
 // descending dot, and put the first s on the left, s = clamp(n0, min_leaf,
@@ -850,30 +829,34 @@ __global__ __launch_bounds__(256) void k_copyback(int64_t n, const NodeRec* __re
     for (int row = row0 + lane; row < row1; row += kWave) perm[base + row] = perm_tmp[base + row];
 }
 
-// Children of every node of the level: runs of size > leaf_max become the
-// next level's nodes (in parent order, left first), the others leaves; next
-// nodes of several chunks are also listed in `big`.  One block; the order is
-// deterministic.
+// Children of every node of the level: runs of size > small_max become the
+// next level's nodes (in parent order, left first), runs of leaf_max <
+// size <= small_max go to the subtree list (chunk0 = their depth), the
+// others are leaves; next nodes of several chunks are also listed in `big`.
+// One block; the order is deterministic.
 __global__ __launch_bounds__(1024) void k_next_level(
     const NodeRec* __restrict__ cur, int n_cur, const int32_t* __restrict__ n0f, int leaf_max,
-    int depth, NodeRec* __restrict__ next, int32_t* __restrict__ big, LeafRec* __restrict__ leaves,
-    int64_t leaves_cap, int32_t* __restrict__ node_log, int64_t node_log_cap,
-    LevelCounters* __restrict__ ctr, int* __restrict__ overflow) {
-    __shared__ int s_int[1024], s_leaf[1024], s_ch[1024], s_big[1024];
-    __shared__ int s_base_leaf, s_base_log;
+    int small_max, int depth, NodeRec* __restrict__ next, int32_t* __restrict__ big,
+    NodeRec* __restrict__ sub, LeafRec* __restrict__ leaves, int64_t leaves_cap,
+    int32_t* __restrict__ node_log, int64_t node_log_cap, LevelCounters* __restrict__ ctr,
+    int* __restrict__ overflow) {
+    __shared__ int s_int[1024], s_leaf[1024], s_ch[1024], s_big[1024], s_sub[1024];
+    __shared__ int s_base_leaf, s_base_log, s_base_sub;
     const int tid = threadIdx.x;
     const int per = (n_cur + 1023) / 1024;
     const int i0 = min(n_cur, tid * per), i1 = min(n_cur, i0 + per);
-    int ci = 0, cl = 0, cc = 0, cb = 0;
+    int ci = 0, cl = 0, cc = 0, cb = 0, cs = 0;
     for (int i = i0; i < i1; ++i) {
         const NodeRec r = cur[i];
         const int sz[2] = {n0f[i], r.size - n0f[i]};
         for (int s = 0; s < 2; ++s) {
-            if (sz[s] > leaf_max) {
+            if (sz[s] > small_max) {
                 ++ci;
                 const int ch = (sz[s] + kChunkRows - 1) / kChunkRows;
                 cc += ch;
                 cb += ch > 1 ? 1 : 0;
+            } else if (sz[s] > leaf_max) {
+                ++cs;
             } else {
                 ++cl;
             }
@@ -883,28 +866,32 @@ __global__ __launch_bounds__(1024) void k_next_level(
     s_leaf[tid] = cl;
     s_ch[tid] = cc;
     s_big[tid] = cb;
+    s_sub[tid] = cs;
     if (tid == 0) {
         s_base_leaf = ctr->n_leaves;
         s_base_log = ctr->n_log;
+        s_base_sub = ctr->n_sub;
     }
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {  // inclusive Hillis-Steele scans
-        int a = 0, b = 0, c = 0, e = 0;
+        int a = 0, b = 0, c = 0, e = 0, f = 0;
         if (tid >= o) {
             a = s_int[tid - o];
             b = s_leaf[tid - o];
             c = s_ch[tid - o];
             e = s_big[tid - o];
+            f = s_sub[tid - o];
         }
         __syncthreads();
         s_int[tid] += a;
         s_leaf[tid] += b;
         s_ch[tid] += c;
         s_big[tid] += e;
+        s_sub[tid] += f;
         __syncthreads();
     }
     int oi = s_int[tid] - ci, ol = s_base_leaf + s_leaf[tid] - cl, oc = s_ch[tid] - cc,
-        ob = s_big[tid] - cb;
+        ob = s_big[tid] - cb, os = s_base_sub + s_sub[tid] - cs;
     for (int i = i0; i < i1; ++i) {
         const NodeRec r = cur[i];
         const int n0 = n0f[i];
@@ -920,11 +907,13 @@ __global__ __launch_bounds__(1024) void k_next_level(
         const int st[2] = {r.start, r.start + n0};
         const int sz[2] = {n0, r.size - n0};
         for (int s = 0; s < 2; ++s) {
-            if (sz[s] > leaf_max) {
+            if (sz[s] > small_max) {
                 const int ch = (sz[s] + kChunkRows - 1) / kChunkRows;
                 if (ch > 1) big[ob++] = oi;
                 next[oi++] = NodeRec{r.tree, st[s], sz[s], oc};
                 oc += ch;
+            } else if (sz[s] > leaf_max) {
+                sub[os++] = NodeRec{r.tree, st[s], sz[s], depth + 1};
             } else {
                 if (ol < leaves_cap)
                     leaves[ol] = LeafRec{r.tree, st[s], sz[s], 0};
@@ -941,6 +930,7 @@ __global__ __launch_bounds__(1024) void k_next_level(
         ctr->n_big = s_big[1023];
         ctr->n_leaves = s_base_leaf + s_leaf[1023];
         ctr->n_log = s_base_log + n_cur;
+        ctr->n_sub = s_base_sub + s_sub[1023];
     }
 }
 
@@ -1106,6 +1096,16 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     const size_t tn = static_cast<size_t>(T) * n;
     const int slices = (D + kUpdDims - 1) / kUpdDims;
 
+    // Nodes of at most small_max rows can be split to leaves by the subtree
+    // kernel (uint8 rows that fit LDS).  Off by default: on MI355X it does
+    // not yet beat the level passes; KNNG_SUBTREE=1 (rows in 128 KiB of LDS)
+    // or 2 (64 KiB) turn it on.
+    const int sub_mode = env_int("KNNG_SUBTREE", 0);
+    const int row_budget = sub_mode == 2 ? 65536 : 131072;
+    const int small_max = (use_u8 && sub_mode != 0)
+                              ? std::max(subtree_max_rows(D, row_budget), L)
+                              : L;
+    NodeRec* sub = nullptr;
     NodeRec* nodes[2] = {nullptr, nullptr};
     int32_t* big[2] = {nullptr, nullptr};
     int32_t *chunk_node = nullptr, *status = nullptr, *n0f = nullptr, *cnt = nullptr,
@@ -1115,7 +1115,7 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     LevelCounters* ctr = nullptr;
     unsigned long long* dstats = nullptr;
     LevelCounters* hctr = nullptr;
-    unsigned long long hstats[2] = {0, 0};
+    unsigned long long hstats[4] = {0, 0, 0, 0};
     int hoverflow = 0;
     int cur = 0;
     int depth = 0;
@@ -1127,6 +1127,7 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&nodes[1]), sizeof(NodeRec) * nmax, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&big[0]), sizeof(int32_t) * nmax, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&big[1]), sizeof(int32_t) * nmax, s));
+    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&sub), sizeof(NodeRec) * nmax, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&chunk_node), sizeof(int32_t) * cmax, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&status), sizeof(int32_t) * nmax, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&n0f), sizeof(int32_t) * nmax, s));
@@ -1137,7 +1138,7 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&dots), sizeof(double) * tn, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&perm_tmp), sizeof(int32_t) * tn, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&ctr), sizeof(LevelCounters), s));
-    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&dstats), sizeof(unsigned long long) * 2, s));
+    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&dstats), sizeof(unsigned long long) * 4, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&overflow), sizeof(int), s));
     k_zero_small<<<1, 64, 0, s>>>(dstats, overflow);
     KNNG_LAUNCH();
@@ -1149,7 +1150,7 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
         k_iota<<<blocks, 256, 0, s>>>(a.perm, n, T);
         KNNG_LAUNCH();
     }
-    k_roots<<<1, 64, 0, s>>>(T, n, L, nodes[0], big[0], a.leaves, ctr);
+    k_roots<<<1, 64, 0, s>>>(T, n, L, small_max, nodes[0], big[0], sub, a.leaves, ctr);
     KNNG_LAUNCH();
     KNNG_HIP(hipMemcpyAsync(hctr, ctr, sizeof(LevelCounters), hipMemcpyDeviceToHost, s));
     KNNG_HIP(hipStreamSynchronize(s));
@@ -1194,9 +1195,9 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
         KNNG_LAUNCH();
         k_copyback<<<cblocks, 256, 0, s>>>(n, nodes[cur], chunk_node, nc, perm_tmp, a.perm);
         KNNG_LAUNCH();
-        k_next_level<<<1, 1024, 0, s>>>(nodes[cur], na, n0f, L, depth, nodes[cur ^ 1], big[cur ^ 1],
-                                        a.leaves, a.leaves_cap, a.node_log, a.node_log_cap, ctr,
-                                        overflow);
+        k_next_level<<<1, 1024, 0, s>>>(nodes[cur], na, n0f, L, small_max, depth, nodes[cur ^ 1],
+                                        big[cur ^ 1], sub, a.leaves, a.leaves_cap, a.node_log,
+                                        a.node_log_cap, ctr, overflow);
         KNNG_LAUNCH();
         KNNG_HIP(hipMemcpyAsync(hctr, ctr, sizeof(LevelCounters), hipMemcpyDeviceToHost, s));
         KNNG_HIP(hipStreamSynchronize(s));
@@ -1204,12 +1205,27 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
         cur ^= 1;
         ++depth;
     }
+    if (hctr->n_sub > 0) {
+        SubtreeArgs sa{a.X8, n, D, sub, hctr->n_sub, a.perm, L, a.min_leaf, a.max_iter, a.seed,
+                       a.tree0, a.leaves, a.leaves_cap, a.node_log, a.node_log_cap, ctr, dstats,
+                       overflow, row_budget, s};
+        if (subtree_launch(sa) != kOk) {
+            std::snprintf(err, errlen, "subtree kernel launch failed");
+            rc = kHip;
+            goto done;
+        }
+        ++launches;
+        KNNG_HIP(hipMemcpyAsync(hctr, ctr, sizeof(LevelCounters), hipMemcpyDeviceToHost, s));
+    }
     KNNG_HIP(hipMemcpyAsync(hstats, dstats, sizeof(hstats), hipMemcpyDeviceToHost, s));
     KNNG_HIP(hipMemcpyAsync(&hoverflow, overflow, sizeof(int), hipMemcpyDeviceToHost, s));
     KNNG_HIP(hipStreamSynchronize(s));
     if (hoverflow) {
-        std::snprintf(err, errlen, "leaf list overflow (capacity %lld)",
-                      static_cast<long long>(a.leaves_cap));
+        if (hoverflow & 2)
+            std::snprintf(err, errlen, "subtree stack overflow");
+        else
+            std::snprintf(err, errlen, "leaf list overflow (capacity %lld)",
+                          static_cast<long long>(a.leaves_cap));
         rc = kHip;
         goto done;
     }
@@ -1217,14 +1233,36 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     res->n_log = hctr->n_log;
     res->assign_rows = static_cast<int64_t>(hstats[0]);
     res->repairs = static_cast<int64_t>(hstats[1]);
-    res->splits = splits;
-    res->levels = depth + 1;
+    res->splits = splits + static_cast<int64_t>(hstats[2]);
+    res->levels = std::max<int64_t>(depth, static_cast<int64_t>(hstats[3])) + 1;
+    if (a.node_log != nullptr && hctr->n_sub > 0) {
+        // subtree splits are logged in completion order: restore the
+        // documented (depth, start) order
+        const int64_t nl = std::min<int64_t>(hctr->n_log, a.node_log_cap);
+        std::vector<int32_t> h(static_cast<size_t>(nl) * 4);
+        KNNG_HIP(hipMemcpyAsync(h.data(), a.node_log, h.size() * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, s));
+        KNNG_HIP(hipStreamSynchronize(s));
+        std::vector<int64_t> idx(static_cast<size_t>(nl));
+        for (int64_t i = 0; i < nl; ++i) idx[i] = i;
+        std::sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) {
+            const int32_t dx = h[4 * x + 3], dy = h[4 * y + 3];
+            return dx != dy ? dx < dy : h[4 * x] < h[4 * y];
+        });
+        std::vector<int32_t> o(h.size());
+        for (int64_t i = 0; i < nl; ++i)
+            for (int f = 0; f < 4; ++f) o[4 * i + f] = h[4 * idx[i] + f];
+        KNNG_HIP(hipMemcpyAsync(a.node_log, o.data(), o.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, s));
+        KNNG_HIP(hipStreamSynchronize(s));
+    }
 
 done:
     if (nodes[0]) hipFreeAsync(nodes[0], s);
     if (nodes[1]) hipFreeAsync(nodes[1], s);
     if (big[0]) hipFreeAsync(big[0], s);
     if (big[1]) hipFreeAsync(big[1], s);
+    if (sub) hipFreeAsync(sub, s);
     if (chunk_node) hipFreeAsync(chunk_node, s);
     if (status) hipFreeAsync(status, s);
     if (n0f) hipFreeAsync(n0f, s);

@@ -1,0 +1,59 @@
+// Device helpers shared by the level-synchronous partition kernels and the
+// subtree kernel: the keyed starting pair, the order key of a double and a
+// block-wide flag scan.
+#pragma once
+#include "knng_internal.hpp"
+#include "wave.hpp"
+
+namespace knng {
+namespace pdev {
+
+// ------------------------------------------------------------- random pair
+// Keyed starting pair.  SplitMix64 output function (Steele, Lea, Flood,
+// OOPSLA 2014); each key word is absorbed as one SplitMix64 step taken from
+// state (h xor word).  Key: (seed, tree, smallest member id, node size, j).
+constexpr uint64_t kGolden = 0x9e3779b97f4a7c15ull;
+
+__device__ __forceinline__ uint64_t splitmix_out(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t pair_hash(uint64_t seed, uint64_t tree, uint64_t min_id,
+                                              uint64_t size, uint64_t j) {
+    uint64_t h = seed;
+    h = splitmix_out((h ^ tree) + kGolden);
+    h = splitmix_out((h ^ min_id) + kGolden);
+    h = splitmix_out((h ^ size) + kGolden);
+    h = splitmix_out((h ^ j) + kGolden);
+    return h;
+}
+
+// Unsigned key with the order of a double (after turning -0 into +0).
+__device__ __forceinline__ uint64_t ordered_key(double v) {
+    v = v + 0.0;
+    const uint64_t u = static_cast<uint64_t>(__double_as_longlong(v));
+    return (u >> 63) ? ~u : (u | (1ull << 63));
+}
+
+// Block-wide exclusive scan of one flag per thread (NW wavefronts).
+template <int NW = 4>
+__device__ __forceinline__ int block_excl_scan_flag(bool f, int* warp_tot, int* total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const unsigned long long b = __ballot(f);
+    const int below = __popcll(b & ((1ull << lane) - 1ull));
+    if (lane == 0) warp_tot[wv] = __popcll(b);
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int i = 0; i < NW; ++i) {
+        if (i < wv) off += warp_tot[i];
+        tot += warp_tot[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + below;
+}
+
+}  // namespace pdev
+}  // namespace knng

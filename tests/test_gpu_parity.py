@@ -72,6 +72,31 @@ def test_partition_variants(K, orc, n, D, kind, L, ml, max_iter):
     assert _nodes_key(nodes) == _nodes_key(o["nodes"])
 
 
+# Integer data in [0, 255] (uint8 copy): nodes of at most 1024 rows (512 for
+# D > 128) are split to leaves by the subtree kernel, one workgroup per node.
+@pytest.mark.parametrize("n,D,kind,L,ml,max_iter", [
+    (20000, 128, "c2", 100, 21, 10),      # level loop hands over at ~1000 rows
+    (900, 128, "c2", 50, 11, 10),         # the root itself is a subtree
+    (5000, 64, "int", 60, 30, 10),        # min_leaf = L/2: repairs on most splits
+    (6000, 32, "small_int", 40, 5, 3),    # exact ties, three-pass budget
+    (4000, 256, "int", 200, 21, 10),      # 256 dims: subtrees of 512 rows
+    (3000, 48, "small_int", 30, 1, 10),   # D = 48: part of a lane group idle
+])
+def test_subtree_kernel_matches_oracle(K, orc, n, D, kind, L, ml, max_iter, monkeypatch):
+    X = datagen.make("c2", n=n) if kind == "c2" else datagen.random_points(n, D, n + D, kind)
+    log("subtree n=%d D=%d kind=%s L=%d" % (n, D, kind, L))
+    o = orc.tree(X, L, ml, max_iter, 4, 2, with_nodes=True)
+    for sub in ("1", "2", "0"):
+        monkeypatch.setenv("KNNG_SUBTREE", sub)
+        perm, loff, nodes = _gpu_tree(K, to_dev(X), L, ml, 4, 2, max_iter=max_iter)
+        assert np.array_equal(loff, o["leaf_off"])
+        assert np.array_equal(perm, o["perm"])
+        assert _nodes_key(nodes) == _nodes_key(o["nodes"])
+        # documented order of the node log: by depth, then start
+        keys = [(int(d), int(st)) for st, _, _, d in nodes.tolist()]
+        assert keys == sorted(keys)
+
+
 def test_partition_identical_points_closed_form(K):
     X = np.full((300, 6), 3.5, np.float32)
     perm, loff, _ = _gpu_tree(K, to_dev(X), 50, 11, 9, 0)
