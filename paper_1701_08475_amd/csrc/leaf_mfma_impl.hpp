@@ -80,58 +80,25 @@ __device__ __forceinline__ uint32_t fkey(float v) {
     return (u >> 31) ? ~u : (u | 0x80000000u);
 }
 
-// d32 of rows a and b of X: per 32-dimension block the sequential fused sum
-// of squared differences, blocks added in order (the canonical FP32 distance).
-template <bool VEC4>
-__device__ __forceinline__ float d32_rows(const float* __restrict__ xa, const float* __restrict__ xb,
-                                          int D) {
-    float tot = 0.f;
-    for (int d0 = 0; d0 < D; d0 += 32) {
-        const int dn = D - d0 < 32 ? D - d0 : 32;
-        float blk = 0.f;
-        if constexpr (VEC4) {
-            for (int dd = 0; dd < dn; dd += 4) {
-                const float4 p = *reinterpret_cast<const float4*>(xa + d0 + dd);
-                const float4 q = *reinterpret_cast<const float4*>(xb + d0 + dd);
-                float df = p.x - q.x;
-                blk = __fmaf_rn(df, df, blk);
-                df = p.y - q.y;
-                blk = __fmaf_rn(df, df, blk);
-                df = p.z - q.z;
-                blk = __fmaf_rn(df, df, blk);
-                df = p.w - q.w;
-                blk = __fmaf_rn(df, df, blk);
-            }
-        } else {
-            for (int dd = 0; dd < dn; ++dd) {
-                const float df = xa[d0 + dd] - xb[d0 + dd];
-                blk = __fmaf_rn(df, df, blk);
-            }
-        }
-        tot = tot + blk;
-    }
-    return tot;
-}
-
 // The leaf's ids into LDS in ascending order, with their norms and scales:
 // a stable rank sort (the rank of entry j counts smaller ids, and equal ids
 // before j, so it is a permutation of 0..m-1 whatever perm holds).  Position
 // order is then id order, and distance ties fall to the smaller id.  raw
 // holds m ints of scratch; the caller synchronises before reading ids.
-template <int MP>
+template <int MP, int NT = 256>
 __device__ __forceinline__ void load_leaf_sorted(const int32_t* __restrict__ lp, int m,
                                                  int32_t* raw, int32_t* ids, float* snrm,
                                                  float* ssinv, const float* __restrict__ nrm,
                                                  const float* __restrict__ sinv) {
     const int tid = threadIdx.x;
-    for (int j = tid; j < m; j += 256) raw[j] = lp[j];
-    for (int j = m + tid; j < MP; j += 256) {
+    for (int j = tid; j < m; j += NT) raw[j] = lp[j];
+    for (int j = m + tid; j < MP; j += NT) {
         ids[j] = 0;
         snrm[j] = 0.f;
         ssinv[j] = 0.f;
     }
     __syncthreads();
-    for (int j = tid; j < m; j += 256) {
+    for (int j = tid; j < m; j += NT) {
         const int32_t id = raw[j];
         int r = 0;
         for (int i = 0; i < m; ++i) {
@@ -144,36 +111,118 @@ __device__ __forceinline__ void load_leaf_sorted(const int32_t* __restrict__ lp,
     }
 }
 
-// EXACT: the first pass is exact (integer data that the format holds exactly,
-// with every product and partial sum below 2^24), so d~ == d32 and the
-// candidates are the k best directly.  VEC4: D % 4 == 0.
-template <int FMT, int MP, int PR, bool EXACT, bool VEC4>
-__global__ __launch_bounds__(256) void k_leaf_mfma(
+// Orders the LDS operations of one wavefront across its lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Key of rank `rank` (0-based) among the valid keys of a wavefront (R per
+// lane), by radix selection on 8-bit digits with a 256-bin histogram in LDS
+// (hist: 256 words owned by this wavefront).  Returns the key; *below gets
+// the number of valid keys smaller than it.
+template <int R>
+__device__ __forceinline__ uint32_t wave_select_rank(const uint32_t (&key)[R], const bool (&valid)[R],
+                                                     int rank, uint32_t* hist, int* below) {
+    const int lane = threadIdx.x & 63;
+    uint32_t prefix = 0u;
+    int rem = rank;
+#pragma unroll
+    for (int shift = 24; shift >= 0; shift -= 8) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) hist[4 * lane + q] = 0u;
+        wave_lds_sync();
+        const uint32_t hi = shift == 24 ? 0u : (0xffffffffu << (shift + 8));
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (valid[r] && (key[r] & hi) == (prefix & hi)) atomicAdd(&hist[(key[r] >> shift) & 255u], 1u);
+        wave_lds_sync();
+        uint32_t h4[4];
+        int local = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            h4[q] = hist[4 * lane + q];
+            local += static_cast<int>(h4[q]);
+        }
+        int total;
+        const int excl = wave_excl_scan(local, &total);
+        // the lane whose 4 bins hold cumulative rank `rem` picks the digit
+        int digit = 0, nrem = 0;
+        const bool mine = excl <= rem && rem < excl + local;
+        if (mine) {
+            int cum = excl;
+            bool done = false;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int hq = static_cast<int>(h4[q]);
+                if (!done && rem < cum + hq) {
+                    digit = 4 * lane + q;
+                    nrem = rem - cum;
+                    done = true;
+                }
+                cum += hq;
+            }
+        }
+        const unsigned long long bm = __ballot(mine);
+        const int src = static_cast<int>(__builtin_ctzll(bm));
+        digit = __shfl(digit, src, kWave);
+        nrem = __shfl(nrem, src, kWave);
+        prefix |= static_cast<uint32_t>(digit) << shift;
+        rem = nrem;
+        wave_lds_sync();
+    }
+    *below = rank - rem;
+    return prefix;
+}
+
+// Leaves of up to MP points (wave per row; NW wavefronts per workgroup).  Panels of PR rows: the Gram of
+// the panel against the whole leaf on MFMA gives d~ in LDS; one wave per row
+// selects its ce candidates exactly by (d~, position) (radix selection).
+// EXACT (the first pass is exact: integer data that the format holds, with
+// every product and partial sum below 2^24, so d~ == d32): the candidates
+// are the k best and are sorted and written at once.  Otherwise their
+// positions go to a leaf-wide table in LDS, and after the last panel the
+// re-rank streams the leaf's FP32 rows through LDS in 32-dimension chunks:
+// thread t owns row t (rows in rounds of 64 NW), accumulates d32 for up to 32
+// candidates at a time (in-block FMA sum, blocks added in order) and keeps
+// the k smallest (d32, id).  CS bounds the candidates per row.
+template <int FMT, int MP, int PR, int CS, int KL, bool EXACT, int NW>
+__global__ __launch_bounds__(NW * 64) void k_leaf_mfma(
     const float* __restrict__ X, const uint8_t* __restrict__ Xr, int64_t n, int D, int Dp,
     const float* __restrict__ nrm, const float* __restrict__ sinv, int k, int c,
     const int32_t* __restrict__ perm, const LeafRec* __restrict__ leaves,
     int32_t* __restrict__ cand_ids, float* __restrict__ cand_d,
     unsigned long long* __restrict__ pairs) {
     using F = Frag<FMT>;
+    using Pos = typename std::conditional<(MP <= 256), uint8_t, uint16_t>::type;
+    constexpr int NTH = NW * kWave;        // threads
     constexpr int NT = MP / 16;            // column tiles
     constexpr int RTP = PR / 16;           // row tiles per panel
-    constexpr int WPR = 4 / RTP;           // waves per row tile
+    constexpr int WPR = NW / RTP;          // waves per row tile
     constexpr int AT = NT / WPR;           // column tiles per wave
     constexpr int R = MP / kWave;          // keys per lane in the selection
-    constexpr int CMAX = 128;              // candidates per row (upper bound)
-    static_assert(R >= 1 && AT >= 1, "tile shape");
+    constexpr int kRowStride = 36;         // floats per staged 32-dim row chunk (16-byte rows)
+    constexpr int kPanel = PR * (MP + 1);
+    constexpr int kStage = MP * kRowStride;
+    constexpr int kRegion = kPanel > kStage ? kPanel : kStage;
+    constexpr int kSel = EXACT ? NW * 128 : MP * CS;
+    static_assert(R >= 1 && AT >= 1 && NW % RTP == 0 && NT % WPR == 0, "tile shape");
 
-    __shared__ float dist[PR][MP + 1];     // d~ of the panel; a row's slots then hold d32
-    __shared__ int16_t sel[4][CMAX];       // selected positions of the row a wave works on
+    __shared__ __align__(16) float region[kRegion];  // d~ panel, later FP32 row chunks
+    __shared__ Pos csel[kSel];  // EXACT: per wave the selection of its row;
+                                // else per row its candidate positions
     __shared__ int32_t ids[MP];
     __shared__ float snrm[MP], ssinv[MP];
+    __shared__ uint32_t s_hist[NW * 256];  // per-wave radix histograms
+    float(*dist)[MP + 1] = reinterpret_cast<float(*)[MP + 1]>(region);
 
     const LeafRec lf = leaves[blockIdx.x];
     const int m = lf.size;
     const size_t base = static_cast<size_t>(lf.tree) * n + lf.start;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    load_leaf_sorted<MP>(perm + base, m, reinterpret_cast<int32_t*>(&dist[0][0]), ids, snrm, ssinv,
-                         nrm, sinv);
+    load_leaf_sorted<MP, NTH>(perm + base, m, reinterpret_cast<int32_t*>(region), ids, snrm, ssinv,
+                              nrm, sinv);
     if (tid == 0 && pairs != nullptr)
         atomicAdd(pairs, static_cast<unsigned long long>(m) * static_cast<unsigned long long>(m - 1));
     __syncthreads();
@@ -233,10 +282,11 @@ __global__ __launch_bounds__(256) void k_leaf_mfma(
             }
         }
         __syncthreads();
-        // ---- per row (one wave): exact top-ce by (d~, position), re-rank, top k
+        // ---- per row (one wave): exact top-ce by (d~, position)
         const int rows = m - p0 < PR ? m - p0 : PR;
-        for (int rl = wv; rl < rows; rl += 4) {
+        for (int rl = wv; rl < rows; rl += NW) {
             const int row = p0 + rl;
+            Pos* sel = EXACT ? csel + wv * 128 : csel + row * CS;
             uint32_t key[R];
             bool valid[R];
 #pragma unroll
@@ -245,21 +295,14 @@ __global__ __launch_bounds__(256) void k_leaf_mfma(
                 valid[r] = col < m && col != row;
                 key[r] = valid[r] ? fkey(dist[rl][col]) : 0xffffffffu;
             }
-            // radix selection of the key of rank ce-1
+            // the key of rank ce-1, by 8-bit radix selection; rem = how many
+            // keys equal to it are taken, minus one
             uint32_t prefix = 0u;
-            int rem = ce - 1;
-            for (int bit = 31; bit >= 0 && ce > 0; --bit) {
-                const uint32_t hi = bit == 31 ? 0u : (0xffffffffu << (bit + 1));
-                int zeros = 0;
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const bool in = valid[r] && ((key[r] & hi) == (prefix & hi));
-                    zeros += __popcll(__ballot(in && ((key[r] >> bit) & 1u) == 0u));
-                }
-                if (rem >= zeros) {
-                    rem -= zeros;
-                    prefix |= 1u << bit;
-                }
+            int rem = 0;
+            if (ce > 0) {
+                int below;
+                prefix = wave_select_rank<R>(key, valid, ce - 1, s_hist + wv * 256, &below);
+                rem = ce - 1 - below;
             }
             // keys < prefix, and the first rem+1 keys == prefix by position
             int taken = 0, eq_seen = 0;
@@ -272,52 +315,116 @@ __global__ __launch_bounds__(256) void k_leaf_mfma(
                 const bool take = ce > 0 && (lt || (eq && eq_rank <= rem));
                 const unsigned long long bt = __ballot(take);
                 if (take)
-                    sel[wv][taken + __popcll(bt & ((1ull << lane) - 1ull))] =
-                        static_cast<int16_t>(r * kWave + lane);
+                    sel[taken + __popcll(bt & ((1ull << lane) - 1ull))] =
+                        static_cast<Pos>(r * kWave + lane);
                 taken += __popcll(bt);
                 eq_seen += __popcll(beq);
             }
-            // candidate distances: d~ itself when exact, else d32 from the rows
-            float dv[2];
+            if constexpr (EXACT) {
+                // the candidates' d~ are their d32: sort by (d, id) and write
+                uint64_t v[2];
 #pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                const int s = lane + r * kWave;
-                dv[r] = 0.f;
-                if (s < ce) {
-                    const int b = sel[wv][s];
-                    if constexpr (EXACT) {
-                        dv[r] = dist[rl][b];
-                    } else {
-                        dv[r] = d32_rows<VEC4>(X + static_cast<size_t>(ids[row]) * D,
-                                               X + static_cast<size_t>(ids[b]) * D, D);
-                    }
+                for (int r = 0; r < 2; ++r) {
+                    const int s = lane * 2 + r;
+                    v[r] = s < ce ? cand_key(dist[rl][sel[s]], ids[sel[s]]) : kNoKey;
                 }
-            }
-            // the wave's reads of dist[rl] are done (same wave), reuse it
+                wave_bitonic_sort<2>(v);
+                const size_t out = (static_cast<size_t>(lf.tree) * n + ids[row]) * k;
 #pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                const int s = lane + r * kWave;
-                if (s < ce) dist[rl][s] = dv[r];
-            }
-            uint64_t v[2];
-#pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                const int s = lane * 2 + r;
-                v[r] = s < ce ? cand_key(dist[rl][s], ids[sel[wv][s]]) : kNoKey;
-            }
-            wave_bitonic_sort<2>(v);
-            const size_t out = (static_cast<size_t>(lf.tree) * n + ids[row]) * k;
-#pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                const int e = lane * 2 + r;
-                if (e < k) {
-                    const bool ok = v[r] != kNoKey;
-                    cand_ids[out + e] = ok ? key_id(v[r]) : -1;
-                    cand_d[out + e] = ok ? key_dist(v[r]) : __int_as_float(0x7f800000);
+                for (int r = 0; r < 2; ++r) {
+                    const int e = lane * 2 + r;
+                    if (e < k) {
+                        const bool ok = v[r] != kNoKey;
+                        cand_ids[out + e] = ok ? key_id(v[r]) : -1;
+                        cand_d[out + e] = ok ? key_dist(v[r]) : __int_as_float(0x7f800000);
+                    }
                 }
             }
         }
         __syncthreads();
+    }
+    if constexpr (!EXACT) {
+        // ---- re-rank: d32 of every (row, candidate) from LDS-staged chunks
+        for (int r0 = 0; r0 < m; r0 += NTH) {
+            const int row = r0 + tid;
+            const bool own = row < m;
+            uint64_t K[KL];
+#pragma unroll
+            for (int i = 0; i < KL; ++i) K[i] = kNoKey;
+            for (int g0 = 0; g0 < ce; g0 += 32) {
+                float tot[32];
+#pragma unroll
+                for (int i = 0; i < 32; ++i) tot[i] = 0.f;
+                for (int d0 = 0; d0 < D; d0 += 32) {
+                    __syncthreads();  // the previous chunk is no longer read
+                    for (int idx = tid; idx < m * 32; idx += NTH) {
+                        const int j = idx >> 5, dd = idx & 31;
+                        region[j * kRowStride + dd] =
+                            d0 + dd < D ? X[static_cast<size_t>(ids[j]) * D + d0 + dd] : 0.f;
+                    }
+                    __syncthreads();
+                    if (own) {
+                        float xr[32];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) {
+                            const float4 v4 = *reinterpret_cast<const float4*>(
+                                region + row * kRowStride + 4 * q);
+                            xr[4 * q] = v4.x;
+                            xr[4 * q + 1] = v4.y;
+                            xr[4 * q + 2] = v4.z;
+                            xr[4 * q + 3] = v4.w;
+                        }
+                        const int gn = ce - g0 < 32 ? ce - g0 : 32;
+#pragma unroll
+                        for (int i = 0; i < 32; ++i) {
+                            if (i < gn) {
+                                const float* xc = region + csel[row * CS + g0 + i] * kRowStride;
+                                float blk = 0.f;  // padding past D adds exact zeros
+#pragma unroll
+                                for (int q = 0; q < 8; ++q) {
+                                    const float4 v4 = *reinterpret_cast<const float4*>(xc + 4 * q);
+                                    float df = xr[4 * q] - v4.x;
+                                    blk = __fmaf_rn(df, df, blk);
+                                    df = xr[4 * q + 1] - v4.y;
+                                    blk = __fmaf_rn(df, df, blk);
+                                    df = xr[4 * q + 2] - v4.z;
+                                    blk = __fmaf_rn(df, df, blk);
+                                    df = xr[4 * q + 3] - v4.w;
+                                    blk = __fmaf_rn(df, df, blk);
+                                }
+                                tot[i] = tot[i] + blk;
+                            }
+                        }
+                    }
+                }
+                if (own) {
+                    const int gn = ce - g0 < 32 ? ce - g0 : 32;
+#pragma unroll
+                    for (int i = 0; i < 32; ++i) {
+                        if (i < gn) {
+                            uint64_t x = cand_key(tot[i], ids[csel[row * CS + g0 + i]]);
+#pragma unroll
+                            for (int s = 0; s < KL; ++s) {
+                                const bool lt = x < K[s];
+                                const uint64_t lo = lt ? x : K[s];
+                                x = lt ? K[s] : x;
+                                K[s] = lo;
+                            }
+                        }
+                    }
+                }
+            }
+            if (own) {
+                const size_t out = (static_cast<size_t>(lf.tree) * n + ids[row]) * k;
+#pragma unroll
+                for (int e = 0; e < KL; ++e)
+                    if (e < k) {
+                        const bool ok = e < ce && K[e] != kNoKey;
+                        cand_ids[out + e] = ok ? key_id(K[e]) : -1;
+                        cand_d[out + e] = ok ? key_dist(K[e]) : __int_as_float(0x7f800000);
+                    }
+            }
+        }
     }
 }
 
@@ -531,14 +638,18 @@ __global__ __launch_bounds__(256) void k_leaf_small(
     }
 }
 
-template <int FMT, bool EXACT, bool VEC4>
+template <int FMT, bool EXACT>
 int launch_fmt(const LeafArgs& a, const ReducedRows& rr, int* launches, char* err, size_t errlen) {
     const int lm = a.leaf_max;
     // candidates per row: the k best directly when the first pass is exact
     const int c = EXACT ? a.k : (a.rerank < a.k ? a.k : a.rerank);
-    auto go = [&](auto kern) -> int {
+    if (!EXACT && a.k > 64) {
+        std::snprintf(err, errlen, "the re-ranked leaf search keeps at most 64 neighbours (k=%d)", a.k);
+        return kUnsupported;
+    }
+    auto go = [&](auto kern, unsigned threads = 256) -> int {
         if (a.timer) a.timer->begin(kKLeaf, a.stream);
-        kern<<<static_cast<unsigned>(a.n_leaves), 256, 0, a.stream>>>(
+        kern<<<static_cast<unsigned>(a.n_leaves), threads, 0, a.stream>>>(
             a.X, rr.Xr, a.n, a.D, rr.Dp, rr.nrm, rr.sinv, a.k, c, a.perm, a.leaves, a.cand_ids,
             a.cand_d, a.pairs);
         if (a.timer) a.timer->end(kKLeaf, a.stream);
@@ -575,23 +686,48 @@ int launch_fmt(const LeafArgs& a, const ReducedRows& rr, int* launches, char* er
         if (lm <= 112) return small(std::integral_constant<int, 112>{});
         return small(std::integral_constant<int, 128>{});
     }
-    if (lm <= 64) return go(k_leaf_mfma<FMT, 64, 64, EXACT, VEC4>);
-    if (lm <= 128) return go(k_leaf_mfma<FMT, 128, 64, EXACT, VEC4>);
-    if (lm <= 256) return go(k_leaf_mfma<FMT, 256, 64, EXACT, VEC4>);
-    return go(k_leaf_mfma<FMT, 512, 32, EXACT, VEC4>);
+    // wave per row; the re-rank list holds k rounded up to 16 (k <= 64 here);
+    // candidates per row at most CS.  Leaves up to 256 points: 4 waves, 32-row
+    // panels above 128 points (two workgroups per CU); 512: 8 waves.
+    auto big = [&](auto mp_tag, auto pr_tag, auto cs_tag, auto nw_tag) -> int {
+        constexpr int MP = decltype(mp_tag)::value, PR = decltype(pr_tag)::value;
+        constexpr int CS = decltype(cs_tag)::value, NW = decltype(nw_tag)::value;
+        constexpr unsigned TH = NW * 64;
+        if constexpr (EXACT) {
+            return go(k_leaf_mfma<FMT, MP, PR, CS, 16, true, NW>, TH);
+        } else {
+            if (a.k <= 16) return go(k_leaf_mfma<FMT, MP, PR, CS, 16, false, NW>, TH);
+            if (a.k <= 32) return go(k_leaf_mfma<FMT, MP, PR, CS, 32, false, NW>, TH);
+            if (a.k <= 48) return go(k_leaf_mfma<FMT, MP, PR, CS, 48, false, NW>, TH);
+            return go(k_leaf_mfma<FMT, MP, PR, CS, 64, false, NW>, TH);
+        }
+    };
+    using I4 = std::integral_constant<int, 4>;
+    using I8 = std::integral_constant<int, 8>;
+    using I32 = std::integral_constant<int, 32>;
+    using I64 = std::integral_constant<int, 64>;
+    using I128 = std::integral_constant<int, 128>;
+    using I256 = std::integral_constant<int, 256>;
+    if (lm <= 64) return c <= 64 ? big(I64{}, I64{}, I64{}, I4{}) : big(I64{}, I64{}, I128{}, I4{});
+    if (lm <= 128)
+        return c <= 64 ? big(I128{}, I64{}, I64{}, I4{}) : big(I128{}, I64{}, I128{}, I4{});
+    if (lm <= 256)
+        return c <= 64 ? big(I256{}, I32{}, I64{}, I4{}) : big(I256{}, I32{}, I128{}, I4{});
+    if (c > 64) {
+        std::snprintf(err, errlen, "leaves above 256 points take at most 64 candidates per row (asked %d)", c);
+        return kUnsupported;
+    }
+    return big(std::integral_constant<int, 512>{}, I32{}, I64{}, I8{});
 }
 
 // The exact first pass exists for BF16 only (integers 0..255 with D <= 129).
 template <int FMT>
 int launch_fmt_any(const LeafArgs& a, const ReducedRows& rr, int* launches, char* err,
                    size_t errlen) {
-    const bool v4 = a.D % 4 == 0;
     if constexpr (FMT == kBF16) {
-        if (rr.exact) return v4 ? launch_fmt<FMT, true, true>(a, rr, launches, err, errlen)
-                                : launch_fmt<FMT, true, false>(a, rr, launches, err, errlen);
+        if (rr.exact) return launch_fmt<FMT, true>(a, rr, launches, err, errlen);
     }
-    return v4 ? launch_fmt<FMT, false, true>(a, rr, launches, err, errlen)
-              : launch_fmt<FMT, false, false>(a, rr, launches, err, errlen);
+    return launch_fmt<FMT, false>(a, rr, launches, err, errlen);
 }
 
 }  // namespace leafk

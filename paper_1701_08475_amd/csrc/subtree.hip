@@ -5,13 +5,23 @@
 // LDS, and every Lloyd pass, the margin-rank repair and the stable partition
 // of it and of all its descendants run in one workgroup reading LDS: no HBM
 // traffic after the first load and no per-level launches.  Each split takes
-// exactly the steps of the level-synchronous kernels in partition.hip: the
-// keyed starting pair (members in id order, key (seed, tree, smallest id,
-// size, j)), passes with the same lane layout and FP64 dot order, labels
-// dot < h, exact integer side sums, the stop rule (no label changed, an
-// empty side or the pass budget), the repair by (mu, id) rank and the stable
-// partition (label-0 members first, in id order).  Results are therefore the
-// same as those of the level kernels, and the node runs of perm the same.
+// the steps of the level-synchronous kernels in partition.hip: the keyed
+// starting pair (members in id order, key (seed, tree, smallest id, size,
+// j)), labels dot < h with the same FP64 values, exact integer side sums,
+// the stop rule (no label changed, an empty side or the pass budget), the
+// repair by (mu, id) rank and the stable partition (label-0 members first,
+// in id order).  The node runs of perm are therefore the same.
+//
+// Margin on the matrix cores.  Centres of uint8 data lie in [0, 255], so
+// w = c0 - c1 has |w| <= 255 and W = rint(w 2^22) fits 31 bits: four
+// balanced int8 digit planes.  With x' = x - 128 (int8), the int8 MFMA gives
+// sum_e x'_e W_e exactly, and x.W = sum x'W + 128 sum W.  Against the FP64
+// margin of the level kernels, |x.W - 2^22 (x.w)| <= 0.5 sum x <= 127.5 D and
+// the FP64 evaluation adds less than one unit, so |x.W - 2^22 h| > 128 D + 2
+// decides dot < h exactly as the FP64 code does; rows inside that band (and
+// every row of a node that needs the margin-rank repair) are evaluated with
+// the FP64 code itself.  Side sums: the first pass of a node adds every row,
+// later passes only the rows whose label changed.
 //
 // Depth-first with an explicit stack; the smaller child is split next and
 // the larger pushed, so the stack never holds more than log2(S) + 1 nodes.
@@ -20,10 +30,13 @@
 #include "wave.hpp"
 
 #include <cstdio>
+#include <type_traits>
 
 namespace knng {
 namespace {
 using namespace pdev;
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 // Largest subtree (rows) per row width DM when its rows take at most RB
 // bytes of LDS (128 KiB: one workgroup per CU; 64 KiB: two).
@@ -33,11 +46,23 @@ constexpr int sub_rows() {
 }
 constexpr int kStack = 32;
 
-// NW wavefronts per workgroup; U rows per lane group and step (independent
-// FMA chains in flight).
+// NW wavefronts per workgroup.
 constexpr int kSubWaves = 8;
 constexpr int kSubThreads = kSubWaves * kWave;
-constexpr int kSubRows = 4;
+constexpr double kScale = 4194304.0;  // 2^22
+
+__device__ __forceinline__ int dpp_i32_sum16(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xf, 0xf, false);   // xor 1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xf, 0xf, false);   // xor 2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xf, 0xf, false);  // mirror in 8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xf, 0xf, false);  // mirror in 16
+    return v;
+}
+
+// Row r of the LDS row store keeps its 16-byte chunk j at chunk j ^ (r & swz)
+// (swz + 1 divides D / 16), which spreads the chunks that lanes of one
+// instruction read from different rows over the LDS banks.
+__device__ __forceinline__ int chunk_at(int r, int j, int swz) { return j ^ (r & swz); }
 
 template <int DM, int G, int RB>
 __global__ __launch_bounds__(kSubThreads) void k_subtree_u8(
@@ -47,29 +72,39 @@ __global__ __launch_bounds__(kSubThreads) void k_subtree_u8(
     int64_t node_log_cap, LevelCounters* __restrict__ ctr,
     unsigned long long* __restrict__ dstats, int* __restrict__ overflow) {
     constexpr int S = sub_rows<DM, RB>();
-    constexpr int NW = kSubWaves, NT = kSubThreads, U = kSubRows;
-    constexpr int RPW = kWave / G;  // rows per lane-group slot of a wave
+    constexpr int NW = kSubWaves, NT = kSubThreads;
+    constexpr int RPW = kWave / G;     // rows per wave step of the FP64 code
+    constexpr int KB = (DM + 63) / 64; // 64-element blocks of the matrix-core margin
     __shared__ __align__(16) uint8_t s_rows[S * DM];
     __shared__ int32_t s_ids[S];
-    __shared__ uint16_t s_ord[S], s_tmp[S];
+    __shared__ uint16_t s_ord[S], s_tmp[S];  // s_tmp: partition buffer, and the list of
+                                             // rows the FP64 code decides in a pass
     __shared__ uint8_t s_lab[S];
     __shared__ double s_dot[S];
     __shared__ double s_cen[2 * DM];
-    __shared__ uint32_t s_a1[2][DM];  // side-1 sums, by pass parity
-    __shared__ uint32_t s_tot[DM];
+    __shared__ __align__(16) int8_t s_dig[4][KB * 64];  // digit planes of W, zero past D
+    __shared__ int32_t s_acc[2][DM];                    // side-1 change sums, by pass parity
+    __shared__ uint32_t s_a1[DM], s_tot[DM];
     __shared__ uint32_t s_hist[256];
-    __shared__ int s_cnt[2][2];        // (ones, changed), by pass parity
+    __shared__ int s_cnt[2][3];  // (ones, changed, FP64 rows), by pass parity
+    __shared__ unsigned long long s_sw[2];
+    __shared__ int8_t s_dl[NW][16];
     __shared__ int s_stack[kStack][3];
     __shared__ int s_sp, s_node[3], s_pair[2], s_warp[NW], s_rem;
     __shared__ unsigned long long s_kmin[NW], s_kmax[NW], s_prefix;
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int g = lane / G, l = lane % G;
+    const int g = lane / G, l = lane % G;     // FP64 code: lane group, lane in group
+    const int tc = lane & 15, tq = lane >> 4; // matrix-core tile: column / row, k-group
     const NodeRec root = roots[blockIdx.x];
     const int M = root.size;
     const size_t pbase = static_cast<size_t>(root.tree) * n + root.start;
     const uint64_t tg = static_cast<uint64_t>(tree0 + root.tree);
-    const int vpr = D / 16;  // 16-byte vectors per row
+    const int vpr = D / 16;  // 16-byte chunks per row
+    int swz = 1;
+    while (swz < 8 && (vpr % (2 * swz)) == 0) swz *= 2;
+    swz -= 1;
+    const double bnd = 128.0 * D + 2.0;
 
     for (int i = tid; i < M; i += NT) {
         s_ids[i] = perm[pbase + i];
@@ -78,7 +113,7 @@ __global__ __launch_bounds__(kSubThreads) void k_subtree_u8(
     __syncthreads();
     for (int q = tid; q < M * vpr; q += NT) {
         const int r = q / vpr, c = q - r * vpr;
-        reinterpret_cast<uint4*>(s_rows)[q] =
+        reinterpret_cast<uint4*>(s_rows)[r * vpr + chunk_at(r, c, swz)] =
             reinterpret_cast<const uint4*>(X8 + static_cast<size_t>(s_ids[r]) * D)[c];
     }
     if (tid == 0) {
@@ -89,6 +124,22 @@ __global__ __launch_bounds__(kSubThreads) void k_subtree_u8(
     }
     unsigned long long assigned = 0, splits = 0, repairs = 0, maxdep = 0;
     __syncthreads();
+
+    // FP64 margin of local row lr (every lane of a group returns it), with the
+    // lane layout and summation order of the level kernels
+    auto fp64_dot = [&](int lr, const double (&w)[16]) -> double {
+        uint4 raw = make_uint4(0u, 0u, 0u, 0u);
+        if (l * 16 < D)
+            raw = *reinterpret_cast<const uint4*>(s_rows + lr * D + 16 * chunk_at(lr, l, swz));
+        const uint32_t wd[4] = {raw.x, raw.y, raw.z, raw.w};
+        double dot = 0.0;
+#pragma unroll
+        for (int k4 = 0; k4 < 4; ++k4)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                dot = fma(static_cast<double>((wd[k4] >> (8 * b)) & 255u), w[4 * k4 + b], dot);
+        return group_sum_f64<G>(dot);
+    };
 
     while (true) {
         if (tid == 0) {
@@ -118,25 +169,33 @@ __global__ __launch_bounds__(kSubThreads) void k_subtree_u8(
         }
         for (int e = tid; e < DM; e += NT) {
             s_tot[e] = 0u;
-            s_a1[0][e] = 0u;
-            s_a1[1][e] = 0u;
+            s_a1[e] = 0u;
+            s_acc[0][e] = 0;
+            s_acc[1][e] = 0;
         }
-        if (tid < 4) s_cnt[tid >> 1][tid & 1] = 0;
+        if (tid < 6) s_cnt[tid / 3][tid % 3] = 0;
+        if (tid < 2) s_sw[tid] = 0ull;
         __syncthreads();
         {
             const int ra = s_ord[s + s_pair[0]], rb = s_ord[s + s_pair[1]];
             for (int e = tid; e < D; e += NT) {
-                s_cen[e] = static_cast<double>(s_rows[ra * D + e]);
-                s_cen[DM + e] = static_cast<double>(s_rows[rb * D + e]);
+                const int b = e & 15;
+                s_cen[e] = static_cast<double>(s_rows[ra * D + 16 * chunk_at(ra, e >> 4, swz) + b]);
+                s_cen[DM + e] = static_cast<double>(s_rows[rb * D + 16 * chunk_at(rb, e >> 4, swz) + b]);
             }
         }
         __syncthreads();
 
         // ---- Lloyd passes
         int n1 = 0;
-        for (int pass = 0; pass < max_iter; ++pass) {
+        double w[16];
+        double h = 0.0;
+        // one Lloyd pass; FIRST = the node's first pass (adds every row to the
+        // side and total sums); returns the stop decision
+        auto run_pass = [&](auto first_tag, int pass) -> bool {
+            constexpr bool first = decltype(first_tag)::value;
             const int par = pass & 1;
-            double w[16];
+            // FP64 weights and threshold, exactly as the level kernels form them
             double q0 = 0.0, q1 = 0.0;
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
@@ -149,101 +208,204 @@ __global__ __launch_bounds__(kSubThreads) void k_subtree_u8(
             }
             q0 = group_sum_f64<G>(q0);
             q1 = group_sum_f64<G>(q1);
-            const double h = 0.5 * (q0 - q1);
-            uint32_t a1[16], tot[16];
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                a1[v] = 0u;
-                tot[v] = 0u;
+            h = 0.5 * (q0 - q1);
+            // digit planes of W = rint(w 2^22) and sum W
+            for (int e = tid; e < KB * 64; e += NT) {
+                int d0 = 0, d1 = 0, d2 = 0, d3 = 0;
+                if (e < D) {
+                    int wv_ = static_cast<int>(rint((s_cen[e] - s_cen[DM + e]) * kScale));
+                    atomicAdd(&s_sw[par], static_cast<unsigned long long>(static_cast<long long>(wv_)));
+                    d0 = ((wv_ + 128) & 255) - 128;
+                    wv_ = (wv_ - d0) / 256;
+                    d1 = ((wv_ + 128) & 255) - 128;
+                    wv_ = (wv_ - d1) / 256;
+                    d2 = ((wv_ + 128) & 255) - 128;
+                    d3 = (wv_ - d2) / 256;
+                }
+                s_dig[0][e] = static_cast<int8_t>(d0);
+                s_dig[1][e] = static_cast<int8_t>(d1);
+                s_dig[2][e] = static_cast<int8_t>(d2);
+                s_dig[3][e] = static_cast<int8_t>(d3);
             }
+            __syncthreads();
+            i32x4 bop[KB];
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) {
+                bop[kb] = i32x4{0, 0, 0, 0};
+                if (tc < 4) bop[kb] = *reinterpret_cast<const i32x4*>(&s_dig[tc][kb * 64 + 16 * tq]);
+            }
+            const double xw0 = 128.0 * static_cast<double>(static_cast<long long>(s_sw[par]));
+            const double hs = h * kScale;
+            const double colscale = tc < 4 ? static_cast<double>(1ll << (8 * tc)) : 0.0;
+
+            int32_t acc1[KB][16];
+            uint32_t tot1[first ? KB : 1][16];
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+                for (int t = 0; t < 16; ++t) {
+                    acc1[kb][t] = 0;
+                    if constexpr (first) tot1[kb][t] = 0u;
+                }
+            bool wave_delta = false;
             int my1 = 0, mych = 0;
-            for (int p0 = wv * U * RPW; p0 < m; p0 += NW * U * RPW) {  // uniform per wave
-                uint32_t xv[U][16];
-                bool valid[U];
-                int pp[U];
+            for (int p0 = 16 * wv; p0 < m; p0 += 16 * NW) {  // uniform per wave
+                const int pr = p0 + tc;
+                const bool valid = pr < m;
+                const int lr = s_ord[s + (valid ? pr : m - 1)];
+                uint4 raw[KB];
+                i32x4 acc = i32x4{0, 0, 0, 0};
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    pp[u] = p0 + u * RPW + g;
-                    valid[u] = pp[u] < m;
-                    const int lr = valid[u] ? s_ord[s + pp[u]] : 0;
-                    uint4 raw = make_uint4(0u, 0u, 0u, 0u);
-                    if (l * 16 < D) raw = *reinterpret_cast<const uint4*>(s_rows + lr * D + l * 16);
-                    const uint32_t wd[4] = {raw.x, raw.y, raw.z, raw.w};
-#pragma unroll
-                    for (int k4 = 0; k4 < 4; ++k4)
-#pragma unroll
-                        for (int b = 0; b < 4; ++b) xv[u][4 * k4 + b] = (wd[k4] >> (8 * b)) & 255u;
+                for (int kb = 0; kb < KB; ++kb) {
+                    const int jj = kb * 4 + tq;
+                    raw[kb] = make_uint4(0u, 0u, 0u, 0u);
+                    if (jj < vpr)
+                        raw[kb] = *reinterpret_cast<const uint4*>(s_rows + lr * D +
+                                                                  16 * chunk_at(lr, jj, swz));
+                    const i32x4 a = i32x4{static_cast<int>(raw[kb].x ^ 0x80808080u),
+                                          static_cast<int>(raw[kb].y ^ 0x80808080u),
+                                          static_cast<int>(raw[kb].z ^ 0x80808080u),
+                                          static_cast<int>(raw[kb].w ^ 0x80808080u)};
+                    acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, bop[kb], acc, 0, 0, 0);
                 }
-                double dot[U];
+                // lane (tq, tc): rows 4 tq + i, column (digit plane) tc
+                double v[4];
 #pragma unroll
-                for (int u = 0; u < U; ++u) dot[u] = 0.0;
-#pragma unroll
-                for (int v = 0; v < 16; ++v)
-#pragma unroll
-                    for (int u = 0; u < U; ++u)
-                        dot[u] = fma(static_cast<double>(xv[u][v]), w[v], dot[u]);
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const double dt = group_sum_f64<G>(dot[u]);
-                    const bool lab = dt < h;
-                    if (valid[u] && l == 0) {
-                        const int old = s_lab[s + pp[u]];
-                        mych += (pass > 0 && old != (lab ? 1 : 0)) ? 1 : 0;
-                        s_lab[s + pp[u]] = lab ? 1 : 0;
-                        s_dot[s + pp[u]] = dt;
-                        my1 += lab ? 1 : 0;
+                for (int i = 0; i < 4; ++i) {
+                    v[i] = static_cast<double>(acc[i]) * colscale;
+                    v[i] += dpp_f64<0xB1>(v[i]);
+                    v[i] += dpp_f64<0x4E>(v[i]);
+                }
+                // lane (tq, c < 4) decides row 4 tq + c
+                int dl = 0;
+                if (tc < 4) {
+                    const double xw = (tc == 0 ? v[0] : tc == 1 ? v[1] : tc == 2 ? v[2] : v[3]) + xw0;
+                    const double mg = xw - hs;
+                    const int pi = p0 + 4 * tq + tc;
+                    if (pi < m) {
+                        if (mg < -bnd || mg > bnd) {
+                            const int lab = mg < -bnd ? 1 : 0;
+                            const int old = s_lab[s + pi];
+                            mych += (!first && old != lab) ? 1 : 0;
+                            s_lab[s + pi] = static_cast<uint8_t>(lab);
+                            my1 += lab;
+                            dl = first ? lab : lab - old;
+                        } else {
+                            s_tmp[atomicAdd(&s_cnt[par][2], 1)] = static_cast<uint16_t>(pi);
+                        }
                     }
-                    const uint32_t one = (valid[u] && lab) ? 1u : 0u;
-                    const uint32_t in = valid[u] ? 1u : 0u;
+                    s_dl[wv][4 * tq + tc] = static_cast<int8_t>(dl);
+                }
+                const bool any = __ballot(dl != 0) != 0ull;
+                if (first || any) {
+                    wave_delta = wave_delta || any;
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    const int d = valid ? static_cast<int>(s_dl[wv][tc]) : 0;
+                    const uint32_t in = valid ? 1u : 0u;
 #pragma unroll
-                    for (int v = 0; v < 16; ++v) {
-                        a1[v] = __umul24(xv[u][v], one) + a1[v];
-                        if (pass == 0) tot[v] = __umul24(xv[u][v], in) + tot[v];
+                    for (int kb = 0; kb < KB; ++kb) {
+                        const uint32_t wd[4] = {raw[kb].x, raw[kb].y, raw[kb].z, raw[kb].w};
+#pragma unroll
+                        for (int k4 = 0; k4 < 4; ++k4)
+#pragma unroll
+                            for (int b = 0; b < 4; ++b) {
+                                const int x = static_cast<int>((wd[k4] >> (8 * b)) & 255u);
+                                acc1[kb][4 * k4 + b] = __mul24(d, x) + acc1[kb][4 * k4 + b];
+                                if constexpr (first) tot1[kb][4 * k4 + b] += in * static_cast<uint32_t>(x);
+                            }
                     }
                 }
             }
+            // the wave's change sums: lanes of one 16-lane row hold the same elements
+            if (first || wave_delta) {
 #pragma unroll
-            for (int o = G; o < kWave; o <<= 1)
+                for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
-                for (int v = 0; v < 16; ++v) {
-                    a1[v] += __shfl_xor(a1[v], o, kWave);
-                    if (pass == 0) tot[v] += __shfl_xor(tot[v], o, kWave);
-                }
+                    for (int t = 0; t < 16; ++t) {
+                        const int e = kb * 64 + 16 * tq + t;
+                        const int sa = dpp_i32_sum16(acc1[kb][t]);
+                        int st = 0;
+                        if constexpr (first) st = dpp_i32_sum16(static_cast<int>(tot1[kb][t]));
+                        if (tc == 0 && e < D) {
+                            if (sa != 0) atomicAdd(&s_acc[par][e], sa);
+                            if constexpr (first) atomicAdd(&s_tot[e], static_cast<uint32_t>(st));
+                        }
+                    }
+            }
             my1 = wave_sum_i32(my1);
             mych = wave_sum_i32(mych);
-            if (g == 0) {
-#pragma unroll
-                for (int v = 0; v < 16; ++v) {
-                    const int e = l * 16 + v;
-                    if (e < D) {
-                        atomicAdd(&s_a1[par][e], a1[v]);
-                        if (pass == 0) atomicAdd(&s_tot[e], tot[v]);
-                    }
-                }
-            }
             if (lane == 0) {
                 atomicAdd(&s_cnt[par][0], my1);
                 atomicAdd(&s_cnt[par][1], mych);
             }
-            assigned += static_cast<unsigned long long>(m);
             __syncthreads();
+            // rows inside the error band: the FP64 code decides them
+            const int nfb = s_cnt[par][2];
+            if (nfb > 0) {
+                int f1 = 0, fch = 0;
+                for (int f0 = wv * RPW; f0 < nfb; f0 += NW * RPW) {  // uniform per wave
+                    const int f = f0 + g;
+                    const bool valid = f < nfb;
+                    const int pi = valid ? s_tmp[f] : 0;
+                    const int lr = s_ord[s + pi];
+                    const double dot = fp64_dot(lr, w);
+                    const int lab = dot < h ? 1 : 0;
+                    const int old = valid ? static_cast<int>(s_lab[s + pi]) : 0;
+                    const int dl = valid ? (first ? lab : lab - old) : 0;
+                    if (valid && l == 0) {
+                        fch += (!first && old != lab) ? 1 : 0;
+                        s_lab[s + pi] = static_cast<uint8_t>(lab);
+                        f1 += lab;
+                    }
+                    if (dl != 0 && l * 16 < D) {
+                        const uint4 raw = *reinterpret_cast<const uint4*>(
+                            s_rows + lr * D + 16 * chunk_at(lr, l, swz));
+                        const uint32_t wd[4] = {raw.x, raw.y, raw.z, raw.w};
+#pragma unroll
+                        for (int k4 = 0; k4 < 4; ++k4)
+#pragma unroll
+                            for (int b = 0; b < 4; ++b)
+                                atomicAdd(&s_acc[par][l * 16 + 4 * k4 + b],
+                                          dl * static_cast<int>((wd[k4] >> (8 * b)) & 255u));
+                    }
+                }
+                f1 = wave_sum_i32(f1);
+                fch = wave_sum_i32(fch);
+                if (lane == 0) {
+                    atomicAdd(&s_cnt[par][0], f1);
+                    atomicAdd(&s_cnt[par][1], fch);
+                }
+                __syncthreads();
+            }
+            assigned += static_cast<unsigned long long>(m);
             n1 = s_cnt[par][0];
             const int ch = s_cnt[par][1];
             const int n0 = m - n1;
             const bool stop =
                 n1 == 0 || n0 == 0 || (pass >= 1 && ch == 0) || pass + 1 >= max_iter;
-            for (int e = tid; e < DM; e += NT) s_a1[par ^ 1][e] = 0u;  // next pass's sums
-            if (tid < 2) s_cnt[par ^ 1][tid] = 0;
+            // next pass's accumulators start at zero
+            for (int e = tid; e < DM; e += NT) s_acc[par ^ 1][e] = 0;
+            if (tid < 3) s_cnt[par ^ 1][tid] = 0;
+            if (tid == 0) s_sw[par ^ 1] = 0ull;
             if (!stop) {
                 const double dn0 = static_cast<double>(n0), dn1 = static_cast<double>(n1);
                 for (int e = tid; e < D; e += NT) {
+                    const uint32_t a1 = s_a1[e] + static_cast<uint32_t>(s_acc[par][e]);
+                    s_a1[e] = a1;
                     const double t = static_cast<double>(s_tot[e]);
-                    const double s1 = static_cast<double>(s_a1[par][e]);
+                    const double s1 = static_cast<double>(a1);
                     s_cen[e] = (t - s1) / dn0;
                     s_cen[DM + e] = s1 / dn1;
                 }
             }
             __syncthreads();
+            return stop;
+        };
+        for (int pass = 0; pass < max_iter; ++pass) {
+            const bool stop = pass == 0 ? run_pass(std::true_type{}, pass)
+                                        : run_pass(std::false_type{}, pass);
             if (stop) break;
         }
         int n0 = m - n1;
@@ -251,6 +413,14 @@ __global__ __launch_bounds__(kSubThreads) void k_subtree_u8(
         // ---- margin-rank repair: first sel members by (mu, id) go left,
         // mu ascending = dot descending = key of -dot ascending
         if (n0 < min_leaf || n1 < min_leaf) {
+            // FP64 margins of the final pass (its weights are still in w, h)
+            for (int p0 = wv * RPW; p0 < m; p0 += NW * RPW) {  // uniform per wave
+                const int p = p0 + g;
+                const bool valid = p < m;
+                const double dot = fp64_dot(s_ord[s + (valid ? p : 0)], w);
+                if (valid && l == 0) s_dot[s + p] = dot;
+            }
+            __syncthreads();
             unsigned long long kmin = ~0ull, kmax = 0ull;
             for (int p = tid; p < m; p += NT) {
                 const unsigned long long key = ordered_key(-s_dot[s + p]);
@@ -408,7 +578,6 @@ int launch_rb(const SubtreeArgs& a) {
         return launch_sub<64, 4, RB>(a);
     }
     if (a.D <= 128) return launch_sub<128, 8, RB>(a);
-    if (a.D <= 256) return launch_sub<256, 16, RB>(a);
     return kUnsupported;
 }
 
@@ -417,7 +586,6 @@ int max_rows_rb(int D) {
     if (D % 16 != 0 || D <= 0) return 0;
     if (D <= 64) return sub_rows<64, RB>();
     if (D <= 128) return sub_rows<128, RB>();
-    if (D <= 256) return sub_rows<256, RB>();
     return 0;
 }
 

@@ -79,7 +79,7 @@ def test_partition_variants(K, orc, n, D, kind, L, ml, max_iter):
     (900, 128, "c2", 50, 11, 10),         # the root itself is a subtree
     (5000, 64, "int", 60, 30, 10),        # min_leaf = L/2: repairs on most splits
     (6000, 32, "small_int", 40, 5, 3),    # exact ties, three-pass budget
-    (4000, 256, "int", 200, 21, 10),      # 256 dims: subtrees of 512 rows
+    (4000, 112, "int", 100, 21, 10),      # 7 chunks per row: no LDS swizzle
     (3000, 48, "small_int", 30, 1, 10),   # D = 48: part of a lane group idle
 ])
 def test_subtree_kernel_matches_oracle(K, orc, n, D, kind, L, ml, max_iter, monkeypatch):
