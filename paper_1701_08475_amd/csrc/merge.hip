@@ -1,11 +1,12 @@
 // Union of the rounds' candidate lists into G (Alg. 1: the rows of G are
 // refined round after round; a pair already compared is not counted twice).
 //
-// One wavefront per row: the row's candidates from every tree are sorted by
-// (d32, id) with a bitonic network, adjacent equal keys are dropped (the same
-// id always carries the same d32 bits, so duplicates are adjacent), and the
+// One wavefront per row: the row's candidates from every tree are ordered by
+// (d32, id) with a bitonic network (a merge of the trees' sorted lists when
+// k <= 32, else a full sort), adjacent equal keys are dropped (the same id
+// always carries the same d32 bits, so duplicates are adjacent), and the
 // first k survivors are written.  When the candidates of all trees do not fit
-// one sort, trees are merged in groups into the output row.
+// one network, trees are merged in groups into the output row.
 #include "knng_internal.hpp"
 #include "wave.hpp"
 
@@ -74,8 +75,80 @@ __global__ __launch_bounds__(256) void k_merge(int64_t n, int k, int t0, int t1,
     }
 }
 
+// k <= 32: every input list (the previous output row, then one list per
+// tree) is already sorted by (d32, id), so each takes a run of 32 slots,
+// loaded ascending (even runs) or reversed (odd runs), and the bitonic
+// network starts at runs of 64: a merge rather than a sort.
+template <int R>
+__global__ __launch_bounds__(256) void k_merge_runs(int64_t n, int k, int t0, int t1,
+                                                    const int32_t* __restrict__ cid,
+                                                    const float* __restrict__ cd,
+                                                    int32_t* __restrict__ oid,
+                                                    float* __restrict__ od, int with_prev) {
+    const int64_t row = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (row >= n) return;
+    const int lane = threadIdx.x & 63;
+    const int lists = (with_prev ? 1 : 0) + (t1 - t0);
+    uint64_t v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = lane * R + r;
+        const int b = e >> 5, q = e & 31;
+        const int idx = (b & 1) ? 31 - q : q;  // odd runs reversed
+        v[r] = kNoKey;
+        if (b < lists && idx < k) {
+            int32_t id;
+            float d;
+            if (with_prev && b == 0) {
+                id = oid[row * k + idx];
+                d = od[row * k + idx];
+            } else {
+                const size_t src =
+                    (static_cast<size_t>(t0 + b - (with_prev ? 1 : 0)) * n + row) * k + idx;
+                id = cid[src];
+                d = cd[src];
+            }
+            if (id >= 0) v[r] = cand_key(d, id);
+        }
+    }
+    wave_bitonic_sort<R, 64>(v);
+    const uint64_t last_of_prev_lane = shfl_u64(v[R - 1], lane > 0 ? lane - 1 : 0);
+    bool keep[R];
+    int cnt = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint64_t before = r > 0 ? v[r - 1] : (lane > 0 ? last_of_prev_lane : kNoKey);
+        keep[r] = v[r] != kNoKey && v[r] != before;
+        cnt += keep[r] ? 1 : 0;
+    }
+    int kept;
+    int pos = wave_excl_scan(cnt, &kept);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (keep[r]) {
+            if (pos < k) {
+                oid[row * k + pos] = key_id(v[r]);
+                od[row * k + pos] = key_dist(v[r]);
+            }
+            ++pos;
+        }
+    }
+    for (int p = kept + lane; p < k; p += kWave) {
+        oid[row * k + p] = -1;
+        od[row * k + p] = __int_as_float(0x7f800000);
+    }
+}
+
 using MergeFn = void (*)(int64_t, int, int, int, const int32_t*, const float*, int32_t*, float*,
                          int);
+
+MergeFn pick_runs(int lists) {
+    if (lists <= 2) return k_merge_runs<1>;
+    if (lists <= 4) return k_merge_runs<2>;
+    if (lists <= 8) return k_merge_runs<4>;
+    if (lists <= 16) return k_merge_runs<8>;
+    return k_merge_runs<16>;
+}
 
 MergeFn pick(int slots) {
     if (slots <= 64) return k_merge<1>;
@@ -93,18 +166,21 @@ int merge_run(const MergeArgs& a, int* launches, char* err, size_t errlen) {
     constexpr int kMaxSlots = 1024;
     int t = 0;
     bool prev = false;
+    const bool runs = k <= 32;  // lists fit runs of 32 slots
+    const int unit = runs ? 32 : k;
     while (t < a.n_trees) {
-        const int room = kMaxSlots - (prev ? k : 0);
-        int g = room / k;
+        const int room = kMaxSlots - (prev ? unit : 0);
+        int g = room / unit;
         if (g < 1) g = 1;
         const int t1 = t + g < a.n_trees ? t + g : a.n_trees;
-        const int slots = (prev ? k : 0) + (t1 - t) * k;
+        const int slots = (prev ? unit : 0) + (t1 - t) * unit;
         if (slots > kMaxSlots) {
             std::snprintf(err, errlen, "k=%d too large for the merge", k);
             return kUnsupported;
         }
+        const MergeFn f = runs ? pick_runs((prev ? 1 : 0) + (t1 - t)) : pick(slots);
         if (a.timer) a.timer->begin(kKMerge, a.stream);
-        pick(slots)<<<static_cast<unsigned>(blocks), 256, 0, a.stream>>>(
+        f<<<static_cast<unsigned>(blocks), 256, 0, a.stream>>>(
             a.n, k, t, t1, a.cand_ids, a.cand_d, a.ids_out, a.dists_out, prev ? 1 : 0);
         if (a.timer) a.timer->end(kKMerge, a.stream);
         ++*launches;

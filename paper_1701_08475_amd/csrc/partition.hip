@@ -78,8 +78,9 @@ __global__ void k_zero_small(unsigned long long* stats, int* flag) {
     if (threadIdx.x == 0) *flag = 0;
 }
 
-// chunk -> node map of a level.
-__global__ void k_chunk_map(const NodeRec* nodes, int32_t* chunk_node) {
+// chunk -> node map of a level; also empties the level's repair list.
+__global__ void k_chunk_map(const NodeRec* nodes, int32_t* chunk_node, int32_t* rep) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) rep[0] = 0;
     const NodeRec r = nodes[blockIdx.x];
     const int nch = chunks_of(r.size);
     for (int c = threadIdx.x; c < nch; c += blockDim.x) chunk_node[r.chunk0 + c] = blockIdx.x;
@@ -158,7 +159,8 @@ __global__ __launch_bounds__(256) void k_assign(
     const NodeRec* __restrict__ nodes, const int32_t* __restrict__ chunk_node, int nc,
     double* __restrict__ C, int32_t* __restrict__ status, int32_t* __restrict__ n0f,
     uint8_t* __restrict__ labels, double* __restrict__ dots, double* __restrict__ P,
-    int32_t* __restrict__ cnt, int pass, int max_iter, unsigned long long* __restrict__ assigned) {
+    int32_t* __restrict__ cnt, int pass, int max_iter, unsigned long long* __restrict__ assigned,
+    int32_t* __restrict__ rep, int min_leaf) {
     using RV = RowVec<TX, VEC>;
     using Acc = typename RV::Acc;
     constexpr int RPW = kWave / G;  // rows per wave step
@@ -309,6 +311,7 @@ __global__ __launch_bounds__(256) void k_assign(
             if (lane == 0) {
                 status[node] = 1;
                 n0f[node] = n0;
+                if (n0 < min_leaf || n1 < min_leaf) rep[1 + atomicAdd(rep, 1)] = node;
             }
             return;
         }
@@ -363,7 +366,8 @@ __global__ __launch_bounds__(256) void k_assign_u8(
     const NodeRec* __restrict__ nodes, const int32_t* __restrict__ chunk_node, int nc,
     double* __restrict__ C, int32_t* __restrict__ status, int32_t* __restrict__ n0f,
     uint8_t* __restrict__ labels, double* __restrict__ dots, double* __restrict__ P,
-    int32_t* __restrict__ cnt, int pass, int max_iter, unsigned long long* __restrict__ assigned) {
+    int32_t* __restrict__ cnt, int pass, int max_iter, unsigned long long* __restrict__ assigned,
+    int32_t* __restrict__ rep, int min_leaf) {
     using V = typename std::conditional<EPL == 16, uint4, uint2>::type;
     constexpr int kWords = EPL / 4;
     constexpr int RPW = kWave / G;  // rows per wave step
@@ -473,7 +477,6 @@ __global__ __launch_bounds__(256) void k_assign_u8(
             const bool lab = dot < h;
             if (valid && l == 0) {
                 labels[base + i] = lab ? 1 : 0;
-                dots[base + i] = dot;
                 changed += (!FIRST && old != (lab ? 1 : 0)) ? 1 : 0;
                 n1 += lab ? 1 : 0;
             }
@@ -538,6 +541,7 @@ __global__ __launch_bounds__(256) void k_assign_u8(
             if (lane == 0) {
                 status[node] = 1;
                 n0f[node] = n0;
+                if (n0 < min_leaf || n1 < min_leaf) rep[1 + atomicAdd(rep, 1)] = node;
             }
             return;
         }
@@ -595,7 +599,8 @@ __global__ __launch_bounds__(256) void k_update_big(const NodeRec* __restrict__ 
                                                     double* __restrict__ C,
                                                     int32_t* __restrict__ status,
                                                     int32_t* __restrict__ n0f, int pass,
-                                                    int max_iter, int totals) {
+                                                    int max_iter, int totals,
+                                                    int32_t* __restrict__ rep, int min_leaf) {
     const int slices = (D + kUpdDims - 1) / kUpdDims;
     const int node = big[blockIdx.x / slices];
     const int slice = blockIdx.x % slices;
@@ -627,6 +632,7 @@ __global__ __launch_bounds__(256) void k_update_big(const NodeRec* __restrict__ 
         if (slice == 0 && tid == 0) {
             status[node] = 1;
             n0f[node] = n0;
+            if (n0 < min_leaf || n1 < min_leaf) rep[1 + atomicAdd(rep, 1)] = node;
         }
         return;
     }
@@ -677,24 +683,82 @@ __global__ __launch_bounds__(256) void k_update_big(const NodeRec* __restrict__ 
 // m - min_leaf), or floor(m/2) when every margin is equal.  Rank s is found
 // exactly by radix selection on the 64-bit key of -dot; equal keys go by
 // position (= id order).  Per-chunk ones counts are rewritten.
-__global__ __launch_bounds__(256) void k_repair(const NodeRec* __restrict__ nodes, int64_t n,
-                                                const double* __restrict__ dots,
+// Nodes whose last pass left a side below min_leaf are listed in rep
+// (rep[0] = count) by the pass that stopped them; blocks walk the list.
+// U8G > 0: uint8 rows, whose assignment pass keeps no margins; the block
+// first recomputes the final pass's FP64 margins of the node into dots, with
+// the lane layout (U8G lanes per row, U8NF vectors of 16 elements per lane)
+// and summation order of k_assign_u8, so they are the same numbers.
+template <int U8G, int U8NF>
+__global__ __launch_bounds__(256) void k_repair(const NodeRec* __restrict__ nodes,
+                                                const int32_t* __restrict__ rep,
+                                                int64_t n, const uint8_t* __restrict__ X8, int D,
+                                                const int32_t* __restrict__ perm,
+                                                const double* __restrict__ C,
+                                                double* __restrict__ dots,
                                                 uint8_t* __restrict__ labels,
                                                 int32_t* __restrict__ n0f, int min_leaf,
                                                 int32_t* __restrict__ cnt,
                                                 unsigned long long* __restrict__ repairs) {
-    const int node = blockIdx.x;
-    const NodeRec r = nodes[node];
-    const int m = r.size;
-    const int n0 = n0f[node];
-    if (n0 >= min_leaf && m - n0 >= min_leaf) return;
-    const size_t base = static_cast<size_t>(r.tree) * n + r.start;
     __shared__ unsigned int hist[256];
     __shared__ unsigned long long s_min[256], s_max[256];
     __shared__ unsigned long long s_prefix;
     __shared__ int s_rem;
     __shared__ int warp_tot[4];
     const int tid = threadIdx.x;
+    const int nrep = rep[0];
+    for (int ri = blockIdx.x; ri < nrep; ri += gridDim.x) {
+    const int node = rep[1 + ri];
+    const NodeRec r = nodes[node];
+    const int m = r.size;
+    const int n0 = n0f[node];
+    if (n0 >= min_leaf && m - n0 >= min_leaf) continue;
+    const size_t base = static_cast<size_t>(r.tree) * n + r.start;
+    if constexpr (U8G > 0) {
+        constexpr int G = U8G, NF = U8NF, RPW = kWave / G;
+        const int lane = tid & 63, wv = tid >> 6, g = lane / G, l = lane % G;
+        const double* cn = C + static_cast<size_t>(node) * 2 * D;
+        double w[NF][16];
+#pragma unroll
+        for (int j = 0; j < NF; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int e = (l + G * j) * 16 + v;
+                w[j][v] = (e < D ? cn[e] : 0.0) - (e < D ? cn[D + e] : 0.0);
+            }
+        constexpr int U = 4;  // rows per lane group in flight
+        for (int p0 = wv * RPW * U; p0 < m; p0 += 4 * RPW * U) {  // uniform per wave
+            uint4 q[U][NF];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int p = p0 + u * RPW + g;
+                const uint8_t* xr = X8 + static_cast<size_t>(p < m ? perm[base + p] : 0) * D;
+#pragma unroll
+                for (int j = 0; j < NF; ++j) {
+                    const int e0 = (l + G * j) * 16;
+                    q[u][j] = e0 < D ? *reinterpret_cast<const uint4*>(xr + e0) : make_uint4(0u, 0u, 0u, 0u);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int p = p0 + u * RPW + g;
+                double dot = 0.0;
+#pragma unroll
+                for (int j = 0; j < NF; ++j) {
+                    const uint32_t wd[4] = {q[u][j].x, q[u][j].y, q[u][j].z, q[u][j].w};
+#pragma unroll
+                    for (int k4 = 0; k4 < 4; ++k4)
+#pragma unroll
+                        for (int b = 0; b < 4; ++b)
+                            dot = fma(static_cast<double>((wd[k4] >> (8 * b)) & 255u), w[j][4 * k4 + b],
+                                      dot);
+                }
+                dot = group_sum_f64<G>(dot);
+                if (p < m && l == 0) dots[base + p] = dot;
+            }
+        }
+        __syncthreads();
+    }
 
     unsigned long long kmin = ~0ull, kmax = 0ull;
     for (int p = tid; p < m; p += 256) {
@@ -775,6 +839,8 @@ __global__ __launch_bounds__(256) void k_repair(const NodeRec* __restrict__ node
     if (tid == 0) {
         n0f[node] = s;
         atomicAdd(repairs, 1ull);
+    }
+    __syncthreads();  // shared state is reused by the next node
     }
 }
 
@@ -938,7 +1004,7 @@ __global__ __launch_bounds__(1024) void k_next_level(
 template <typename TX>
 using AssignFn = void (*)(const TX*, int64_t, int, const int32_t*, const NodeRec*, const int32_t*,
                           int, double*, int32_t*, int32_t*, uint8_t*, double*, double*, int32_t*,
-                          int, int, unsigned long long*);
+                          int, int, unsigned long long*, int32_t*, int);
 
 // Rows per lane group and step; more rows keep more loads in flight.
 template <typename TX, int VEC, int G, int NF>
@@ -987,52 +1053,52 @@ AssignFn<float> pick_assign_f32(int D, int epl, int u) {
     return nullptr;
 }
 
-// uint8 rows (D % 16 == 0): EPL (8 or 16) elements per lane; f[0] for a
-// level's first pass, f[1] for the later ones.
-template <int EPL, int G, int NF, int U>
-void pick_u8_depth(int pd, AssignFn<uint8_t>* f) {
+using RepairFn = void (*)(const NodeRec*, const int32_t*, int64_t, const uint8_t*, int, const int32_t*,
+                         const double*, double*, uint8_t*, int32_t*, int, int32_t*,
+                         unsigned long long*);
+
+// uint8 rows (D % 16 == 0): 16 elements per lane; f[0] for a level's first
+// pass, f[1] for the later ones; *rep recomputes their margins for repairs.
+template <int G, int NF, int U>
+void pick_u8_depth(int pd, AssignFn<uint8_t>* f, RepairFn* rep) {
     if (pd == 2) {
-        f[0] = k_assign_u8<EPL, G, NF, U, 2, true>;
-        f[1] = k_assign_u8<EPL, G, NF, U, 2, false>;
+        f[0] = k_assign_u8<16, G, NF, U, 2, true>;
+        f[1] = k_assign_u8<16, G, NF, U, 2, false>;
     } else {
-        f[0] = k_assign_u8<EPL, G, NF, U, 1, true>;
-        f[1] = k_assign_u8<EPL, G, NF, U, 1, false>;
+        f[0] = k_assign_u8<16, G, NF, U, 1, true>;
+        f[1] = k_assign_u8<16, G, NF, U, 1, false>;
     }
+    *rep = k_repair<G, NF>;
 }
 
-template <int EPL, int G, int NF>
-void pick_u8_unroll(int u, int pd, AssignFn<uint8_t>* f) {
+template <int G, int NF>
+void pick_u8_unroll(int u, int pd, AssignFn<uint8_t>* f, RepairFn* rep) {
     switch (u) {
-        case 1: pick_u8_depth<EPL, G, NF, 1>(pd, f); break;
-        case 2: pick_u8_depth<EPL, G, NF, 2>(pd, f); break;
-        default: pick_u8_depth<EPL, G, NF, 4>(pd, f); break;
+        case 1: pick_u8_depth<G, NF, 1>(pd, f, rep); break;
+        case 2: pick_u8_depth<G, NF, 2>(pd, f, rep); break;
+        default: pick_u8_depth<G, NF, 4>(pd, f, rep); break;
     }
 }
 
-template <int EPL>
-bool pick_u8_epl(int D, int u, int pd, AssignFn<uint8_t>* f) {
-    const int E = D / EPL;
+bool pick_assign_u8(int D, int u, int pd, AssignFn<uint8_t>* f, RepairFn* rep) {
+    const int E = D / 16;
     int G = 1;
     while (G < 64 && G < E) G <<= 1;
     f[0] = f[1] = nullptr;
     switch (G) {
-        case 1: pick_u8_unroll<EPL, 1, 1>(u, pd, f); break;
-        case 2: pick_u8_unroll<EPL, 2, 1>(u, pd, f); break;
-        case 4: pick_u8_unroll<EPL, 4, 1>(u, pd, f); break;
-        case 8: pick_u8_unroll<EPL, 8, 1>(u, pd, f); break;
-        case 16: pick_u8_unroll<EPL, 16, 1>(u, pd, f); break;
-        case 32: pick_u8_unroll<EPL, 32, 1>(u, pd, f); break;
+        case 1: pick_u8_unroll<1, 1>(u, pd, f, rep); break;
+        case 2: pick_u8_unroll<2, 1>(u, pd, f, rep); break;
+        case 4: pick_u8_unroll<4, 1>(u, pd, f, rep); break;
+        case 8: pick_u8_unroll<8, 1>(u, pd, f, rep); break;
+        case 16: pick_u8_unroll<16, 1>(u, pd, f, rep); break;
+        case 32: pick_u8_unroll<32, 1>(u, pd, f, rep); break;
         default:
-            if (E <= 64) pick_u8_unroll<EPL, 64, 1>(u, pd, f);
-            else if (E <= 128) pick_u8_depth<EPL, 64, 2, 1>(pd, f);
-            else if (E <= 256) pick_u8_depth<EPL, 64, 4, 1>(pd, f);
+            if (E <= 64) pick_u8_unroll<64, 1>(u, pd, f, rep);
+            else if (E <= 128) pick_u8_depth<64, 2, 1>(pd, f, rep);
+            else if (E <= 256) pick_u8_depth<64, 4, 1>(pd, f, rep);
             break;
     }
     return f[0] != nullptr;
-}
-
-bool pick_assign_u8(int D, int epl, int u, int pd, AssignFn<uint8_t>* f) {
-    return epl == 8 ? pick_u8_epl<8>(D, u, pd, f) : pick_u8_epl<16>(D, u, pd, f);
 }
 
 int env_int(const char* name, int dflt) {
@@ -1073,8 +1139,8 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     hipStream_t s = a.stream;
     // Tuned on MI355X (1M x 128 rows): FP32 rows 8 elements per lane, one row
     // per lane group and step; uint8 rows 16 elements per lane, two rows per
-    // step, one step of loads ahead.  The environment may override
-    // both for tuning runs.
+    // step, one step of loads ahead.  The environment may override the
+    // elements per lane (FP32), rows per step and load depth for tuning runs.
     const bool use_u8 = a.X8 != nullptr && D % 16 == 0;
     int epl = env_int("KNNG_ASSIGN_EPL", 8);
     int unroll = env_int("KNNG_ASSIGN_UNROLL", use_u8 ? 2 : 1);
@@ -1082,9 +1148,9 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     if (unroll != 1 && unroll != 2 && unroll != 4) unroll = use_u8 ? 2 : 1;
     AssignFn<float> assign = use_u8 ? nullptr : pick_assign_f32(D, epl, unroll);
     AssignFn<uint8_t> assign8[2] = {nullptr, nullptr};
-    const int epl8 = env_int("KNNG_ASSIGN_U8_EPL", 16) == 8 ? 8 : 16;
+    RepairFn repair = k_repair<0, 1>;
     const int depth8 = env_int("KNNG_ASSIGN_U8_DEPTH", 1) == 2 ? 2 : 1;
-    if (use_u8) pick_assign_u8(D, epl8, unroll, depth8, assign8);
+    if (use_u8) pick_assign_u8(D, unroll, depth8, assign8, &repair);
     if (assign == nullptr && assign8[0] == nullptr) {
         std::snprintf(err, errlen, "dimension %d not supported by the partition kernels", D);
         return kUnsupported;
@@ -1108,7 +1174,7 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     NodeRec* sub = nullptr;
     NodeRec* nodes[2] = {nullptr, nullptr};
     int32_t* big[2] = {nullptr, nullptr};
-    int32_t *chunk_node = nullptr, *status = nullptr, *n0f = nullptr, *cnt = nullptr,
+    int32_t *chunk_node = nullptr, *rep = nullptr, *status = nullptr, *n0f = nullptr, *cnt = nullptr,
             *perm_tmp = nullptr, *overflow = nullptr;
     double *C = nullptr, *P = nullptr, *dots = nullptr;
     uint8_t* labels = nullptr;
@@ -1129,6 +1195,7 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&big[1]), sizeof(int32_t) * nmax, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&sub), sizeof(NodeRec) * nmax, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&chunk_node), sizeof(int32_t) * cmax, s));
+    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&rep), sizeof(int32_t) * (nmax + 1), s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&status), sizeof(int32_t) * nmax, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&n0f), sizeof(int32_t) * nmax, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&C), sizeof(double) * nmax * 2 * D, s));
@@ -1165,7 +1232,7 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
         const int nc = hctr->nc_next;
         const int nb = hctr->n_big;
         const int cblocks = (nc + 3) / 4;
-        k_chunk_map<<<na, 64, 0, s>>>(nodes[cur], chunk_node);
+        k_chunk_map<<<na, 64, 0, s>>>(nodes[cur], chunk_node, rep);
         KNNG_LAUNCH();
         k_init_nodes<<<na, 64, 0, s>>>(nodes[cur], a.perm, a.X, n, D, a.seed, a.tree0, C, status);
         KNNG_LAUNCH();
@@ -1174,21 +1241,22 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
             if (use_u8)
                 assign8[pass == 0 ? 0 : 1]<<<cblocks, 256, 0, s>>>(
                     a.X8, n, D, a.perm, nodes[cur], chunk_node, nc, C, status, n0f, labels, dots,
-                    P, cnt, pass, a.max_iter, dstats);
+                    P, cnt, pass, a.max_iter, dstats, rep, a.min_leaf);
             else
                 assign<<<cblocks, 256, 0, s>>>(a.X, n, D, a.perm, nodes[cur], chunk_node, nc, C,
                                                status, n0f, labels, dots, P, cnt, pass,
-                                               a.max_iter, dstats);
+                                               a.max_iter, dstats, rep, a.min_leaf);
             if (a.timer) a.timer->end(kKAssign, s);
             KNNG_LAUNCH();
             if (nb > 0) {
                 k_update_big<<<nb * slices, 256, 0, s>>>(nodes[cur], big[cur], D, P, cnt, C,
                                                          status, n0f, pass, a.max_iter,
-                                                         use_u8 ? 1 : 0);
+                                                         use_u8 ? 1 : 0, rep, a.min_leaf);
                 KNNG_LAUNCH();
             }
         }
-        k_repair<<<na, 256, 0, s>>>(nodes[cur], n, dots, labels, n0f, a.min_leaf, cnt, dstats + 1);
+        repair<<<std::min(na, 2048), 256, 0, s>>>(nodes[cur], rep, n, a.X8, D, a.perm, C, dots,
+                                                  labels, n0f, a.min_leaf, cnt, dstats + 1);
         KNNG_LAUNCH();
         k_scatter<<<cblocks, 256, 0, s>>>(n, nodes[cur], chunk_node, nc, labels, cnt, n0f, a.perm,
                                           perm_tmp);
@@ -1264,6 +1332,7 @@ done:
     if (big[1]) hipFreeAsync(big[1], s);
     if (sub) hipFreeAsync(sub, s);
     if (chunk_node) hipFreeAsync(chunk_node, s);
+    if (rep) hipFreeAsync(rep, s);
     if (status) hipFreeAsync(status, s);
     if (n0f) hipFreeAsync(n0f, s);
     if (C) hipFreeAsync(C, s);

@@ -75,11 +75,13 @@ __device__ __forceinline__ int32_t key_id(uint64_t k) { return static_cast<int32
 constexpr uint64_t kNoKey = ~0ull;
 
 // Ascending bitonic sort of 64*R keys held R per lane; element e = lane*R + r.
-template <int R>
+// FROM > 2: the keys already form sorted runs of FROM/2 elements, ascending
+// in even runs and descending in odd ones, and the first stages are skipped.
+template <int R, int FROM = 2>
 __device__ __forceinline__ void wave_bitonic_sort(uint64_t (&v)[R]) {
     const int lane = lane_id();
 #pragma unroll
-    for (int size = 2; size <= kWave * R; size <<= 1) {
+    for (int size = FROM; size <= kWave * R; size <<= 1) {
 #pragma unroll
         for (int j = size >> 1; j >= 1; j >>= 1) {
             if (j >= R) {
