@@ -676,6 +676,60 @@ __global__ __launch_bounds__(256) void k_update_big(const NodeRec* __restrict__ 
     }
 }
 
+// Centre update of multi-chunk nodes when they span few chunks: one block per
+// node for all 2D values (thread v sums the chunks in order), so a level of
+// many two- or three-chunk nodes launches one block per node, not per slice.
+__global__ __launch_bounds__(256) void k_update_nodes(const NodeRec* __restrict__ nodes,
+                                                      const int32_t* __restrict__ big, int D,
+                                                      const double* __restrict__ P,
+                                                      const int32_t* __restrict__ cnt,
+                                                      double* __restrict__ C,
+                                                      int32_t* __restrict__ status,
+                                                      int32_t* __restrict__ n0f, int pass,
+                                                      int max_iter, int totals,
+                                                      int32_t* __restrict__ rep, int min_leaf) {
+    const int node = big[blockIdx.x];
+    if (status[node]) return;
+    const NodeRec r = nodes[node];
+    const int nch = chunks_of(r.size);
+    __shared__ int s_n[2];
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        int a = 0, b = 0;
+        for (int c = 0; c < nch; ++c) {
+            a += cnt[2 * (r.chunk0 + c)];
+            b += cnt[2 * (r.chunk0 + c) + 1];
+        }
+        s_n[0] = a;
+        s_n[1] = b;
+    }
+    __syncthreads();
+    const int n1 = s_n[0], changed = s_n[1];
+    const int n0 = r.size - n1;
+    const bool stop = n1 == 0 || n0 == 0 || (pass >= 1 && changed == 0) || pass + 1 >= max_iter;
+    if (stop) {
+        if (tid == 0) {
+            status[node] = 1;
+            n0f[node] = n0;
+            if (n0 < min_leaf || n1 < min_leaf) rep[1 + atomicAdd(rep, 1)] = node;
+        }
+        return;
+    }
+    const size_t sD = static_cast<size_t>(D);
+    const double* q = P + static_cast<size_t>(r.chunk0) * 2 * sD;
+    double* cn = C + static_cast<size_t>(node) * 2 * sD;
+    for (int d = tid; d < D; d += 256) {
+        double t0 = 0.0, t1 = 0.0;
+        for (int c = 0; c < nch; ++c) {
+            t0 += q[c * 2 * sD + d];
+            t1 += q[c * 2 * sD + sD + d];
+        }
+        if (totals) t0 -= t1;  // P holds totals and side-1 sums (exact integers)
+        cn[d] = t0 / static_cast<double>(n0);
+        cn[sD + d] = t1 / static_cast<double>(n1);
+    }
+}
+
 // ------------------------------------------------------------- repair
 // Margin-rank repair of nodes with a side smaller than min_leaf: order the
 // members by (mu, id), mu = |x-c0|^2 - |x-c1|^2 = 2 (h - dot), i.e. by
@@ -1232,6 +1286,8 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
         const int nc = hctr->nc_next;
         const int nb = hctr->n_big;
         const int cblocks = (nc + 3) / 4;
+        // chunks of the multi-chunk nodes: nc less one per single-chunk node
+        const bool few_chunks = nb > 0 && (nc - (na - nb)) <= 8 * nb;
         k_chunk_map<<<na, 64, 0, s>>>(nodes[cur], chunk_node, rep);
         KNNG_LAUNCH();
         k_init_nodes<<<na, 64, 0, s>>>(nodes[cur], a.perm, a.X, n, D, a.seed, a.tree0, C, status);
@@ -1249,9 +1305,14 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
             if (a.timer) a.timer->end(kKAssign, s);
             KNNG_LAUNCH();
             if (nb > 0) {
-                k_update_big<<<nb * slices, 256, 0, s>>>(nodes[cur], big[cur], D, P, cnt, C,
-                                                         status, n0f, pass, a.max_iter,
-                                                         use_u8 ? 1 : 0, rep, a.min_leaf);
+                if (few_chunks)
+                    k_update_nodes<<<nb, 256, 0, s>>>(nodes[cur], big[cur], D, P, cnt, C, status,
+                                                      n0f, pass, a.max_iter, use_u8 ? 1 : 0, rep,
+                                                      a.min_leaf);
+                else
+                    k_update_big<<<nb * slices, 256, 0, s>>>(nodes[cur], big[cur], D, P, cnt, C,
+                                                             status, n0f, pass, a.max_iter,
+                                                             use_u8 ? 1 : 0, rep, a.min_leaf);
                 KNNG_LAUNCH();
             }
         }
