@@ -756,8 +756,7 @@ __global__ __launch_bounds__(256) void k_repair(const NodeRec* __restrict__ node
                                                 unsigned long long* __restrict__ repairs) {
     __shared__ unsigned int hist[256];
     __shared__ unsigned long long s_min[256], s_max[256];
-    __shared__ unsigned long long s_prefix;
-    __shared__ int s_rem;
+    __shared__ int s_bin, s_rem;
     __shared__ int warp_tot[4];
     const int tid = threadIdx.x;
     const int nrep = rep[0];
@@ -851,20 +850,8 @@ __global__ __launch_bounds__(256) void k_repair(const NodeRec* __restrict__ node
             if ((key & hi) == (prefix & hi)) atomicAdd(&hist[(key >> shift) & 255ull], 1u);
         }
         __syncthreads();
-        if (tid == 0) {
-            int cum = 0;
-            for (int dg = 0; dg < 256; ++dg) {
-                const int c = static_cast<int>(hist[dg]);
-                if (cum + c > rem) {
-                    s_prefix = prefix | (static_cast<unsigned long long>(dg) << shift);
-                    s_rem = rem - cum;
-                    break;
-                }
-                cum += c;
-            }
-        }
-        __syncthreads();
-        prefix = s_prefix;
+        block_hist_pick<4>(hist, rem, warp_tot, &s_bin, &s_rem);
+        prefix |= static_cast<unsigned long long>(s_bin) << shift;
         rem = s_rem;
         __syncthreads();
     }

@@ -55,5 +55,33 @@ __device__ __forceinline__ int block_excl_scan_flag(bool f, int* warp_tot, int* 
     return off + below;
 }
 
+// Radix-selection step over a 256-bin histogram held in LDS (one bin per
+// thread for the first 256 threads of an NW-wavefront block): finds the bin
+// whose cumulative count first exceeds rem and writes (bin, rem within it)
+// to *out_bin, *out_rem.  Every thread calls it; it ends with a barrier.
+template <int NW = 4>
+__device__ __forceinline__ void block_hist_pick(const unsigned int* hist, int rem, int* wtot,
+                                                int* out_bin, int* out_rem) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int c = tid < 256 ? static_cast<int>(hist[tid]) : 0;
+    int x = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63 && wv < 4) wtot[wv] = x;
+    __syncthreads();
+    int off = 0;
+    for (int i = 0; i < 4; ++i)
+        if (i < wv) off += wtot[i];
+    const int incl = off + x, excl = incl - c;
+    if (tid < 256 && excl <= rem && rem < incl) {
+        *out_bin = tid;
+        *out_rem = rem - excl;
+    }
+    __syncthreads();
+}
+
 }  // namespace pdev
 }  // namespace knng

@@ -90,8 +90,8 @@ __global__ __launch_bounds__(kSubThreads) void k_subtree_u8(
     __shared__ unsigned long long s_sw[2];
     __shared__ int8_t s_dl[NW][16];
     __shared__ int s_stack[kStack][3];
-    __shared__ int s_sp, s_node[3], s_pair[2], s_warp[NW], s_rem;
-    __shared__ unsigned long long s_kmin[NW], s_kmax[NW], s_prefix;
+    __shared__ int s_sp, s_node[3], s_pair[2], s_warp[NW], s_rem, s_bin;
+    __shared__ unsigned long long s_kmin[NW], s_kmax[NW];
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int g = lane / G, l = lane % G;     // FP64 code: lane group, lane in group
@@ -462,20 +462,8 @@ __global__ __launch_bounds__(kSubThreads) void k_subtree_u8(
                     if ((key & hi) == (prefix & hi)) atomicAdd(&s_hist[(key >> shift) & 255ull], 1u);
                 }
                 __syncthreads();
-                if (tid == 0) {
-                    int cum = 0;
-                    for (int dg = 0; dg < 256; ++dg) {
-                        const int c = static_cast<int>(s_hist[dg]);
-                        if (cum + c > rem) {
-                            s_prefix = prefix | (static_cast<unsigned long long>(dg) << shift);
-                            s_rem = rem - cum;
-                            break;
-                        }
-                        cum += c;
-                    }
-                }
-                __syncthreads();
-                prefix = s_prefix;
+                block_hist_pick<NW>(s_hist, rem, s_warp, &s_bin, &s_rem);
+                prefix |= static_cast<unsigned long long>(s_bin) << shift;
                 rem = s_rem;
                 __syncthreads();
             }
