@@ -95,7 +95,8 @@ struct SubtreeArgs {
     LevelCounters* ctr;
     unsigned long long* dstats;  // [assigned rows, repairs, splits, deepest split depth + 1]
     int* overflow;               // bit 0: leaf list full, bit 1: subtree stack full
-    int row_budget;              // LDS bytes for rows per workgroup: 131072 or 65536
+    int row_budget;              // LDS bytes for rows per workgroup: 131072 or 65536;
+                                 // 0: one wavefront per subtree (kernel k_subtree_wave_u8)
     hipStream_t stream;
 };
 int subtree_max_rows(int D, int row_budget);  // 0: the subtree kernel does not take this D

@@ -111,13 +111,6 @@ __device__ __forceinline__ void load_leaf_sorted(const int32_t* __restrict__ lp,
     }
 }
 
-// Orders the LDS operations of one wavefront across its lanes.
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Key of rank `rank` (0-based) among the valid keys of a wavefront (R per
 // lane), by radix selection on 8-bit digits with a 256-bin histogram in LDS
 // (hist: 256 words owned by this wavefront).  Returns the key; *below gets

@@ -1203,12 +1203,14 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     const size_t tn = static_cast<size_t>(T) * n;
     const int slices = (D + kUpdDims - 1) / kUpdDims;
 
-    // Nodes of at most small_max rows can be split to leaves by the subtree
-    // kernel (uint8 rows that fit LDS).  Off by default: on MI355X it does
-    // not yet beat the level passes; KNNG_SUBTREE=1 (rows in 128 KiB of LDS)
-    // or 2 (64 KiB) turn it on.
-    const int sub_mode = env_int("KNNG_SUBTREE", 0);
-    const int row_budget = sub_mode == 2 ? 65536 : 131072;
+    // Nodes of at most small_max rows are split to leaves by a subtree kernel
+    // that keeps their uint8 rows in LDS.  Default (KNNG_SUBTREE=3): one
+    // wavefront per subtree of at most 240 rows.  KNNG_SUBTREE=1 or 2: one
+    // eight-wave workgroup per subtree with rows in 128 or 64 KiB of LDS
+    // (slower on MI355X: per-pass barriers over few rows); 0: level passes
+    // down to the leaves.
+    const int sub_mode = env_int("KNNG_SUBTREE", 3);
+    const int row_budget = sub_mode == 2 ? 65536 : sub_mode == 3 ? 0 : 131072;
     const int small_max = (use_u8 && sub_mode != 0)
                               ? std::max(subtree_max_rows(D, row_budget), L)
                               : L;

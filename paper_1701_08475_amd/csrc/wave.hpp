@@ -58,6 +58,13 @@ __device__ __forceinline__ double group_sum_f64(double v) {
     return v;
 }
 
+// Orders the LDS operations of one wavefront across its lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Sum over all 64 lanes of an integer (order irrelevant).
 __device__ __forceinline__ int wave_sum_i32(int v) {
 #pragma unroll

@@ -86,7 +86,7 @@ def test_subtree_kernel_matches_oracle(K, orc, n, D, kind, L, ml, max_iter, monk
     X = datagen.make("c2", n=n) if kind == "c2" else datagen.random_points(n, D, n + D, kind)
     log("subtree n=%d D=%d kind=%s L=%d" % (n, D, kind, L))
     o = orc.tree(X, L, ml, max_iter, 4, 2, with_nodes=True)
-    for sub in ("1", "2", "0"):
+    for sub in ("1", "2", "3", "0"):
         monkeypatch.setenv("KNNG_SUBTREE", sub)
         perm, loff, nodes = _gpu_tree(K, to_dev(X), L, ml, 4, 2, max_iter=max_iter)
         assert np.array_equal(loff, o["leaf_off"])
