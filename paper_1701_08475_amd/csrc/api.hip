@@ -207,7 +207,7 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
     int64_t n_leaves_total = 0;
     hipError_t e;
     unsigned long long* dpairs = nullptr;
-    unsigned long long hpairs = 0;
+    std::vector<unsigned long long> hpairs(knng::kStatWords, 0ull);
     uint8_t* x8 = nullptr;
     // BF16 holds integers 0..255 exactly, and with 2 D 255^2 < 2^24 (D <= 129)
     // every product, norm, sum of two norms and partial sum of the first pass
@@ -227,8 +227,10 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
     if (e == hipSuccess && !direct)
         e = hipMallocAsync(reinterpret_cast<void**>(&cand_d), sizeof(float) * T * n * k, s);
     if (e == hipSuccess)
-        e = hipMallocAsync(reinterpret_cast<void**>(&dpairs), sizeof(unsigned long long), s);
-    if (e == hipSuccess) e = hipMemsetAsync(dpairs, 0, sizeof(unsigned long long), s);
+        e = hipMallocAsync(reinterpret_cast<void**>(&dpairs),
+                           sizeof(unsigned long long) * knng::kStatWords, s);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(dpairs, 0, sizeof(unsigned long long) * knng::kStatWords, s);
     if (e == hipSuccess && use_u8)
         e = hipMallocAsync(reinterpret_cast<void**>(&x8), static_cast<size_t>(n) * D, s);
     if (e == hipSuccess && leaf_prec != KNNG_FP32)
@@ -331,10 +333,11 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
         }
     }
     ev.record(4, s);
-    e = hipMemcpyAsync(&hpairs, dpairs, sizeof(hpairs), hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(hpairs.data(), dpairs, sizeof(unsigned long long) * hpairs.size(),
+                       hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) rc = hip_fail(e, "build");
-    pairs = static_cast<int64_t>(hpairs);
+    pairs = static_cast<int64_t>(knng::stat_total(hpairs.data()));
 
 done:
     if (perm) hipFreeAsync(perm, s);

@@ -15,6 +15,34 @@ constexpr int kMaxLeaf = 512;
 // Largest dimension the partition kernels accept.
 constexpr int kMaxDim = 4096;
 
+// Statistics counters (rows assigned, leaf pairs, ...) are spread over
+// kStatSlots 128-byte lines: atomics from thousands of wavefronts on one
+// address queue behind each other in one L2 channel.  Counter c of a block
+// of counters lives at words c * kStatWords + slot * kStatStride.
+constexpr int kStatSlots = 64;
+constexpr int kStatStride = 16;
+constexpr int kStatWords = kStatSlots * kStatStride;
+
+__device__ __forceinline__ void stat_add(unsigned long long* c, unsigned key,
+                                         unsigned long long v) {
+    atomicAdd(c + (key & (kStatSlots - 1)) * kStatStride, v);
+}
+__device__ __forceinline__ void stat_max(unsigned long long* c, unsigned key,
+                                         unsigned long long v) {
+    atomicMax(c + (key & (kStatSlots - 1)) * kStatStride, v);
+}
+// Host side: total (or maximum) of one spread counter copied back.
+inline unsigned long long stat_total(const unsigned long long* c) {
+    unsigned long long t = 0;
+    for (int i = 0; i < kStatSlots; ++i) t += c[i * kStatStride];
+    return t;
+}
+inline unsigned long long stat_peak(const unsigned long long* c) {
+    unsigned long long t = 0;
+    for (int i = 0; i < kStatSlots; ++i) t = c[i * kStatStride] > t ? c[i * kStatStride] : t;
+    return t;
+}
+
 // A node of the current level: a run [start, start+size) of perm[tree].
 struct NodeRec {
     int32_t tree;    // tree slot 0..T-1 within this call
@@ -93,7 +121,8 @@ struct SubtreeArgs {
     int32_t* node_log;
     int64_t node_log_cap;
     LevelCounters* ctr;
-    unsigned long long* dstats;  // [assigned rows, repairs, splits, deepest split depth + 1]
+    unsigned long long* dstats;  // spread counters (kStatWords each): assigned rows, repairs,
+                                 // splits, deepest split depth + 1
     int* overflow;               // bit 0: leaf list full, bit 1: subtree stack full
     int row_budget;              // LDS bytes for rows per workgroup: 131072 or 65536;
                                  // 0: one wavefront per subtree (kernel k_subtree_wave_u8)
@@ -101,6 +130,19 @@ struct SubtreeArgs {
 };
 int subtree_max_rows(int D, int row_budget);  // 0: the subtree kernel does not take this D
 int subtree_launch(const SubtreeArgs& a);
+
+// One assignment pass over the chunks of the active nodes (one wavefront per
+// chunk of kChunkRows rows): X, n, D, perm, nodes, chunk_node, number of
+// chunks, centres C, status, n0f, labels, dots, per-chunk sums P, per-chunk
+// counts, pass, max_iter, assigned-row counter, repair list, min_leaf.
+template <typename TX>
+using AssignFn = void (*)(const TX*, int64_t, int, const int32_t*, const NodeRec*, const int32_t*,
+                          int, double*, int32_t*, int32_t*, uint8_t*, double*, double*, int32_t*,
+                          int, int, unsigned long long*, int32_t*, int);
+// Matrix-core assignment passes for uint8 rows (D % 16 == 0, D <= 128):
+// f[0] for a level's first pass, f[1] for the later ones; rows per step u
+// (1 or 2) and pipeline depth pd (1 or 2).  False if D is not covered.
+bool pick_assign_u8_mfma(int D, int u, int pd, AssignFn<uint8_t>* f);
 
 // ---------------------------------------------------------------- partition
 struct PartitionArgs {
@@ -156,7 +198,7 @@ struct LeafArgs {
     int rerank;              // candidates per row for reduced precision
     int32_t* cand_ids;       // device [n_trees][n][k]
     float* cand_d;           // device [n_trees][n][k]
-    unsigned long long* pairs;  // device nullable: += m*(m-1) per leaf
+    unsigned long long* pairs;  // device nullable, spread counter: += m*(m-1) per leaf
     KernelTimer* timer;      // nullable
     hipStream_t stream;
 };

@@ -41,7 +41,7 @@ __global__ __launch_bounds__(256) void k_leaf_fp32(const float* __restrict__ X, 
     const int tid = threadIdx.x;
     for (int j = tid; j < m; j += 256) ids[j] = perm[base + j];
     if (tid == 0 && pairs != nullptr)
-        atomicAdd(pairs, static_cast<unsigned long long>(m) * static_cast<unsigned long long>(m - 1));
+        stat_add(pairs, blockIdx.x, static_cast<unsigned long long>(m) * static_cast<unsigned long long>(m - 1));
     __syncthreads();
 
     const int ri = tid & (kPanel - 1);

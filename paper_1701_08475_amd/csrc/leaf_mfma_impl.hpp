@@ -217,7 +217,7 @@ __global__ __launch_bounds__(NW * 64) void k_leaf_mfma(
     load_leaf_sorted<MP, NTH>(perm + base, m, reinterpret_cast<int32_t*>(region), ids, snrm, ssinv,
                               nrm, sinv);
     if (tid == 0 && pairs != nullptr)
-        atomicAdd(pairs, static_cast<unsigned long long>(m) * static_cast<unsigned long long>(m - 1));
+        stat_add(pairs, blockIdx.x, static_cast<unsigned long long>(m) * static_cast<unsigned long long>(m - 1));
     __syncthreads();
     const int cc = EXACT ? k : c;          // candidates wanted per row
     const int ce = cc < m - 1 ? cc : m - 1;
@@ -457,7 +457,7 @@ __global__ __launch_bounds__(256) void k_leaf_small(
     load_leaf_sorted<MP>(perm + base, m, reinterpret_cast<int32_t*>(lds), ids, snrm, ssinv, nrm,
                          sinv);
     if (tid == 0 && pairs != nullptr)
-        atomicAdd(pairs, static_cast<unsigned long long>(m) * static_cast<unsigned long long>(m - 1));
+        stat_add(pairs, blockIdx.x, static_cast<unsigned long long>(m) * static_cast<unsigned long long>(m - 1));
     __syncthreads();
 
     // ---- Gram: wave w has row tiles w*RPW .. w*RPW+RPW-1 and every column tile

@@ -29,8 +29,6 @@ namespace knng {
 namespace {
 using namespace pdev;
 
-__device__ __forceinline__ int chunks_of(int size) { return (size + kChunkRows - 1) / kChunkRows; }
-
 // ------------------------------------------------------------- level setup
 // Root nodes (or root leaves when n <= leaf_max) of every tree slot; roots
 // of at most small_max rows go straight to the subtree list (depth 0).
@@ -73,8 +71,8 @@ __global__ void k_fill_u8(uint8_t* p, int64_t count) {
         p[i] = 0;
 }
 
-__global__ void k_zero_small(unsigned long long* stats, int* flag) {
-    if (threadIdx.x < 4) stats[threadIdx.x] = 0ull;
+__global__ void k_zero_small(unsigned long long* stats, int words, int* flag) {
+    for (int i = threadIdx.x; i < words; i += blockDim.x) stats[i] = 0ull;
     if (threadIdx.x == 0) *flag = 0;
 }
 
@@ -300,7 +298,7 @@ __global__ __launch_bounds__(256) void k_assign(
     if (lane == 0) {
         cnt[2 * wave] = n1;  // ones of this chunk (also read by the scatter)
         cnt[2 * wave + 1] = changed;
-        atomicAdd(assigned, static_cast<unsigned long long>(row1 - row0));
+        stat_add(assigned, static_cast<unsigned>(wave), static_cast<unsigned long long>(row1 - row0));
     }
 
     if (nch == 1) {  // the wave holds the whole node
@@ -530,7 +528,7 @@ __global__ __launch_bounds__(256) void k_assign_u8(
     if (lane == 0) {
         cnt[2 * wave] = n1;  // ones of this chunk (also read by the scatter)
         cnt[2 * wave + 1] = changed;
-        atomicAdd(assigned, static_cast<unsigned long long>(nrows));
+        stat_add(assigned, static_cast<unsigned>(wave), static_cast<unsigned long long>(nrows));
     }
 
     if (nch == 1) {  // the wave holds the whole node
@@ -879,7 +877,7 @@ __global__ __launch_bounds__(256) void k_repair(const NodeRec* __restrict__ node
     }
     if (tid == 0) {
         n0f[node] = s;
-        atomicAdd(repairs, 1ull);
+        stat_add(repairs, static_cast<unsigned>(blockIdx.x), 1ull);
     }
     __syncthreads();  // shared state is reused by the next node
     }
@@ -1042,10 +1040,6 @@ __global__ __launch_bounds__(1024) void k_next_level(
 }
 
 // ------------------------------------------------------------- dispatch
-template <typename TX>
-using AssignFn = void (*)(const TX*, int64_t, int, const int32_t*, const NodeRec*, const int32_t*,
-                          int, double*, int32_t*, int32_t*, uint8_t*, double*, double*, int32_t*,
-                          int, int, unsigned long long*, int32_t*, int);
 
 // Rows per lane group and step; more rows keep more loads in flight.
 template <typename TX, int VEC, int G, int NF>
@@ -1191,7 +1185,18 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     AssignFn<uint8_t> assign8[2] = {nullptr, nullptr};
     RepairFn repair = k_repair<0, 1>;
     const int depth8 = env_int("KNNG_ASSIGN_U8_DEPTH", 1) == 2 ? 2 : 1;
-    if (use_u8) pick_assign_u8(D, unroll, depth8, assign8, &repair);
+    if (use_u8) {
+        pick_assign_u8(D, unroll, depth8, assign8, &repair);
+        // margin on the matrix cores where D allows (KNNG_ASSIGN_MFMA=0: FP64 VALU kernel)
+        if (env_int("KNNG_ASSIGN_MFMA", 1) != 0) {
+            AssignFn<uint8_t> fm[2];
+            if (pick_assign_u8_mfma(D, env_int("KNNG_ASSIGN_M_U", 1),
+                                    env_int("KNNG_ASSIGN_M_PD", 2), fm)) {
+                assign8[0] = fm[0];
+                assign8[1] = fm[1];
+            }
+        }
+    }
     if (assign == nullptr && assign8[0] == nullptr) {
         std::snprintf(err, errlen, "dimension %d not supported by the partition kernels", D);
         return kUnsupported;
@@ -1224,7 +1229,7 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     LevelCounters* ctr = nullptr;
     unsigned long long* dstats = nullptr;
     LevelCounters* hctr = nullptr;
-    unsigned long long hstats[4] = {0, 0, 0, 0};
+    std::vector<unsigned long long> hstats(4 * kStatWords, 0ull);
     int hoverflow = 0;
     int cur = 0;
     int depth = 0;
@@ -1248,9 +1253,10 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&dots), sizeof(double) * tn, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&perm_tmp), sizeof(int32_t) * tn, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&ctr), sizeof(LevelCounters), s));
-    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&dstats), sizeof(unsigned long long) * 4, s));
+    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&dstats),
+                            sizeof(unsigned long long) * 4 * kStatWords, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&overflow), sizeof(int), s));
-    k_zero_small<<<1, 64, 0, s>>>(dstats, overflow);
+    k_zero_small<<<1, 256, 0, s>>>(dstats, 4 * kStatWords, overflow);
     KNNG_LAUNCH();
     {
         const int64_t want = (static_cast<int64_t>(tn) + 255) / 256;
@@ -1306,7 +1312,7 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
             }
         }
         repair<<<std::min(na, 2048), 256, 0, s>>>(nodes[cur], rep, n, a.X8, D, a.perm, C, dots,
-                                                  labels, n0f, a.min_leaf, cnt, dstats + 1);
+                                                  labels, n0f, a.min_leaf, cnt, dstats + kStatWords);
         KNNG_LAUNCH();
         k_scatter<<<cblocks, 256, 0, s>>>(n, nodes[cur], chunk_node, nc, labels, cnt, n0f, a.perm,
                                           perm_tmp);
@@ -1335,7 +1341,8 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
         ++launches;
         KNNG_HIP(hipMemcpyAsync(hctr, ctr, sizeof(LevelCounters), hipMemcpyDeviceToHost, s));
     }
-    KNNG_HIP(hipMemcpyAsync(hstats, dstats, sizeof(hstats), hipMemcpyDeviceToHost, s));
+    KNNG_HIP(hipMemcpyAsync(hstats.data(), dstats, sizeof(unsigned long long) * hstats.size(),
+                            hipMemcpyDeviceToHost, s));
     KNNG_HIP(hipMemcpyAsync(&hoverflow, overflow, sizeof(int), hipMemcpyDeviceToHost, s));
     KNNG_HIP(hipStreamSynchronize(s));
     if (hoverflow) {
@@ -1349,10 +1356,11 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     }
     res->n_leaves = hctr->n_leaves;
     res->n_log = hctr->n_log;
-    res->assign_rows = static_cast<int64_t>(hstats[0]);
-    res->repairs = static_cast<int64_t>(hstats[1]);
-    res->splits = splits + static_cast<int64_t>(hstats[2]);
-    res->levels = std::max<int64_t>(depth, static_cast<int64_t>(hstats[3])) + 1;
+    res->assign_rows = static_cast<int64_t>(stat_total(hstats.data()));
+    res->repairs = static_cast<int64_t>(stat_total(hstats.data() + kStatWords));
+    res->splits = splits + static_cast<int64_t>(stat_total(hstats.data() + 2 * kStatWords));
+    res->levels =
+        std::max<int64_t>(depth, static_cast<int64_t>(stat_peak(hstats.data() + 3 * kStatWords))) + 1;
     if (a.node_log != nullptr && hctr->n_sub > 0) {
         // subtree splits are logged in completion order: restore the
         // documented (depth, start) order

@@ -8,6 +8,9 @@
 namespace knng {
 namespace pdev {
 
+// Chunks of kChunkRows rows (one wavefront each) of a node of `size` rows.
+__device__ __forceinline__ int chunks_of(int size) { return (size + kChunkRows - 1) / kChunkRows; }
+
 // ------------------------------------------------------------- random pair
 // Keyed starting pair.  SplitMix64 output function (Steele, Lea, Flood,
 // OOPSLA 2014); each key word is absorbed as one SplitMix64 step taken from
