@@ -14,7 +14,11 @@
  *     as "host" are ordinary host memory.
  *   - All work is ordered on `stream`; each call returns after that work has
  *     completed (it synchronises the stream).  Scratch memory is taken with
- *     hipMallocAsync on `stream` and freed before return.
+ *     hipMallocAsync on `stream` and freed (hipFreeAsync) before return.  The
+ *     first call on a device raises the release threshold of that device's
+ *     current memory pool to unlimited, so freed scratch stays reserved for
+ *     the next call instead of being returned to the driver at every
+ *     synchronisation; hipMemPoolTrimTo gives it back.
  *   - Return value: KNNG_OK (0) or a negative status below.  On an argument
  *     error (KNNG_ERR_INVALID_ARG, KNNG_ERR_UNSUPPORTED) nothing is launched
  *     and no output is written.  On KNNG_ERR_NONFINITE the outputs are not

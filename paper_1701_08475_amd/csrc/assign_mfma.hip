@@ -17,7 +17,11 @@
 // decides dot < h as the FP64 code does.  Rows inside that band are
 // evaluated by the FP64 code itself (lanes 0 .. G-1 of the wavefront).
 //
-// Layout.  One wavefront per chunk of kChunkRows rows, tiles of 16 rows: lane
+// Layout.  A chunk of kChunkRows rows is split into tiles of 16 rows, dealt
+// round-robin to the four wavefronts of a workgroup (or all taken by one
+// wavefront, four chunks per workgroup; slower on MI355X at every level
+// size: a quarter of the tiles per wave shortens each wave's serial chain
+// and the id, centre and label set-up is shared).  In a tile, lane
 // (q, c) = (lane / 16, lane % 16) loads bytes 64 kb + 16 q .. + 15 of row c of
 // the tile (the A operand), and the B operand holds the four digit planes in
 // columns 0..3.  Output element i of lane (q, c) is digit plane c of row
@@ -54,8 +58,9 @@ __device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
 }
 
 // KB 64-element blocks (D <= 64 KB), G lanes per row in the FP64 code, U
-// tiles per step, PD steps of loads in flight.
-template <int KB, int G, int U, int PD, bool FIRST>
+// tiles per step, PD steps of loads in flight, WPC wavefronts per chunk (1:
+// four chunks per workgroup; 4: one chunk per workgroup).
+template <int KB, int G, int U, int PD, bool FIRST, int WPC>
 __global__ __launch_bounds__(256) void k_assign_u8m(
     const uint8_t* __restrict__ X, int64_t n, int D, const int32_t* __restrict__ perm,
     const NodeRec* __restrict__ nodes, const int32_t* __restrict__ chunk_node, int nc,
@@ -63,29 +68,37 @@ __global__ __launch_bounds__(256) void k_assign_u8m(
     uint8_t* __restrict__ labels, double* __restrict__ /*dots: not used for uint8 rows*/,
     double* __restrict__ P, int32_t* __restrict__ cnt, int pass, int max_iter,
     unsigned long long* __restrict__ assigned, int32_t* __restrict__ rep, int min_leaf) {
+    static_assert(WPC == 1 || WPC == 4, "one or four wavefronts per chunk");
     constexpr int DM = KB * 64;
-    constexpr int kFill = kChunkRows / kWave;
+    constexpr int CPB = 4 / WPC;                  // chunks per workgroup
+    constexpr int kFill = kChunkRows / (kWave * WPC);
+    constexpr int kList = WPC == 1 ? 1 : kChunkRows / WPC;  // changed-row list per wave
     static_assert(16 * G <= DM, "FP64 lane layout exceeds the row block");
-    __shared__ int32_t s_ids[4][kChunkRows];
-    __shared__ uint8_t s_old[4][kChunkRows];
+    __shared__ int32_t s_ids[CPB][kChunkRows];
+    __shared__ uint8_t s_old[CPB][kChunkRows];
     __shared__ __align__(16) int8_t s_dig[4][4][DM];
     __shared__ double s_w[4][DM];
+    __shared__ int32_t s_lid[WPC == 1 ? 1 : 4][kList];
+    __shared__ uint8_t s_lsg[WPC == 1 ? 1 : 4][kList];
+    __shared__ int32_t s_red[WPC == 1 ? 1 : 4][2 * kWave + 2];
 
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
+    const int wc = wl % WPC, cs = wl / WPC;  // wave within its chunk, chunk slot
+    const int wave = blockIdx.x * CPB + cs;  // chunk index
     if (wave >= nc) return;
     const int node = chunk_node[wave];
-    if (status[node]) return;
+    if (status[node]) return;  // the same for every wave of the chunk
     const NodeRec r = nodes[node];
-    const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
     const int tc = lane & 15, tq = lane >> 4;
     const int l = lane % G;
     const int nch = chunks_of(r.size);
     const int row0 = (wave - r.chunk0) * kChunkRows;
     const int nrows = min(r.size - row0, kChunkRows);
     const size_t base = static_cast<size_t>(r.tree) * n + r.start + row0;
-    int32_t* ids = s_ids[wl];
-    uint8_t* olds = s_old[wl];
+    int32_t* ids = s_ids[cs];
+    uint8_t* olds = s_old[cs];
     double* sw = s_w[wl];
+    const int ctid = wc * kWave + lane;  // thread index within the chunk's waves
 
     // row ids and previous labels of the chunk: loads issued now, stored to
     // LDS after the centres are done with the same LDS space
@@ -93,14 +106,16 @@ __global__ __launch_bounds__(256) void k_assign_u8m(
     uint8_t pl[kFill];
 #pragma unroll
     for (int q = 0; q < kFill; ++q) {
-        const int i = min(q * kWave + lane, nrows - 1);
+        const int i = min(q * kWave * WPC + ctid, nrows - 1);
         pid[q] = perm[base + i];
         pl[q] = FIRST ? 0 : labels[base + i];
     }
 
     double* cn = C + static_cast<size_t>(node) * 2 * D;
     double* p0 = P + static_cast<size_t>(wave) * 2 * D;
-    double* scn = reinterpret_cast<double*>(ids);  // centres, [2][DM] (before the ids)
+    // centres, [2][DM], in the id space before the ids (every wave of the
+    // chunk writes the same values)
+    double* scn = reinterpret_cast<double*>(ids);
 #pragma unroll
     for (int e0 = 0; e0 < DM; e0 += kWave) {
         const int e = e0 + lane;
@@ -155,15 +170,17 @@ __global__ __launch_bounds__(256) void k_assign_u8m(
         bop[kb] = i32x4{0, 0, 0, 0};
         if (tc < 4) bop[kb] = *reinterpret_cast<const i32x4*>(&s_dig[wl][tc][kb * 64 + 16 * tq]);
     }
+    if constexpr (WPC > 1) __syncthreads();  // every wave is done with the centre scratch
 #pragma unroll
     for (int q = 0; q < kFill; ++q) {
-        const int i = q * kWave + lane;
+        const int i = q * kWave * WPC + ctid;
         if (i < nrows) {
             ids[i] = pid[q];
             olds[i] = pl[q];
         }
     }
-    wave_lds_sync();
+    if constexpr (WPC > 1) __syncthreads();
+    else wave_lds_sync();
     const double xw0 = 128.0 * wsum;
     const double hs = h * kMarginScale;
     const double bnd = 128.0 * D + 2.0;
@@ -182,13 +199,18 @@ __global__ __launch_bounds__(256) void k_assign_u8m(
             one[kb][k] = 0u;
         }
     int n1 = 0, changed = 0, nchg = 0;
+    // changed-row list: in place in the id list (one wave per chunk: every
+    // later read of the id list is past the current tile), else per wave
+    int32_t* lid = WPC == 1 ? ids : s_lid[wl % (WPC == 1 ? 1 : 4)];
+    uint8_t* lsg = WPC == 1 ? olds : s_lsg[wl % (WPC == 1 ? 1 : 4)];
     const int ntiles = (nrows + 15) >> 4;
-    const int steps = (ntiles + U - 1) / U;
+    const int mytiles = ntiles > wc ? (ntiles - wc + WPC - 1) / WPC : 0;
+    const int steps = (mytiles + U - 1) / U;
 
     auto load_tiles = [&](int st, uint4 (&x)[U][KB]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int i = min((st * U + u) * 16 + tc, nrows - 1);
+            const int i = min(((st * U + u) * WPC + wc) * 16 + tc, nrows - 1);
             const uint8_t* xr = X + static_cast<size_t>(ids[i]) * D;
 #pragma unroll
             for (int kb = 0; kb < KB; ++kb) x[u][kb] = *reinterpret_cast<const uint4*>(xr + off[kb]);
@@ -197,7 +219,7 @@ __global__ __launch_bounds__(256) void k_assign_u8m(
     auto compute = [&](int st, const uint4 (&x)[U][KB]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int t0 = (st * U + u) * 16;
+            const int t0 = ((st * U + u) * WPC + wc) * 16;
             if (t0 >= nrows) break;
             i32x4 acc = i32x4{0, 0, 0, 0};
 #pragma unroll
@@ -228,13 +250,16 @@ __global__ __launch_bounds__(256) void k_assign_u8m(
                 const uint4 raw = *reinterpret_cast<const uint4*>(
                     X + static_cast<size_t>(ids[t0 + rr]) * D + (16 * l < D ? 16 * l : 0));
                 const uint32_t wd[4] = {raw.x, raw.y, raw.z, raw.w};
+                // w re-read from LDS here (not held in registers for this rare path)
+                const double* swl = sw + 16 * l;
+                asm volatile("" : "+v"(swl));
                 double dot = 0.0;
 #pragma unroll
                 for (int k4 = 0; k4 < 4; ++k4)
 #pragma unroll
                     for (int b = 0; b < 4; ++b)
-                        dot = fma(static_cast<double>((wd[k4] >> (8 * b)) & 255u),
-                                  sw[16 * l + 4 * k4 + b], dot);
+                        dot = fma(static_cast<double>((wd[k4] >> (8 * b)) & 255u), swl[4 * k4 + b],
+                                  dot);
                 dot = group_sum_f64<G>(dot);
                 if (__builtin_amdgcn_readfirstlane(dot < h ? 1 : 0) != 0) m1 |= 1u << rr;
             }
@@ -264,13 +289,13 @@ __global__ __launch_bounds__(256) void k_assign_u8m(
                     __builtin_amdgcn_ballot_w64(tq == 0 && vrow && olds[t0 + tc] != 0) & 0xFFFFull);
                 const uint32_t ch = (m1 ^ old16) & vm;
                 if (ch != 0u) {
-                    // append (id, new label); list slot <= the row's own slot,
-                    // and every later read of the id list is past this tile
+                    // append (id, new label); with the in-place list the slot
+                    // is at most the row's own slot
                     if (tq == 0 && ((ch >> tc) & 1u)) {
                         const int k = nchg + __builtin_popcount(ch & ((1u << tc) - 1u));
                         const int32_t id = ids[t0 + tc];
-                        ids[k] = id;
-                        olds[k] = static_cast<uint8_t>(my);
+                        lid[k] = id;
+                        lsg[k] = static_cast<uint8_t>(my);
                     }
                     const int c = __builtin_popcount(ch);
                     nchg += c;
@@ -293,11 +318,14 @@ __global__ __launch_bounds__(256) void k_assign_u8m(
     }
     wave_lds_sync();
 
-    // side sums of the chunk, lane l holding elements 2 l and 2 l + 1
+    // side sums of the wave's rows, lane l holding elements 2 l and 2 l + 1
     int32_t s1v[2] = {0, 0};
     int32_t totv[2] = {0, 0};
     if constexpr (FIRST) {
-        uint32_t* sc = reinterpret_cast<uint32_t*>(ids);  // [2][DM] scratch (ids are spent)
+        if constexpr (WPC > 1) __syncthreads();  // the id list is spent for every wave
+        // [2][DM] scratch in the id space (WPC == 4: one quarter per wave)
+        uint32_t* sc = reinterpret_cast<uint32_t*>(ids) + (WPC > 1 ? wc * (kChunkRows / WPC) : 0);
+        static_assert(2 * DM <= kChunkRows / WPC, "side-sum scratch exceeds the id space");
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
@@ -339,10 +367,12 @@ __global__ __launch_bounds__(256) void k_assign_u8m(
             }
         }
     } else {
+        if (wc == 0) {
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int e = 2 * lane + c;
-            if (e < D) s1v[c] = static_cast<int32_t>(p0[D + e]);
+            for (int c = 0; c < 2; ++c) {
+                const int e = 2 * lane + c;
+                if (e < D) s1v[c] = static_cast<int32_t>(p0[D + e]);
+            }
         }
         // changed rows: +x for 0 -> 1, -x for 1 -> 0 (four rows in flight)
         const int eo = 2 * lane < D ? 2 * lane : 0;
@@ -352,8 +382,8 @@ __global__ __launch_bounds__(256) void k_assign_u8m(
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int k = min(k0 + j, nchg - 1);
-                two[j] = *reinterpret_cast<const uint16_t*>(X + static_cast<size_t>(ids[k]) * D + eo);
-                sg[j] = k0 + j < nchg ? (olds[k] ? 1 : -1) : 0;
+                two[j] = *reinterpret_cast<const uint16_t*>(X + static_cast<size_t>(lid[k]) * D + eo);
+                sg[j] = k0 + j < nchg ? (lsg[k] ? 1 : -1) : 0;
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -362,13 +392,43 @@ __global__ __launch_bounds__(256) void k_assign_u8m(
             }
         }
     }
+    if constexpr (WPC > 1) {
+        // the chunk's waves add their sums and counts; wave 0 finishes
+        int32_t* red = s_red[wl % (WPC == 1 ? 1 : 4)];
+        red[2 * lane] = FIRST ? totv[0] : 0;
+        red[2 * lane + 1] = FIRST ? totv[1] : 0;
+        if (lane == 0) {
+            red[2 * kWave] = n1;
+            red[2 * kWave + 1] = changed;
+        }
+        __syncthreads();
+        int32_t* red1 = reinterpret_cast<int32_t*>(s_lid[wl % (WPC == 1 ? 1 : 4)]);
+        red1[2 * lane] = s1v[0];
+        red1[2 * lane + 1] = s1v[1];
+        __syncthreads();
+        if (wc != 0) return;
+        n1 = 0;
+        changed = 0;
+        for (int w = 0; w < WPC; ++w) {
+            const int32_t* rw = s_red[wl + w];
+            const int32_t* r1 = reinterpret_cast<const int32_t*>(s_lid[wl + w]);
+            if (w > 0) {
+                totv[0] += rw[2 * lane];
+                totv[1] += rw[2 * lane + 1];
+                s1v[0] += r1[2 * lane];
+                s1v[1] += r1[2 * lane + 1];
+            }
+            n1 += rw[2 * kWave];
+            changed += rw[2 * kWave + 1];
+        }
+    }
 
     if (lane == 0) {
         cnt[2 * wave] = n1;  // ones of this chunk (also read by the scatter)
         cnt[2 * wave + 1] = changed;
         stat_add(assigned, static_cast<unsigned>(wave), static_cast<unsigned long long>(nrows));
     }
-    if (nch == 1) {  // the wave holds the whole node
+    if (nch == 1) {  // the chunk holds the whole node
         const int n0 = r.size - n1;
         const bool stop =
             n1 == 0 || n0 == 0 || (pass >= 1 && changed == 0) || pass + 1 >= max_iter;
@@ -410,32 +470,32 @@ __global__ __launch_bounds__(256) void k_assign_u8m(
     }
 }
 
-template <int KB, int G, int U>
+template <int KB, int G, int U, int WPC>
 void pick_pd(int pd, AssignFn<uint8_t>* f) {
     switch (pd) {
-        case 1: f[0] = k_assign_u8m<KB, G, U, 1, true>; f[1] = k_assign_u8m<KB, G, U, 1, false>; break;
-        case 2: f[0] = k_assign_u8m<KB, G, U, 2, true>; f[1] = k_assign_u8m<KB, G, U, 2, false>; break;
-        case 3: f[0] = k_assign_u8m<KB, G, U, 3, true>; f[1] = k_assign_u8m<KB, G, U, 3, false>; break;
-        default: f[0] = k_assign_u8m<KB, G, U, 4, true>; f[1] = k_assign_u8m<KB, G, U, 4, false>; break;
+        case 1: f[0] = k_assign_u8m<KB, G, U, 1, true, WPC>; f[1] = k_assign_u8m<KB, G, U, 1, false, WPC>; break;
+        case 2: f[0] = k_assign_u8m<KB, G, U, 2, true, WPC>; f[1] = k_assign_u8m<KB, G, U, 2, false, WPC>; break;
+        default: f[0] = k_assign_u8m<KB, G, U, 3, true, WPC>; f[1] = k_assign_u8m<KB, G, U, 3, false, WPC>; break;
     }
 }
 
 template <int KB, int G>
-void pick_u(int u, int pd, AssignFn<uint8_t>* f) {
-    if (u == 2) pick_pd<KB, G, 2>(pd, f);
-    else pick_pd<KB, G, 1>(pd, f);
+void pick_u(int u, int pd, AssignFn<uint8_t>* f, AssignFn<uint8_t>* f4) {
+    if (u == 2) pick_pd<KB, G, 2, 1>(pd, f);
+    else pick_pd<KB, G, 1, 1>(pd, f);
+    pick_pd<KB, G, 1, 4>(pd, f4);
 }
 
 }  // namespace
 
-bool pick_assign_u8_mfma(int D, int u, int pd, AssignFn<uint8_t>* f) {
-    f[0] = f[1] = nullptr;
+bool pick_assign_u8_mfma(int D, int u, int pd, AssignFn<uint8_t>* f, AssignFn<uint8_t>* f4) {
+    f[0] = f[1] = f4[0] = f4[1] = nullptr;
     if (D <= 0 || D % 16 != 0 || D > 128) return false;
     const int E = D / 16;
-    if (E == 1) pick_u<1, 1>(u, pd, f);
-    else if (E == 2) pick_u<1, 2>(u, pd, f);
-    else if (E <= 4) pick_u<1, 4>(u, pd, f);
-    else pick_u<2, 8>(u, pd, f);
+    if (E == 1) pick_u<1, 1>(u, pd, f, f4);
+    else if (E == 2) pick_u<1, 2>(u, pd, f, f4);
+    else if (E <= 4) pick_u<1, 4>(u, pd, f, f4);
+    else pick_u<2, 8>(u, pd, f, f4);
     return true;
 }
 

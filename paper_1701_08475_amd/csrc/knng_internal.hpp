@@ -141,8 +141,10 @@ using AssignFn = void (*)(const TX*, int64_t, int, const int32_t*, const NodeRec
                           int, int, unsigned long long*, int32_t*, int);
 // Matrix-core assignment passes for uint8 rows (D % 16 == 0, D <= 128):
 // f[0] for a level's first pass, f[1] for the later ones; rows per step u
-// (1 or 2) and pipeline depth pd (1 or 2).  False if D is not covered.
-bool pick_assign_u8_mfma(int D, int u, int pd, AssignFn<uint8_t>* f);
+// (1 or 2) and pipeline depth pd (1 to 3).  f: one wavefront per chunk, four
+// chunks per 256-thread workgroup (grid: chunks / 4); f4: four wavefronts
+// per chunk (grid: chunks).  False if D is not covered.
+bool pick_assign_u8_mfma(int D, int u, int pd, AssignFn<uint8_t>* f, AssignFn<uint8_t>* f4);
 
 // ---------------------------------------------------------------- partition
 struct PartitionArgs {

@@ -1183,17 +1183,23 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     if (unroll != 1 && unroll != 2 && unroll != 4) unroll = use_u8 ? 2 : 1;
     AssignFn<float> assign = use_u8 ? nullptr : pick_assign_f32(D, epl, unroll);
     AssignFn<uint8_t> assign8[2] = {nullptr, nullptr};
+    AssignFn<uint8_t> assign8w[2] = {nullptr, nullptr};  // four wavefronts per chunk
     RepairFn repair = k_repair<0, 1>;
     const int depth8 = env_int("KNNG_ASSIGN_U8_DEPTH", 1) == 2 ? 2 : 1;
+    // levels with at most this many chunks take four wavefronts per chunk
+    // (all levels by default: faster on MI355X whatever the chunk count)
+    const int wide_max = env_int("KNNG_ASSIGN_WIDE_MAX", 1 << 30);
     if (use_u8) {
         pick_assign_u8(D, unroll, depth8, assign8, &repair);
         // margin on the matrix cores where D allows (KNNG_ASSIGN_MFMA=0: FP64 VALU kernel)
         if (env_int("KNNG_ASSIGN_MFMA", 1) != 0) {
-            AssignFn<uint8_t> fm[2];
+            AssignFn<uint8_t> fm[2], fw[2];
             if (pick_assign_u8_mfma(D, env_int("KNNG_ASSIGN_M_U", 1),
-                                    env_int("KNNG_ASSIGN_M_PD", 2), fm)) {
+                                    env_int("KNNG_ASSIGN_M_PD", 1), fm, fw)) {
                 assign8[0] = fm[0];
                 assign8[1] = fm[1];
+                assign8w[0] = fw[0];
+                assign8w[1] = fw[1];
             }
         }
     }
@@ -1235,8 +1241,15 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     int depth = 0;
     int64_t splits = 0;
 
-    KNNG_HIP(hipHostMalloc(reinterpret_cast<void**>(&hctr), sizeof(LevelCounters),
-                           hipHostMallocDefault));
+    {
+        // pinned counter mirror, one per host thread for the life of the
+        // process (freeing pinned memory would synchronise the device)
+        thread_local LevelCounters* t_hctr = nullptr;
+        if (t_hctr == nullptr)
+            KNNG_HIP(hipHostMalloc(reinterpret_cast<void**>(&t_hctr), sizeof(LevelCounters),
+                                   hipHostMallocDefault));
+        hctr = t_hctr;
+    }
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&nodes[0]), sizeof(NodeRec) * nmax, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&nodes[1]), sizeof(NodeRec) * nmax, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&big[0]), sizeof(int32_t) * nmax, s));
@@ -1289,7 +1302,11 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
         KNNG_LAUNCH();
         for (int pass = 0; pass < a.max_iter; ++pass) {
             if (a.timer) a.timer->begin(kKAssign, s);
-            if (use_u8)
+            if (use_u8 && assign8w[0] != nullptr && nc <= wide_max)
+                assign8w[pass == 0 ? 0 : 1]<<<nc, 256, 0, s>>>(
+                    a.X8, n, D, a.perm, nodes[cur], chunk_node, nc, C, status, n0f, labels, dots,
+                    P, cnt, pass, a.max_iter, dstats, rep, a.min_leaf);
+            else if (use_u8)
                 assign8[pass == 0 ? 0 : 1]<<<cblocks, 256, 0, s>>>(
                     a.X8, n, D, a.perm, nodes[cur], chunk_node, nc, C, status, n0f, labels, dots,
                     P, cnt, pass, a.max_iter, dstats, rep, a.min_leaf);
@@ -1402,8 +1419,7 @@ done:
     if (ctr) hipFreeAsync(ctr, s);
     if (dstats) hipFreeAsync(dstats, s);
     if (overflow) hipFreeAsync(overflow, s);
-    hipStreamSynchronize(s);
-    if (hctr) hipHostFree(hctr);
+    if (rc != kOk) hipStreamSynchronize(s);  // copies into hctr may still be pending
     res->launches += launches;
     return rc;
 }

@@ -97,6 +97,30 @@ def test_subtree_kernel_matches_oracle(K, orc, n, D, kind, L, ml, max_iter, monk
         assert keys == sorted(keys)
 
 
+# Integer data in [0, 255] through the level passes alone (no subtree kernel):
+# the matrix-core assignment kernel with one and with four wavefronts per
+# chunk, and the FP64 VALU kernel, each give the oracle's tree.
+@pytest.mark.parametrize("n,D,kind,L,ml,max_iter", [
+    (30000, 128, "c2", 100, 21, 10),
+    (9000, 64, "int", 60, 30, 10),        # repairs on most splits
+    (7000, 48, "small_int", 30, 1, 10),   # ties; D = 48: one lane of four idle
+    (6000, 112, "int", 80, 5, 4),
+    (5000, 16, "small_int", 25, 3, 10),   # one 16-byte slice per row
+])
+def test_level_assignment_kernels_match_oracle(K, orc, n, D, kind, L, ml, max_iter, monkeypatch):
+    X = datagen.make("c2", n=n) if kind == "c2" else datagen.random_points(n, D, n + D, kind)
+    o = orc.tree(X, L, ml, max_iter, 7, 1, with_nodes=True)
+    monkeypatch.setenv("KNNG_SUBTREE", "0")
+    for mfma, wide in (("1", "0"), ("1", "1000000"), ("0", "0")):
+        log("level kernels n=%d D=%d kind=%s mfma=%s wide_max=%s" % (n, D, kind, mfma, wide))
+        monkeypatch.setenv("KNNG_ASSIGN_MFMA", mfma)
+        monkeypatch.setenv("KNNG_ASSIGN_WIDE_MAX", wide)
+        perm, loff, nodes = _gpu_tree(K, to_dev(X), L, ml, 7, 1, max_iter=max_iter)
+        assert np.array_equal(loff, o["leaf_off"])
+        assert np.array_equal(perm, o["perm"])
+        assert _nodes_key(nodes) == _nodes_key(o["nodes"])
+
+
 def test_partition_identical_points_closed_form(K):
     X = np.full((300, 6), 3.5, np.float32)
     perm, loff, _ = _gpu_tree(K, to_dev(X), 50, 11, 9, 0)
