@@ -24,16 +24,21 @@ METRIC = "kNN-graph build points/sec at recall@k≥target; leaf MFMA util vs pla
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 PROFILES = os.path.join(ROOT, "profiles")
-PARTITION_SRC = os.path.join(ROOT, "paper_1701_08475_amd", "csrc", "partition.hip")
+# sources of the assignment kernels: stored HBM counters are void once they change
+ASSIGN_SRCS = [os.path.join(ROOT, "paper_1701_08475_amd", "csrc", f)
+               for f in ("partition.hip", "assign_mfma.hip")]
 
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def source_sha(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def source_sha(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def stored_traffic(config):
@@ -44,8 +49,8 @@ def stored_traffic(config):
         return None
     txt = open(path).read()
     m = re.search(r"traffic_bytes_per_launch\s*=\s*([0-9.eE+]+)", txt)
-    s = re.search(r"partition_hip_sha256_16\s*=\s*([0-9a-f]+)", txt)
-    if not m or not s or s.group(1) != source_sha(PARTITION_SRC):
+    s = re.search(r"assign_sources_sha256_16\s*=\s*([0-9a-f]+)", txt)
+    if not m or not s or s.group(1) != source_sha(ASSIGN_SRCS):
         return None
     return float(m.group(1))
 
@@ -58,7 +63,7 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--precision", default=None, help="override the config's leaf precision")
     ap.add_argument("--recall-rows", type=int, default=500)
-    ap.add_argument("--cpu-sample", type=int, default=250_000)
+    ap.add_argument("--cpu-sample", type=int, default=500_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-recall", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain schedule")
@@ -103,9 +108,10 @@ def main():
         del a, b
         log("copy calibration kernel: 1 GiB read + 1 GiB write")
 
-    def step(stats=True):
-        return knng.build(xd, k, T, L, seed=seed, precision=c["precision"], stats=stats,
-                          time_kernels=stats, compact=not args.no_compact, out=(ids, ds))
+    def step(timed_kernels=False):
+        return knng.build(xd, k, T, L, seed=seed, precision=c["precision"], stats=True,
+                          time_kernels=timed_kernels, compact=not args.no_compact,
+                          out=(ids, ds))
 
     for w in range(args.warmup):
         step()
@@ -114,19 +120,23 @@ def main():
     sts = []
     t0 = time.perf_counter()
     for s in range(args.steps):
-        sts.append(step()[2])
+        # HIP events around every kernel launch (about 300 per build) cost
+        # about 2 ms per build: they are recorded in the last timed step only
+        sts.append(step(timed_kernels=(s == args.steps - 1))[2])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = n / (ms_per_step / 1e3)
     log("timed %d steps: %.2f ms/step, %.3e points/s" % (args.steps, ms_per_step, value))
 
-    # dominant kernel: two-means assignment pass, bound by HBM
+    # dominant kernel: two-means assignment pass, bound by HBM (kernel times
+    # from the last timed step, the one with per-launch events)
     st_last = sts[-1]
+    ksts = [st_last]
     elem_bytes = 1.0 if st_last["compact_used"] else 4.0  # uint8 copy or FP32 rows
-    a_bytes = sum(s["assign_rows"] for s in sts) * D * elem_bytes
-    a_ms = sum(s["ms_k_assign"] for s in sts)
-    a_launches = sum(s["n_k_assign"] for s in sts)
+    a_bytes = sum(s["assign_rows"] for s in ksts) * D * elem_bytes
+    a_ms = sum(s["ms_k_assign"] for s in ksts)
+    a_launches = sum(s["n_k_assign"] for s in ksts)
     achieved = a_bytes / (a_ms / 1e3) / 1e9
     traffic = stored_traffic(args.config)
     roofline = {
@@ -136,12 +146,13 @@ def main():
         "traffic": traffic,
         "bytes_per_launch": a_bytes / a_launches, "avg_launch_ms": a_ms / a_launches,
         "row_storage": "uint8 (lossless: integer data)" if st_last["compact_used"] else "fp32",
-        "launches_per_step": a_launches / args.steps,
+        "launches_per_step": a_launches / len(ksts),
+        "events_in": "last timed step",
     }
     st = sts[-1]
     pairs = st["ordered_pairs"]
-    leaf_ms = sum(s["ms_k_leaf"] for s in sts) / args.steps
-    merge_ms = sum(s["ms_k_merge"] for s in sts) / args.steps
+    leaf_ms = sum(s["ms_k_leaf"] for s in ksts) / len(ksts)
+    merge_ms = sum(s["ms_k_merge"] for s in ksts) / len(ksts)
     leaf_flops = 2.0 * D * pairs  # one D-long dot product per ordered pair
     mfma_leaf = c["precision"] != "fp32" or st["exact_first_pass"]
     leaf_peak = {"bf16": 2500.0, "fp16": 2500.0, "fp8": 5000.0}.get(
@@ -183,7 +194,7 @@ def main():
         plain = {"ms_per_step": round(plain_ms, 2), "speedup_of_batched": round(plain_ms / ms_per_step, 3),
                  "definition": "same rules; trees one after another; FP32 rows; FP32 direct leaf"}
         log("plain schedule: %.2f ms/step" % plain_ms)
-        step(stats=False)  # leave the batched graph in (ids, ds)
+        step()  # leave the batched graph in (ids, ds)
         torch.cuda.synchronize()
 
     recall = None
