@@ -67,7 +67,8 @@ __global__ __launch_bounds__(256) void k_assign_u8m(
     double* __restrict__ C, int32_t* __restrict__ status, int32_t* __restrict__ n0f,
     uint8_t* __restrict__ labels, double* __restrict__ /*dots: not used for uint8 rows*/,
     double* __restrict__ P, int32_t* __restrict__ cnt, int pass, int max_iter,
-    unsigned long long* __restrict__ assigned, int32_t* __restrict__ rep, int min_leaf) {
+    unsigned long long* __restrict__ assigned, int32_t* __restrict__ rep, int min_leaf,
+    const int32_t* __restrict__ order, int xcd_per) {
     static_assert(WPC == 1 || WPC == 4, "one or four wavefronts per chunk");
     constexpr int DM = KB * 64;
     constexpr int CPB = 4 / WPC;                  // chunks per workgroup
@@ -84,8 +85,8 @@ __global__ __launch_bounds__(256) void k_assign_u8m(
 
     const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
     const int wc = wl % WPC, cs = wl / WPC;  // wave within its chunk, chunk slot
-    const int wave = blockIdx.x * CPB + cs;  // chunk index
-    if (wave >= nc) return;
+    const int wave = dispatch_chunk(order, xcd_per, blockIdx.x, cs, CPB, nc);  // chunk index
+    if (wave < 0) return;
     const int node = chunk_node[wave];
     if (status[node]) return;  // the same for every wave of the chunk
     const NodeRec r = nodes[node];

@@ -134,11 +134,12 @@ int subtree_launch(const SubtreeArgs& a);
 // One assignment pass over the chunks of the active nodes (one wavefront per
 // chunk of kChunkRows rows): X, n, D, perm, nodes, chunk_node, number of
 // chunks, centres C, status, n0f, labels, dots, per-chunk sums P, per-chunk
-// counts, pass, max_iter, assigned-row counter, repair list, min_leaf.
+// counts, pass, max_iter, assigned-row counter, repair list, min_leaf,
+// dispatch order and XCD share (dispatch_chunk in partition_dev.hpp).
 template <typename TX>
 using AssignFn = void (*)(const TX*, int64_t, int, const int32_t*, const NodeRec*, const int32_t*,
                           int, double*, int32_t*, int32_t*, uint8_t*, double*, double*, int32_t*,
-                          int, int, unsigned long long*, int32_t*, int);
+                          int, int, unsigned long long*, int32_t*, int, const int32_t*, int);
 // Matrix-core assignment passes for uint8 rows (D % 16 == 0, D <= 128):
 // f[0] for a level's first pass, f[1] for the later ones; rows per step u
 // (1 or 2) and pipeline depth pd (1 to 3).  f: one wavefront per chunk, four

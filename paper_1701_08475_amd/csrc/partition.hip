@@ -77,11 +77,50 @@ __global__ void k_zero_small(unsigned long long* stats, int words, int* flag) {
 }
 
 // chunk -> node map of a level; also empties the level's repair list.
-__global__ void k_chunk_map(const NodeRec* nodes, int32_t* chunk_node, int32_t* rep) {
+// chunk_key (nullable): the chunk's first row id, for the dispatch order.
+__global__ void k_chunk_map(const NodeRec* nodes, const int32_t* perm, int64_t n,
+                            int32_t* chunk_node, int32_t* chunk_key, int32_t* rep) {
     if (blockIdx.x == 0 && threadIdx.x == 0) rep[0] = 0;
     const NodeRec r = nodes[blockIdx.x];
     const int nch = chunks_of(r.size);
-    for (int c = threadIdx.x; c < nch; c += blockDim.x) chunk_node[r.chunk0 + c] = blockIdx.x;
+    for (int c = threadIdx.x; c < nch; c += blockDim.x) {
+        chunk_node[r.chunk0 + c] = blockIdx.x;
+        if (chunk_key != nullptr)
+            chunk_key[r.chunk0 + c] =
+                perm[static_cast<size_t>(r.tree) * n + r.start + static_cast<size_t>(c) * kChunkRows];
+    }
+}
+
+// Dispatch order of a level's chunks: a counting sort by first row id >> shift
+// (at most 4096 bins; order within a bin arbitrary).  One block.
+__global__ __launch_bounds__(1024) void k_chunk_order(const int32_t* __restrict__ key, int nc,
+                                                      int shift, int32_t* __restrict__ order) {
+    constexpr int kBins = 4096;
+    __shared__ int s_bin[kBins];
+    __shared__ int s_part[1024];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kBins; i += 1024) s_bin[i] = 0;
+    __syncthreads();
+    for (int j = tid; j < nc; j += 1024) atomicAdd(&s_bin[key[j] >> shift], 1);
+    __syncthreads();
+    const int a0 = s_bin[4 * tid], a1 = s_bin[4 * tid + 1], a2 = s_bin[4 * tid + 2],
+              a3 = s_bin[4 * tid + 3];
+    const int own = a0 + a1 + a2 + a3;
+    s_part[tid] = own;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {  // inclusive Hillis-Steele scan
+        const int v = tid >= o ? s_part[tid - o] : 0;
+        __syncthreads();
+        s_part[tid] += v;
+        __syncthreads();
+    }
+    const int b = s_part[tid] - own;
+    s_bin[4 * tid] = b;
+    s_bin[4 * tid + 1] = b + a0;
+    s_bin[4 * tid + 2] = b + a0 + a1;
+    s_bin[4 * tid + 3] = b + a0 + a1 + a2;
+    __syncthreads();
+    for (int j = tid; j < nc; j += 1024) order[atomicAdd(&s_bin[key[j] >> shift], 1)] = j;
 }
 
 // Starting centres c0 = x[S[a]], c1 = x[S[b]] of every node; one wave each.
@@ -158,12 +197,12 @@ __global__ __launch_bounds__(256) void k_assign(
     double* __restrict__ C, int32_t* __restrict__ status, int32_t* __restrict__ n0f,
     uint8_t* __restrict__ labels, double* __restrict__ dots, double* __restrict__ P,
     int32_t* __restrict__ cnt, int pass, int max_iter, unsigned long long* __restrict__ assigned,
-    int32_t* __restrict__ rep, int min_leaf) {
+    int32_t* __restrict__ rep, int min_leaf, const int32_t* __restrict__ order, int xcd_per) {
     using RV = RowVec<TX, VEC>;
     using Acc = typename RV::Acc;
     constexpr int RPW = kWave / G;  // rows per wave step
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (wave >= nc) return;
+    const int wave = dispatch_chunk(order, xcd_per, blockIdx.x, threadIdx.x >> 6, 4, nc);
+    if (wave < 0) return;
     const int node = chunk_node[wave];
     if (status[node]) return;
     const NodeRec r = nodes[node];
@@ -365,7 +404,7 @@ __global__ __launch_bounds__(256) void k_assign_u8(
     double* __restrict__ C, int32_t* __restrict__ status, int32_t* __restrict__ n0f,
     uint8_t* __restrict__ labels, double* __restrict__ dots, double* __restrict__ P,
     int32_t* __restrict__ cnt, int pass, int max_iter, unsigned long long* __restrict__ assigned,
-    int32_t* __restrict__ rep, int min_leaf) {
+    int32_t* __restrict__ rep, int min_leaf, const int32_t* __restrict__ order, int xcd_per) {
     using V = typename std::conditional<EPL == 16, uint4, uint2>::type;
     constexpr int kWords = EPL / 4;
     constexpr int RPW = kWave / G;  // rows per wave step
@@ -373,8 +412,8 @@ __global__ __launch_bounds__(256) void k_assign_u8(
     __shared__ int32_t s_ids[4][kChunkRows];
     __shared__ uint8_t s_old[4][kChunkRows];
 
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (wave >= nc) return;
+    const int wave = dispatch_chunk(order, xcd_per, blockIdx.x, threadIdx.x >> 6, 4, nc);
+    if (wave < 0) return;
     const int node = chunk_node[wave];
     if (status[node]) return;
     const NodeRec r = nodes[node];
@@ -1228,6 +1267,13 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     NodeRec* sub = nullptr;
     NodeRec* nodes[2] = {nullptr, nullptr};
     int32_t* big[2] = {nullptr, nullptr};
+    // dispatch order of the assignment chunks: bit 0 sorted by first row id
+    // (default: 2-4% faster passes, chunks that gather nearby rows run
+    // together), bit 1 XCD-aware workgroup placement (slower on MI355X)
+    const int order_mode = env_int("KNNG_CHUNK_ORDER", 1);
+    int key_shift = 0;
+    while (((n - 1) >> key_shift) >= 4096) ++key_shift;
+    int32_t *chunk_key = nullptr, *corder = nullptr;
     int32_t *chunk_node = nullptr, *rep = nullptr, *status = nullptr, *n0f = nullptr, *cnt = nullptr,
             *perm_tmp = nullptr, *overflow = nullptr;
     double *C = nullptr, *P = nullptr, *dots = nullptr;
@@ -1256,6 +1302,10 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&big[1]), sizeof(int32_t) * nmax, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&sub), sizeof(NodeRec) * nmax, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&chunk_node), sizeof(int32_t) * cmax, s));
+    if (order_mode & 1) {
+        KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&chunk_key), sizeof(int32_t) * cmax, s));
+        KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&corder), sizeof(int32_t) * cmax, s));
+    }
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&rep), sizeof(int32_t) * (nmax + 1), s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&status), sizeof(int32_t) * nmax, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&n0f), sizeof(int32_t) * nmax, s));
@@ -1296,24 +1346,35 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
         const int cblocks = (nc + 3) / 4;
         // chunks of the multi-chunk nodes: nc less one per single-chunk node
         const bool few_chunks = nb > 0 && (nc - (na - nb)) <= 8 * nb;
-        k_chunk_map<<<na, 64, 0, s>>>(nodes[cur], chunk_node, rep);
+        k_chunk_map<<<na, 64, 0, s>>>(nodes[cur], a.perm, n, chunk_node,
+                                      (order_mode & 1) ? chunk_key : nullptr, rep);
         KNNG_LAUNCH();
+        if (order_mode & 1) {
+            k_chunk_order<<<1, 1024, 0, s>>>(chunk_key, nc, key_shift, corder);
+            KNNG_LAUNCH();
+        }
+        const int32_t* ord = (order_mode & 1) ? corder : nullptr;
+        // workgroups of the one-chunk-per-workgroup and four-chunk kernels
+        const bool wide = use_u8 && assign8w[0] != nullptr && nc <= wide_max;
+        const int nwg = wide ? nc : cblocks;
+        const int xper = (order_mode & 2) ? (nwg + 7) / 8 : 0;
+        const unsigned agrid = static_cast<unsigned>(xper > 0 ? 8 * xper : nwg);
         k_init_nodes<<<na, 64, 0, s>>>(nodes[cur], a.perm, a.X, n, D, a.seed, a.tree0, C, status);
         KNNG_LAUNCH();
         for (int pass = 0; pass < a.max_iter; ++pass) {
             if (a.timer) a.timer->begin(kKAssign, s);
-            if (use_u8 && assign8w[0] != nullptr && nc <= wide_max)
-                assign8w[pass == 0 ? 0 : 1]<<<nc, 256, 0, s>>>(
+            if (wide)
+                assign8w[pass == 0 ? 0 : 1]<<<agrid, 256, 0, s>>>(
                     a.X8, n, D, a.perm, nodes[cur], chunk_node, nc, C, status, n0f, labels, dots,
-                    P, cnt, pass, a.max_iter, dstats, rep, a.min_leaf);
+                    P, cnt, pass, a.max_iter, dstats, rep, a.min_leaf, ord, xper);
             else if (use_u8)
-                assign8[pass == 0 ? 0 : 1]<<<cblocks, 256, 0, s>>>(
+                assign8[pass == 0 ? 0 : 1]<<<agrid, 256, 0, s>>>(
                     a.X8, n, D, a.perm, nodes[cur], chunk_node, nc, C, status, n0f, labels, dots,
-                    P, cnt, pass, a.max_iter, dstats, rep, a.min_leaf);
+                    P, cnt, pass, a.max_iter, dstats, rep, a.min_leaf, ord, xper);
             else
-                assign<<<cblocks, 256, 0, s>>>(a.X, n, D, a.perm, nodes[cur], chunk_node, nc, C,
-                                               status, n0f, labels, dots, P, cnt, pass,
-                                               a.max_iter, dstats, rep, a.min_leaf);
+                assign<<<agrid, 256, 0, s>>>(a.X, n, D, a.perm, nodes[cur], chunk_node, nc, C,
+                                             status, n0f, labels, dots, P, cnt, pass, a.max_iter,
+                                             dstats, rep, a.min_leaf, ord, xper);
             if (a.timer) a.timer->end(kKAssign, s);
             KNNG_LAUNCH();
             if (nb > 0) {
@@ -1407,6 +1468,8 @@ done:
     if (big[1]) hipFreeAsync(big[1], s);
     if (sub) hipFreeAsync(sub, s);
     if (chunk_node) hipFreeAsync(chunk_node, s);
+    if (chunk_key) hipFreeAsync(chunk_key, s);
+    if (corder) hipFreeAsync(corder, s);
     if (rep) hipFreeAsync(rep, s);
     if (status) hipFreeAsync(status, s);
     if (n0f) hipFreeAsync(n0f, s);

@@ -11,6 +11,20 @@ namespace pdev {
 // Chunks of kChunkRows rows (one wavefront each) of a node of `size` rows.
 __device__ __forceinline__ int chunks_of(int size) { return (size + kChunkRows - 1) / kChunkRows; }
 
+// Chunk index taken by chunk slot cs (0 .. per_block-1) of workgroup b, or -1.
+// order (nullable): chunk indices sorted by the smallest row id of the
+// chunk, so that chunks that gather nearby rows run together.  xcd_per > 0:
+// workgroup b (placed by the hardware on XCD b mod 8) takes the positions
+// from XCD (b mod 8)'s contiguous share of xcd_per workgroups, so that
+// those chunks also share one L2.
+__device__ __forceinline__ int dispatch_chunk(const int32_t* order, int xcd_per, int b, int cs,
+                                              int per_block, int nc) {
+    const int bp = xcd_per > 0 ? (b & 7) * xcd_per + (b >> 3) : b;
+    const int pos = bp * per_block + cs;
+    if (pos >= nc) return -1;
+    return order != nullptr ? order[pos] : pos;
+}
+
 // ------------------------------------------------------------- random pair
 // Keyed starting pair.  SplitMix64 output function (Steele, Lea, Flood,
 // OOPSLA 2014); each key word is absorbed as one SplitMix64 step taken from

@@ -111,10 +111,13 @@ def test_level_assignment_kernels_match_oracle(K, orc, n, D, kind, L, ml, max_it
     X = datagen.make("c2", n=n) if kind == "c2" else datagen.random_points(n, D, n + D, kind)
     o = orc.tree(X, L, ml, max_iter, 7, 1, with_nodes=True)
     monkeypatch.setenv("KNNG_SUBTREE", "0")
-    for mfma, wide in (("1", "0"), ("1", "1000000"), ("0", "0")):
-        log("level kernels n=%d D=%d kind=%s mfma=%s wide_max=%s" % (n, D, kind, mfma, wide))
+    for mfma, wide, order in (("1", "0", "0"), ("1", "1000000", "1"), ("0", "0", "3"),
+                              ("1", "1000000", "2")):
+        log("level kernels n=%d D=%d kind=%s mfma=%s wide_max=%s order=%s" % (
+            n, D, kind, mfma, wide, order))
         monkeypatch.setenv("KNNG_ASSIGN_MFMA", mfma)
         monkeypatch.setenv("KNNG_ASSIGN_WIDE_MAX", wide)
+        monkeypatch.setenv("KNNG_CHUNK_ORDER", order)
         perm, loff, nodes = _gpu_tree(K, to_dev(X), L, ml, 7, 1, max_iter=max_iter)
         assert np.array_equal(loff, o["leaf_off"])
         assert np.array_equal(perm, o["perm"])
