@@ -67,6 +67,7 @@ struct LevelCounters {
     int32_t n_leaves;   // leaves so far
     int32_t n_log;      // bisected nodes logged so far
     int32_t n_sub;      // nodes handed to the subtree kernel so far
+    int32_t seq;        // host mirror only: level whose counts are in place
 };
 
 // Status codes (mirror include/knng.h).

@@ -428,7 +428,8 @@ __global__ __launch_bounds__(NW * 64) void k_leaf_mfma(
 //
 // EXACT (first pass exact, so d~ is the integer d32 < 2^23): the 32-bit key
 // (d << 7) | position orders by (distance, position) = (distance, id), and
-// insertion is one min and one max per slot; the list is the answer.
+// insertion is one min and one max per slot; two lanes share a row (half
+// the candidates each, then a merge of their lists); the list is the answer.
 // Otherwise the key is the 64-bit (order key of d~) << 32 | position, the
 // list is re-ranked with d32 by streaming the leaf's FP32 rows through LDS
 // in 32-dimension blocks, and the k smallest (d32, id) are kept.
@@ -526,13 +527,20 @@ __global__ __launch_bounds__(256) void k_leaf_small(
     const bool own = t < m;
     const int ce = (c < m - 1 ? c : m - 1);
     if constexpr (EXACT) {
-        // ---- thread t: the CL smallest keys of row t (sorted insertion by min/max)
+        // ---- two adjacent lanes per row (2 r, 2 r + 1): each keeps the CL
+        // smallest keys of every other candidate of row r (sorted insertion
+        // by min/max), then the pair merges its two sorted lists: bitonic
+        // half-cleaner and merge over CP = 2^ceil(log2 CL) slots.  Keys are
+        // distinct (position bits), so the first CL are the row's CL smallest.
+        static_assert(2 * MP <= 256, "two lanes per row");
+        constexpr int CP = CL <= 8 ? 8 : CL <= 16 ? 16 : 32;
+        const int r = tid >> 1, h = tid & 1;
         uint32_t L[CL];
 #pragma unroll
         for (int i = 0; i < CL; ++i) L[i] = 0xffffffffu;
-        if (own) {
-            const uint32_t* krow = lds + t * (MP + 1);
-            for (int j = 0; j < m; ++j) {
+        if (r < m) {
+            const uint32_t* krow = lds + r * (MP + 1);
+            for (int j = h; j < m; j += 2) {
                 uint32_t x = krow[j];
 #pragma unroll
                 for (int i = 0; i < CL; ++i) {
@@ -541,13 +549,34 @@ __global__ __launch_bounds__(256) void k_leaf_small(
                     x = hi;
                 }
             }
-            const size_t out = (static_cast<size_t>(lf.tree) * n + ids[t]) * k;
+        }
+        uint32_t C[CP];
+#pragma unroll
+        for (int i = 0; i < CP; ++i) {
+            const int bi = CP - 1 - i;  // the partner's list, reversed
+            const uint32_t b = bi < CL ? static_cast<uint32_t>(__builtin_amdgcn_update_dpp(
+                                             0, static_cast<int>(L[bi < CL ? bi : 0]), 0xB1, 0xf,
+                                             0xf, false))
+                                       : 0xffffffffu;
+            C[i] = min(i < CL ? L[i] : 0xffffffffu, b);
+        }
+#pragma unroll
+        for (int sd = CP / 2; sd >= 1; sd >>= 1)
+#pragma unroll
+            for (int i = 0; i < CP; ++i)
+                if ((i & sd) == 0) {
+                    const uint32_t lo = min(C[i], C[i + sd]), hi = max(C[i], C[i + sd]);
+                    C[i] = lo;
+                    C[i + sd] = hi;
+                }
+        if (r < m && h == 0) {
+            const size_t out = (static_cast<size_t>(lf.tree) * n + ids[r]) * k;
 #pragma unroll
             for (int e = 0; e < CL; ++e)
                 if (e < k) {
                     const bool ok = e < ce;
-                    cand_ids[out + e] = ok ? ids[L[e] & 127u] : -1;
-                    cand_d[out + e] = ok ? static_cast<float>(L[e] >> 7) : __int_as_float(0x7f800000);
+                    cand_ids[out + e] = ok ? ids[C[e] & 127u] : -1;
+                    cand_d[out + e] = ok ? static_cast<float>(C[e] >> 7) : __int_as_float(0x7f800000);
                 }
         }
         return;

@@ -1,7 +1,8 @@
 // Union of the rounds' candidate lists into G (Alg. 1: the rows of G are
 // refined round after round; a pair already compared is not counted twice).
 //
-// One wavefront per row: the row's candidates from every tree are ordered by
+// k <= 32: one thread per row (k_merge_rows).  Otherwise (or with
+// KNNG_MERGE_NETWORK set) one wavefront per row: the row's candidates from every tree are ordered by
 // (d32, id) with a bitonic network (a merge of the trees' sorted lists when
 // k <= 32, else a full sort), adjacent equal keys are dropped (the same id
 // always carries the same d32 bits, so duplicates are adjacent), and the
@@ -11,6 +12,7 @@
 #include "wave.hpp"
 
 #include <cstdio>
+#include <cstdlib>
 
 namespace knng {
 namespace {
@@ -139,8 +141,80 @@ __global__ __launch_bounds__(256) void k_merge_runs(int64_t n, int k, int t0, in
     }
 }
 
+// k <= 32, one thread per row: the row's best K (k rounded up to 4) distinct
+// keys in registers, sorted.  The first tree's list is taken as it is (sorted,
+// distinct ids); every later list is read in order until its key reaches the
+// current K-th best (the rest of that list is larger), and each key not yet
+// held is inserted with a compare-exchange network (slot i takes
+// min(old[i], max(old[i-1], key))).  Same result as the bitonic merge: the
+// first k of the sorted distinct union.
+template <int K>
+__global__ __launch_bounds__(256) void k_merge_rows(int64_t n, int k, int T,
+                                                    const int32_t* __restrict__ cid,
+                                                    const float* __restrict__ cd,
+                                                    int32_t* __restrict__ oid,
+                                                    float* __restrict__ od) {
+    const int64_t row = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (row >= n) return;
+    uint64_t top[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) top[i] = kNoKey;
+    {
+        const size_t src = static_cast<size_t>(row) * k;
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if (i < k) {
+                const int32_t id = cid[src + i];
+                if (id >= 0) top[i] = cand_key(cd[src + i], id);
+            }
+    }
+    for (int t = 1; t < T; ++t) {
+        const size_t src = (static_cast<size_t>(t) * n + row) * k;
+        for (int j = 0; j < k; ++j) {
+            const int32_t id = cid[src + j];
+            if (id < 0) break;  // padding: the rest of the list is empty
+            const uint64_t key = cand_key(cd[src + j], id);
+            if (key >= top[K - 1]) break;  // the rest of this list is larger
+            bool dup = false;
+#pragma unroll
+            for (int i = 0; i < K; ++i) dup |= top[i] == key;
+            if (dup) continue;
+            uint64_t prev = 0ull;
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                const uint64_t cur = top[i];
+                const uint64_t hi = prev > key ? prev : key;
+                top[i] = cur < hi ? cur : hi;
+                prev = cur;
+            }
+        }
+    }
+    const size_t dst = static_cast<size_t>(row) * k;
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        if (i < k) {
+            const bool ok = top[i] != kNoKey;
+            oid[dst + i] = ok ? key_id(top[i]) : -1;
+            od[dst + i] = ok ? key_dist(top[i]) : __int_as_float(0x7f800000);
+        }
+}
+
 using MergeFn = void (*)(int64_t, int, int, int, const int32_t*, const float*, int32_t*, float*,
                          int);
+using RowMergeFn = void (*)(int64_t, int, int, const int32_t*, const float*, int32_t*, float*);
+
+RowMergeFn pick_rows(int k) {
+    switch ((k + 3) / 4) {
+        case 1: return k_merge_rows<4>;
+        case 2: return k_merge_rows<8>;
+        case 3: return k_merge_rows<12>;
+        case 4: return k_merge_rows<16>;
+        case 5: return k_merge_rows<20>;
+        case 6: return k_merge_rows<24>;
+        case 7: return k_merge_rows<28>;
+        default: return k_merge_rows<32>;
+    }
+}
 
 MergeFn pick_runs(int lists) {
     if (lists <= 2) return k_merge_runs<1>;
@@ -162,6 +236,20 @@ MergeFn pick(int slots) {
 
 int merge_run(const MergeArgs& a, int* launches, char* err, size_t errlen) {
     const int k = a.k;
+    if (k <= 32 && std::getenv("KNNG_MERGE_NETWORK") == nullptr) {
+        const RowMergeFn f = pick_rows(k);
+        if (a.timer) a.timer->begin(kKMerge, a.stream);
+        f<<<static_cast<unsigned>((a.n + 255) / 256), 256, 0, a.stream>>>(
+            a.n, k, a.n_trees, a.cand_ids, a.cand_d, a.ids_out, a.dists_out);
+        if (a.timer) a.timer->end(kKMerge, a.stream);
+        ++*launches;
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            std::snprintf(err, errlen, "merge launch failed: %s", hipGetErrorString(e));
+            return kHip;
+        }
+        return kOk;
+    }
     const int64_t blocks = (a.n + 3) / 4;
     constexpr int kMaxSlots = 1024;
     int t = 0;

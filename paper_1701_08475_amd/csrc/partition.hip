@@ -983,7 +983,9 @@ __global__ __launch_bounds__(1024) void k_next_level(
     int small_max, int depth, NodeRec* __restrict__ next, int32_t* __restrict__ big,
     NodeRec* __restrict__ sub, LeafRec* __restrict__ leaves, int64_t leaves_cap,
     int32_t* __restrict__ node_log, int64_t node_log_cap, LevelCounters* __restrict__ ctr,
-    int* __restrict__ overflow) {
+    int* __restrict__ overflow, LevelCounters* __restrict__ mirror, int seq) {
+    // leaves and log entries are reserved with one atomic each: subtree
+    // kernels on another stream append to the same lists meanwhile
     __shared__ int s_int[1024], s_leaf[1024], s_ch[1024], s_big[1024], s_sub[1024];
     __shared__ int s_base_leaf, s_base_log, s_base_sub;
     const int tid = threadIdx.x;
@@ -1011,11 +1013,7 @@ __global__ __launch_bounds__(1024) void k_next_level(
     s_ch[tid] = cc;
     s_big[tid] = cb;
     s_sub[tid] = cs;
-    if (tid == 0) {
-        s_base_leaf = ctr->n_leaves;
-        s_base_log = ctr->n_log;
-        s_base_sub = ctr->n_sub;
-    }
+    if (tid == 0) s_base_sub = ctr->n_sub;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {  // inclusive Hillis-Steele scans
         int a = 0, b = 0, c = 0, e = 0, f = 0;
@@ -1034,6 +1032,11 @@ __global__ __launch_bounds__(1024) void k_next_level(
         s_sub[tid] += f;
         __syncthreads();
     }
+    if (tid == 1023) {
+        s_base_leaf = atomicAdd(&ctr->n_leaves, s_leaf[1023]);
+        s_base_log = atomicAdd(&ctr->n_log, n_cur);
+    }
+    __syncthreads();
     int oi = s_int[tid] - ci, ol = s_base_leaf + s_leaf[tid] - cl, oc = s_ch[tid] - cc,
         ob = s_big[tid] - cb, os = s_base_sub + s_sub[tid] - cs;
     for (int i = i0; i < i1; ++i) {
@@ -1072,9 +1075,17 @@ __global__ __launch_bounds__(1024) void k_next_level(
         ctr->n_next = s_int[1023];
         ctr->nc_next = s_ch[1023];
         ctr->n_big = s_big[1023];
-        ctr->n_leaves = s_base_leaf + s_leaf[1023];
-        ctr->n_log = s_base_log + n_cur;
         ctr->n_sub = s_base_sub + s_sub[1023];
+        if (mirror != nullptr) {
+            // the next level's sizes into mapped host memory, then the level
+            // number: the host polls it instead of copying and synchronising
+            mirror->n_next = s_int[1023];
+            mirror->nc_next = s_ch[1023];
+            mirror->n_big = s_big[1023];
+            mirror->n_sub = s_base_sub + s_sub[1023];
+            __threadfence_system();
+            *reinterpret_cast<volatile int32_t*>(&mirror->seq) = seq;
+        }
     }
 }
 
@@ -1173,6 +1184,25 @@ bool pick_assign_u8(int D, int u, int pd, AssignFn<uint8_t>* f, RepairFn* rep) {
             break;
     }
     return f[0] != nullptr;
+}
+
+// Waits until the level kernel has written the counts of level `seq` into
+// the mapped host mirror; fails if the stream reports an error or goes idle
+// without them.
+int wait_mirror(LevelCounters* m, int seq, hipStream_t s) {
+    for (long spin = 1;; ++spin) {
+        if (__atomic_load_n(&m->seq, __ATOMIC_ACQUIRE) == seq) return kOk;
+        if ((spin & 4095) == 0) {
+            const hipError_t q = hipStreamQuery(s);
+            if (q == hipSuccess) {
+                // the kernel has finished: its system-scope stores land shortly
+                for (long t = 0; t < (1l << 22); ++t)
+                    if (__atomic_load_n(&m->seq, __ATOMIC_ACQUIRE) == seq) return kOk;
+                return kHip;
+            }
+            if (q != hipErrorNotReady) return kHip;
+        }
+    }
 }
 
 int env_int(const char* name, int dflt) {
@@ -1281,20 +1311,48 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     LevelCounters* ctr = nullptr;
     unsigned long long* dstats = nullptr;
     LevelCounters* hctr = nullptr;
+    LevelCounters* dmirror = nullptr;  // device address of hctr
     std::vector<unsigned long long> hstats(4 * kStatWords, 0ull);
     int hoverflow = 0;
     int cur = 0;
     int depth = 0;
     int64_t splits = 0;
+    hipStream_t s2 = nullptr;      // subtree stream (overlap with the level loop)
+    hipEvent_t s2_done = nullptr;
+    bool s2_used = false;
+    int sub_launched = 0;
 
+    if (use_u8 && sub_mode != 0 && small_max > L && env_int("KNNG_SUBTREE_OVERLAP", 1) != 0) {
+        // second stream (default priority) and event for the subtree
+        // kernels, one per host thread and device for the life of the process
+        thread_local hipStream_t t_s2[64] = {};
+        thread_local hipEvent_t t_ev[64] = {};
+        int dev = 0;
+        KNNG_HIP(hipGetDevice(&dev));
+        if (dev >= 0 && dev < 64) {
+            if (t_s2[dev] == nullptr)
+                KNNG_HIP(hipStreamCreateWithFlags(&t_s2[dev], hipStreamNonBlocking));
+            if (t_ev[dev] == nullptr)
+                KNNG_HIP(hipEventCreateWithFlags(&t_ev[dev], hipEventDisableTiming));
+            s2 = t_s2[dev];
+            s2_done = t_ev[dev];
+        }
+    }
     {
         // pinned counter mirror, one per host thread for the life of the
         // process (freeing pinned memory would synchronise the device)
+        // (mapped, coherent: the level kernel writes the next level's sizes
+        // into it directly)
         thread_local LevelCounters* t_hctr = nullptr;
-        if (t_hctr == nullptr)
+        thread_local LevelCounters* t_dctr = nullptr;
+        if (t_hctr == nullptr) {
             KNNG_HIP(hipHostMalloc(reinterpret_cast<void**>(&t_hctr), sizeof(LevelCounters),
-                                   hipHostMallocDefault));
+                                   hipHostMallocMapped | hipHostMallocPortable |
+                                       hipHostMallocCoherent));
+            KNNG_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&t_dctr), t_hctr, 0));
+        }
         hctr = t_hctr;
+        dmirror = t_dctr;
     }
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&nodes[0]), sizeof(NodeRec) * nmax, s));
     KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&nodes[1]), sizeof(NodeRec) * nmax, s));
@@ -1331,8 +1389,15 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     }
     k_roots<<<1, 64, 0, s>>>(T, n, L, small_max, nodes[0], big[0], sub, a.leaves, ctr);
     KNNG_LAUNCH();
-    KNNG_HIP(hipMemcpyAsync(hctr, ctr, sizeof(LevelCounters), hipMemcpyDeviceToHost, s));
-    KNNG_HIP(hipStreamSynchronize(s));
+    {  // the roots' counts, as k_roots sets them
+        const int nch0 = static_cast<int>((n + kChunkRows - 1) / kChunkRows);
+        const bool rsplit = n > L, rsmall = rsplit && n <= small_max, rlevel = rsplit && !rsmall;
+        hctr->n_next = rlevel ? T : 0;
+        hctr->nc_next = rlevel ? T * nch0 : 0;
+        hctr->n_big = (rlevel && nch0 > 1) ? T : 0;
+        hctr->n_sub = rsmall ? T : 0;
+        __atomic_store_n(&hctr->seq, -1, __ATOMIC_RELEASE);
+    }
 
     while (hctr->n_next > 0) {
         if (depth > n) {  // every split shrinks both sides, so depth < n
@@ -1399,26 +1464,51 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
         KNNG_LAUNCH();
         k_next_level<<<1, 1024, 0, s>>>(nodes[cur], na, n0f, L, small_max, depth, nodes[cur ^ 1],
                                         big[cur ^ 1], sub, a.leaves, a.leaves_cap, a.node_log,
-                                        a.node_log_cap, ctr, overflow);
+                                        a.node_log_cap, ctr, overflow, dmirror, depth);
         KNNG_LAUNCH();
-        KNNG_HIP(hipMemcpyAsync(hctr, ctr, sizeof(LevelCounters), hipMemcpyDeviceToHost, s));
-        KNNG_HIP(hipStreamSynchronize(s));
+        if (wait_mirror(hctr, depth, s) != kOk) {
+            std::snprintf(err, errlen, "level %d: counters not received", depth);
+            rc = kHip;
+            goto done;
+        }
         splits += na;
         cur ^= 1;
         ++depth;
+        if (s2 != nullptr && hctr->n_sub > sub_launched) {
+            // this level's new subtree roots run on the second stream while
+            // the level loop goes on (disjoint perm ranges; shared lists are
+            // appended with atomics)
+            SubtreeArgs sa{a.X8, n, D, sub + sub_launched, hctr->n_sub - sub_launched, a.perm, L,
+                           a.min_leaf, a.max_iter, a.seed, a.tree0, a.leaves, a.leaves_cap,
+                           a.node_log, a.node_log_cap, ctr, dstats, overflow, row_budget, s2};
+            s2_used = true;
+            if (subtree_launch(sa) != kOk) {
+                std::snprintf(err, errlen, "subtree kernel launch failed");
+                rc = kHip;
+                goto done;
+            }
+            ++launches;
+            sub_launched = hctr->n_sub;
+        }
     }
-    if (hctr->n_sub > 0) {
-        SubtreeArgs sa{a.X8, n, D, sub, hctr->n_sub, a.perm, L, a.min_leaf, a.max_iter, a.seed,
-                       a.tree0, a.leaves, a.leaves_cap, a.node_log, a.node_log_cap, ctr, dstats,
-                       overflow, row_budget, s};
+    if (hctr->n_sub > sub_launched) {
+        SubtreeArgs sa{a.X8, n, D, sub + sub_launched, hctr->n_sub - sub_launched, a.perm, L,
+                       a.min_leaf, a.max_iter, a.seed, a.tree0, a.leaves, a.leaves_cap, a.node_log,
+                       a.node_log_cap, ctr, dstats, overflow, row_budget, s};
         if (subtree_launch(sa) != kOk) {
             std::snprintf(err, errlen, "subtree kernel launch failed");
             rc = kHip;
             goto done;
         }
         ++launches;
-        KNNG_HIP(hipMemcpyAsync(hctr, ctr, sizeof(LevelCounters), hipMemcpyDeviceToHost, s));
+        sub_launched = hctr->n_sub;
     }
+    if (s2_used) {  // the build stream waits for the subtree stream
+        KNNG_HIP(hipEventRecord(s2_done, s2));
+        KNNG_HIP(hipStreamWaitEvent(s, s2_done, 0));
+        s2_used = false;
+    }
+    KNNG_HIP(hipMemcpyAsync(hctr, ctr, sizeof(LevelCounters), hipMemcpyDeviceToHost, s));
     KNNG_HIP(hipMemcpyAsync(hstats.data(), dstats, sizeof(unsigned long long) * hstats.size(),
                             hipMemcpyDeviceToHost, s));
     KNNG_HIP(hipMemcpyAsync(&hoverflow, overflow, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1462,6 +1552,10 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     }
 
 done:
+    if (s2_used) {  // error path: the frees below must follow the subtree kernels
+        hipEventRecord(s2_done, s2);
+        hipStreamWaitEvent(s, s2_done, 0);
+    }
     if (nodes[0]) hipFreeAsync(nodes[0], s);
     if (nodes[1]) hipFreeAsync(nodes[1], s);
     if (big[0]) hipFreeAsync(big[0], s);

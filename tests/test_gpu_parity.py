@@ -86,8 +86,10 @@ def test_subtree_kernel_matches_oracle(K, orc, n, D, kind, L, ml, max_iter, monk
     X = datagen.make("c2", n=n) if kind == "c2" else datagen.random_points(n, D, n + D, kind)
     log("subtree n=%d D=%d kind=%s L=%d" % (n, D, kind, L))
     o = orc.tree(X, L, ml, max_iter, 4, 2, with_nodes=True)
-    for sub in ("1", "2", "3", "0"):
+    for sub, overlap in (("1", "1"), ("2", "0"), ("3", "1"), ("3", "0"), ("0", "1")):
+        # overlap: subtree kernels on a second stream while the levels go on
         monkeypatch.setenv("KNNG_SUBTREE", sub)
+        monkeypatch.setenv("KNNG_SUBTREE_OVERLAP", overlap)
         perm, loff, nodes = _gpu_tree(K, to_dev(X), L, ml, 4, 2, max_iter=max_iter)
         assert np.array_equal(loff, o["leaf_off"])
         assert np.array_equal(perm, o["perm"])
