@@ -148,7 +148,7 @@ __global__ __launch_bounds__(256) void k_merge_runs(int64_t n, int k, int t0, in
 // held is inserted with a compare-exchange network (slot i takes
 // min(old[i], max(old[i-1], key))).  Same result as the bitonic merge: the
 // first k of the sorted distinct union.
-template <int K>
+template <int K, bool VEC>
 __global__ __launch_bounds__(256) void k_merge_rows(int64_t n, int k, int T,
                                                     const int32_t* __restrict__ cid,
                                                     const float* __restrict__ cd,
@@ -168,24 +168,49 @@ __global__ __launch_bounds__(256) void k_merge_rows(int64_t n, int k, int T,
                 if (id >= 0) top[i] = cand_key(cd[src + i], id);
             }
     }
+    auto insert = [&](uint64_t key) {
+        bool dup = false;
+#pragma unroll
+        for (int i = 0; i < K; ++i) dup |= top[i] == key;
+        if (dup) return;
+        uint64_t prev = 0ull;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const uint64_t cur = top[i];
+            const uint64_t hi = prev > key ? prev : key;
+            top[i] = cur < hi ? cur : hi;
+            prev = cur;
+        }
+    };
     for (int t = 1; t < T; ++t) {
         const size_t src = (static_cast<size_t>(t) * n + row) * k;
-        for (int j = 0; j < k; ++j) {
-            const int32_t id = cid[src + j];
-            if (id < 0) break;  // padding: the rest of the list is empty
-            const uint64_t key = cand_key(cd[src + j], id);
-            if (key >= top[K - 1]) break;  // the rest of this list is larger
-            bool dup = false;
+        if (VEC) {
+            // four entries per 16-byte load, loaded ahead of the tests
+            for (int j0 = 0; j0 < k; j0 += 4) {
+                const int4 i4 = *reinterpret_cast<const int4*>(cid + src + j0);
+                const float4 d4 = *reinterpret_cast<const float4*>(cd + src + j0);
+                const int32_t iv[4] = {i4.x, i4.y, i4.z, i4.w};
+                const float dv[4] = {d4.x, d4.y, d4.z, d4.w};
+                bool more = true;
 #pragma unroll
-            for (int i = 0; i < K; ++i) dup |= top[i] == key;
-            if (dup) continue;
-            uint64_t prev = 0ull;
-#pragma unroll
-            for (int i = 0; i < K; ++i) {
-                const uint64_t cur = top[i];
-                const uint64_t hi = prev > key ? prev : key;
-                top[i] = cur < hi ? cur : hi;
-                prev = cur;
+                for (int q = 0; q < 4; ++q) {
+                    if (more && iv[q] >= 0) {
+                        const uint64_t key = cand_key(dv[q], iv[q]);
+                        if (key < top[K - 1]) insert(key);
+                        else more = false;  // the rest of this list is larger
+                    } else {
+                        more = false;  // padding: the rest of the list is empty
+                    }
+                }
+                if (!more) break;
+            }
+        } else {
+            for (int j = 0; j < k; ++j) {
+                const int32_t id = cid[src + j];
+                if (id < 0) break;  // padding: the rest of the list is empty
+                const uint64_t key = cand_key(cd[src + j], id);
+                if (key >= top[K - 1]) break;  // the rest of this list is larger
+                insert(key);
             }
         }
     }
@@ -203,17 +228,26 @@ using MergeFn = void (*)(int64_t, int, int, int, const int32_t*, const float*, i
                          int);
 using RowMergeFn = void (*)(int64_t, int, int, const int32_t*, const float*, int32_t*, float*);
 
-RowMergeFn pick_rows(int k) {
+template <bool VEC>
+RowMergeFn pick_rows_vec(int k) {
     switch ((k + 3) / 4) {
-        case 1: return k_merge_rows<4>;
-        case 2: return k_merge_rows<8>;
-        case 3: return k_merge_rows<12>;
-        case 4: return k_merge_rows<16>;
-        case 5: return k_merge_rows<20>;
-        case 6: return k_merge_rows<24>;
-        case 7: return k_merge_rows<28>;
-        default: return k_merge_rows<32>;
+        case 1: return k_merge_rows<4, VEC>;
+        case 2: return k_merge_rows<8, VEC>;
+        case 3: return k_merge_rows<12, VEC>;
+        case 4: return k_merge_rows<16, VEC>;
+        case 5: return k_merge_rows<20, VEC>;
+        case 6: return k_merge_rows<24, VEC>;
+        case 7: return k_merge_rows<28, VEC>;
+        default: return k_merge_rows<32, VEC>;
     }
+}
+
+// 16-byte loads when every list starts 16-byte aligned (k % 4 == 0; the
+// candidate buffers come from hipMallocAsync, 256-byte aligned)
+RowMergeFn pick_rows(int k, const void* ids, const void* d) {
+    const bool vec = k % 4 == 0 && (reinterpret_cast<uintptr_t>(ids) & 15) == 0 &&
+                     (reinterpret_cast<uintptr_t>(d) & 15) == 0;
+    return vec ? pick_rows_vec<true>(k) : pick_rows_vec<false>(k);
 }
 
 MergeFn pick_runs(int lists) {
@@ -237,7 +271,7 @@ MergeFn pick(int slots) {
 int merge_run(const MergeArgs& a, int* launches, char* err, size_t errlen) {
     const int k = a.k;
     if (k <= 32 && std::getenv("KNNG_MERGE_NETWORK") == nullptr) {
-        const RowMergeFn f = pick_rows(k);
+        const RowMergeFn f = pick_rows(k, a.cand_ids, a.cand_d);
         if (a.timer) a.timer->begin(kKMerge, a.stream);
         f<<<static_cast<unsigned>((a.n + 255) / 256), 256, 0, a.stream>>>(
             a.n, k, a.n_trees, a.cand_ids, a.cand_d, a.ids_out, a.dists_out);

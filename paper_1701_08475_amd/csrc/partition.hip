@@ -1301,6 +1301,7 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     // (default: 2-4% faster passes, chunks that gather nearby rows run
     // together), bit 1 XCD-aware workgroup placement (slower on MI355X)
     const int order_mode = env_int("KNNG_CHUNK_ORDER", 1);
+    const int order_min = env_int("KNNG_CHUNK_ORDER_MIN", 4096);  // chunks per level
     int key_shift = 0;
     while (((n - 1) >> key_shift) >= 4096) ++key_shift;
     int32_t *chunk_key = nullptr, *corder = nullptr;
@@ -1411,14 +1412,16 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
         const int cblocks = (nc + 3) / 4;
         // chunks of the multi-chunk nodes: nc less one per single-chunk node
         const bool few_chunks = nb > 0 && (nc - (na - nb)) <= 8 * nb;
+        // the order pays off on levels with many chunks only
+        const bool sorted = (order_mode & 1) && nc >= order_min;
         k_chunk_map<<<na, 64, 0, s>>>(nodes[cur], a.perm, n, chunk_node,
-                                      (order_mode & 1) ? chunk_key : nullptr, rep);
+                                      sorted ? chunk_key : nullptr, rep);
         KNNG_LAUNCH();
-        if (order_mode & 1) {
+        if (sorted) {
             k_chunk_order<<<1, 1024, 0, s>>>(chunk_key, nc, key_shift, corder);
             KNNG_LAUNCH();
         }
-        const int32_t* ord = (order_mode & 1) ? corder : nullptr;
+        const int32_t* ord = sorted ? corder : nullptr;
         // workgroups of the one-chunk-per-workgroup and four-chunk kernels
         const bool wide = use_u8 && assign8w[0] != nullptr && nc <= wide_max;
         const int nwg = wide ? nc : cblocks;

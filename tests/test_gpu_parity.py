@@ -120,6 +120,7 @@ def test_level_assignment_kernels_match_oracle(K, orc, n, D, kind, L, ml, max_it
         monkeypatch.setenv("KNNG_ASSIGN_MFMA", mfma)
         monkeypatch.setenv("KNNG_ASSIGN_WIDE_MAX", wide)
         monkeypatch.setenv("KNNG_CHUNK_ORDER", order)
+        monkeypatch.setenv("KNNG_CHUNK_ORDER_MIN", "0")  # small cases: order every level
         perm, loff, nodes = _gpu_tree(K, to_dev(X), L, ml, 7, 1, max_iter=max_iter)
         assert np.array_equal(loff, o["leaf_off"])
         assert np.array_equal(perm, o["perm"])
