@@ -1319,11 +1319,16 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     int depth = 0;
     int64_t splits = 0;
     hipStream_t s2 = nullptr;      // subtree stream (overlap with the level loop)
+    // levels of at most this many chunks run beside the subtree kernels
+    const int overlap_nc = env_int("KNNG_SUBTREE_OVERLAP_NC", 4096);
     hipEvent_t s2_done = nullptr;
     bool s2_used = false;
     int sub_launched = 0;
 
-    if (use_u8 && sub_mode != 0 && small_max > L && env_int("KNNG_SUBTREE_OVERLAP", 1) != 0) {
+    // KNNG_SUBTREE_OVERLAP=1: subtree kernels on a second stream beside the
+    // smaller levels.  Off by default: on MI355X the build is no faster
+    // (the level passes slow down by what the subtree kernels save).
+    if (use_u8 && sub_mode != 0 && small_max > L && env_int("KNNG_SUBTREE_OVERLAP", 0) != 0) {
         // second stream (default priority) and event for the subtree
         // kernels, one per host thread and device for the life of the process
         thread_local hipStream_t t_s2[64] = {};
@@ -1477,10 +1482,11 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
         splits += na;
         cur ^= 1;
         ++depth;
-        if (s2 != nullptr && hctr->n_sub > sub_launched) {
-            // this level's new subtree roots run on the second stream while
-            // the level loop goes on (disjoint perm ranges; shared lists are
-            // appended with atomics)
+        if (s2 != nullptr && hctr->n_sub > sub_launched && hctr->nc_next <= overlap_nc) {
+            // the subtree roots so far run on the second stream while the
+            // level loop goes on (disjoint perm ranges; shared lists are
+            // appended with atomics), once the levels are small enough that
+            // their passes no longer fill the GPU
             SubtreeArgs sa{a.X8, n, D, sub + sub_launched, hctr->n_sub - sub_launched, a.perm, L,
                            a.min_leaf, a.max_iter, a.seed, a.tree0, a.leaves, a.leaves_cap,
                            a.node_log, a.node_log_cap, ctr, dstats, overflow, row_budget, s2};
