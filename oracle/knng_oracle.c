@@ -633,3 +633,134 @@ int orc_graph_from_leaves_reduced(const float *X, int64_t n, int D, int k, int n
     free(cnt);
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Enhanced hill-climbing search over a kNN graph (Alg. 2, E-GNNS).    */
+/*   R10 A node is visited once its distance to the query has been     */
+/*       taken (seeds included); each node enters the rank list once;  */
+/*       seed ids outside [0, n) are ignored.                          */
+/*   R11 The rank list R is ordered by ascending (d, id).  Only its k   */
+/*       best entries are kept: an entry outside them can never return, */
+/*       since the k-th distance of R never grows.                     */
+/*   R12 Each round expands every member of the top-k of R as R stood   */
+/*       at the start of the round; the new neighbours T are merged     */
+/*       after the round (R <- R u T).  A member expanded in an earlier */
+/*       round adds nothing (its neighbours are visited), and a round   */
+/*       without an unexpanded member ends the search (later rounds add */
+/*       nothing either).  Graph entries < 0 are padding.               */
+/*   R13 The output is the top-k of R, padded with (-1, +inf).  The     */
+/*       rank order is taken in d64 (dist_mode 0, R1) or in the         */
+/*       canonical FP32 d32 (dist_mode 1): per block of 32 dimensions a */
+/*       sequential fused multiply-add of (q_d - x_d)^2 from 0, blocks  */
+/*       added in increasing order in FP32 -- the GPU search's order.   */
+/* ------------------------------------------------------------------ */
+static float d32_canonical(const float *a, const float *b, int D)
+{
+    float tot = 0.0f;
+    for (int d0 = 0; d0 < D; d0 += 32) {
+        int dn = D - d0 < 32 ? D - d0 : 32;
+        float blk = 0.0f;
+        for (int dd = 0; dd < dn; ++dd) {
+            float df = a[d0 + dd] - b[d0 + dd];
+            blk = fmaf(df, df, blk);
+        }
+        tot = tot + blk;
+    }
+    return tot;
+}
+
+double orc_d32(const float *a, const float *b, int D) { return (double)d32_canonical(a, b, D); }
+
+static double query_dist(const float *q, const float *x, int D, int dist_mode)
+{
+    if (dist_mode == 1) return (double)d32_canonical(q, x, D);
+    double s = 0.0;
+    for (int d = 0; d < D; ++d) {
+        double df = (double)q[d] - (double)x[d];
+        s += df * df;
+    }
+    return s;
+}
+
+/* Insert (j, d) unexpanded into the rank list (rid, rd, rx, *rn <= k). */
+static void rank_insert(int32_t *rid, double *rd, unsigned char *rx, int *rn, int k,
+                        int32_t j, double d)
+{
+    if (*rn == k && !pair_less(d, j, rd[k - 1], rid[k - 1])) return;
+    int p = (*rn < k) ? *rn : k - 1;
+    while (p > 0 && pair_less(d, j, rd[p - 1], rid[p - 1])) {
+        rid[p] = rid[p - 1];
+        rd[p] = rd[p - 1];
+        rx[p] = rx[p - 1];
+        --p;
+    }
+    rid[p] = j;
+    rd[p] = d;
+    rx[p] = 0;
+    if (*rn < k) ++*rn;
+}
+
+/* Queries Q [nq, D], graph G [n, kg], seeds [nq, ns]; outputs [nq, k]. */
+int orc_egnns(const float *X, int64_t n, int D, const int32_t *G, int kg, const float *Q,
+              int64_t nq, const int32_t *seeds, int ns, int k, int rounds, int dist_mode,
+              int32_t *ids_out, double *d_out)
+{
+    int fail = 0;
+#pragma omp parallel
+    {
+        unsigned char *vis = (unsigned char *)calloc((size_t)n, 1);
+        int32_t *touched = (int32_t *)malloc(sizeof(int32_t) *
+                                             ((size_t)ns + (size_t)rounds * k * kg + 1));
+        int32_t *rid = (int32_t *)malloc(sizeof(int32_t) * (size_t)k);
+        double *rd = (double *)malloc(sizeof(double) * (size_t)k);
+        unsigned char *rx = (unsigned char *)malloc((size_t)k);
+        int32_t *front = (int32_t *)malloc(sizeof(int32_t) * (size_t)k);
+        int32_t *tid = (int32_t *)malloc(sizeof(int32_t) * (size_t)k * kg);
+        double *td = (double *)malloc(sizeof(double) * (size_t)k * kg);
+        if (!vis || !touched || !rid || !rd || !rx || !front || !tid || !td) {
+#pragma omp atomic write
+            fail = 1;
+        } else {
+#pragma omp for schedule(dynamic, 4)
+            for (int64_t qi = 0; qi < nq; ++qi) {
+                const float *q = Q + (size_t)qi * D;
+                int rn = 0, nt = 0;
+                for (int s = 0; s < ns; ++s) {
+                    int32_t j = seeds[(size_t)qi * ns + s];
+                    if (j < 0 || j >= n || vis[j]) continue;
+                    vis[j] = 1;
+                    touched[nt++] = j;
+                    rank_insert(rid, rd, rx, &rn, k, j, query_dist(q, X + (size_t)j * D, D, dist_mode));
+                }
+                for (int t = 0; t < rounds; ++t) {
+                    int nf = 0;
+                    for (int p = 0; p < rn; ++p)
+                        if (!rx[p]) {
+                            front[nf++] = rid[p];
+                            rx[p] = 1;
+                        }
+                    if (nf == 0) break;
+                    int nT = 0;
+                    for (int f = 0; f < nf; ++f)
+                        for (int e = 0; e < kg; ++e) {
+                            int32_t j = G[(size_t)front[f] * kg + e];
+                            if (j < 0 || j >= n || vis[j]) continue;
+                            vis[j] = 1;
+                            touched[nt++] = j;
+                            tid[nT] = j;
+                            td[nT] = query_dist(q, X + (size_t)j * D, D, dist_mode);
+                            ++nT;
+                        }
+                    for (int e = 0; e < nT; ++e) rank_insert(rid, rd, rx, &rn, k, tid[e], td[e]);
+                }
+                for (int p = 0; p < k; ++p) {
+                    ids_out[(size_t)qi * k + p] = p < rn ? rid[p] : -1;
+                    d_out[(size_t)qi * k + p] = p < rn ? rd[p] : INFINITY;
+                }
+                for (int e = 0; e < nt; ++e) vis[touched[e]] = 0;
+            }
+        }
+        free(vis); free(touched); free(rid); free(rd); free(rx); free(front); free(tid); free(td);
+    }
+    return fail ? -1 : 0;
+}

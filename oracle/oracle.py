@@ -69,6 +69,10 @@ def lib():
                                                     vp, vp]
         L.orc_graph.restype = i32
         L.orc_graph.argtypes = [vp, i64, i32, i32, i32, i32, i32, i32, u64, vp, vp, vp]
+        L.orc_d32.restype = ctypes.c_double
+        L.orc_d32.argtypes = [vp, vp, i32]
+        L.orc_egnns.restype = i32
+        L.orc_egnns.argtypes = [vp, i64, i32, vp, i32, vp, i64, vp, i32, i32, i32, i32, vp, vp]
         L.orc_num_threads.restype = i32
         L.orc_set_num_threads.restype = None
         L.orc_set_num_threads.argtypes = [i32]
@@ -283,3 +287,29 @@ def recall(X, rows, G_ids, E_ids, E_d):
             if j >= 0 and (j in ex or dG[q, p] <= kth):
                 hits += 1
     return hits / float(len(rows) * k)
+
+
+def d32(a, b):
+    """Canonical FP32 distance of two vectors (reading R13)."""
+    a, b = _f32(np.asarray(a).reshape(1, -1)), _f32(np.asarray(b).reshape(1, -1))
+    return lib().orc_d32(_p(a), _p(b), a.shape[1])
+
+
+def egnns(X, G, Q, seeds, k, rounds, dist_mode=1):
+    """Alg. 2 (E-GNNS, readings R10-R13) for every query row of Q.
+
+    G: [n, kg] int32 graph (-1 padding); seeds: [nq, ns] int32.
+    Returns (ids int32 [nq, k], dists float64 [nq, k])."""
+    X, Q = _f32(X), _f32(Q)
+    G = np.ascontiguousarray(G, dtype=np.int32)
+    S = np.ascontiguousarray(seeds, dtype=np.int32)
+    n, D = X.shape
+    nq = Q.shape[0]
+    assert Q.shape[1] == D and G.shape[0] == n and S.shape[0] == nq
+    ids = np.empty((nq, k), np.int32)
+    ds = np.empty((nq, k), np.float64)
+    rc = lib().orc_egnns(_p(X), n, D, _p(G), G.shape[1], _p(Q), nq, _p(S), S.shape[1], k,
+                         rounds, dist_mode, _p(ids), _p(ds))
+    if rc != 0:
+        raise MemoryError("orc_egnns")
+    return ids, ds
