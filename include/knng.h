@@ -173,6 +173,33 @@ int knng_leaf_search(const float* data, int64_t n, int32_t D, int32_t k, int32_t
                      const int32_t* n_leaves, const knng_options* opt,
                      int32_t* ids_out, float* dists_out, hipStream_t stream);
 
+/*
+ * knng_search -- enhanced hill-climbing nearest-neighbour search over a kNN
+ * graph (Alg. 2, E-GNNS), one call for a batch of queries.  For each query
+ * q, the rank list R starts from the seeds; each of `rounds` rounds takes
+ * every member of the k best of R not expanded before, visits its graph
+ * neighbours not visited before (distance to q), and merges them into R
+ * after the round.  A round with nothing to expand ends that query's search.
+ *   data       device, float[n][D]: the reference set (16-byte aligned)
+ *   graph      device, int32[n][kg]: neighbour ids per point (e.g. the output
+ *              of knng_build); entries < 0 or >= n are skipped
+ *   queries    device, float[nq][D] (16-byte aligned)
+ *   seeds      device, int32[nq][ns]: starting points per query (for example
+ *              drawn at random); entries < 0 or >= n and repeats are skipped
+ *   k          rank-list length and number of results per query, >= 1
+ *   rounds     expansion rounds t_0 (>= 0; 0 returns the k best seeds)
+ *   ids_out    device, int32[nq][k]; dists_out device, float[nq][k]: the k
+ *              best (d32, id) of R in ascending order, padded with (-1, +inf)
+ * Distances are d32 (squared Euclidean, canonical FP32 order), which also
+ * orders R; ties go to the smaller id.  The per-query state (visited ids,
+ * rank list) lives in LDS and must fit 64 KiB: roughly
+ * 8 (ns + rounds k kg) + 8 (k + k kg) + 4 D bytes; larger requests return
+ * KNNG_ERR_UNSUPPORTED.  NaN/Inf inputs are not checked.
+ */
+int knng_search(const float* data, int64_t n, int32_t D, const int32_t* graph, int32_t kg,
+                const float* queries, int64_t nq, const int32_t* seeds, int32_t ns, int32_t k,
+                int32_t rounds, int32_t* ids_out, float* dists_out, hipStream_t stream);
+
 /* Static description of a status code. */
 const char* knng_status_string(int status);
 

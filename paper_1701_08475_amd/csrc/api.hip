@@ -690,3 +690,37 @@ done:
     if (rc == KNNG_OK && e != hipSuccess) rc = hip_fail(e, "leaf search");
     return rc;
 }
+
+extern "C" int knng_search(const float* data, int64_t n, int32_t D, const int32_t* graph,
+                           int32_t kg, const float* queries, int64_t nq, const int32_t* seeds,
+                           int32_t ns, int32_t k, int32_t rounds, int32_t* ids_out,
+                           float* dists_out, hipStream_t stream) {
+    g_err[0] = '\0';
+    if (data == nullptr || graph == nullptr || queries == nullptr || seeds == nullptr ||
+        ids_out == nullptr || dists_out == nullptr)
+        return set_err(KNNG_ERR_INVALID_ARG, "null pointer argument");
+    if (!aligned16(data) || !aligned16(queries))
+        return set_err(KNNG_ERR_INVALID_ARG, "data and queries must be 16-byte aligned");
+    if (n < 1 || n > 2147483647LL)
+        return set_err(KNNG_ERR_INVALID_ARG, "n=%lld out of [1, 2^31-1]", static_cast<long long>(n));
+    if (D < 1 || D > knng::kMaxDim)
+        return set_err(D < 1 ? KNNG_ERR_INVALID_ARG : KNNG_ERR_UNSUPPORTED, "D=%d out of [1, %d]", D,
+                       knng::kMaxDim);
+    if (kg < 1) return set_err(KNNG_ERR_INVALID_ARG, "graph degree %d must be >= 1", kg);
+    if (nq < 0 || nq > 2147483647LL)
+        return set_err(KNNG_ERR_INVALID_ARG, "nq=%lld out of [0, 2^31-1]", static_cast<long long>(nq));
+    if (ns < 1) return set_err(KNNG_ERR_INVALID_ARG, "seeds per query %d must be >= 1", ns);
+    if (k < 1) return set_err(KNNG_ERR_INVALID_ARG, "k=%d must be >= 1", k);
+    if (rounds < 0) return set_err(KNNG_ERR_INVALID_ARG, "rounds=%d must be >= 0", rounds);
+    if (static_cast<int64_t>(k) * kg > (1 << 20) || ns > (1 << 20))
+        return set_err(KNNG_ERR_UNSUPPORTED, "k x graph degree or seeds too large");
+    hipStream_t s = stream;
+    knng::SearchArgs sa{data, n, D, graph, kg, queries, nq, seeds, ns, k, rounds, ids_out,
+                        dists_out, s};
+    char err[400] = "";
+    int rc = knng::search_run(sa, err, sizeof(err));
+    if (rc != KNNG_OK) return set_err(rc, "search: %s", err);
+    const hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "search");
+    return KNNG_OK;
+}

@@ -236,6 +236,27 @@ struct MergeArgs {
 };
 int merge_run(const MergeArgs& a, int* launches, char* err, size_t errlen);
 
+// ---------------------------------------------------------------- search
+// E-GNNS (Alg. 2) for nq queries, one workgroup each (search.hip).
+constexpr size_t kSearchLdsMax = 65536;  // visited table + rank list + query, per query
+struct SearchArgs {
+    const float* X;       // [n][D]
+    int64_t n;
+    int D;
+    const int32_t* G;     // [n][kg], -1 padding
+    int kg;
+    const float* Q;       // [nq][D]
+    int64_t nq;
+    const int32_t* seeds; // [nq][ns]
+    int ns;
+    int k;
+    int rounds;
+    int32_t* ids_out;     // [nq][k]
+    float* d_out;
+    hipStream_t stream;
+};
+int search_run(const SearchArgs& a, char* err, size_t errlen);
+
 // ---------------------------------------------------------------- prep
 // flags[0] <- 1 if X holds a NaN or Inf; flags[1] <- 1 if some value is not
 // an integer in [0, 255] (flags: device int[2]).

@@ -85,6 +85,8 @@ def lib():
     L.knng_leaf_search.restype = ctypes.c_int
     L.knng_leaf_search.argtypes = [vp, i64, i32, i32, i32, vp, vp, ctypes.POINTER(i32),
                                    ctypes.POINTER(KnngOptions), vp, vp, vp]
+    L.knng_search.restype = ctypes.c_int
+    L.knng_search.argtypes = [vp, i64, i32, vp, i32, vp, i64, vp, i32, i32, i32, vp, vp, vp]
     L.knng_default_options.restype = None
     L.knng_default_options.argtypes = [ctypes.POINTER(KnngOptions)]
     L.knng_status_string.restype = ctypes.c_char_p
@@ -206,5 +208,35 @@ def leaf_search(x, k, perms, leaf_offs, precision="fp32", rerank_factor=2, strea
                                 ctypes.c_void_p(perms.data_ptr()), ctypes.c_void_p(cat.data_ptr()),
                                 nl, ctypes.byref(o), ctypes.c_void_p(ids.data_ptr()),
                                 ctypes.c_void_p(ds.data_ptr()), _stream(stream))
+    _check(rc)
+    return ids, ds
+
+
+def search(x, graph, queries, seeds, k, rounds, stream=None):
+    """E-GNNS (Alg. 2) for a batch of queries over a kNN graph.
+
+    x: float32 CUDA [n, D]; graph: int32 CUDA [n, kg]; queries: float32 CUDA
+    [nq, D]; seeds: int32 CUDA [nq, ns].  Returns (ids int32 [nq, k], dists
+    float32 [nq, k])."""
+    import torch
+    x = _dev_f32(x)
+    queries = _dev_f32(queries)
+    n, D = x.shape
+    if queries.shape[1] != D:
+        raise ValueError("queries must have D columns")
+    for name, t in (("graph", graph), ("seeds", seeds)):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.int32
+                and t.dim() == 2 and t.is_contiguous()):
+            raise ValueError("%s must be a contiguous 2-D int32 CUDA tensor" % name)
+    if graph.shape[0] != n or seeds.shape[0] != queries.shape[0]:
+        raise ValueError("graph needs n rows and seeds one row per query")
+    nq = queries.shape[0]
+    ids = torch.empty((nq, k), dtype=torch.int32, device=x.device)
+    ds = torch.empty((nq, k), dtype=torch.float32, device=x.device)
+    rc = lib().knng_search(ctypes.c_void_p(x.data_ptr()), n, D, ctypes.c_void_p(graph.data_ptr()),
+                           graph.shape[1], ctypes.c_void_p(queries.data_ptr()), nq,
+                           ctypes.c_void_p(seeds.data_ptr()), seeds.shape[1], k, rounds,
+                           ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(ds.data_ptr()),
+                           _stream(stream))
     _check(rc)
     return ids, ds

@@ -1,0 +1,104 @@
+"""E-GNNS search (Alg. 2) on the GPU against the oracle's search in its d32
+mode (reading R13: both rank by the canonical FP32 distance), id for id and
+bit for bit.  Graphs, queries and seeds come from the oracle and the seeded
+generators only."""
+import numpy as np
+import pytest
+
+from paper_1701_08475_amd import datagen
+from tests.gpu_helpers import log, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1701_08475_amd import knng
+    knng.lib()
+    return knng
+
+
+def _i32(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, np.int32)).cuda()
+
+
+def _run(K, orc, X, G, Q, S, k, rounds):
+    ids, ds = K.search(to_dev(X), _i32(G), to_dev(Q), _i32(S), k, rounds)
+    ids, ds = ids.cpu().numpy(), ds.cpu().numpy()
+    o_ids, o_d = orc.egnns(X, G, Q, S, k, rounds, dist_mode=1)
+    assert np.array_equal(ids, o_ids)
+    assert np.array_equal(ds.astype(np.float64), o_d)
+    return ids, ds
+
+
+@pytest.mark.parametrize("name,n,D,kind,kg,k,rounds,ns", [
+    ("gmm", 5000, 32, "c1", 10, 10, 6, 8),
+    ("gmm-wide-k", 4000, 32, "c1", 10, 24, 4, 3),
+    ("int128", 12000, 128, "c2", 20, 20, 8, 16),
+    ("odd-D", 3000, 33, "normal", 8, 6, 5, 4),    # last 32-block of one dimension
+    ("tiny-D", 2000, 3, "normal", 12, 8, 10, 2),  # scalar path, many rounds
+])
+def test_search_matches_oracle(K, orc, name, n, D, kind, kg, k, rounds, ns):
+    if kind == "c1":
+        X = datagen.make("c1", n=n)
+    elif kind == "c2":
+        X = datagen.make("c2", n=n)
+    else:
+        X = datagen.random_points(n, D, n + D, kind)
+    G, _, _ = orc.graph(X, kg, 2, max(2 * kg + 2, 40), 5)
+    rng = np.random.default_rng(n + kg)
+    nq = 300
+    Q = X[rng.integers(0, n, nq)] + rng.normal(0, 0.5, size=(nq, X.shape[1])).astype(np.float32)
+    if kind == "c2":
+        Q = np.rint(np.clip(Q, 0, 255)).astype(np.float32)
+    S = rng.integers(0, n, size=(nq, ns)).astype(np.int32)
+    log("search %s n=%d D=%d kg=%d k=%d rounds=%d" % (name, n, X.shape[1], kg, k, rounds))
+    _run(K, orc, X, G, Q, S, k, rounds)
+
+
+def test_search_zero_rounds_and_seed_edge_cases(K, orc):
+    X = datagen.random_points(500, 16, 3, "normal")
+    G, _, _ = orc.graph(X, 6, 1, 20, 2)
+    Q = datagen.random_points(40, 16, 4, "normal")
+    rng = np.random.default_rng(5)
+    S = rng.integers(-3, 503, size=(40, 7)).astype(np.int32)  # out-of-range ids included
+    S[:, 3] = S[:, 2]                                          # repeats
+    S[0, :] = -1                                               # no valid seed: all padding
+    for rounds in (0, 1, 3):
+        ids, ds = _run(K, orc, X, G, Q, S, 5, rounds)
+        assert np.all(ids[0] == -1) and np.all(np.isinf(ds[0]))
+
+
+def test_search_complete_graph_is_exact(K, orc):
+    """Every point linked to every other: one round visits all points, so
+    the result is the exact k nearest (brute force in FP64, same ids)."""
+    n, D, k = 200, 24, 7
+    X = datagen.random_points(n, D, 9, "normal")
+    G = np.array([[j for j in range(n) if j != i] for i in range(n)], np.int32)
+    Q = datagen.random_points(50, D, 10, "normal")
+    S = (np.arange(50) % n).reshape(50, 1).astype(np.int32)
+    ids, ds = _run(K, orc, X, G, Q, S, k, 1)
+    for q in range(50):
+        d = np.sum((X.astype(np.float64) - Q[q].astype(np.float64)) ** 2, axis=1)
+        order = np.lexsort((np.arange(n), d))[:k]
+        assert np.array_equal(ids[q], order)
+
+
+def test_search_disconnected_graph_pads(K, orc):
+    X = np.array([[0.0, 0, 0, 0], [1, 0, 0, 0], [10, 0, 0, 0], [11, 0, 0, 0]], np.float32)
+    G = np.array([[1], [0], [3], [2]], np.int32)
+    Q = np.array([[10.5, 0, 0, 0]], np.float32)
+    ids, ds = _run(K, orc, X, G, Q, np.array([[0]], np.int32), 4, 5)
+    assert ids[0].tolist() == [1, 0, -1, -1]
+
+
+def test_search_rejects_oversized_state(K):
+    import torch
+    X = torch.zeros((100, 8), dtype=torch.float32, device="cuda")
+    G = torch.zeros((100, 64), dtype=torch.int32, device="cuda")
+    S = torch.zeros((1, 1), dtype=torch.int32, device="cuda")
+    with pytest.raises(K.KnngError):
+        K.search(X, G, X[:1].contiguous(), S, 64, 50)  # 64 x 64 x 50 visited ids
