@@ -69,6 +69,11 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain schedule")
     ap.add_argument("--no-compact", action="store_true",
                     help="stream FP32 rows in the partition even for integer data")
+    ap.add_argument("--no-search", action="store_true",
+                    help="skip the E-GNNS search over the built graph")
+    ap.add_argument("--search-queries", type=int, default=10_000)
+    ap.add_argument("--search-seeds", type=int, default=64)
+    ap.add_argument("--search-rounds", type=int, default=10)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 1 GiB elementwise copy first (HBM counter calibration)")
     args = ap.parse_args()
@@ -225,6 +230,35 @@ def main():
                          "lower)" % (ns, n, T, k, L)}
         log("cpu oracle: %d points in %.1fs on %d threads" % (ns, el, threads))
 
+    search = None
+    if not args.no_search:
+        # E-GNNS (Alg. 2) over the graph just built: queries from the same
+        # mixture, random seeds; recall against FP64 brute force (oracle)
+        Qn = datagen.queries(args.config, args.search_queries)
+        S = datagen.seeds(n, len(Qn), args.search_seeds)
+        qd = torch.from_numpy(Qn).to(dev)
+        sd = torch.from_numpy(S).to(dev)
+        rounds = args.search_rounds
+        knng.search(xd, ids, qd, sd, k, rounds)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            s_ids, s_d = knng.search(xd, ids, qd, sd, k, rounds)
+        torch.cuda.synchronize()
+        s_ms = (time.perf_counter() - ts) * 1e3 / reps
+        search = {"queries": len(Qn), "k": k, "graph_degree": k, "rounds": rounds,
+                  "seeds": args.search_seeds, "ms": round(s_ms, 3),
+                  "queries_per_s": round(len(Qn) / (s_ms / 1e3), 1),
+                  "data": "synthetic queries from the config's mixture"}
+        if not args.no_recall:
+            from oracle import oracle
+            rq = min(200, len(Qn))
+            E, _ = oracle.exact_knn_points(X, Qn[:rq], k)
+            search["recall_at_k"] = round(oracle.search_recall(s_ids.cpu().numpy()[:rq], E), 5)
+            search["recall_queries"] = rq
+        log("search: %d queries in %.2f ms (%s)" % (len(Qn), s_ms, search.get("recall_at_k")))
+
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "points/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
@@ -240,6 +274,7 @@ def main():
         "recall": recall,
         "plain_schedule": plain,
         "phases": phases,
+        "search": search,
         "gpu": torch.cuda.get_device_name(0),
     }
     print(json.dumps(out), flush=True)

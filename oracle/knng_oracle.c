@@ -764,3 +764,22 @@ int orc_egnns(const float *X, int64_t n, int D, const int32_t *G, int kg, const 
     }
     return fail ? -1 : 0;
 }
+
+/* Exact k nearest reference points of external query points (brute force,
+ * FP64, R1; ascending (d, id)); ground truth for the search's recall. */
+int orc_exact_knn_points(const float *X, int64_t n, int D, const float *Q, int64_t nq, int k,
+                         int32_t *ids, double *dists)
+{
+    if (n < 1 || D < 1 || k < 1) return -1;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < nq; ++q) {
+        int *ri = (int *)ids + q * k;
+        double *rd = dists + q * k;
+        int cnt = 0;
+        for (int p = 0; p < k; ++p) { ri[p] = -1; rd[p] = INFINITY; }
+        for (int64_t j = 0; j < n; ++j)
+            row_insert(ri, rd, &cnt, k, (int)j,
+                       query_dist(Q + (size_t)q * D, X + (size_t)j * D, D, 0));
+    }
+    return 0;
+}

@@ -73,6 +73,8 @@ def lib():
         L.orc_d32.argtypes = [vp, vp, i32]
         L.orc_egnns.restype = i32
         L.orc_egnns.argtypes = [vp, i64, i32, vp, i32, vp, i64, vp, i32, i32, i32, i32, vp, vp]
+        L.orc_exact_knn_points.restype = i32
+        L.orc_exact_knn_points.argtypes = [vp, i64, i32, vp, i64, i32, vp, vp]
         L.orc_num_threads.restype = i32
         L.orc_set_num_threads.restype = None
         L.orc_set_num_threads.argtypes = [i32]
@@ -313,3 +315,23 @@ def egnns(X, G, Q, seeds, k, rounds, dist_mode=1):
     if rc != 0:
         raise MemoryError("orc_egnns")
     return ids, ds
+
+
+def exact_knn_points(X, Q, k):
+    """Exact k nearest rows of X for each query row of Q (FP64 brute force)."""
+    X, Q = _f32(X), _f32(Q)
+    ids = np.empty((Q.shape[0], k), np.int32)
+    ds = np.empty((Q.shape[0], k), np.float64)
+    rc = lib().orc_exact_knn_points(_p(X), X.shape[0], X.shape[1], _p(Q), Q.shape[0], k,
+                                    _p(ids), _p(ds))
+    assert rc == 0
+    return ids, ds
+
+
+def search_recall(ids, E_ids):
+    """Mean fraction of the exact k nearest ids found per query."""
+    k = E_ids.shape[1]
+    hit = 0
+    for a, b in zip(ids, E_ids):
+        hit += len(set(a[a >= 0].tolist()) & set(b[b >= 0].tolist()))
+    return hit / float(E_ids.shape[0] * k)

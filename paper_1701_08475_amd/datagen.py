@@ -86,6 +86,38 @@ def make(name, n=None):
     raise ValueError(kind)
 
 
+def queries(name, nq, seed=77):
+    """nq query points from the mixture of config `name`: the same centres
+    (the generator's first draw from the config seed), labels and noise from
+    their own stream `seed`."""
+    c = CONFIGS[name]
+    kind, D, K = c["data"], c["D"], c["K"]
+    rc = np.random.Generator(np.random.PCG64(c["seed"]))
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if kind in ("gmm_uniform", "gmm_sift"):
+        centres = rc.uniform(c["lo"], c["hi"], size=(K, D)).astype(np.float32)
+        lab = rng.integers(0, K, size=nq)
+        z = rng.standard_normal(size=(nq, D), dtype=np.float32)
+        x = centres[lab] + np.float32(c["sigma"]) * z
+        if kind == "gmm_sift":
+            np.clip(x, 0.0, 255.0, out=x)
+            np.rint(x, out=x)
+        return x.astype(np.float32)
+    if kind == "gmm_unit":
+        centres = rc.standard_normal(size=(K, D))
+        lab = rng.integers(0, K, size=nq)
+        x = centres[lab] + c["sigma"] * rng.standard_normal(size=(nq, D))
+        x /= np.linalg.norm(x, axis=1, keepdims=True)
+        return x.astype(np.float32)
+    raise ValueError(kind)
+
+
+def seeds(n, nq, ns, seed=78):
+    """Random starting points for the search: nq x ns ids in [0, n)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.integers(0, n, size=(nq, ns)).astype(np.int32)
+
+
 def sample_rows(n, q, seed=99):
     """q distinct row indices (ascending) for recall / sampled parity."""
     rng = np.random.Generator(np.random.PCG64(seed))

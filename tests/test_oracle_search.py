@@ -129,3 +129,27 @@ def test_d32_order_equals_d64_on_integer_data(orc):
     b = orc.egnns(X, ids_g, Q, S, 8, 6, dist_mode=1)
     assert np.array_equal(a[0], b[0])
     assert np.array_equal(a[1], b[1])
+
+
+def test_exact_knn_points_brute_force(orc):
+    """Tiny inputs: against a sort of all distances (numpy, FP64)."""
+    X = datagen.random_points(150, 5, 41, "normal")
+    Q = datagen.random_points(12, 5, 42, "normal")
+    ids, ds = orc.exact_knn_points(X, Q, 7)
+    for q in range(12):
+        d = np.sum((X.astype(np.float64) - Q[q].astype(np.float64)) ** 2, axis=1)
+        order = np.lexsort((np.arange(150), d))[:7]
+        assert np.array_equal(ids[q], order)
+        np.testing.assert_allclose(ds[q], d[order], rtol=1e-12)
+
+
+def test_query_generator_shares_the_mixture():
+    """Queries come from the same centres as the config's data: every
+    query of the small C1 mixture lies near some data point's centre."""
+    X = datagen.make("c1", n=20000)
+    Q = datagen.queries("c1", 50)
+    d = ((Q[:, None, :].astype(np.float64) - X[None, :2000, :]) ** 2).sum(-1).min(1)
+    # same mixture: nearest of 2000 data points is within the noise scale
+    # (sigma = 1, D = 32: squared distances ~ 2 * 32); an unrelated draw of
+    # centres in [-10, 10]^32 would be hundreds away
+    assert np.median(d) < 150
