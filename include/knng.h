@@ -13,12 +13,12 @@
  *     caller, row-major and contiguous, 16-byte aligned.  Pointers documented
  *     as "host" are ordinary host memory.
  *   - All work is ordered on `stream`; each call returns after that work has
- *     completed (it synchronises the stream).  Scratch memory is taken with
- *     hipMallocAsync on `stream` and freed (hipFreeAsync) before return.  The
- *     first call on a device raises the release threshold of that device's
- *     current memory pool to unlimited, so freed scratch stays reserved for
- *     the next call instead of being returned to the driver at every
- *     synchronisation; hipMemPoolTrimTo gives it back.
+ *     completed (it synchronises the stream).  Scratch memory comes from a
+ *     per-device cache inside the library: blocks are allocated with
+ *     hipMalloc on first need and kept for later calls (returning them to
+ *     the driver every call costs milliseconds per build);
+ *     knng_release_workspace() frees them.  Calls that use scratch memory on
+ *     the same device run one at a time (a per-device lock).
  *   - Return value: KNNG_OK (0) or a negative status below.  On an argument
  *     error (KNNG_ERR_INVALID_ARG, KNNG_ERR_UNSUPPORTED) nothing is launched
  *     and no output is written.  On KNNG_ERR_NONFINITE the outputs are not
@@ -199,6 +199,12 @@ int knng_leaf_search(const float* data, int64_t n, int32_t D, int32_t k, int32_t
 int knng_search(const float* data, int64_t n, int32_t D, const int32_t* graph, int32_t kg,
                 const float* queries, int64_t nq, const int32_t* seeds, int32_t ns, int32_t k,
                 int32_t rounds, int32_t* ids_out, float* dists_out, hipStream_t stream);
+
+/*
+ * knng_release_workspace -- free the scratch blocks the library keeps cached
+ * for the current device (none is in use when no call is running).
+ */
+void knng_release_workspace(void);
 
 /* Static description of a status code. */
 const char* knng_status_string(int status);

@@ -109,7 +109,7 @@ int hip_fail(hipError_t e, const char* what) {
 // [0, 255].  Returns KNNG_ERR_NONFINITE for NaN/Inf input.
 int scan_input(const float* data, int64_t count, bool want_finite, int* u8, hipStream_t s) {
     int32_t* flags = nullptr;
-    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&flags), 2 * sizeof(int32_t), s);
+    hipError_t e = knng::ws_malloc(reinterpret_cast<void**>(&flags), 2 * sizeof(int32_t), s);
     if (e != hipSuccess) return hip_fail(e, "hipMallocAsync");
     int rc = knng::prep_scan(data, count, flags, s);
     int32_t h[2] = {0, 0};
@@ -120,7 +120,7 @@ int scan_input(const float* data, int64_t count, bool want_finite, int* u8, hipS
     } else {
         rc = set_err(KNNG_ERR_HIP, "input-scan launch failed");
     }
-    hipFreeAsync(flags, s);
+    knng::ws_free(flags, s);
     if (rc == KNNG_OK && want_finite && h[0]) rc = set_err(KNNG_ERR_NONFINITE, "input holds NaN or Inf");
     if (u8) *u8 = (h[1] == 0 && h[0] == 0) ? 1 : 0;
     return rc;
@@ -130,23 +130,6 @@ int check_finite(const float* data, int64_t count, hipStream_t s) {
     return scan_input(data, count, true, nullptr, s);
 }
 
-// Memory freed with hipFreeAsync stays in the current device's memory pool
-// (release threshold raised to unlimited) instead of going back to the
-// driver at the next synchronisation: returning and re-mapping the
-// per-call workspace cost about 1.5 ms per C2-sized build.  Once per device.
-void keep_pool_memory() {
-    static std::atomic<uint64_t> done{0};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
-    const uint64_t bit = 1ull << dev;
-    if (done.load() & bit) return;
-    hipMemPool_t pool = nullptr;
-    if (hipDeviceGetMemPool(&pool, dev) == hipSuccess && pool != nullptr) {
-        uint64_t thr = UINT64_MAX;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-    }
-    done.fetch_or(bit);
-}
 
 }  // namespace
 
@@ -201,7 +184,7 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
         return set_err(KNNG_ERR_UNSUPPORTED, "rerank_factor*k = %d exceeds 128", o.rerank * k);
 
     hipStream_t s = stream;
-    keep_pool_memory();
+    knng::DeviceLock dlock;  // workspace blocks: one call per device at a time
     Events ev(stats_out != nullptr);
     knng::KernelTimer timer(o.time_kernels != 0 && stats_out != nullptr);
     ev.record(0, s);
@@ -239,27 +222,27 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
     const int leaf_prec = exact_bf16 ? KNNG_BF16 : o.precision;
     knng::ReducedRows rr{nullptr, nullptr, nullptr, knng::reduced_rows_dp(D), exact_bf16};
 
-    e = hipMallocAsync(reinterpret_cast<void**>(&perm), sizeof(int32_t) * slots * n, s);
+    e = knng::ws_malloc(reinterpret_cast<void**>(&perm), sizeof(int32_t) * slots * n, s);
     if (e == hipSuccess)
-        e = hipMallocAsync(reinterpret_cast<void**>(&leaves), sizeof(knng::LeafRec) * lcap, s);
+        e = knng::ws_malloc(reinterpret_cast<void**>(&leaves), sizeof(knng::LeafRec) * lcap, s);
     if (e == hipSuccess && !direct)
-        e = hipMallocAsync(reinterpret_cast<void**>(&cand_ids), sizeof(int32_t) * T * n * k, s);
+        e = knng::ws_malloc(reinterpret_cast<void**>(&cand_ids), sizeof(int32_t) * T * n * k, s);
     if (e == hipSuccess && !direct)
-        e = hipMallocAsync(reinterpret_cast<void**>(&cand_d), sizeof(float) * T * n * k, s);
+        e = knng::ws_malloc(reinterpret_cast<void**>(&cand_d), sizeof(float) * T * n * k, s);
     if (e == hipSuccess)
-        e = hipMallocAsync(reinterpret_cast<void**>(&dpairs),
+        e = knng::ws_malloc(reinterpret_cast<void**>(&dpairs),
                            sizeof(unsigned long long) * knng::kStatWords, s);
     if (e == hipSuccess)
         e = hipMemsetAsync(dpairs, 0, sizeof(unsigned long long) * knng::kStatWords, s);
     if (e == hipSuccess && use_u8)
-        e = hipMallocAsync(reinterpret_cast<void**>(&x8), static_cast<size_t>(n) * D, s);
+        e = knng::ws_malloc(reinterpret_cast<void**>(&x8), static_cast<size_t>(n) * D, s);
     if (e == hipSuccess && leaf_prec != KNNG_FP32)
-        e = hipMallocAsync(reinterpret_cast<void**>(&rr.Xr),
+        e = knng::ws_malloc(reinterpret_cast<void**>(&rr.Xr),
                            knng::reduced_rows_bytes(leaf_prec, n, D), s);
     if (e == hipSuccess && leaf_prec != KNNG_FP32)
-        e = hipMallocAsync(reinterpret_cast<void**>(&rr.nrm), sizeof(float) * n, s);
+        e = knng::ws_malloc(reinterpret_cast<void**>(&rr.nrm), sizeof(float) * n, s);
     if (e == hipSuccess && leaf_prec != KNNG_FP32)
-        e = hipMallocAsync(reinterpret_cast<void**>(&rr.sinv), sizeof(float) * n, s);
+        e = knng::ws_malloc(reinterpret_cast<void**>(&rr.sinv), sizeof(float) * n, s);
     if (e != hipSuccess) {
         rc = hip_fail(e, "workspace allocation");
         goto done;
@@ -360,16 +343,16 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
     pairs = static_cast<int64_t>(knng::stat_total(hpairs.data()));
 
 done:
-    if (perm) hipFreeAsync(perm, s);
-    if (leaves) hipFreeAsync(leaves, s);
-    if (dpairs) hipFreeAsync(dpairs, s);
-    if (x8) hipFreeAsync(x8, s);
-    if (rr.Xr) hipFreeAsync(rr.Xr, s);
-    if (rr.nrm) hipFreeAsync(rr.nrm, s);
-    if (rr.sinv) hipFreeAsync(rr.sinv, s);
+    if (perm) knng::ws_free(perm, s);
+    if (leaves) knng::ws_free(leaves, s);
+    if (dpairs) knng::ws_free(dpairs, s);
+    if (x8) knng::ws_free(x8, s);
+    if (rr.Xr) knng::ws_free(rr.Xr, s);
+    if (rr.nrm) knng::ws_free(rr.nrm, s);
+    if (rr.sinv) knng::ws_free(rr.sinv, s);
     if (!direct) {
-        if (cand_ids) hipFreeAsync(cand_ids, s);
-        if (cand_d) hipFreeAsync(cand_d, s);
+        if (cand_ids) knng::ws_free(cand_ids, s);
+        if (cand_d) knng::ws_free(cand_d, s);
     }
     e = hipStreamSynchronize(s);
     if (rc == KNNG_OK && e != hipSuccess) rc = hip_fail(e, "build");
@@ -435,7 +418,7 @@ int knng_partition(const float* data, int64_t n, int32_t D, int32_t leaf_max, in
         return set_err(KNNG_ERR_INVALID_ARG, "leaf_max < 2*min_leaf-1");
 
     hipStream_t s = stream;
-    keep_pool_memory();
+    knng::DeviceLock dlock;  // workspace blocks: one call per device at a time
     int all_u8 = 0;
     int rc = scan_input(data, n * static_cast<int64_t>(D), true, &all_u8, s);
     if (rc != KNNG_OK) return rc;
@@ -447,10 +430,10 @@ int knng_partition(const float* data, int64_t n, int32_t D, int32_t leaf_max, in
     int32_t hcount = 0;
     char err[400] = "";
     knng::PartitionResult r;
-    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&leaves), sizeof(knng::LeafRec) * lcap, s);
-    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&dcount), sizeof(int32_t), s);
+    hipError_t e = knng::ws_malloc(reinterpret_cast<void**>(&leaves), sizeof(knng::LeafRec) * lcap, s);
+    if (e == hipSuccess) e = knng::ws_malloc(reinterpret_cast<void**>(&dcount), sizeof(int32_t), s);
     if (e == hipSuccess && use_u8)
-        e = hipMallocAsync(reinterpret_cast<void**>(&x8), static_cast<size_t>(n) * D, s);
+        e = knng::ws_malloc(reinterpret_cast<void**>(&x8), static_cast<size_t>(n) * D, s);
     if (e != hipSuccess) {
         rc = hip_fail(e, "workspace allocation");
         goto done;
@@ -499,9 +482,9 @@ int knng_partition(const float* data, int64_t n, int32_t D, int32_t leaf_max, in
     if (n_nodes_out) *n_nodes_out = static_cast<int32_t>(r.n_log);
 
 done:
-    if (leaves) hipFreeAsync(leaves, s);
-    if (x8) hipFreeAsync(x8, s);
-    if (dcount) hipFreeAsync(dcount, s);
+    if (leaves) knng::ws_free(leaves, s);
+    if (x8) knng::ws_free(x8, s);
+    if (dcount) knng::ws_free(dcount, s);
     e = hipStreamSynchronize(s);
     if (rc == KNNG_OK && e != hipSuccess) rc = hip_fail(e, "partition");
     return rc;
@@ -559,7 +542,7 @@ extern "C" int knng_leaf_search(const float* data, int64_t n, int32_t D, int32_t
         total += n_leaves[t];
     }
     hipStream_t s = stream;
-    keep_pool_memory();
+    knng::DeviceLock dlock;  // workspace blocks: one call per device at a time
     knng::LeafRec* leaves = nullptr;
     int32_t* flags = nullptr;  // [0] max leaf size, [1] malformed
     int32_t hflags[2] = {0, 0};
@@ -569,8 +552,8 @@ extern "C" int knng_leaf_search(const float* data, int64_t n, int32_t D, int32_t
     char err[400] = "";
     int launches = 0;
     knng::ReducedRows rr{nullptr, nullptr, nullptr, knng::reduced_rows_dp(D), false};
-    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&leaves), sizeof(knng::LeafRec) * total, s);
-    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&flags), sizeof(int32_t) * 2, s);
+    hipError_t e = knng::ws_malloc(reinterpret_cast<void**>(&leaves), sizeof(knng::LeafRec) * total, s);
+    if (e == hipSuccess) e = knng::ws_malloc(reinterpret_cast<void**>(&flags), sizeof(int32_t) * 2, s);
     if (e != hipSuccess) {
         rc = hip_fail(e, "workspace allocation");
         goto done;
@@ -610,19 +593,19 @@ extern "C" int knng_leaf_search(const float* data, int64_t n, int32_t D, int32_t
         cand_ids = ids_out;
         cand_d = dists_out;
     } else {
-        e = hipMallocAsync(reinterpret_cast<void**>(&cand_ids), sizeof(int32_t) * n_trees * n * k, s);
+        e = knng::ws_malloc(reinterpret_cast<void**>(&cand_ids), sizeof(int32_t) * n_trees * n * k, s);
         if (e == hipSuccess)
-            e = hipMallocAsync(reinterpret_cast<void**>(&cand_d), sizeof(float) * n_trees * n * k, s);
+            e = knng::ws_malloc(reinterpret_cast<void**>(&cand_d), sizeof(float) * n_trees * n * k, s);
         if (e != hipSuccess) {
             rc = hip_fail(e, "workspace allocation");
             goto done;
         }
     }
     if (o.precision != KNNG_FP32) {
-        e = hipMallocAsync(reinterpret_cast<void**>(&rr.Xr),
+        e = knng::ws_malloc(reinterpret_cast<void**>(&rr.Xr),
                            knng::reduced_rows_bytes(o.precision, n, D), s);
-        if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&rr.nrm), sizeof(float) * n, s);
-        if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&rr.sinv), sizeof(float) * n, s);
+        if (e == hipSuccess) e = knng::ws_malloc(reinterpret_cast<void**>(&rr.nrm), sizeof(float) * n, s);
+        if (e == hipSuccess) e = knng::ws_malloc(reinterpret_cast<void**>(&rr.sinv), sizeof(float) * n, s);
         if (e != hipSuccess) {
             rc = hip_fail(e, "workspace allocation");
             goto done;
@@ -677,14 +660,14 @@ extern "C" int knng_leaf_search(const float* data, int64_t n, int32_t D, int32_t
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) rc = hip_fail(e, "leaf search");
 done:
-    if (leaves) hipFreeAsync(leaves, s);
-    if (flags) hipFreeAsync(flags, s);
-    if (rr.Xr) hipFreeAsync(rr.Xr, s);
-    if (rr.nrm) hipFreeAsync(rr.nrm, s);
-    if (rr.sinv) hipFreeAsync(rr.sinv, s);
+    if (leaves) knng::ws_free(leaves, s);
+    if (flags) knng::ws_free(flags, s);
+    if (rr.Xr) knng::ws_free(rr.Xr, s);
+    if (rr.nrm) knng::ws_free(rr.nrm, s);
+    if (rr.sinv) knng::ws_free(rr.sinv, s);
     if (!direct) {
-        if (cand_ids) hipFreeAsync(cand_ids, s);
-        if (cand_d) hipFreeAsync(cand_d, s);
+        if (cand_ids) knng::ws_free(cand_ids, s);
+        if (cand_d) knng::ws_free(cand_d, s);
     }
     e = hipStreamSynchronize(s);
     if (rc == KNNG_OK && e != hipSuccess) rc = hip_fail(e, "leaf search");
@@ -723,4 +706,9 @@ extern "C" int knng_search(const float* data, int64_t n, int32_t D, const int32_
     const hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "search");
     return KNNG_OK;
+}
+
+extern "C" void knng_release_workspace(void) {
+    knng::DeviceLock dlock;
+    knng::ws_release_device(dlock.device());
 }

@@ -15,6 +15,25 @@ constexpr int kMaxLeaf = 512;
 // Largest dimension the partition kernels accept.
 constexpr int kMaxDim = 4096;
 
+// Device workspace cache (workspace.hip): stream-ordered use like
+// hipMallocAsync / hipFreeAsync, but blocks stay cached per device between
+// calls.  Calls that allocate hold the device's DeviceLock until their
+// stream has been synchronised.
+hipError_t ws_malloc(void** p, size_t bytes, hipStream_t s);
+void ws_free(void* p, hipStream_t s);
+void ws_release_device(int dev);  // frees every cached (unused) block of the device
+class DeviceLock {
+  public:
+    DeviceLock();
+    ~DeviceLock();
+    DeviceLock(const DeviceLock&) = delete;
+    DeviceLock& operator=(const DeviceLock&) = delete;
+    int device() const;
+
+  private:
+    int dev_;
+};
+
 // Statistics counters (rows assigned, leaf pairs, ...) are spread over
 // kStatSlots 128-byte lines: atomics from thousands of wavefronts on one
 // address queue behind each other in one L2 channel.  Counter c of a block

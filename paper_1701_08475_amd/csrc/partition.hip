@@ -1360,29 +1360,29 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
         hctr = t_hctr;
         dmirror = t_dctr;
     }
-    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&nodes[0]), sizeof(NodeRec) * nmax, s));
-    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&nodes[1]), sizeof(NodeRec) * nmax, s));
-    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&big[0]), sizeof(int32_t) * nmax, s));
-    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&big[1]), sizeof(int32_t) * nmax, s));
-    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&sub), sizeof(NodeRec) * nmax, s));
-    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&chunk_node), sizeof(int32_t) * cmax, s));
+    KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&nodes[0]), sizeof(NodeRec) * nmax, s));
+    KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&nodes[1]), sizeof(NodeRec) * nmax, s));
+    KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&big[0]), sizeof(int32_t) * nmax, s));
+    KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&big[1]), sizeof(int32_t) * nmax, s));
+    KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&sub), sizeof(NodeRec) * nmax, s));
+    KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&chunk_node), sizeof(int32_t) * cmax, s));
     if (order_mode & 1) {
-        KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&chunk_key), sizeof(int32_t) * cmax, s));
-        KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&corder), sizeof(int32_t) * cmax, s));
+        KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&chunk_key), sizeof(int32_t) * cmax, s));
+        KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&corder), sizeof(int32_t) * cmax, s));
     }
-    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&rep), sizeof(int32_t) * (nmax + 1), s));
-    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&status), sizeof(int32_t) * nmax, s));
-    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&n0f), sizeof(int32_t) * nmax, s));
-    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&C), sizeof(double) * nmax * 2 * D, s));
-    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&P), sizeof(double) * cmax * 2 * D, s));
-    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&cnt), sizeof(int32_t) * cmax * 2, s));
-    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&labels), tn, s));
-    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&dots), sizeof(double) * tn, s));
-    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&perm_tmp), sizeof(int32_t) * tn, s));
-    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&ctr), sizeof(LevelCounters), s));
-    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&dstats),
+    KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&rep), sizeof(int32_t) * (nmax + 1), s));
+    KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&status), sizeof(int32_t) * nmax, s));
+    KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&n0f), sizeof(int32_t) * nmax, s));
+    KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&C), sizeof(double) * nmax * 2 * D, s));
+    KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&P), sizeof(double) * cmax * 2 * D, s));
+    KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&cnt), sizeof(int32_t) * cmax * 2, s));
+    KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&labels), tn, s));
+    KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&dots), sizeof(double) * tn, s));
+    KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&perm_tmp), sizeof(int32_t) * tn, s));
+    KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&ctr), sizeof(LevelCounters), s));
+    KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&dstats),
                             sizeof(unsigned long long) * 4 * kStatWords, s));
-    KNNG_HIP(hipMallocAsync(reinterpret_cast<void**>(&overflow), sizeof(int), s));
+    KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&overflow), sizeof(int), s));
     k_zero_small<<<1, 256, 0, s>>>(dstats, 4 * kStatWords, overflow);
     KNNG_LAUNCH();
     {
@@ -1565,26 +1565,26 @@ done:
         hipEventRecord(s2_done, s2);
         hipStreamWaitEvent(s, s2_done, 0);
     }
-    if (nodes[0]) hipFreeAsync(nodes[0], s);
-    if (nodes[1]) hipFreeAsync(nodes[1], s);
-    if (big[0]) hipFreeAsync(big[0], s);
-    if (big[1]) hipFreeAsync(big[1], s);
-    if (sub) hipFreeAsync(sub, s);
-    if (chunk_node) hipFreeAsync(chunk_node, s);
-    if (chunk_key) hipFreeAsync(chunk_key, s);
-    if (corder) hipFreeAsync(corder, s);
-    if (rep) hipFreeAsync(rep, s);
-    if (status) hipFreeAsync(status, s);
-    if (n0f) hipFreeAsync(n0f, s);
-    if (C) hipFreeAsync(C, s);
-    if (P) hipFreeAsync(P, s);
-    if (cnt) hipFreeAsync(cnt, s);
-    if (labels) hipFreeAsync(labels, s);
-    if (dots) hipFreeAsync(dots, s);
-    if (perm_tmp) hipFreeAsync(perm_tmp, s);
-    if (ctr) hipFreeAsync(ctr, s);
-    if (dstats) hipFreeAsync(dstats, s);
-    if (overflow) hipFreeAsync(overflow, s);
+    if (nodes[0]) ws_free(nodes[0], s);
+    if (nodes[1]) ws_free(nodes[1], s);
+    if (big[0]) ws_free(big[0], s);
+    if (big[1]) ws_free(big[1], s);
+    if (sub) ws_free(sub, s);
+    if (chunk_node) ws_free(chunk_node, s);
+    if (chunk_key) ws_free(chunk_key, s);
+    if (corder) ws_free(corder, s);
+    if (rep) ws_free(rep, s);
+    if (status) ws_free(status, s);
+    if (n0f) ws_free(n0f, s);
+    if (C) ws_free(C, s);
+    if (P) ws_free(P, s);
+    if (cnt) ws_free(cnt, s);
+    if (labels) ws_free(labels, s);
+    if (dots) ws_free(dots, s);
+    if (perm_tmp) ws_free(perm_tmp, s);
+    if (ctr) ws_free(ctr, s);
+    if (dstats) ws_free(dstats, s);
+    if (overflow) ws_free(overflow, s);
     if (rc != kOk) hipStreamSynchronize(s);  // copies into hctr may still be pending
     res->launches += launches;
     return rc;

@@ -138,10 +138,10 @@ int leaves_to_offsets(const LeafRec* leaves, int64_t n_leaves, int64_t n, int tr
                       int32_t* offsets_out, int32_t* count_out_dev, hipStream_t s) {
     int32_t *mark = nullptr, *bcount = nullptr;
     const int64_t nb = (n + 1023) / 1024;
-    if (hipMallocAsync(reinterpret_cast<void**>(&mark), sizeof(int32_t) * n, s) != hipSuccess)
+    if (ws_malloc(reinterpret_cast<void**>(&mark), sizeof(int32_t) * n, s) != hipSuccess)
         return kOom;
-    if (hipMallocAsync(reinterpret_cast<void**>(&bcount), sizeof(int32_t) * nb, s) != hipSuccess) {
-        hipFreeAsync(mark, s);
+    if (ws_malloc(reinterpret_cast<void**>(&bcount), sizeof(int32_t) * nb, s) != hipSuccess) {
+        ws_free(mark, s);
         return kOom;
     }
     const int fb = static_cast<int>((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
@@ -152,8 +152,8 @@ int leaves_to_offsets(const LeafRec* leaves, int64_t n_leaves, int64_t n, int tr
     k_emit_offsets<<<static_cast<unsigned>(nb), 256, 0, s>>>(mark, n, bcount, offsets_out);
     k_set_last<<<1, 1, 0, s>>>(offsets_out, count_out_dev, static_cast<int32_t>(n));
     const hipError_t e = hipGetLastError();
-    hipFreeAsync(mark, s);
-    hipFreeAsync(bcount, s);
+    ws_free(mark, s);
+    ws_free(bcount, s);
     return e == hipSuccess ? kOk : kHip;
 }
 

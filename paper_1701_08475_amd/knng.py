@@ -87,6 +87,8 @@ def lib():
                                    ctypes.POINTER(KnngOptions), vp, vp, vp]
     L.knng_search.restype = ctypes.c_int
     L.knng_search.argtypes = [vp, i64, i32, vp, i32, vp, i64, vp, i32, i32, i32, vp, vp, vp]
+    L.knng_release_workspace.restype = None
+    L.knng_release_workspace.argtypes = []
     L.knng_default_options.restype = None
     L.knng_default_options.argtypes = [ctypes.POINTER(KnngOptions)]
     L.knng_status_string.restype = ctypes.c_char_p
@@ -240,3 +242,8 @@ def search(x, graph, queries, seeds, k, rounds, stream=None):
                            _stream(stream))
     _check(rc)
     return ids, ds
+
+
+def release_workspace():
+    """Free the scratch blocks the library keeps cached on the current device."""
+    lib().knng_release_workspace()
