@@ -76,21 +76,6 @@ __global__ void k_zero_small(unsigned long long* stats, int words, int* flag) {
     if (threadIdx.x == 0) *flag = 0;
 }
 
-// chunk -> node map of a level; also empties the level's repair list.
-// chunk_key (nullable): the chunk's first row id, for the dispatch order.
-__global__ void k_chunk_map(const NodeRec* nodes, const int32_t* perm, int64_t n,
-                            int32_t* chunk_node, int32_t* chunk_key, int32_t* rep) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) rep[0] = 0;
-    const NodeRec r = nodes[blockIdx.x];
-    const int nch = chunks_of(r.size);
-    for (int c = threadIdx.x; c < nch; c += blockDim.x) {
-        chunk_node[r.chunk0 + c] = blockIdx.x;
-        if (chunk_key != nullptr)
-            chunk_key[r.chunk0 + c] =
-                perm[static_cast<size_t>(r.tree) * n + r.start + static_cast<size_t>(c) * kChunkRows];
-    }
-}
-
 // Dispatch order of a level's chunks: a counting sort by first row id >> shift
 // (at most 4096 bins; order within a bin arbitrary).  One block.
 __global__ __launch_bounds__(1024) void k_chunk_order(const int32_t* __restrict__ key, int nc,
@@ -124,13 +109,17 @@ __global__ __launch_bounds__(1024) void k_chunk_order(const int32_t* __restrict_
 }
 
 // Starting centres c0 = x[S[a]], c1 = x[S[b]] of every node; one wave each.
-// C holds per node c0[D] then c1[D] (FP64).
+// C holds per node c0[D] then c1[D] (FP64).  Also empties the level's
+// repair list.
 __global__ __launch_bounds__(64) void k_init_nodes(const NodeRec* __restrict__ nodes,
                                                    const int32_t* __restrict__ perm,
                                                    const float* __restrict__ X, int64_t n, int D,
                                                    uint64_t seed, int tree0,
                                                    double* __restrict__ C,
-                                                   int32_t* __restrict__ status) {
+                                                   int32_t* __restrict__ status,
+                                                   int32_t* __restrict__ chunk_node,
+                                                   int32_t* __restrict__ chunk_key,
+                                                   int32_t* __restrict__ rep) {
     const int node = blockIdx.x;
     const NodeRec r = nodes[node];
     const size_t base = static_cast<size_t>(r.tree) * n + r.start;
@@ -148,6 +137,15 @@ __global__ __launch_bounds__(64) void k_init_nodes(const NodeRec* __restrict__ n
         c[D + d] = static_cast<double>(x1[d]);
     }
     if (threadIdx.x == 0) status[node] = 0;
+    // the level's chunk -> node map and, when the chunks are dispatched in
+    // order of their first row id, that id (chunk_key, nullable)
+    if (blockIdx.x == 0 && threadIdx.x == 0) rep[0] = 0;
+    const int nch = chunks_of(r.size);
+    for (int ch = threadIdx.x; ch < nch; ch += blockDim.x) {
+        chunk_node[r.chunk0 + ch] = node;
+        if (chunk_key != nullptr)
+            chunk_key[r.chunk0 + ch] = perm[base + static_cast<size_t>(ch) * kChunkRows];
+    }
 }
 
 // ------------------------------------------------------------- Lloyd pass
@@ -1419,8 +1417,9 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
         const bool few_chunks = nb > 0 && (nc - (na - nb)) <= 8 * nb;
         // the order pays off on levels with many chunks only
         const bool sorted = (order_mode & 1) && nc >= order_min;
-        k_chunk_map<<<na, 64, 0, s>>>(nodes[cur], a.perm, n, chunk_node,
-                                      sorted ? chunk_key : nullptr, rep);
+        // starting pairs, the chunk -> node map (and chunk keys), repair list reset
+        k_init_nodes<<<na, 64, 0, s>>>(nodes[cur], a.perm, a.X, n, D, a.seed, a.tree0, C, status,
+                                       chunk_node, sorted ? chunk_key : nullptr, rep);
         KNNG_LAUNCH();
         if (sorted) {
             k_chunk_order<<<1, 1024, 0, s>>>(chunk_key, nc, key_shift, corder);
@@ -1432,8 +1431,6 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
         const int nwg = wide ? nc : cblocks;
         const int xper = (order_mode & 2) ? (nwg + 7) / 8 : 0;
         const unsigned agrid = static_cast<unsigned>(xper > 0 ? 8 * xper : nwg);
-        k_init_nodes<<<na, 64, 0, s>>>(nodes[cur], a.perm, a.X, n, D, a.seed, a.tree0, C, status);
-        KNNG_LAUNCH();
         for (int pass = 0; pass < a.max_iter; ++pass) {
             if (a.timer) a.timer->begin(kKAssign, s);
             if (wide)
