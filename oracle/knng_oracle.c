@@ -783,3 +783,285 @@ int orc_exact_knn_points(const float *X, int64_t n, int D, const float *Q, int64
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Inverted index from residue vector quantisation, feeding search     */
+/* seeds (Sec. 4.1-4.2, Eqns 1-3).  Readings:                          */
+/*   R14 Two RVQ stages (Eqn 1 with two terms): a vocabulary V1 of K1  */
+/*       words trained on sample rows of X, and V2 of K2 words trained */
+/*       on the sample's stage-1 residues r = x - w1[c1(x)].  Each is  */
+/*       trained by Lloyd k-means (the paper names no trainer).  The   */
+/*       sample (row ids) and the starting words (distinct positions in */
+/*       the sample, one list per stage) are inputs.                   */
+/*   R15 Quantiser distance: FP64 squared Euclidean, each term added   */
+/*       by a fused multiply-add, dimensions in increasing order from  */
+/*       0 (d64f).  The nearest word is the lowest index among equals. */
+/*   R16 Lloyd: assign; then up to `iters` rounds of (update, assign), */
+/*       stopping after a round whose codes equal the previous ones.   */
+/*       Sums run over the sample in increasing position; a word with  */
+/*       no member keeps its value; the new word is sum / count.       */
+/*   R17 Encoding: c1 = nearest V1 word of x, c2 = nearest V2 word of  */
+/*       x - w1[c1]; the index key is I = c1 * K2 + c2, and the list   */
+/*       of I holds the ids with that key in increasing id order.      */
+/*   R18 Eqn 3 as printed loses signs and a factor 2; its two terms    */
+/*       are read as the expansion of Eqn 2:                           */
+/*         term1 = (q.q - 2 w1.q) + w1.w1                              */
+/*         term2 = (2 w1.w2 + w2.w2) - 2 w2.q,   d(q, I) = term1+term2 */
+/*       with every dot product an FP64 fma chain in dimension order   */
+/*       over the FP32 query taken exactly; the factors 2 are exact,   */
+/*       so the order of each sum is the one written.                  */
+/*   R19 Cascade: keep the n1 first-stage words with the smallest      */
+/*       (term1, c1); rank their n1 * K2 keys by (d(q, I), I); walk    */
+/*       the lists in that order and take their ids as seeds until ns  */
+/*       are taken; fewer than ns are padded with -1.                  */
+/* ------------------------------------------------------------------ */
+static double d64f(const double *v, const double *w, int D)
+{
+    double s = 0.0;
+    for (int d = 0; d < D; ++d) {
+        double t = v[d] - w[d];
+        s = fma(t, t, s);
+    }
+    return s;
+}
+
+static double dot64f(const double *a, const double *b, int D)
+{
+    double s = 0.0;
+    for (int d = 0; d < D; ++d) s = fma(a[d], b[d], s);
+    return s;
+}
+
+static int nearest_word(const double *v, const double *W, int K, int D)
+{
+    int best = 0;
+    double bd = d64f(v, W, D);
+    for (int j = 1; j < K; ++j) {
+        double dj = d64f(v, W + (size_t)j * D, D);
+        if (dj < bd) {
+            bd = dj;
+            best = j;
+        }
+    }
+    return best;
+}
+
+static int64_t assign_words(const double *P, int64_t m, int D, const double *W, int K,
+                            int32_t *codes)
+{
+    int64_t changed = 0;
+#pragma omp parallel for schedule(static) reduction(+ : changed)
+    for (int64_t p = 0; p < m; ++p) {
+        int c = nearest_word(P + (size_t)p * D, W, K, D);
+        if (c != codes[p]) ++changed;
+        codes[p] = c;
+    }
+    return changed;
+}
+
+/* Lloyd k-means (R15, R16) on the rows P [m, D]; W [K, D] starts from the
+ * rows init[K] of P; codes [m] = the nearest word of each row under the
+ * final W.  Returns the number of update rounds taken, or -1. */
+int orc_kmeans(const double *P, int64_t m, int D, int K, const int32_t *init, int iters,
+               double *W, int32_t *codes)
+{
+    if (m < 1 || D < 1 || K < 1 || iters < 0) return -1;
+    for (int j = 0; j < K; ++j) {
+        if (init[j] < 0 || init[j] >= m) return -1;
+        memcpy(W + (size_t)j * D, P + (size_t)init[j] * D, sizeof(double) * (size_t)D);
+    }
+    for (int64_t p = 0; p < m; ++p) codes[p] = -1;
+    assign_words(P, m, D, W, K, codes);
+    double *sum = (double *)malloc(sizeof(double) * (size_t)K * D);
+    int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)K);
+    if (!sum || !cnt) {
+        free(sum);
+        free(cnt);
+        return -1;
+    }
+    int rounds = 0;
+    while (rounds < iters) {
+        memset(sum, 0, sizeof(double) * (size_t)K * D);
+        memset(cnt, 0, sizeof(int64_t) * (size_t)K);
+        for (int64_t p = 0; p < m; ++p) {
+            int c = codes[p];
+            ++cnt[c];
+            for (int d = 0; d < D; ++d) sum[(size_t)c * D + d] += P[(size_t)p * D + d];
+        }
+        for (int j = 0; j < K; ++j)
+            if (cnt[j] > 0)
+                for (int d = 0; d < D; ++d)
+                    W[(size_t)j * D + d] = sum[(size_t)j * D + d] / (double)cnt[j];
+        ++rounds;
+        if (assign_words(P, m, D, W, K, codes) == 0) break;
+    }
+    free(sum);
+    free(cnt);
+    return rounds;
+}
+
+/* Two-stage RVQ training (R14): sample rows train_ids[m] of X, starting
+ * positions init1[K1], init2[K2] in the sample.  Outputs W1 [K1, D],
+ * W2 [K2, D] (FP64), the sample's codes (nullable) and rounds [2]
+ * (nullable).  Returns 0 or -1. */
+int orc_rvq_train(const float *X, int64_t n, int D, const int32_t *train_ids, int64_t m,
+                  int K1, int K2, const int32_t *init1, const int32_t *init2, int iters,
+                  double *W1, double *W2, int32_t *codes1, int32_t *codes2, int32_t *rounds)
+{
+    if (m < 1 || D < 1) return -1;
+    double *P = (double *)malloc(sizeof(double) * (size_t)m * D);
+    int32_t *c1 = (int32_t *)malloc(sizeof(int32_t) * (size_t)m);
+    int32_t *c2 = (int32_t *)malloc(sizeof(int32_t) * (size_t)m);
+    int rc = -1;
+    if (!P || !c1 || !c2) goto out;
+    for (int64_t p = 0; p < m; ++p) {
+        if (train_ids[p] < 0 || train_ids[p] >= n) goto out;
+        for (int d = 0; d < D; ++d)
+            P[(size_t)p * D + d] = (double)X[(size_t)train_ids[p] * D + d];
+    }
+    int r1 = orc_kmeans(P, m, D, K1, init1, iters, W1, c1);
+    if (r1 < 0) goto out;
+    for (int64_t p = 0; p < m; ++p)
+        for (int d = 0; d < D; ++d) P[(size_t)p * D + d] -= W1[(size_t)c1[p] * D + d];
+    int r2 = orc_kmeans(P, m, D, K2, init2, iters, W2, c2);
+    if (r2 < 0) goto out;
+    if (codes1) memcpy(codes1, c1, sizeof(int32_t) * (size_t)m);
+    if (codes2) memcpy(codes2, c2, sizeof(int32_t) * (size_t)m);
+    if (rounds) {
+        rounds[0] = r1;
+        rounds[1] = r2;
+    }
+    rc = 0;
+out:
+    free(P);
+    free(c1);
+    free(c2);
+    return rc;
+}
+
+/* RVQ encoding and index key of every row (R17): key [n]. */
+int orc_rvq_encode(const float *X, int64_t n, int D, const double *W1, int K1,
+                   const double *W2, int K2, int32_t *key)
+{
+    if (n < 0 || D < 1 || K1 < 1 || K2 < 1) return -1;
+    int fail = 0;
+#pragma omp parallel
+    {
+        double *v = (double *)malloc(sizeof(double) * (size_t)D);
+        if (!v) {
+#pragma omp atomic write
+            fail = 1;
+        } else {
+#pragma omp for schedule(static)
+            for (int64_t i = 0; i < n; ++i) {
+                for (int d = 0; d < D; ++d) v[d] = (double)X[(size_t)i * D + d];
+                int c1 = nearest_word(v, W1, K1, D);
+                for (int d = 0; d < D; ++d) v[d] -= W1[(size_t)c1 * D + d];
+                int c2 = nearest_word(v, W2, K2, D);
+                key[i] = c1 * K2 + c2;
+            }
+        }
+        free(v);
+    }
+    return fail ? -1 : 0;
+}
+
+/* Inverted lists of the keys (R17): offsets [nkeys + 1], ids [n]. */
+int orc_ivf_lists(const int32_t *key, int64_t n, int nkeys, int32_t *offsets, int32_t *ids)
+{
+    if (n < 0 || nkeys < 1) return -1;
+    for (int j = 0; j <= nkeys; ++j) offsets[j] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (key[i] < 0 || key[i] >= nkeys) return -1;
+        ++offsets[key[i] + 1];
+    }
+    for (int j = 0; j < nkeys; ++j) offsets[j + 1] += offsets[j];
+    int32_t *fill = (int32_t *)malloc(sizeof(int32_t) * (size_t)nkeys);
+    if (!fill) return -1;
+    memcpy(fill, offsets, sizeof(int32_t) * (size_t)nkeys);
+    for (int64_t i = 0; i < n; ++i) ids[fill[key[i]]++] = (int32_t)i;
+    free(fill);
+    return 0;
+}
+
+/* term1 [K1] and d(q, I) [K1 * K2] of one query (R18), for every key. */
+int orc_ivf_key_dist(const float *q, int D, const double *W1, int K1, const double *W2, int K2,
+                     double *term1, double *dist)
+{
+    double *qv = (double *)malloc(sizeof(double) * (size_t)D);
+    if (!qv) return -1;
+    for (int d = 0; d < D; ++d) qv[d] = (double)q[d];
+    const double qq = dot64f(qv, qv, D);
+    for (int j = 0; j < K1; ++j) {
+        const double *w1 = W1 + (size_t)j * D;
+        term1[j] = (qq - 2.0 * dot64f(w1, qv, D)) + dot64f(w1, w1, D);
+        for (int l = 0; l < K2; ++l) {
+            const double *w2 = W2 + (size_t)l * D;
+            double term2 = (2.0 * dot64f(w1, w2, D) + dot64f(w2, w2, D)) - 2.0 * dot64f(w2, qv, D);
+            dist[(size_t)j * K2 + l] = term1[j] + term2;
+        }
+    }
+    free(qv);
+    return 0;
+}
+
+typedef struct {
+    double d;
+    int32_t key;
+} key_rank;
+
+static int key_rank_cmp(const void *a, const void *b)
+{
+    const key_rank *x = (const key_rank *)a, *y = (const key_rank *)b;
+    if (x->d < y->d) return -1;
+    if (x->d > y->d) return 1;
+    return (x->key > y->key) - (x->key < y->key);
+}
+
+/* Cascaded seeds of each query (R18, R19): seeds [nq, ns]. */
+int orc_ivf_seeds(const float *Q, int64_t nq, int D, const double *W1, int K1, const double *W2,
+                  int K2, const int32_t *offsets, const int32_t *ids, int n1, int ns,
+                  int32_t *seeds)
+{
+    if (n1 < 1 || n1 > K1 || ns < 0) return -1;
+    int fail = 0;
+#pragma omp parallel
+    {
+        double *t1 = (double *)malloc(sizeof(double) * (size_t)K1);
+        double *dist = (double *)malloc(sizeof(double) * (size_t)K1 * K2);
+        key_rank *first = (key_rank *)malloc(sizeof(key_rank) * (size_t)K1);
+        key_rank *keys = (key_rank *)malloc(sizeof(key_rank) * (size_t)n1 * K2);
+        if (!t1 || !dist || !first || !keys) {
+#pragma omp atomic write
+            fail = 1;
+        } else {
+#pragma omp for schedule(dynamic, 4)
+            for (int64_t qi = 0; qi < nq; ++qi) {
+                int32_t *out = seeds + (size_t)qi * ns;
+                orc_ivf_key_dist(Q + (size_t)qi * D, D, W1, K1, W2, K2, t1, dist);
+                for (int j = 0; j < K1; ++j) {
+                    first[j].d = t1[j];
+                    first[j].key = j;
+                }
+                qsort(first, (size_t)K1, sizeof(key_rank), key_rank_cmp);
+                for (int a = 0; a < n1; ++a)
+                    for (int l = 0; l < K2; ++l) {
+                        const int32_t I = first[a].key * K2 + l;
+                        keys[(size_t)a * K2 + l].d = dist[I];
+                        keys[(size_t)a * K2 + l].key = I;
+                    }
+                qsort(keys, (size_t)n1 * K2, sizeof(key_rank), key_rank_cmp);
+                int s = 0;
+                for (int64_t e = 0; e < (int64_t)n1 * K2 && s < ns; ++e)
+                    for (int32_t p = offsets[keys[e].key]; p < offsets[keys[e].key + 1] && s < ns; ++p)
+                        out[s++] = ids[p];
+                for (; s < ns; ++s) out[s] = -1;
+            }
+        }
+        free(t1);
+        free(dist);
+        free(first);
+        free(keys);
+    }
+    return fail ? -1 : 0;
+}

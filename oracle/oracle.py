@@ -75,6 +75,19 @@ def lib():
         L.orc_egnns.argtypes = [vp, i64, i32, vp, i32, vp, i64, vp, i32, i32, i32, i32, vp, vp]
         L.orc_exact_knn_points.restype = i32
         L.orc_exact_knn_points.argtypes = [vp, i64, i32, vp, i64, i32, vp, vp]
+        L.orc_kmeans.restype = i32
+        L.orc_kmeans.argtypes = [vp, i64, i32, i32, vp, i32, vp, vp]
+        L.orc_rvq_train.restype = i32
+        L.orc_rvq_train.argtypes = [vp, i64, i32, vp, i64, i32, i32, vp, vp, i32, vp, vp, vp, vp,
+                                    vp]
+        L.orc_rvq_encode.restype = i32
+        L.orc_rvq_encode.argtypes = [vp, i64, i32, vp, i32, vp, i32, vp]
+        L.orc_ivf_lists.restype = i32
+        L.orc_ivf_lists.argtypes = [vp, i64, i32, vp, vp]
+        L.orc_ivf_key_dist.restype = i32
+        L.orc_ivf_key_dist.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp]
+        L.orc_ivf_seeds.restype = i32
+        L.orc_ivf_seeds.argtypes = [vp, i64, i32, vp, i32, vp, i32, vp, vp, i32, i32, vp]
         L.orc_num_threads.restype = i32
         L.orc_set_num_threads.restype = None
         L.orc_set_num_threads.argtypes = [i32]
@@ -335,3 +348,90 @@ def search_recall(ids, E_ids):
     for a, b in zip(ids, E_ids):
         hit += len(set(a[a >= 0].tolist()) & set(b[b >= 0].tolist()))
     return hit / float(E_ids.shape[0] * k)
+
+
+# ---------------------------------------------------------------- RVQ index
+# Sec. 4.1-4.2 and Eqns 1-3, readings R14-R19 in knng_oracle.c.
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def kmeans(P, init, iters):
+    """Lloyd k-means (R15, R16) of the FP64 rows P from the rows init.
+    Returns (W float64 [K, D], codes int32 [m], update rounds)."""
+    P, init = _f64(P), _i32(init)
+    m, D = P.shape
+    W = np.empty((len(init), D), np.float64)
+    codes = np.empty(m, np.int32)
+    r = lib().orc_kmeans(_p(P), m, D, len(init), _p(init), iters, _p(W), _p(codes))
+    if r < 0:
+        raise ValueError("orc_kmeans")
+    return W, codes, r
+
+
+def rvq_train(X, train_ids, init1, init2, iters):
+    """Two-stage RVQ vocabularies (R14).  Returns (W1, W2, codes1, codes2,
+    rounds [2]); codes are those of the sample rows."""
+    X, train_ids, init1, init2 = _f32(X), _i32(train_ids), _i32(init1), _i32(init2)
+    m, D = len(train_ids), X.shape[1]
+    W1 = np.empty((len(init1), D), np.float64)
+    W2 = np.empty((len(init2), D), np.float64)
+    c1 = np.empty(m, np.int32)
+    c2 = np.empty(m, np.int32)
+    rounds = np.zeros(2, np.int32)
+    rc = lib().orc_rvq_train(_p(X), X.shape[0], D, _p(train_ids), m, len(init1), len(init2),
+                             _p(init1), _p(init2), iters, _p(W1), _p(W2), _p(c1), _p(c2),
+                             _p(rounds))
+    if rc != 0:
+        raise ValueError("orc_rvq_train")
+    return W1, W2, c1, c2, rounds
+
+
+def rvq_encode(X, W1, W2):
+    """Index key c1 * K2 + c2 of every row (R17)."""
+    X, W1, W2 = _f32(X), _f64(W1), _f64(W2)
+    key = np.empty(X.shape[0], np.int32)
+    rc = lib().orc_rvq_encode(_p(X), X.shape[0], X.shape[1], _p(W1), W1.shape[0], _p(W2),
+                              W2.shape[0], _p(key))
+    assert rc == 0
+    return key
+
+
+def ivf_lists(key, nkeys):
+    """Inverted lists (R17): (offsets int32 [nkeys + 1], ids int32 [n])."""
+    key = _i32(key)
+    offsets = np.empty(nkeys + 1, np.int32)
+    ids = np.empty(len(key), np.int32)
+    rc = lib().orc_ivf_lists(_p(key), len(key), nkeys, _p(offsets), _p(ids))
+    if rc != 0:
+        raise ValueError("orc_ivf_lists")
+    return offsets, ids
+
+
+def ivf_key_dist(q, W1, W2):
+    """term1 [K1] and d(q, I) [K1, K2] of one query (R18)."""
+    q = _f32(np.asarray(q).reshape(1, -1))
+    W1, W2 = _f64(W1), _f64(W2)
+    t1 = np.empty(W1.shape[0], np.float64)
+    dist = np.empty((W1.shape[0], W2.shape[0]), np.float64)
+    rc = lib().orc_ivf_key_dist(_p(q), q.shape[1], _p(W1), W1.shape[0], _p(W2), W2.shape[0],
+                                _p(t1), _p(dist))
+    assert rc == 0
+    return t1, dist
+
+
+def ivf_seeds(Q, W1, W2, offsets, ids, n1, ns):
+    """Cascaded seeds of each query (R18, R19): int32 [nq, ns], -1 padded."""
+    Q, W1, W2 = _f32(Q), _f64(W1), _f64(W2)
+    offsets, ids = _i32(offsets), _i32(ids)
+    out = np.empty((Q.shape[0], ns), np.int32)
+    rc = lib().orc_ivf_seeds(_p(Q), Q.shape[0], Q.shape[1], _p(W1), W1.shape[0], _p(W2),
+                             W2.shape[0], _p(offsets), _p(ids), n1, ns, _p(out))
+    if rc != 0:
+        raise ValueError("orc_ivf_seeds")
+    return out

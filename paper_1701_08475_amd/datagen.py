@@ -135,3 +135,15 @@ def random_points(n, D, seed, kind="normal"):
     if kind == "small_int":
         return rng.integers(0, 4, size=(n, D)).astype(np.float32)
     raise ValueError(kind)
+
+
+def rvq_sample(n, m, K1, K2, seed=91):
+    """Training sample of the RVQ vocabularies: m distinct row ids of [0, n)
+    in increasing order, and the starting words of each stage as K1 and K2
+    distinct positions in that sample."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = min(m, n)
+    train = np.sort(rng.choice(n, size=m, replace=False)).astype(np.int32)
+    init1 = rng.choice(m, size=K1, replace=False).astype(np.int32)
+    init2 = rng.choice(m, size=K2, replace=False).astype(np.int32)
+    return train, init1, init2
