@@ -201,6 +201,69 @@ int knng_search(const float* data, int64_t n, int32_t D, const int32_t* graph, i
                 int32_t rounds, int32_t* ids_out, float* dists_out, hipStream_t stream);
 
 /*
+ * Inverted index for search seeds (Sec. 4.1-4.2, Eqns 1-3).  A point is
+ * encoded by two-stage residue vector quantisation (Eqn 1 with two terms): c1
+ * is its nearest word in the first vocabulary, c2 the nearest word of the
+ * second to its residue x - w1[c1]; the index key is c1 * K2 + c2.  All
+ * quantiser arithmetic is FP64: squared distances add each term with a fused
+ * multiply-add in increasing dimension order, and the lowest word index wins
+ * among equal distances.  Vocabularies are row-major double[K][D].
+ *
+ * knng_rvq_train -- train both vocabularies by Lloyd k-means: stage 1 on the
+ * sample rows, stage 2 on their stage-1 residues.  Each stage starts from the
+ * given sample positions, then repeats (update, assign) at most `iters` times,
+ * stopping after a round that changes no code.  The update adds the members of
+ * each word in increasing sample position and divides by their count; a word
+ * without members keeps its value.
+ *   data        device, float[n][D] (16-byte aligned)
+ *   train_ids   device, int32[m]: sample rows of data, 1 <= m <= n
+ *   init1/init2 device, int32[K1] / int32[K2]: starting words as positions in
+ *               the sample, in [0, m); K1, K2 in [1, 256]
+ *   words1_out  device, double[K1][D]; words2_out device, double[K2][D]
+ *   codes1_out, codes2_out  device, int32[m], nullable: final codes of the sample
+ *   rounds_out  host, int32[2], nullable: update rounds taken per stage
+ * Out-of-range ids or positions give KNNG_ERR_INVALID_ARG before any output
+ * is written.  NaN/Inf inputs are not checked.
+ */
+int knng_rvq_train(const float* data, int64_t n, int32_t D, const int32_t* train_ids, int64_t m,
+                   int32_t K1, int32_t K2, const int32_t* init1, const int32_t* init2,
+                   int32_t iters, double* words1_out, double* words2_out, int32_t* codes1_out,
+                   int32_t* codes2_out, int32_t* rounds_out, hipStream_t stream);
+
+/*
+ * knng_ivf_build -- encode every point and build the inverted lists.
+ *   keys_out     device, int32[n], nullable: c1 * K2 + c2 of every point
+ *   offsets_out  device, int32[K1 K2 + 1]: list I is ids_out[offsets[I],
+ *                offsets[I + 1])
+ *   ids_out      device, int32[n]: point ids grouped by key, increasing
+ *                within each list
+ */
+int knng_ivf_build(const float* data, int64_t n, int32_t D, const double* words1, int32_t K1,
+                   const double* words2, int32_t K2, int32_t* keys_out, int32_t* offsets_out,
+                   int32_t* ids_out, hipStream_t stream);
+
+/*
+ * knng_ivf_seeds -- cascaded seeds of a batch of queries (Eqn 3).  Per query
+ * q, term 1 = (q.q - 2 w1.q) + w1.w1 is ranked over the first vocabulary; under
+ * the n1 best words every key I gets d(q, I) = term 1 + ((2 w1.w2 + w2.w2) -
+ * 2 w2.q), which equals |q - w1 - w2|^2 (Eqn 2); keys are ranked by
+ * (d(q, I), I) and their lists walked in that order, their ids taken as seeds
+ * until ns are taken.  Dot products are FP64 fma chains in dimension order
+ * over the FP32 query.
+ *   queries      device, float[nq][D]
+ *   offsets      device, int32[K1 K2 + 1], ids device, int32[n_ids]: the
+ *                lists of knng_ivf_build; malformed offsets (not rising from
+ *                0 to n_ids) give KNNG_ERR_INVALID_ARG
+ *   n1           first-stage words kept, 1 <= n1 <= K1, n1 K2 <= 4096
+ *   seeds_out    device, int32[nq][ns], padded with -1 when the visited lists
+ *                hold fewer than ns ids; suitable as knng_search's seeds
+ */
+int knng_ivf_seeds(const float* queries, int64_t nq, int32_t D, const double* words1, int32_t K1,
+                   const double* words2, int32_t K2, const int32_t* offsets, const int32_t* ids,
+                   int64_t n_ids, int32_t n1, int32_t ns, int32_t* seeds_out,
+                   hipStream_t stream);
+
+/*
  * knng_release_workspace -- free the scratch blocks the library keeps cached
  * for the current device (none is in use when no call is running).
  */

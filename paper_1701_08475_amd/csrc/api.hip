@@ -712,3 +712,97 @@ extern "C" void knng_release_workspace(void) {
     knng::DeviceLock dlock;
     knng::ws_release_device(dlock.device());
 }
+
+// ---------------------------------------------------------------- RVQ index
+
+extern "C" int knng_rvq_train(const float* data, int64_t n, int32_t D, const int32_t* train_ids,
+                              int64_t m, int32_t K1, int32_t K2, const int32_t* init1,
+                              const int32_t* init2, int32_t iters, double* words1_out,
+                              double* words2_out, int32_t* codes1_out, int32_t* codes2_out,
+                              int32_t* rounds_out, hipStream_t stream) {
+    g_err[0] = '\0';
+    if (data == nullptr || train_ids == nullptr || init1 == nullptr || init2 == nullptr ||
+        words1_out == nullptr || words2_out == nullptr)
+        return set_err(KNNG_ERR_INVALID_ARG, "null pointer argument");
+    if (n < 1 || n > 2147483647LL)
+        return set_err(KNNG_ERR_INVALID_ARG, "n=%lld out of [1, 2^31-1]", static_cast<long long>(n));
+    if (D < 1 || D > knng::kMaxDim)
+        return set_err(D < 1 ? KNNG_ERR_INVALID_ARG : KNNG_ERR_UNSUPPORTED, "D=%d out of [1, %d]", D,
+                       knng::kMaxDim);
+    if (m < 1 || m > n)
+        return set_err(KNNG_ERR_INVALID_ARG, "training rows m=%lld out of [1, n]",
+                       static_cast<long long>(m));
+    if (K1 < 1 || K2 < 1 || K1 > knng::kRvqMaxWords || K2 > knng::kRvqMaxWords)
+        return set_err(K1 < 1 || K2 < 1 ? KNNG_ERR_INVALID_ARG : KNNG_ERR_UNSUPPORTED,
+                       "vocabulary sizes K1=%d, K2=%d out of [1, %d]", K1, K2, knng::kRvqMaxWords);
+    if (iters < 0) return set_err(KNNG_ERR_INVALID_ARG, "iters=%d must be >= 0", iters);
+    knng::DeviceLock dlock;
+    int rounds[2] = {0, 0};
+    knng::RvqTrainArgs ra{data, n, D, train_ids, m, K1, K2, init1, init2, iters, words1_out,
+                          words2_out, codes1_out, codes2_out, rounds, stream};
+    char err[400] = "";
+    const int rc = knng::rvq_train_run(ra, err, sizeof(err));
+    if (rc != KNNG_OK) return set_err(rc, "rvq train: %s", err);
+    if (rounds_out != nullptr) {
+        rounds_out[0] = rounds[0];
+        rounds_out[1] = rounds[1];
+    }
+    return KNNG_OK;
+}
+
+extern "C" int knng_ivf_build(const float* data, int64_t n, int32_t D, const double* words1,
+                              int32_t K1, const double* words2, int32_t K2, int32_t* keys_out,
+                              int32_t* offsets_out, int32_t* ids_out, hipStream_t stream) {
+    g_err[0] = '\0';
+    if (data == nullptr || words1 == nullptr || words2 == nullptr || offsets_out == nullptr ||
+        (ids_out == nullptr && n > 0))
+        return set_err(KNNG_ERR_INVALID_ARG, "null pointer argument");
+    if (n < 0 || n > 2147483647LL)
+        return set_err(KNNG_ERR_INVALID_ARG, "n=%lld out of [0, 2^31-1]", static_cast<long long>(n));
+    if (D < 1 || D > knng::kMaxDim)
+        return set_err(D < 1 ? KNNG_ERR_INVALID_ARG : KNNG_ERR_UNSUPPORTED, "D=%d out of [1, %d]", D,
+                       knng::kMaxDim);
+    if (K1 < 1 || K2 < 1 || K1 > knng::kRvqMaxWords || K2 > knng::kRvqMaxWords)
+        return set_err(K1 < 1 || K2 < 1 ? KNNG_ERR_INVALID_ARG : KNNG_ERR_UNSUPPORTED,
+                       "vocabulary sizes K1=%d, K2=%d out of [1, %d]", K1, K2, knng::kRvqMaxWords);
+    knng::DeviceLock dlock;
+    knng::IvfBuildArgs ba{data, n, D, words1, K1, words2, K2, keys_out, offsets_out, ids_out, stream};
+    char err[400] = "";
+    const int rc = knng::ivf_build_run(ba, err, sizeof(err));
+    if (rc != KNNG_OK) return set_err(rc, "ivf build: %s", err);
+    return KNNG_OK;
+}
+
+extern "C" int knng_ivf_seeds(const float* queries, int64_t nq, int32_t D, const double* words1,
+                              int32_t K1, const double* words2, int32_t K2, const int32_t* offsets,
+                              const int32_t* ids, int64_t n_ids, int32_t n1, int32_t ns,
+                              int32_t* seeds_out, hipStream_t stream) {
+    g_err[0] = '\0';
+    if (queries == nullptr || words1 == nullptr || words2 == nullptr || offsets == nullptr ||
+        seeds_out == nullptr || (ids == nullptr && n_ids > 0))
+        return set_err(KNNG_ERR_INVALID_ARG, "null pointer argument");
+    if (nq < 0 || nq > 2147483647LL)
+        return set_err(KNNG_ERR_INVALID_ARG, "nq=%lld out of [0, 2^31-1]", static_cast<long long>(nq));
+    if (n_ids < 0 || n_ids > 2147483647LL)
+        return set_err(KNNG_ERR_INVALID_ARG, "n_ids=%lld out of [0, 2^31-1]",
+                       static_cast<long long>(n_ids));
+    if (D < 1 || D > knng::kMaxDim)
+        return set_err(D < 1 ? KNNG_ERR_INVALID_ARG : KNNG_ERR_UNSUPPORTED, "D=%d out of [1, %d]", D,
+                       knng::kMaxDim);
+    if (K1 < 1 || K2 < 1 || K1 > knng::kRvqMaxWords || K2 > knng::kRvqMaxWords)
+        return set_err(K1 < 1 || K2 < 1 ? KNNG_ERR_INVALID_ARG : KNNG_ERR_UNSUPPORTED,
+                       "vocabulary sizes K1=%d, K2=%d out of [1, %d]", K1, K2, knng::kRvqMaxWords);
+    if (n1 < 1 || n1 > K1) return set_err(KNNG_ERR_INVALID_ARG, "n1=%d out of [1, K1=%d]", n1, K1);
+    if (n1 * K2 > knng::kSeedMaxKeys)
+        return set_err(KNNG_ERR_UNSUPPORTED, "n1 x K2 = %d keys exceeds %d", n1 * K2,
+                       knng::kSeedMaxKeys);
+    if (ns < 1 || ns > (1 << 20))
+        return set_err(KNNG_ERR_INVALID_ARG, "seeds per query %d out of [1, 2^20]", ns);
+    knng::DeviceLock dlock;
+    knng::IvfSeedArgs sa{queries, nq, D, words1, K1, words2, K2, offsets, ids, n_ids, n1, ns,
+                         seeds_out, stream};
+    char err[400] = "";
+    const int rc = knng::ivf_seeds_run(sa, err, sizeof(err));
+    if (rc != KNNG_OK) return set_err(rc, "ivf seeds: %s", err);
+    return KNNG_OK;
+}

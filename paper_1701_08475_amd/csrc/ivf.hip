@@ -1,0 +1,622 @@
+// Inverted index from two-stage residue vector quantisation (Sec. 4.1-4.2,
+// Eqns 1-3) and the cascaded search seeds it supplies.
+//
+//  - k_nearest: the nearest vocabulary word of each point in FP64, every term
+//    of the squared distance added by a fused multiply-add in dimension
+//    order, the lowest index among equal distances.  One thread per point;
+//    the words pass through LDS in tiles of 32 words x 16 dimensions, stored
+//    dimension-major so all lanes read the same two words (a broadcast).  A
+//    point is a row of X (stage 1) or its stage-1 residue x - w1[c1]
+//    (stage 2), formed on the fly.
+//  - Lloyd's update: the training positions are bucketed by code with a
+//    stable counting sort, then one thread per (word, dimension) adds its
+//    members in increasing position and divides by their count.
+//  - Inverted lists: a stable radix sort of the keys, 8 bits a pass, carries
+//    the point ids, so every list comes out in increasing id order.
+//  - Seeds: one workgroup per query computes the query's dot products with
+//    all words, term 1 of every first-stage word, the n1 best, d(q, I) of the
+//    n1 x K2 keys under them, sorts the keys, scans the list sizes in that
+//    order and takes the first ns ids.
+#include "knng_internal.hpp"
+#include "wave.hpp"
+
+#include <climits>
+#include <cstdio>
+
+namespace knng {
+namespace {
+
+constexpr int kNearThreads = 256;
+constexpr int kTJ = 32;  // words per LDS tile
+constexpr int kDC = 16;  // dimensions per LDS tile
+constexpr int kSortB = 2048;  // elements per block of the stable digit sort
+constexpr int kSortT = 256;
+constexpr int kSeedThreads = 256;
+
+// codes[p] <- the nearest word of W [K][D] to point p, whose value is
+// X[row(p)][d] - (W1 ? W1[c1[p]][d] : 0) with row(p) = rows ? rows[p] : p.
+// changed (nullable) counts the points whose code differs from codes[p] on
+// entry; codes (nullable) is written; key_out (nullable) <- c1[p] * K2 + code.
+__global__ __launch_bounds__(kNearThreads) void k_nearest(
+    const float* __restrict__ X, int D, const int32_t* __restrict__ rows, int64_t m,
+    const double* __restrict__ W1, const int32_t* __restrict__ c1, const double* __restrict__ W,
+    int K, int32_t* __restrict__ codes, int32_t* __restrict__ changed, int32_t* __restrict__ key_out,
+    int K2) {
+    __shared__ __align__(16) double s_w[kDC][kTJ];
+    const int64_t p = blockIdx.x * static_cast<int64_t>(kNearThreads) + threadIdx.x;
+    const bool live = p < m;
+    const int64_t row = live ? (rows != nullptr ? rows[p] : p) : 0;
+    const float* x = X + row * D;
+    const int32_t base = (W1 != nullptr && live) ? c1[p] : 0;
+    const double* r = W1 != nullptr ? W1 + static_cast<size_t>(base) * D : nullptr;
+    double best = 0.0;
+    int bj = 0;
+    for (int j0 = 0; j0 < K; j0 += kTJ) {
+        double acc[kTJ];
+#pragma unroll
+        for (int j = 0; j < kTJ; ++j) acc[j] = 0.0;
+        for (int d0 = 0; d0 < D; d0 += kDC) {
+            double v[kDC];
+#pragma unroll
+            for (int dd = 0; dd < kDC; ++dd) {
+                const int d = d0 + dd;
+                double xv = 0.0;
+                if (live && d < D) {
+                    xv = static_cast<double>(x[d]);
+                    if (r != nullptr) xv = __dsub_rn(xv, r[d]);
+                }
+                v[dd] = xv;
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < kDC * kTJ; e += kNearThreads) {
+                const int dd = e / kTJ, j = e % kTJ;
+                const int d = d0 + dd, jj = j0 + j;
+                s_w[dd][j] = (d < D && jj < K) ? W[static_cast<size_t>(jj) * D + d] : 0.0;
+            }
+            __syncthreads();
+            // padding dimensions give t = 0 and leave the sums unchanged
+#pragma unroll
+            for (int dd = 0; dd < kDC; ++dd) {
+#pragma unroll
+                for (int j = 0; j < kTJ; j += 2) {
+                    const double2 w = *reinterpret_cast<const double2*>(&s_w[dd][j]);
+                    const double t0 = __dsub_rn(v[dd], w.x);
+                    const double t1 = __dsub_rn(v[dd], w.y);
+                    acc[j] = __fma_rn(t0, t0, acc[j]);
+                    acc[j + 1] = __fma_rn(t1, t1, acc[j + 1]);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kTJ; ++j)
+            if (j0 + j < K && (j0 + j == 0 || acc[j] < best)) {
+                best = acc[j];
+                bj = j0 + j;
+            }
+    }
+    if (changed != nullptr) {
+        const bool ch = live && codes[p] != bj;
+        const uint64_t mask = __ballot(ch);
+        if (lane_id() == 0 && mask != 0) atomicAdd(changed, static_cast<int32_t>(__popcll(mask)));
+    }
+    if (!live) return;
+    if (codes != nullptr) codes[p] = bj;
+    if (key_out != nullptr) key_out[p] = base * K2 + bj;
+}
+
+// W[j] <- value of training position init[j] (as in k_nearest).
+__global__ void k_init_words(const float* __restrict__ X, int D, const int32_t* __restrict__ rows,
+                             const double* __restrict__ W1, const int32_t* __restrict__ c1,
+                             const int32_t* __restrict__ init, double* __restrict__ W) {
+    const int j = blockIdx.x;
+    const int32_t p = init[j];
+    const int64_t row = rows[p];
+    for (int d = threadIdx.x; d < D; d += blockDim.x) {
+        double v = static_cast<double>(X[row * D + d]);
+        if (W1 != nullptr) v = __dsub_rn(v, W1[static_cast<size_t>(c1[p]) * D + d]);
+        W[static_cast<size_t>(j) * D + d] = v;
+    }
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ a, int64_t count, int32_t v) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < count;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        a[i] = v;
+}
+
+// bad <- 1 if some a[i] lies outside [lo, hi).
+__global__ void k_check_range(const int32_t* __restrict__ a, int64_t count, int64_t lo, int64_t hi,
+                              int32_t* __restrict__ bad) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < count;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        if (a[i] < lo || a[i] >= hi) atomicOr(bad, 1);
+}
+
+// bad <- 1 unless off[0] = 0, off is non-decreasing and off[nk] = total.
+__global__ void k_check_offsets(const int32_t* __restrict__ off, int nk, int64_t total,
+                                int32_t* __restrict__ bad) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nk; i += gridDim.x * blockDim.x)
+        if (off[i + 1] < off[i] || (i == 0 && off[0] != 0) || (i == nk - 1 && off[nk] != total))
+            atomicOr(bad, 1);
+}
+
+// ------------------------------------------------------ stable digit sort
+// hist[dig * nb + b] <- elements of block b whose digit (key >> shift) & 255 is dig.
+__global__ __launch_bounds__(kSortT) void k_digit_count(const int32_t* __restrict__ key, int64_t m,
+                                                        int shift, int nb, int32_t* __restrict__ hist) {
+    __shared__ int32_t cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kSortB;
+    for (int i = threadIdx.x; i < kSortB; i += kSortT) {
+        const int64_t e = b0 + i;
+        if (e < m) atomicAdd(&cnt[(key[e] >> shift) & 255], 1);
+    }
+    __syncthreads();
+    hist[static_cast<int64_t>(threadIdx.x) * nb + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// In-place exclusive prefix sum of a[0, T) (one workgroup).
+__global__ __launch_bounds__(1024) void k_scan_excl(int32_t* __restrict__ a, int64_t T) {
+    __shared__ int32_t part[1024];
+    const int64_t per = (T + 1023) / 1024;
+    const int64_t lo = threadIdx.x * per;
+    const int64_t hi = lo + per < T ? lo + per : T;
+    int32_t s = 0;
+    for (int64_t i = lo; i < hi; ++i) s += a[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int32_t v = threadIdx.x >= static_cast<unsigned>(off) ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
+    for (int64_t i = lo; i < hi; ++i) {
+        const int32_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+}
+
+// Stable scatter by digit: block b places its elements, in order, at the
+// scanned bases of hist.  val (nullable) defaults to the element index.
+// Within a wave, lanes of equal digit are ranked by a match mask built from
+// eight ballots; the block's four waves take their turn in order.
+__global__ __launch_bounds__(kSortT) void k_digit_scatter(
+    const int32_t* __restrict__ key, const int32_t* __restrict__ val, int64_t m, int shift, int nb,
+    const int32_t* __restrict__ hist, int32_t* __restrict__ key_out, int32_t* __restrict__ val_out) {
+    __shared__ int32_t base[256];
+    base[threadIdx.x] = hist[static_cast<int64_t>(threadIdx.x) * nb + blockIdx.x];
+    __syncthreads();
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kSortB;
+    for (int t0 = 0; t0 < kSortB; t0 += kSortT) {
+        const int64_t e = b0 + t0 + threadIdx.x;
+        const bool ok = e < m;
+        const int32_t k = ok ? key[e] : 0;
+        const int32_t v = ok ? (val != nullptr ? val[e] : static_cast<int32_t>(e)) : 0;
+        const int dig = (k >> shift) & 255;
+        uint64_t same = __ballot(ok);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const uint64_t bb = __ballot((dig >> bit) & 1);
+            same &= ((dig >> bit) & 1) ? bb : ~bb;
+        }
+        const int rank = __popcll(same & ((1ull << lane) - 1ull));
+        const int cnt = __popcll(same);
+        for (int w = 0; w < kSortT / kWave; ++w) {
+            if (wave == w && ok) {
+                const int32_t pos = base[dig] + rank;
+                key_out[pos] = k;
+                val_out[pos] = v;
+                if (rank == cnt - 1) base[dig] = pos + 1;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// off[kk] <- first position whose sorted key is >= kk, kk in [0, nk]
+// (off[nk] = m).  Keys in [0, nk), ascending.
+__global__ void k_key_offsets(const int32_t* __restrict__ skey, int64_t m, int nk,
+                              int32_t* __restrict__ off) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i <= m;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int32_t lo = i == 0 ? 0 : skey[i - 1] + 1;
+        const int32_t hi = i == m ? nk : skey[i];
+        for (int32_t kk = lo; kk <= hi; ++kk) off[kk] = static_cast<int32_t>(i);
+    }
+}
+
+// W[j][d] <- mean of the values of the members of word j, added in
+// increasing position; a word without members keeps its value.
+// Grid (K, ceil(D / 64)), 64 threads.
+__global__ void k_word_means(const float* __restrict__ X, int D, const int32_t* __restrict__ rows,
+                             const double* __restrict__ W1, const int32_t* __restrict__ c1,
+                             const int32_t* __restrict__ order, const int32_t* __restrict__ woff,
+                             double* __restrict__ W) {
+    const int j = blockIdx.x;
+    const int d = blockIdx.y * blockDim.x + threadIdx.x;
+    if (d >= D) return;
+    const int32_t a = woff[j], b = woff[j + 1];
+    if (b <= a) return;
+    double s = 0.0;
+    for (int32_t i = a; i < b; ++i) {
+        const int32_t p = order[i];
+        double v = static_cast<double>(X[static_cast<int64_t>(rows[p]) * D + d]);
+        if (W1 != nullptr) v = __dsub_rn(v, W1[static_cast<size_t>(c1[p]) * D + d]);
+        s = __dadd_rn(s, v);
+    }
+    W[static_cast<size_t>(j) * D + d] = s / static_cast<double>(b - a);
+}
+
+// -------------------------------------------------------------- seeds
+// x12[j][l] = w1_j . w2_l, nw1[j] = w1_j . w1_j, nw2[l] = w2_l . w2_l (fma
+// chains in dimension order) and the dimension-major copies W1T [D][K1],
+// W2T [D][K2].  Grid K1, 256 threads (K2 <= 256).
+__global__ __launch_bounds__(256) void k_ivf_tables(const double* __restrict__ W1, int K1,
+                                                    const double* __restrict__ W2, int K2, int D,
+                                                    double* __restrict__ x12, double* __restrict__ nw1,
+                                                    double* __restrict__ nw2, double* __restrict__ W1T,
+                                                    double* __restrict__ W2T) {
+    const int j = blockIdx.x;
+    const int l = threadIdx.x;
+    const double* w1 = W1 + static_cast<size_t>(j) * D;
+    if (l < K2) {
+        const double* w2 = W2 + static_cast<size_t>(l) * D;
+        double s = 0.0;
+        for (int d = 0; d < D; ++d) s = __fma_rn(w1[d], w2[d], s);
+        x12[static_cast<size_t>(j) * K2 + l] = s;
+        if (j == 0) {
+            double t = 0.0;
+            for (int d = 0; d < D; ++d) t = __fma_rn(w2[d], w2[d], t);
+            nw2[l] = t;
+        }
+        for (int d = j; d < D; d += gridDim.x) W2T[static_cast<size_t>(d) * K2 + l] = w2[d];
+    }
+    if (l == 0) {
+        double t = 0.0;
+        for (int d = 0; d < D; ++d) t = __fma_rn(w1[d], w1[d], t);
+        nw1[j] = t;
+    }
+    for (int d = l; d < D; d += blockDim.x) W1T[static_cast<size_t>(d) * K1 + j] = w1[d];
+}
+
+__device__ __forceinline__ bool dk_less(double da, int32_t ka, double db, int32_t kb) {
+    return da < db || (da == db && ka < kb);
+}
+
+// Ascending bitonic sort of (d, k) pairs, N a power of two (whole block).
+__device__ void bitonic_dk(double* d, int32_t* k, int N) {
+    for (int size = 2; size <= N; size <<= 1)
+        for (int stride = size >> 1; stride >= 1; stride >>= 1) {
+            for (int i = threadIdx.x; i < (N >> 1); i += blockDim.x) {
+                const int lo = 2 * i - (i & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                if (dk_less(d[hi], k[hi], d[lo], k[lo]) == up) {
+                    const double td = d[lo];
+                    d[lo] = d[hi];
+                    d[hi] = td;
+                    const int32_t tk = k[lo];
+                    k[lo] = k[hi];
+                    k[hi] = tk;
+                }
+            }
+            __syncthreads();
+        }
+}
+
+struct SeedShape {
+    int p1;  // power of two >= K1
+    int p2;  // power of two >= n1 * K2
+};
+
+size_t seed_lds_bytes(const SeedShape& sh, int D) {
+    return 12 * static_cast<size_t>(sh.p2) + 8 * static_cast<size_t>(D) + 2 * 8 * 256 +
+           12 * static_cast<size_t>(sh.p1);
+}
+
+__global__ __launch_bounds__(kSeedThreads) void k_ivf_seeds(
+    const float* __restrict__ Q, int D, const double* __restrict__ W1T, int K1,
+    const double* __restrict__ W2T, int K2, const double* __restrict__ x12,
+    const double* __restrict__ nw1, const double* __restrict__ nw2, const int32_t* __restrict__ off,
+    const int32_t* __restrict__ ids, int n1, int ns, SeedShape sh, int32_t* __restrict__ seeds) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* sd = reinterpret_cast<double*>(smem);         // [p2] key distances
+    int32_t* sc = reinterpret_cast<int32_t*>(smem);        // [p2] list-size scan (after the sort)
+    int32_t* sk = reinterpret_cast<int32_t*>(sd + sh.p2);  // [p2] keys
+    double* q = reinterpret_cast<double*>(sk + sh.p2);     // [D]
+    double* ip1 = q + D;                                   // [256] w1.q, then term 1
+    double* ip2 = ip1 + 256;                               // [256] w2.q
+    double* fd = ip2 + 256;                                // [p1] term 1, sorted
+    int32_t* fk = reinterpret_cast<int32_t*>(fd + sh.p1);  // [p1] first-stage words, sorted
+    __shared__ double s_qq;
+    __shared__ int32_t s_part[kSeedThreads];
+
+    const int tid = threadIdx.x;
+    const int64_t qi = blockIdx.x;
+    for (int d = tid; d < D; d += kSeedThreads) q[d] = static_cast<double>(Q[qi * D + d]);
+    __syncthreads();
+    if (tid < K1) {
+        double s = 0.0;
+        for (int d = 0; d < D; ++d) s = __fma_rn(W1T[static_cast<size_t>(d) * K1 + tid], q[d], s);
+        ip1[tid] = s;
+    }
+    if (tid < K2) {
+        double s = 0.0;
+        for (int d = 0; d < D; ++d) s = __fma_rn(W2T[static_cast<size_t>(d) * K2 + tid], q[d], s);
+        ip2[tid] = s;
+    }
+    if (tid == 0) {
+        double s = 0.0;
+        for (int d = 0; d < D; ++d) s = __fma_rn(q[d], q[d], s);
+        s_qq = s;
+    }
+    __syncthreads();
+    // term 1 = (q.q - 2 w1.q) + w1.w1 of every first-stage word
+    if (tid < K1) ip1[tid] = __dadd_rn(__dsub_rn(s_qq, __dmul_rn(2.0, ip1[tid])), nw1[tid]);
+    __syncthreads();
+    for (int j = tid; j < sh.p1; j += kSeedThreads) {
+        fd[j] = j < K1 ? ip1[j] : __longlong_as_double(0x7ff0000000000000ll);
+        fk[j] = j < K1 ? j : INT_MAX;
+    }
+    __syncthreads();
+    bitonic_dk(fd, fk, sh.p1);
+    // d(q, I) = term 1 + ((2 w1.w2 + w2.w2) - 2 w2.q) of the keys under the n1 best
+    const int M = n1 * K2;
+    const int nk = K1 * K2;
+    for (int e = tid; e < sh.p2; e += kSeedThreads) {
+        const int a = e / K2, l = e % K2;
+        const int j = e < M ? fk[a] : INT_MAX;
+        if (j < K1) {  // a padding word can only rank this high if term 1 is NaN
+            const double t2 = __dsub_rn(
+                __dadd_rn(__dmul_rn(2.0, x12[static_cast<size_t>(j) * K2 + l]), nw2[l]),
+                __dmul_rn(2.0, ip2[l]));
+            sd[e] = __dadd_rn(ip1[j], t2);
+            sk[e] = j * K2 + l;
+        } else {
+            sd[e] = __longlong_as_double(0x7ff0000000000000ll);
+            sk[e] = INT_MAX;
+        }
+    }
+    __syncthreads();
+    bitonic_dk(sd, sk, sh.p2);
+    // inclusive scan of the list sizes in key order (sc overwrites sd)
+    const int per = (sh.p2 + kSeedThreads - 1) / kSeedThreads;
+    const int lo = tid * per;
+    const int hi = lo + per < M ? lo + per : M;
+    int32_t run = 0;
+    // keys of padding words (NaN input only) count as empty lists
+    auto list_size = [&](int e) { return sk[e] < nk ? off[sk[e] + 1] - off[sk[e]] : 0; };
+    for (int e = lo; e < hi; ++e) run += list_size(e);
+    s_part[tid] = run;
+    __syncthreads();
+    for (int o = 1; o < kSeedThreads; o <<= 1) {
+        const int32_t v = tid >= o ? s_part[tid - o] : 0;
+        __syncthreads();
+        s_part[tid] += v;
+        __syncthreads();
+    }
+    run = tid ? s_part[tid - 1] : 0;
+    for (int e = lo; e < hi; ++e) {
+        run += list_size(e);
+        sc[e] = run;
+    }
+    __syncthreads();
+    const int32_t total = M > 0 ? sc[M - 1] : 0;
+    for (int s = tid; s < ns; s += kSeedThreads) {
+        int32_t out = -1;
+        if (s < total) {
+            int a = 0, b = M - 1;  // first e with sc[e] > s
+            while (a < b) {
+                const int mid = (a + b) >> 1;
+                if (sc[mid] > s) b = mid;
+                else a = mid + 1;
+            }
+            const int32_t before = a ? sc[a - 1] : 0;
+            out = ids[off[sk[a]] + (s - before)];
+        }
+        seeds[qi * ns + s] = out;
+    }
+}
+
+int nblocks(int64_t count, int per) { return static_cast<int>((count + per - 1) / per); }
+
+// Stable sort of (key, val) by the digit at shift (val nullable: index).
+void digit_pass(const int32_t* key, const int32_t* val, int64_t m, int shift, int32_t* hist,
+                int32_t* key_out, int32_t* val_out, hipStream_t s) {
+    const int nb = nblocks(m, kSortB);
+    k_digit_count<<<nb, kSortT, 0, s>>>(key, m, shift, nb, hist);
+    k_scan_excl<<<1, 1024, 0, s>>>(hist, 256 * static_cast<int64_t>(nb));
+    k_digit_scatter<<<nb, kSortT, 0, s>>>(key, val, m, shift, nb, hist, key_out, val_out);
+}
+
+struct Ws {
+    hipStream_t s;
+    void* blk[16] = {};
+    int nblk = 0;
+    hipError_t e = hipSuccess;
+    template <class T>
+    T* get(size_t count) {
+        void* p = nullptr;
+        if (e == hipSuccess) e = ws_malloc(&p, count * sizeof(T) + 16, s);
+        if (e == hipSuccess) blk[nblk++] = p;
+        return static_cast<T*>(p);
+    }
+    ~Ws() {
+        for (int i = 0; i < nblk; ++i) ws_free(blk[i], s);
+    }
+};
+
+int finish(hipError_t e, const char* what, char* err, size_t errlen) {
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) {
+        std::snprintf(err, errlen, "%s: %s", what, hipGetErrorString(e));
+        return kHip;
+    }
+    return kOk;
+}
+
+// One Lloyd run (R16) over the training positions; W holds the start words.
+int kmeans_run(const float* X, int D, const int32_t* rows, int64_t m, const double* W1,
+               const int32_t* c1, double* W, int K, int iters, int32_t* codes, int32_t* skey,
+               int32_t* order, int32_t* hist, int32_t* woff, int32_t* dchanged, int* rounds_out,
+               hipStream_t s, char* err, size_t errlen) {
+    const int nb = nblocks(m, kNearThreads);
+    k_fill_i32<<<nblocks(m, 256) < 1024 ? nblocks(m, 256) : 1024, 256, 0, s>>>(codes, m, -1);
+    k_nearest<<<nb, kNearThreads, 0, s>>>(X, D, rows, m, W1, c1, W, K, codes, nullptr, nullptr, 0);
+    int rounds = 0;
+    while (rounds < iters) {
+        digit_pass(codes, nullptr, m, 0, hist, skey, order, s);
+        k_key_offsets<<<nblocks(m + 1, 256) < 1024 ? nblocks(m + 1, 256) : 1024, 256, 0, s>>>(
+            skey, m, K, woff);
+        k_word_means<<<dim3(K, (D + 63) / 64), 64, 0, s>>>(X, D, rows, W1, c1, order, woff, W);
+        k_fill_i32<<<1, 64, 0, s>>>(dchanged, 1, 0);
+        k_nearest<<<nb, kNearThreads, 0, s>>>(X, D, rows, m, W1, c1, W, K, codes, dchanged,
+                                              nullptr, 0);
+        int32_t h = 0;
+        hipError_t e = hipMemcpyAsync(&h, dchanged, sizeof(h), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return finish(e, "k-means round", err, errlen);
+        ++rounds;
+        if (h == 0) break;
+    }
+    *rounds_out = rounds;
+    return finish(hipSuccess, "k-means", err, errlen);
+}
+
+int read_flag(const int32_t* dflag, int32_t* h, hipStream_t s, char* err, size_t errlen) {
+    hipError_t e = hipMemcpyAsync(h, dflag, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return finish(e, "argument check", err, errlen);
+}
+
+}  // namespace
+
+int rvq_train_run(const RvqTrainArgs& a, char* err, size_t errlen) {
+    hipStream_t s = a.stream;
+    const int64_t m = a.m;
+    const int K = a.K1 > a.K2 ? a.K1 : a.K2;
+    Ws ws{s};
+    int32_t* flag = ws.get<int32_t>(1);
+    int32_t* codes1 = ws.get<int32_t>(m);
+    int32_t* codes2 = ws.get<int32_t>(m);
+    int32_t* skey = ws.get<int32_t>(m);
+    int32_t* order = ws.get<int32_t>(m);
+    int32_t* hist = ws.get<int32_t>(256 * static_cast<size_t>(nblocks(m, kSortB)));
+    int32_t* woff = ws.get<int32_t>(K + 1);
+    int32_t* changed = ws.get<int32_t>(1);
+    if (ws.e != hipSuccess) {
+        std::snprintf(err, errlen, "workspace: %s", hipGetErrorString(ws.e));
+        return kOom;
+    }
+    k_fill_i32<<<1, 64, 0, s>>>(flag, 1, 0);
+    k_check_range<<<256, 256, 0, s>>>(a.train_ids, m, 0, a.n, flag);
+    k_check_range<<<1, 256, 0, s>>>(a.init1, a.K1, 0, m, flag);
+    k_check_range<<<1, 256, 0, s>>>(a.init2, a.K2, 0, m, flag);
+    int32_t bad = 0;
+    int rc = read_flag(flag, &bad, s, err, errlen);
+    if (rc != kOk) return rc;
+    if (bad) {
+        std::snprintf(err, errlen, "a training id is outside [0, n) or a starting position outside [0, m)");
+        return kInvalid;
+    }
+    k_init_words<<<a.K1, 64, 0, s>>>(a.X, a.D, a.train_ids, nullptr, nullptr, a.init1, a.W1);
+    rc = kmeans_run(a.X, a.D, a.train_ids, m, nullptr, nullptr, a.W1, a.K1, a.iters, codes1, skey,
+                    order, hist, woff, changed, a.rounds, s, err, errlen);
+    if (rc != kOk) return rc;
+    k_init_words<<<a.K2, 64, 0, s>>>(a.X, a.D, a.train_ids, a.W1, codes1, a.init2, a.W2);
+    rc = kmeans_run(a.X, a.D, a.train_ids, m, a.W1, codes1, a.W2, a.K2, a.iters, codes2, skey,
+                    order, hist, woff, changed, a.rounds + 1, s, err, errlen);
+    if (rc != kOk) return rc;
+    if (a.codes1 != nullptr)
+        rc = finish(hipMemcpyAsync(a.codes1, codes1, sizeof(int32_t) * m, hipMemcpyDeviceToDevice, s),
+                    "copy", err, errlen);
+    if (rc == kOk && a.codes2 != nullptr)
+        rc = finish(hipMemcpyAsync(a.codes2, codes2, sizeof(int32_t) * m, hipMemcpyDeviceToDevice, s),
+                    "copy", err, errlen);
+    if (rc == kOk) rc = finish(hipStreamSynchronize(s), "rvq train", err, errlen);
+    return rc;
+}
+
+int ivf_build_run(const IvfBuildArgs& a, char* err, size_t errlen) {
+    hipStream_t s = a.stream;
+    const int64_t n = a.n;
+    const int nk = a.K1 * a.K2;
+    Ws ws{s};
+    int32_t* c1 = ws.get<int32_t>(n);
+    int32_t* key = a.keys_out != nullptr ? a.keys_out : ws.get<int32_t>(n);
+    int32_t* k2 = ws.get<int32_t>(n);
+    int32_t* v2 = ws.get<int32_t>(n);
+    int32_t* k3 = ws.get<int32_t>(n);
+    int32_t* hist = ws.get<int32_t>(256 * static_cast<size_t>(nblocks(n, kSortB)));
+    if (ws.e != hipSuccess) {
+        std::snprintf(err, errlen, "workspace: %s", hipGetErrorString(ws.e));
+        return kOom;
+    }
+    if (n > 0) {
+        const int nb = nblocks(n, kNearThreads);
+        k_nearest<<<nb, kNearThreads, 0, s>>>(a.X, a.D, nullptr, n, nullptr, nullptr, a.W1, a.K1,
+                                              c1, nullptr, nullptr, 0);
+        k_nearest<<<nb, kNearThreads, 0, s>>>(a.X, a.D, nullptr, n, a.W1, c1, a.W2, a.K2, nullptr,
+                                              nullptr, key, a.K2);
+        if (nk <= 256) {
+            digit_pass(key, nullptr, n, 0, hist, k3, a.ids_out, s);
+        } else {
+            digit_pass(key, nullptr, n, 0, hist, k2, v2, s);
+            digit_pass(k2, v2, n, 8, hist, k3, a.ids_out, s);
+        }
+    }
+    const int64_t cnt = n + 1;
+    const int g = nblocks(cnt, 256) < 1024 ? nblocks(cnt, 256) : 1024;
+    k_key_offsets<<<g, 256, 0, s>>>(k3, n, nk, a.offsets_out);
+    return finish(hipStreamSynchronize(s), "ivf build", err, errlen);
+}
+
+int ivf_seeds_run(const IvfSeedArgs& a, char* err, size_t errlen) {
+    hipStream_t s = a.stream;
+    const int nk = a.K1 * a.K2;
+    SeedShape sh;
+    sh.p1 = 1;
+    while (sh.p1 < a.K1) sh.p1 <<= 1;
+    sh.p2 = 2;  // keeps the LDS arrays after the keys 8-byte aligned
+    while (sh.p2 < a.n1 * a.K2) sh.p2 <<= 1;
+    const size_t lds = seed_lds_bytes(sh, a.D);
+    if (lds > kSeedLdsMax) {
+        std::snprintf(err, errlen,
+                      "seed state needs %zu bytes of LDS (n1 %d x K2 %d keys, D %d); at most %zu",
+                      lds, a.n1, a.K2, a.D, kSeedLdsMax);
+        return kUnsupported;
+    }
+    Ws ws{s};
+    int32_t* flag = ws.get<int32_t>(1);
+    double* x12 = ws.get<double>(static_cast<size_t>(nk));
+    double* nw1 = ws.get<double>(a.K1);
+    double* nw2 = ws.get<double>(a.K2);
+    double* W1T = ws.get<double>(static_cast<size_t>(a.D) * a.K1);
+    double* W2T = ws.get<double>(static_cast<size_t>(a.D) * a.K2);
+    if (ws.e != hipSuccess) {
+        std::snprintf(err, errlen, "workspace: %s", hipGetErrorString(ws.e));
+        return kOom;
+    }
+    k_fill_i32<<<1, 64, 0, s>>>(flag, 1, 0);
+    k_check_offsets<<<nblocks(nk, 256) < 256 ? nblocks(nk, 256) : 256, 256, 0, s>>>(
+        a.offsets, nk, a.n_ids, flag);
+    int32_t bad = 0;
+    int rc = read_flag(flag, &bad, s, err, errlen);
+    if (rc != kOk) return rc;
+    if (bad) {
+        std::snprintf(err, errlen, "offsets must rise from 0 to the number of listed ids");
+        return kInvalid;
+    }
+    if (a.nq == 0) return kOk;
+    k_ivf_tables<<<a.K1, 256, 0, s>>>(a.W1, a.K1, a.W2, a.K2, a.D, x12, nw1, nw2, W1T, W2T);
+    k_ivf_seeds<<<static_cast<unsigned>(a.nq), kSeedThreads, lds, s>>>(
+        a.Q, a.D, W1T, a.K1, W2T, a.K2, x12, nw1, nw2, a.offsets, a.ids, a.n1, a.ns, sh, a.seeds_out);
+    return finish(hipStreamSynchronize(s), "ivf seeds", err, errlen);
+}
+
+}  // namespace knng

@@ -276,6 +276,62 @@ struct SearchArgs {
 };
 int search_run(const SearchArgs& a, char* err, size_t errlen);
 
+// ---------------------------------------------------------------- RVQ index
+// Two-stage residue vector quantisation, inverted lists and cascaded search
+// seeds (Sec. 4.1-4.2, Eqns 1-3); csrc/ivf.hip.
+constexpr int kRvqMaxWords = 256;          // words per stage
+constexpr int kSeedMaxKeys = 4096;         // n1 * K2 keys ranked per query
+constexpr size_t kSeedLdsMax = 65536;      // per-query seed state in LDS
+struct RvqTrainArgs {
+    const float* X;            // [n][D]
+    int64_t n;
+    int D;
+    const int32_t* train_ids;  // [m] rows of X
+    int64_t m;
+    int K1, K2;
+    const int32_t* init1;      // [K1] positions in the sample
+    const int32_t* init2;      // [K2]
+    int iters;
+    double* W1;                // [K1][D]
+    double* W2;                // [K2][D]
+    int32_t* codes1;           // [m], nullable
+    int32_t* codes2;           // [m], nullable
+    int* rounds;               // host [2]
+    hipStream_t stream;
+};
+int rvq_train_run(const RvqTrainArgs& a, char* err, size_t errlen);
+struct IvfBuildArgs {
+    const float* X;            // [n][D]
+    int64_t n;
+    int D;
+    const double* W1;          // [K1][D]
+    int K1;
+    const double* W2;          // [K2][D]
+    int K2;
+    int32_t* keys_out;         // [n], nullable
+    int32_t* offsets_out;      // [K1 K2 + 1]
+    int32_t* ids_out;          // [n]
+    hipStream_t stream;
+};
+int ivf_build_run(const IvfBuildArgs& a, char* err, size_t errlen);
+struct IvfSeedArgs {
+    const float* Q;            // [nq][D]
+    int64_t nq;
+    int D;
+    const double* W1;
+    int K1;
+    const double* W2;
+    int K2;
+    const int32_t* offsets;    // [K1 K2 + 1]
+    const int32_t* ids;        // [n_ids]
+    int64_t n_ids;
+    int n1;
+    int ns;
+    int32_t* seeds_out;        // [nq][ns]
+    hipStream_t stream;
+};
+int ivf_seeds_run(const IvfSeedArgs& a, char* err, size_t errlen);
+
 // ---------------------------------------------------------------- prep
 // flags[0] <- 1 if X holds a NaN or Inf; flags[1] <- 1 if some value is not
 // an integer in [0, 255] (flags: device int[2]).

@@ -89,6 +89,10 @@ def lib():
     L.knng_search.argtypes = [vp, i64, i32, vp, i32, vp, i64, vp, i32, i32, i32, vp, vp, vp]
     L.knng_release_workspace.restype = None
     L.knng_release_workspace.argtypes = []
+    L.knng_rvq_train.argtypes = [vp, i64, i32, vp, i64, i32, i32, vp, vp, i32, vp, vp, vp, vp,
+                                 ctypes.POINTER(i32), vp]
+    L.knng_ivf_build.argtypes = [vp, i64, i32, vp, i32, vp, i32, vp, vp, vp, vp]
+    L.knng_ivf_seeds.argtypes = [vp, i64, i32, vp, i32, vp, i32, vp, vp, i64, i32, i32, vp, vp]
     L.knng_default_options.restype = None
     L.knng_default_options.argtypes = [ctypes.POINTER(KnngOptions)]
     L.knng_status_string.restype = ctypes.c_char_p
@@ -247,3 +251,93 @@ def search(x, graph, queries, seeds, k, rounds, stream=None):
 def release_workspace():
     """Free the scratch blocks the library keeps cached on the current device."""
     lib().knng_release_workspace()
+
+
+def _dev_i32(t, name, dim=1):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.int32
+            and t.dim() == dim and t.is_contiguous()):
+        raise ValueError("%s must be a contiguous %d-D int32 CUDA tensor" % (name, dim))
+    return t
+
+
+def _dev_f64(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+            and t.dim() == 2 and t.is_contiguous()):
+        raise ValueError("%s must be a contiguous 2-D float64 CUDA tensor" % name)
+    return t
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def rvq_train(x, train_ids, init1, init2, iters, codes=False, stream=None):
+    """Two-stage RVQ vocabularies by Lloyd k-means (Sec. 4.1, Eqn 1).
+
+    x: float32 CUDA [n, D]; train_ids: int32 CUDA [m] sample rows; init1,
+    init2: int32 CUDA [K1] / [K2] starting positions in the sample.  Returns
+    (words1 float64 [K1, D], words2 float64 [K2, D], rounds (r1, r2)) and,
+    with codes=True, the sample's codes (int32 [m] each) as well."""
+    import torch
+    x = _dev_f32(x)
+    _dev_i32(train_ids, "train_ids")
+    _dev_i32(init1, "init1")
+    _dev_i32(init2, "init2")
+    n, D = x.shape
+    m, K1, K2 = train_ids.shape[0], init1.shape[0], init2.shape[0]
+    W1 = torch.empty((K1, D), dtype=torch.float64, device=x.device)
+    W2 = torch.empty((K2, D), dtype=torch.float64, device=x.device)
+    c1 = torch.empty(m, dtype=torch.int32, device=x.device) if codes else None
+    c2 = torch.empty(m, dtype=torch.int32, device=x.device) if codes else None
+    rounds = (ctypes.c_int * 2)()
+    rc = lib().knng_rvq_train(_ptr(x), n, D, _ptr(train_ids), m, K1, K2, _ptr(init1), _ptr(init2),
+                              iters, _ptr(W1), _ptr(W2), _ptr(c1) if codes else None,
+                              _ptr(c2) if codes else None, rounds, _stream(stream))
+    _check(rc)
+    if codes:
+        return W1, W2, (rounds[0], rounds[1]), c1, c2
+    return W1, W2, (rounds[0], rounds[1])
+
+
+def ivf_build(x, words1, words2, stream=None):
+    """Keys and inverted lists of every point (Sec. 4.2).  Returns (keys int32
+    [n], offsets int32 [K1 K2 + 1], ids int32 [n])."""
+    import torch
+    x = _dev_f32(x)
+    _dev_f64(words1, "words1")
+    _dev_f64(words2, "words2")
+    n, D = x.shape
+    if words1.shape[1] != D or words2.shape[1] != D:
+        raise ValueError("vocabularies must have D columns")
+    K1, K2 = words1.shape[0], words2.shape[0]
+    keys = torch.empty(n, dtype=torch.int32, device=x.device)
+    offsets = torch.empty(K1 * K2 + 1, dtype=torch.int32, device=x.device)
+    ids = torch.empty(n, dtype=torch.int32, device=x.device)
+    rc = lib().knng_ivf_build(_ptr(x), n, D, _ptr(words1), K1, _ptr(words2), K2, _ptr(keys),
+                              _ptr(offsets), _ptr(ids), _stream(stream))
+    _check(rc)
+    return keys, offsets, ids
+
+
+def ivf_seeds(queries, words1, words2, offsets, ids, n1, ns, stream=None):
+    """Cascaded seeds (Eqns 2-3): int32 [nq, ns], -1 padded."""
+    import torch
+    queries = _dev_f32(queries)
+    _dev_f64(words1, "words1")
+    _dev_f64(words2, "words2")
+    _dev_i32(offsets, "offsets")
+    _dev_i32(ids, "ids")
+    nq, D = queries.shape
+    if words1.shape[1] != D or words2.shape[1] != D:
+        raise ValueError("vocabularies must have D columns")
+    K1, K2 = words1.shape[0], words2.shape[0]
+    if offsets.shape[0] != K1 * K2 + 1:
+        raise ValueError("offsets must hold K1 * K2 + 1 entries")
+    seeds = torch.empty((nq, ns), dtype=torch.int32, device=queries.device)
+    rc = lib().knng_ivf_seeds(_ptr(queries), nq, D, _ptr(words1), K1, _ptr(words2), K2,
+                              _ptr(offsets), _ptr(ids), ids.shape[0], n1, ns, _ptr(seeds),
+                              _stream(stream))
+    _check(rc)
+    return seeds

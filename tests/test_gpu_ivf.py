@@ -1,0 +1,157 @@
+"""RVQ inverted index and cascaded seeds (Sec. 4.1-4.2, Eqns 1-3) on the GPU
+against the oracle (readings R14-R19): vocabularies, codes, lists and seeds
+bit for bit, since both sides take every decision in the same FP64
+arithmetic.  Vocabularies handed to the GPU come from the oracle; every
+input comes from the seeded generators."""
+import numpy as np
+import pytest
+
+from paper_1701_08475_amd import datagen
+from tests.gpu_helpers import log, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1701_08475_amd import knng
+    knng.lib()
+    return knng
+
+
+def _i32(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, np.int32)).cuda()
+
+
+def _f64(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, np.float64)).cuda()
+
+
+def _data(kind, n, D, seed):
+    if kind == "c1":
+        return datagen.make("c1", n=n)
+    if kind == "c2":
+        return datagen.make("c2", n=n)
+    return datagen.random_points(n, D, seed, kind)
+
+
+TRAIN_CASES = [
+    # name, data, n, D, m, K1, K2, iters
+    ("gmm32", "c1", 4000, 32, 3000, 16, 8, 20),
+    ("sift-like", "c2", 6000, 128, 6000, 64, 32, 10),
+    ("odd-D-256", "normal", 3000, 33, 2500, 256, 256, 4),
+    ("tiny-D", "normal", 2000, 3, 1500, 5, 3, 30),
+    ("one-word", "int", 500, 17, 400, 1, 2, 5),
+]
+
+
+@pytest.mark.parametrize("name,kind,n,D,m,K1,K2,iters", TRAIN_CASES)
+def test_rvq_train_matches_oracle(K, orc, name, kind, n, D, m, K1, K2, iters):
+    X = _data(kind, n, D, n + D)
+    train, init1, init2 = datagen.rvq_sample(n, m, K1, K2, seed=n + K1)
+    log("rvq train %s n=%d D=%d m=%d K1=%d K2=%d" % (name, n, X.shape[1], m, K1, K2))
+    W1, W2, rounds, c1, c2 = K.rvq_train(to_dev(X), _i32(train), _i32(init1), _i32(init2), iters,
+                                         codes=True)
+    o1, o2, oc1, oc2, orounds = orc.rvq_train(X, train, init1, init2, iters)
+    assert tuple(rounds) == tuple(orounds.tolist())
+    assert np.array_equal(c1.cpu().numpy(), oc1)
+    assert np.array_equal(c2.cpu().numpy(), oc2)
+    assert np.array_equal(W1.cpu().numpy(), o1)
+    assert np.array_equal(W2.cpu().numpy(), o2)
+
+
+@pytest.mark.parametrize("name,kind,n,D,m,K1,K2,iters", TRAIN_CASES[:4])
+def test_ivf_build_matches_oracle(K, orc, name, kind, n, D, m, K1, K2, iters):
+    X = _data(kind, n, D, n + D + 1)
+    train, init1, init2 = datagen.rvq_sample(n, m, K1, K2, seed=n + K2)
+    W1, W2, _, _, _ = orc.rvq_train(X, train, init1, init2, iters)
+    log("ivf build %s n=%d K1=%d K2=%d" % (name, n, K1, K2))
+    keys, offsets, ids = K.ivf_build(to_dev(X), _f64(W1), _f64(W2))
+    o_key = orc.rvq_encode(X, W1, W2)
+    o_off, o_ids = orc.ivf_lists(o_key, K1 * K2)
+    assert np.array_equal(keys.cpu().numpy(), o_key)
+    assert np.array_equal(offsets.cpu().numpy(), o_off)
+    assert np.array_equal(ids.cpu().numpy(), o_ids)
+
+
+def _index(orc, X, K1, K2, m, iters, seed):
+    train, init1, init2 = datagen.rvq_sample(len(X), m, K1, K2, seed=seed)
+    W1, W2, _, _, _ = orc.rvq_train(X, train, init1, init2, iters)
+    key = orc.rvq_encode(X, W1, W2)
+    off, ids = orc.ivf_lists(key, K1 * K2)
+    return W1, W2, off, ids
+
+
+@pytest.mark.parametrize("name,kind,n,D,K1,K2,n1,ns", [
+    ("gmm32", "c1", 5000, 32, 16, 16, 4, 64),
+    ("sift-like", "c2", 8000, 128, 64, 64, 8, 100),
+    ("full-width", "c2", 8000, 128, 256, 16, 256, 50),  # every first-stage word kept
+    ("keys-4096", "normal", 3000, 20, 32, 256, 16, 500),
+    ("pads", "normal", 300, 8, 4, 4, 1, 400),            # fewer ids than seeds: -1 padding
+    ("one-key", "normal", 200, 5, 1, 1, 1, 7),
+])
+def test_ivf_seeds_match_oracle(K, orc, name, kind, n, D, K1, K2, n1, ns):
+    X = _data(kind, n, D, n + 3)
+    W1, W2, off, ids = _index(orc, X, K1, K2, n, 8, n + 4)
+    Q = datagen.queries("c1", 200) if kind == "c1" else (
+        datagen.queries("c2", 200) if kind == "c2" else datagen.random_points(200, D, n + 5))
+    log("ivf seeds %s K1=%d K2=%d n1=%d ns=%d" % (name, K1, K2, n1, ns))
+    S = K.ivf_seeds(to_dev(Q), _f64(W1), _f64(W2), _i32(off), _i32(ids), n1, ns)
+    o_S = orc.ivf_seeds(Q, W1, W2, off, ids, n1, ns)
+    assert np.array_equal(S.cpu().numpy(), o_S)
+
+
+def test_ivf_seeded_search_matches_oracle(K, orc):
+    """IVF + E-GNNS: seeds from the index, then Alg. 2 over the graph, each
+    step against the oracle's."""
+    X = datagen.make("c1", n=6000)
+    G, _, _ = orc.graph(X, 10, 2, 40, 5)
+    W1, W2, off, ids = _index(orc, X, 16, 16, 6000, 10, 17)
+    Q = datagen.queries("c1", 300)
+    S = K.ivf_seeds(to_dev(Q), _f64(W1), _f64(W2), _i32(off), _i32(ids), 4, 32)
+    o_S = orc.ivf_seeds(Q, W1, W2, off, ids, 4, 32)
+    assert np.array_equal(S.cpu().numpy(), o_S)
+    g_ids, g_d = K.search(to_dev(X), _i32(G), to_dev(Q), S, 10, 6)
+    o_ids, o_d = orc.egnns(X, G, Q, o_S, 10, 6, dist_mode=1)
+    assert np.array_equal(g_ids.cpu().numpy(), o_ids)
+    assert np.array_equal(g_d.cpu().numpy().astype(np.float64), o_d)
+
+
+def test_ivf_argument_errors(K):
+    import torch
+    X = torch.zeros((100, 8), dtype=torch.float32, device="cuda")
+    W = torch.zeros((4, 8), dtype=torch.float64, device="cuda")
+    bad_ids = _i32(np.array([0, 5, 100], np.int32))  # 100 is outside [0, n)
+    with pytest.raises(K.KnngError):
+        K.rvq_train(X, bad_ids, _i32([0, 1]), _i32([0, 2]), 3)
+    with pytest.raises(K.KnngError):
+        K.rvq_train(X, _i32([0, 5, 9]), _i32([0, 3]), _i32([0, 1]), 3)  # position 3 >= m
+    off = _i32(np.array([0] * 8 + [5, 4] + [100] * 7, np.int32))      # falls at key 9
+    with pytest.raises(K.KnngError):
+        K.ivf_seeds(X[:2].contiguous(), W, W, off, _i32(np.arange(100)), 2, 4)
+    with pytest.raises(K.KnngError):
+        K.ivf_seeds(X[:2].contiguous(), W, W, _i32(np.arange(17)), _i32(np.arange(16)), 5, 4)
+
+
+def test_ivf_full_size(K, orc):
+    """SIFT-shaped 1M x 128 with 256 x 256 words (oracle-trained on a 16384-row
+    sample): every key, offset and list entry equals the oracle's, and the
+    seeds of a query batch over the full lists too."""
+    X = datagen.make("c2")
+    n = len(X)
+    train, init1, init2 = datagen.rvq_sample(n, 16384, 256, 256, seed=5)
+    W1, W2, _, _, _ = orc.rvq_train(X, train, init1, init2, 6)
+    o_key = orc.rvq_encode(X, W1, W2)
+    o_off, o_ids = orc.ivf_lists(o_key, 256 * 256)
+    log("ivf full size: n=%d" % n)
+    keys, offsets, ids = K.ivf_build(to_dev(X), _f64(W1), _f64(W2))
+    assert np.array_equal(keys.cpu().numpy(), o_key)
+    assert np.array_equal(offsets.cpu().numpy(), o_off)
+    assert np.array_equal(ids.cpu().numpy(), o_ids)
+    Q = datagen.queries("c2", 200)
+    S = K.ivf_seeds(to_dev(Q), _f64(W1), _f64(W2), _i32(o_off), _i32(o_ids), 8, 64)
+    assert np.array_equal(S.cpu().numpy(), orc.ivf_seeds(Q, W1, W2, o_off, o_ids, 8, 64))
