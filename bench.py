@@ -8,6 +8,9 @@ search, merge) of the resident synthetic input.  Prints one JSON line with
 points/s, the roofline position of the dominant kernel (the two-means
 assignment pass, HBM-bound), recall@k on sampled rows against exact FP64
 brute force, and the CPU oracle timed on a bounded sample on the host.
+Outside the timed steps it also reports the graph's consumers: E-GNNS search
+(Alg. 2) from random seeds, and from the seeds of an RVQ inverted index
+(Sec. 4) trained, listed and queried on the GPU.
 """
 import argparse
 import hashlib
@@ -74,6 +77,12 @@ def main():
     ap.add_argument("--search-queries", type=int, default=10_000)
     ap.add_argument("--search-seeds", type=int, default=64)
     ap.add_argument("--search-rounds", type=int, default=10)
+    ap.add_argument("--no-ivf", action="store_true",
+                    help="skip the RVQ inverted index (training, lists, seeded search)")
+    ap.add_argument("--ivf-train", type=int, default=65536, help="RVQ training rows")
+    ap.add_argument("--ivf-words", type=int, default=256, help="words per RVQ stage")
+    ap.add_argument("--ivf-iters", type=int, default=10, help="Lloyd rounds per stage")
+    ap.add_argument("--ivf-n1", type=int, default=8, help="first-stage words kept per query")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 1 GiB elementwise copy first (HBM counter calibration)")
     args = ap.parse_args()
@@ -259,6 +268,48 @@ def main():
             search["recall_queries"] = rq
         log("search: %d queries in %.2f ms (%s)" % (len(Qn), s_ms, search.get("recall_at_k")))
 
+    ivf = None
+    if not args.no_ivf and not args.no_search:
+        # Sec. 4: two-stage RVQ vocabularies (Lloyd k-means on a row sample),
+        # inverted lists of all points, cascaded seeds (Eqn 3), then E-GNNS
+        # from those seeds over the same graph and queries as above
+        K1 = K2 = args.ivf_words
+        tr, i1, i2 = datagen.rvq_sample(n, args.ivf_train, K1, K2)
+        trd, i1d, i2d = (torch.from_numpy(a).to(dev) for a in (tr, i1, i2))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        W1, W2, rounds_tr = knng.rvq_train(xd, trd, i1d, i2d, args.ivf_iters)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, offs, lids = knng.ivf_build(xd, W1, W2)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        ns_ivf = args.search_seeds
+        knng.ivf_seeds(qd, W1, W2, offs, lids, args.ivf_n1, ns_ivf)
+        torch.cuda.synchronize()
+        reps = 3
+        ta = time.perf_counter()
+        for _ in range(reps):
+            S_ivf = knng.ivf_seeds(qd, W1, W2, offs, lids, args.ivf_n1, ns_ivf)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        for _ in range(reps):
+            v_ids, _ = knng.search(xd, ids, qd, S_ivf, k, rounds)
+        torch.cuda.synchronize()
+        tc2 = time.perf_counter()
+        seed_ms = (tb - ta) * 1e3 / reps
+        srch_ms = (tc2 - tb) * 1e3 / reps
+        ivf = {"words": [K1, K2], "train_rows": len(tr), "iters": args.ivf_iters,
+               "rounds": list(rounds_tr), "train_ms": round((t1 - t0) * 1e3, 2),
+               "build_ms": round((t2 - t1) * 1e3, 2), "n1": args.ivf_n1, "seeds": ns_ivf,
+               "seeds_ms": round(seed_ms, 3), "search_ms": round(srch_ms, 3),
+               "queries_per_s": round(len(Qn) / ((seed_ms + srch_ms) / 1e3), 1),
+               "non_empty_lists": int((offs[1:] > offs[:-1]).sum().item())}
+        if not args.no_recall:
+            ivf["recall_at_k"] = round(oracle.search_recall(v_ids.cpu().numpy()[:rq], E), 5)
+        log("ivf: train %.1f ms, build %.1f ms, seeds %.2f ms + search %.2f ms (%s)"
+            % (ivf["train_ms"], ivf["build_ms"], seed_ms, srch_ms, ivf.get("recall_at_k")))
+
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "points/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
@@ -275,6 +326,7 @@ def main():
         "plain_schedule": plain,
         "phases": phases,
         "search": search,
+        "ivf_search": ivf,
         "gpu": torch.cuda.get_device_name(0),
     }
     print(json.dumps(out), flush=True)
