@@ -305,6 +305,12 @@ def main():
                "seeds_ms": round(seed_ms, 3), "search_ms": round(srch_ms, 3),
                "queries_per_s": round(len(Qn) / ((seed_ms + srch_ms) / 1e3), 1),
                "non_empty_lists": int((offs[1:] > offs[:-1]).sum().item())}
+        # encoding work: per point and stage, K words x D dimensions of one
+        # FP64 subtraction and one FMA (3 flops); the call also sorts the keys,
+        # so this rate is a lower bound for the encoding kernel
+        enc_flops = 2 * n * K1 * D * 3
+        ivf["encode_fp64_tflops_whole_call"] = round(enc_flops / ((t2 - t1) * 1e12), 2)
+        ivf["fp64_peak_tflops"] = 78.6
         if not args.no_recall:
             ivf["recall_at_k"] = round(oracle.search_recall(v_ids.cpu().numpy()[:rq], E), 5)
         log("ivf: train %.1f ms, build %.1f ms, seeds %.2f ms + search %.2f ms (%s)"

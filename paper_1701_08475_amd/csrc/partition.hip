@@ -1292,6 +1292,8 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     const int small_max = (use_u8 && sub_mode != 0)
                               ? std::max(subtree_max_rows(D, row_budget), L)
                               : L;
+    // KNNG_TRACE_LEVELS=1: one line per level on stderr (nodes, chunks)
+    const bool trace_levels = env_int("KNNG_TRACE_LEVELS", 0) != 0;
     NodeRec* sub = nullptr;
     NodeRec* nodes[2] = {nullptr, nullptr};
     int32_t* big[2] = {nullptr, nullptr};
@@ -1467,6 +1469,9 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
         KNNG_LAUNCH();
         k_copyback<<<cblocks, 256, 0, s>>>(n, nodes[cur], chunk_node, nc, perm_tmp, a.perm);
         KNNG_LAUNCH();
+        if (trace_levels)
+            std::fprintf(stderr, "[knng] level %d: %d nodes, %d chunks, %d multi-chunk\n", depth,
+                         na, nc, nb);
         k_next_level<<<1, 1024, 0, s>>>(nodes[cur], na, n0f, L, small_max, depth, nodes[cur ^ 1],
                                         big[cur ^ 1], sub, a.leaves, a.leaves_cap, a.node_log,
                                         a.node_log_cap, ctr, overflow, dmirror, depth);

@@ -36,6 +36,9 @@ def _data(kind, n, D, seed):
         return datagen.make("c1", n=n)
     if kind == "c2":
         return datagen.make("c2", n=n)
+    if kind == "unit":  # GIST-shaped: unit-norm rows
+        X = datagen.random_points(n, D, seed, "normal").astype(np.float64)
+        return (X / np.linalg.norm(X, axis=1, keepdims=True)).astype(np.float32)
     return datagen.random_points(n, D, seed, kind)
 
 
@@ -46,6 +49,7 @@ TRAIN_CASES = [
     ("odd-D-256", "normal", 3000, 33, 2500, 256, 256, 4),
     ("tiny-D", "normal", 2000, 3, 1500, 5, 3, 30),
     ("one-word", "int", 500, 17, 400, 1, 2, 5),
+    ("gist-like", "unit", 3000, 960, 2000, 32, 16, 6),  # 60 dimension tiles per word tile
 ]
 
 
@@ -93,12 +97,13 @@ def _index(orc, X, K1, K2, m, iters, seed):
     ("keys-4096", "normal", 3000, 20, 32, 256, 16, 500),
     ("pads", "normal", 300, 8, 4, 4, 1, 400),            # fewer ids than seeds: -1 padding
     ("one-key", "normal", 200, 5, 1, 1, 1, 7),
+    ("gist-like", "unit", 2000, 960, 16, 32, 4, 80),
 ])
 def test_ivf_seeds_match_oracle(K, orc, name, kind, n, D, K1, K2, n1, ns):
     X = _data(kind, n, D, n + 3)
     W1, W2, off, ids = _index(orc, X, K1, K2, n, 8, n + 4)
     Q = datagen.queries("c1", 200) if kind == "c1" else (
-        datagen.queries("c2", 200) if kind == "c2" else datagen.random_points(200, D, n + 5))
+        datagen.queries("c2", 200) if kind == "c2" else _data(kind, 200, D, n + 5))
     log("ivf seeds %s K1=%d K2=%d n1=%d ns=%d" % (name, K1, K2, n1, ns))
     S = K.ivf_seeds(to_dev(Q), _f64(W1), _f64(W2), _i32(off), _i32(ids), n1, ns)
     o_S = orc.ivf_seeds(Q, W1, W2, off, ids, n1, ns)
