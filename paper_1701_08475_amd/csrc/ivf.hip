@@ -37,12 +37,19 @@ constexpr int kSeedThreads = 256;
 // X[row(p)][d] - (W1 ? W1[c1[p]][d] : 0) with row(p) = rows ? rows[p] : p.
 // changed (nullable) counts the points whose code differs from codes[p] on
 // entry; codes (nullable) is written; key_out (nullable) <- c1[p] * K2 + code.
+// VEC: D % 16 == 0 and 16-byte aligned rows, so each slice of a point is read
+// as four float4 (and its stage-1 word as eight double2) instead of 16 loads
+// of single elements, each touching 64 cache lines per wave.
+template <bool VEC>
 __global__ __launch_bounds__(kNearThreads) void k_nearest(
     const float* __restrict__ X, int D, const int32_t* __restrict__ rows, int64_t m,
     const double* __restrict__ W1, const int32_t* __restrict__ c1, const double* __restrict__ W,
     int K, int32_t* __restrict__ codes, int32_t* __restrict__ changed, int32_t* __restrict__ key_out,
     int K2) {
-    __shared__ __align__(16) double s_w[kDC][kTJ];
+    // two LDS buffers: the slice of step s+1 is loaded while step s computes
+    __shared__ __align__(16) double s_w[2][kDC][kTJ];
+    constexpr int kPer = kDC * kTJ / kNearThreads;  // tile values loaded per thread
+    static_assert(kDC * kTJ % kNearThreads == 0, "whole tile per pass of the block");
     const int64_t p = blockIdx.x * static_cast<int64_t>(kNearThreads) + threadIdx.x;
     const bool live = p < m;
     const int64_t row = live ? (rows != nullptr ? rows[p] : p) : 0;
@@ -51,12 +58,57 @@ __global__ __launch_bounds__(kNearThreads) void k_nearest(
     const double* r = W1 != nullptr ? W1 + static_cast<size_t>(base) * D : nullptr;
     double best = 0.0;
     int bj = 0;
-    for (int j0 = 0; j0 < K; j0 += kTJ) {
-        double acc[kTJ];
+    // steps run over (word tile j0, dimension slice d0), d0 fastest
+    const int nd = (D + kDC - 1) / kDC;
+    const int nsteps = ((K + kTJ - 1) / kTJ) * nd;
+    auto fetch = [&](int st, double (&q)[kPer]) {
+        const int j0 = (st / nd) * kTJ, d0 = (st % nd) * kDC;
 #pragma unroll
-        for (int j = 0; j < kTJ; ++j) acc[j] = 0.0;
-        for (int d0 = 0; d0 < D; d0 += kDC) {
-            double v[kDC];
+        for (int i = 0; i < kPer; ++i) {
+            const int e = threadIdx.x + i * kNearThreads;
+            const int dd = e / kTJ, j = e % kTJ;
+            const int d = d0 + dd, jj = j0 + j;
+            q[i] = (d < D && jj < K) ? W[static_cast<size_t>(jj) * D + d] : 0.0;
+        }
+    };
+    auto stash = [&](int buf, const double (&q)[kPer]) {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int e = threadIdx.x + i * kNearThreads;
+            s_w[buf][e / kTJ][e % kTJ] = q[i];
+        }
+    };
+    double q[kPer];
+    fetch(0, q);
+    stash(0, q);
+    __syncthreads();
+    double acc[kTJ];
+    for (int st = 0; st < nsteps; ++st) {
+        const int j0 = (st / nd) * kTJ, d0 = (st % nd) * kDC;
+        if (d0 == 0) {
+#pragma unroll
+            for (int j = 0; j < kTJ; ++j) acc[j] = 0.0;
+        }
+        if (st + 1 < nsteps) fetch(st + 1, q);
+        double v[kDC];
+        if constexpr (VEC) {  // whole slices: d0 + kDC <= D
+#pragma unroll
+            for (int i = 0; i < kDC / 4; ++i) {
+                const float4 f = *reinterpret_cast<const float4*>(x + d0 + 4 * i);
+                v[4 * i] = static_cast<double>(f.x);
+                v[4 * i + 1] = static_cast<double>(f.y);
+                v[4 * i + 2] = static_cast<double>(f.z);
+                v[4 * i + 3] = static_cast<double>(f.w);
+            }
+            if (r != nullptr) {
+#pragma unroll
+                for (int i = 0; i < kDC / 2; ++i) {
+                    const double2 w1 = *reinterpret_cast<const double2*>(r + d0 + 2 * i);
+                    v[2 * i] = __dsub_rn(v[2 * i], w1.x);
+                    v[2 * i + 1] = __dsub_rn(v[2 * i + 1], w1.y);
+                }
+            }
+        } else {
 #pragma unroll
             for (int dd = 0; dd < kDC; ++dd) {
                 const int d = d0 + dd;
@@ -67,32 +119,30 @@ __global__ __launch_bounds__(kNearThreads) void k_nearest(
                 }
                 v[dd] = xv;
             }
-            __syncthreads();
-            for (int e = threadIdx.x; e < kDC * kTJ; e += kNearThreads) {
-                const int dd = e / kTJ, j = e % kTJ;
-                const int d = d0 + dd, jj = j0 + j;
-                s_w[dd][j] = (d < D && jj < K) ? W[static_cast<size_t>(jj) * D + d] : 0.0;
-            }
-            __syncthreads();
-            // padding dimensions give t = 0 and leave the sums unchanged
+        }
+        const int buf = st & 1;
+        // padding dimensions give t = 0 and leave the sums unchanged
 #pragma unroll
-            for (int dd = 0; dd < kDC; ++dd) {
+        for (int dd = 0; dd < kDC; ++dd) {
 #pragma unroll
-                for (int j = 0; j < kTJ; j += 2) {
-                    const double2 w = *reinterpret_cast<const double2*>(&s_w[dd][j]);
-                    const double t0 = __dsub_rn(v[dd], w.x);
-                    const double t1 = __dsub_rn(v[dd], w.y);
-                    acc[j] = __fma_rn(t0, t0, acc[j]);
-                    acc[j + 1] = __fma_rn(t1, t1, acc[j + 1]);
-                }
+            for (int j = 0; j < kTJ; j += 2) {
+                const double2 w = *reinterpret_cast<const double2*>(&s_w[buf][dd][j]);
+                const double t0 = __dsub_rn(v[dd], w.x);
+                const double t1 = __dsub_rn(v[dd], w.y);
+                acc[j] = __fma_rn(t0, t0, acc[j]);
+                acc[j + 1] = __fma_rn(t1, t1, acc[j + 1]);
             }
         }
+        if (d0 + kDC >= D) {  // last slice of the word tile
 #pragma unroll
-        for (int j = 0; j < kTJ; ++j)
-            if (j0 + j < K && (j0 + j == 0 || acc[j] < best)) {
-                best = acc[j];
-                bj = j0 + j;
-            }
+            for (int j = 0; j < kTJ; ++j)
+                if (j0 + j < K && (j0 + j == 0 || acc[j] < best)) {
+                    best = acc[j];
+                    bj = j0 + j;
+                }
+        }
+        if (st + 1 < nsteps) stash(buf ^ 1, q);
+        __syncthreads();
     }
     if (changed != nullptr) {
         const bool ch = live && codes[p] != bj;
@@ -243,7 +293,8 @@ __global__ void k_word_means(const float* __restrict__ X, int D, const int32_t* 
     const int32_t a = woff[j], b = woff[j + 1];
     if (b <= a) return;
     double s = 0.0;
-    for (int32_t i = a; i < b; ++i) {
+#pragma unroll 8
+    for (int32_t i = a; i < b; ++i) {  // unrolled: loads in flight, adds in order
         const int32_t p = order[i];
         double v = static_cast<double>(X[static_cast<int64_t>(rows[p]) * D + d]);
         if (W1 != nullptr) v = __dsub_rn(v, W1[static_cast<size_t>(c1[p]) * D + d]);
@@ -425,6 +476,22 @@ __global__ __launch_bounds__(kSeedThreads) void k_ivf_seeds(
 
 int nblocks(int64_t count, int per) { return static_cast<int>((count + per - 1) / per); }
 
+// Nearest word of every point (k_nearest), with vector loads when the rows
+// allow them.
+void nearest(const float* X, int D, const int32_t* rows, int64_t m, const double* W1,
+             const int32_t* c1, const double* W, int K, int32_t* codes, int32_t* changed,
+             int32_t* key_out, int K2, hipStream_t s) {
+    const bool vec = D % kDC == 0 && (reinterpret_cast<uintptr_t>(X) & 15u) == 0 &&
+                     (W1 == nullptr || (reinterpret_cast<uintptr_t>(W1) & 15u) == 0);
+    const int nb = nblocks(m, kNearThreads);
+    if (vec)
+        k_nearest<true><<<nb, kNearThreads, 0, s>>>(X, D, rows, m, W1, c1, W, K, codes, changed,
+                                                    key_out, K2);
+    else
+        k_nearest<false><<<nb, kNearThreads, 0, s>>>(X, D, rows, m, W1, c1, W, K, codes, changed,
+                                                     key_out, K2);
+}
+
 // Stable sort of (key, val) by the digit at shift (val nullable: index).
 void digit_pass(const int32_t* key, const int32_t* val, int64_t m, int shift, int32_t* hist,
                 int32_t* key_out, int32_t* val_out, hipStream_t s) {
@@ -465,9 +532,8 @@ int kmeans_run(const float* X, int D, const int32_t* rows, int64_t m, const doub
                const int32_t* c1, double* W, int K, int iters, int32_t* codes, int32_t* skey,
                int32_t* order, int32_t* hist, int32_t* woff, int32_t* dchanged, int* rounds_out,
                hipStream_t s, char* err, size_t errlen) {
-    const int nb = nblocks(m, kNearThreads);
     k_fill_i32<<<nblocks(m, 256) < 1024 ? nblocks(m, 256) : 1024, 256, 0, s>>>(codes, m, -1);
-    k_nearest<<<nb, kNearThreads, 0, s>>>(X, D, rows, m, W1, c1, W, K, codes, nullptr, nullptr, 0);
+    nearest(X, D, rows, m, W1, c1, W, K, codes, nullptr, nullptr, 0, s);
     int rounds = 0;
     while (rounds < iters) {
         digit_pass(codes, nullptr, m, 0, hist, skey, order, s);
@@ -475,8 +541,7 @@ int kmeans_run(const float* X, int D, const int32_t* rows, int64_t m, const doub
             skey, m, K, woff);
         k_word_means<<<dim3(K, (D + 63) / 64), 64, 0, s>>>(X, D, rows, W1, c1, order, woff, W);
         k_fill_i32<<<1, 64, 0, s>>>(dchanged, 1, 0);
-        k_nearest<<<nb, kNearThreads, 0, s>>>(X, D, rows, m, W1, c1, W, K, codes, dchanged,
-                                              nullptr, 0);
+        nearest(X, D, rows, m, W1, c1, W, K, codes, dchanged, nullptr, 0, s);
         int32_t h = 0;
         hipError_t e = hipMemcpyAsync(&h, dchanged, sizeof(h), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -558,11 +623,8 @@ int ivf_build_run(const IvfBuildArgs& a, char* err, size_t errlen) {
         return kOom;
     }
     if (n > 0) {
-        const int nb = nblocks(n, kNearThreads);
-        k_nearest<<<nb, kNearThreads, 0, s>>>(a.X, a.D, nullptr, n, nullptr, nullptr, a.W1, a.K1,
-                                              c1, nullptr, nullptr, 0);
-        k_nearest<<<nb, kNearThreads, 0, s>>>(a.X, a.D, nullptr, n, a.W1, c1, a.W2, a.K2, nullptr,
-                                              nullptr, key, a.K2);
+        nearest(a.X, a.D, nullptr, n, nullptr, nullptr, a.W1, a.K1, c1, nullptr, nullptr, 0, s);
+        nearest(a.X, a.D, nullptr, n, a.W1, c1, a.W2, a.K2, nullptr, nullptr, key, a.K2, s);
         if (nk <= 256) {
             digit_pass(key, nullptr, n, 0, hist, k3, a.ids_out, s);
         } else {
