@@ -257,6 +257,7 @@ int knng_ivf_build(const float* data, int64_t n, int32_t D, const double* words1
  *   n1           first-stage words kept, 1 <= n1 <= K1, n1 K2 <= 4096
  *   seeds_out    device, int32[nq][ns], padded with -1 when the visited lists
  *                hold fewer than ns ids; suitable as knng_search's seeds
+ * queries and seeds_out may be null when nq = 0, ids when n_ids = 0.
  */
 int knng_ivf_seeds(const float* queries, int64_t nq, int32_t D, const double* words1, int32_t K1,
                    const double* words2, int32_t K2, const int32_t* offsets, const int32_t* ids,

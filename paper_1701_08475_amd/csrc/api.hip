@@ -778,8 +778,8 @@ extern "C" int knng_ivf_seeds(const float* queries, int64_t nq, int32_t D, const
                               const int32_t* ids, int64_t n_ids, int32_t n1, int32_t ns,
                               int32_t* seeds_out, hipStream_t stream) {
     g_err[0] = '\0';
-    if (queries == nullptr || words1 == nullptr || words2 == nullptr || offsets == nullptr ||
-        seeds_out == nullptr || (ids == nullptr && n_ids > 0))
+    if (words1 == nullptr || words2 == nullptr || offsets == nullptr ||
+        ((queries == nullptr || seeds_out == nullptr) && nq > 0) || (ids == nullptr && n_ids > 0))
         return set_err(KNNG_ERR_INVALID_ARG, "null pointer argument");
     if (nq < 0 || nq > 2147483647LL)
         return set_err(KNNG_ERR_INVALID_ARG, "nq=%lld out of [0, 2^31-1]", static_cast<long long>(nq));

@@ -282,25 +282,39 @@ __global__ void k_key_offsets(const int32_t* __restrict__ skey, int64_t m, int n
 
 // W[j][d] <- mean of the values of the members of word j, added in
 // increasing position; a word without members keeps its value.
-// Grid (K, ceil(D / 64)), 64 threads.
-__global__ void k_word_means(const float* __restrict__ X, int D, const int32_t* __restrict__ rows,
-                             const double* __restrict__ W1, const int32_t* __restrict__ c1,
-                             const int32_t* __restrict__ order, const int32_t* __restrict__ woff,
-                             double* __restrict__ W) {
+// Grid (K, ceil(D / 64)), one wave: the row ids (and stage-1 words) of 64
+// members at a time go to LDS in one load, so the in-order sum issues only
+// independent row loads.
+__global__ __launch_bounds__(64) void k_word_means(
+    const float* __restrict__ X, int D, const int32_t* __restrict__ rows,
+    const double* __restrict__ W1, const int32_t* __restrict__ c1,
+    const int32_t* __restrict__ order, const int32_t* __restrict__ woff, double* __restrict__ W) {
+    __shared__ int64_t s_row[64];
+    __shared__ int32_t s_w1[64];
     const int j = blockIdx.x;
-    const int d = blockIdx.y * blockDim.x + threadIdx.x;
-    if (d >= D) return;
+    const int d = blockIdx.y * 64 + threadIdx.x;
     const int32_t a = woff[j], b = woff[j + 1];
-    if (b <= a) return;
+    if (b <= a) return;  // uniform: the word keeps its value
     double s = 0.0;
+    for (int32_t i0 = a; i0 < b; i0 += 64) {
+        const int cnt = b - i0 < 64 ? b - i0 : 64;
+        if (static_cast<int>(threadIdx.x) < cnt) {
+            const int32_t p = order[i0 + threadIdx.x];
+            s_row[threadIdx.x] = rows[p];
+            s_w1[threadIdx.x] = W1 != nullptr ? c1[p] : 0;
+        }
+        __syncthreads();
+        if (d < D) {
 #pragma unroll 8
-    for (int32_t i = a; i < b; ++i) {  // unrolled: loads in flight, adds in order
-        const int32_t p = order[i];
-        double v = static_cast<double>(X[static_cast<int64_t>(rows[p]) * D + d]);
-        if (W1 != nullptr) v = __dsub_rn(v, W1[static_cast<size_t>(c1[p]) * D + d]);
-        s = __dadd_rn(s, v);
+            for (int t = 0; t < cnt; ++t) {  // loads in flight, adds in order
+                double v = static_cast<double>(X[s_row[t] * D + d]);
+                if (W1 != nullptr) v = __dsub_rn(v, W1[static_cast<size_t>(s_w1[t]) * D + d]);
+                s = __dadd_rn(s, v);
+            }
+        }
+        __syncthreads();
     }
-    W[static_cast<size_t>(j) * D + d] = s / static_cast<double>(b - a);
+    if (d < D) W[static_cast<size_t>(j) * D + d] = s / static_cast<double>(b - a);
 }
 
 // -------------------------------------------------------------- seeds

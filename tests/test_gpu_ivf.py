@@ -160,3 +160,34 @@ def test_ivf_full_size(K, orc):
     Q = datagen.queries("c2", 200)
     S = K.ivf_seeds(to_dev(Q), _f64(W1), _f64(W2), _i32(o_off), _i32(o_ids), 8, 64)
     assert np.array_equal(S.cpu().numpy(), orc.ivf_seeds(Q, W1, W2, o_off, o_ids, 8, 64))
+
+
+def test_rvq_more_words_than_rows_and_repeated_starts(K, orc):
+    """64 words from a 50-row sample with repeated starting positions: equal
+    words tie, the lowest index takes the members and the others keep their
+    value (R15, R16) -- on both sides."""
+    X = datagen.random_points(400, 24, 41, "normal")
+    rng = np.random.default_rng(42)
+    train = np.sort(rng.choice(400, 50, replace=False)).astype(np.int32)
+    init1 = rng.integers(0, 50, 64).astype(np.int32)   # repeats
+    init2 = np.zeros(1, np.int32)                      # a one-word second stage
+    W1, W2, rounds, c1, c2 = K.rvq_train(to_dev(X), _i32(train), _i32(init1), _i32(init2), 7,
+                                         codes=True)
+    o1, o2, oc1, oc2, orounds = orc.rvq_train(X, train, init1, init2, 7)
+    assert tuple(rounds) == tuple(orounds.tolist())
+    assert np.array_equal(W1.cpu().numpy(), o1) and np.array_equal(W2.cpu().numpy(), o2)
+    assert np.array_equal(c1.cpu().numpy(), oc1) and np.array_equal(c2.cpu().numpy(), oc2)
+    assert np.all(c2.cpu().numpy() == 0)
+
+
+def test_ivf_seeds_empty_lists_and_no_queries(K):
+    import torch
+    W1 = _f64(datagen.random_points(4, 8, 43, "normal"))
+    W2 = _f64(datagen.random_points(3, 8, 44, "normal"))
+    Q = to_dev(datagen.random_points(5, 8, 45, "normal"))
+    off = _i32(np.zeros(13, np.int32))                 # 12 keys, no ids
+    ids = torch.zeros(0, dtype=torch.int32, device="cuda")
+    S = K.ivf_seeds(Q, W1, W2, off, ids, 2, 6)
+    assert np.all(S.cpu().numpy() == -1)
+    S0 = K.ivf_seeds(Q[:0].contiguous(), W1, W2, off, ids, 2, 6)
+    assert S0.shape == (0, 6)
