@@ -20,8 +20,9 @@
  *     knng_release_workspace() frees them.  Calls that use scratch memory on
  *     the same device run one at a time (a per-device lock).
  *   - Return value: KNNG_OK (0) or a negative status below.  On an argument
- *     error (KNNG_ERR_INVALID_ARG, KNNG_ERR_UNSUPPORTED) nothing is launched
- *     and no output is written.  On KNNG_ERR_NONFINITE the outputs are not
+ *     error (KNNG_ERR_INVALID_ARG, KNNG_ERR_UNSUPPORTED) no output is
+ *     written; nothing is launched except, where a call checks device-side
+ *     arguments (ids, offsets, positions), the kernel that checks them.  On KNNG_ERR_NONFINITE the outputs are not
  *     written.  On KNNG_ERR_OOM / KNNG_ERR_HIP output contents are
  *     unspecified.  knng_last_error() gives a message for the calling thread.
  *   - Distances are squared Euclidean distances in FP32.  Every reported

@@ -515,14 +515,18 @@ void digit_pass(const int32_t* key, const int32_t* val, int64_t m, int shift, in
     k_digit_scatter<<<nb, kSortT, 0, s>>>(key, val, m, shift, nb, hist, key_out, val_out);
 }
 
+// Scratch blocks of one call from the workspace cache, returned on exit
+// (stream-ordered); at most kMaxBlocks per call.
 struct Ws {
+    static constexpr int kMaxBlocks = 16;
     hipStream_t s;
-    void* blk[16] = {};
+    void* blk[kMaxBlocks] = {};
     int nblk = 0;
     hipError_t e = hipSuccess;
     template <class T>
     T* get(size_t count) {
         void* p = nullptr;
+        if (e == hipSuccess && nblk == kMaxBlocks) e = hipErrorOutOfMemory;
         if (e == hipSuccess) e = ws_malloc(&p, count * sizeof(T) + 16, s);
         if (e == hipSuccess) blk[nblk++] = p;
         return static_cast<T*>(p);
