@@ -134,6 +134,8 @@ def main():
     ap.add_argument("--precision", default=None, help="override the config's leaf precision")
     ap.add_argument("--recall-rows", type=int, default=500)
     ap.add_argument("--cpu-sample", type=int, default=500_000)
+    ap.add_argument("--cpu-sample-1t", type=int, default=50_000,
+                    help="rows of the one-thread oracle timing (the paper's setting)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-recall", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain schedule")
@@ -305,6 +307,18 @@ def main():
                          "(per-point cost grows with log n, so the full-size rate is somewhat "
                          "lower)" % (ns, n, T, k, L)}
         log("cpu oracle: %d points in %.1fs on %d threads" % (ns, el, threads))
+        if args.cpu_sample_1t > 0:
+            # the paper times its construction on one thread (Sec. 5)
+            n1 = min(args.cpu_sample_1t, n)
+            oracle.set_num_threads(1)
+            t1 = time.perf_counter()
+            oracle.graph(np.ascontiguousarray(X[:n1]), k, T, L, seed)
+            el1 = time.perf_counter() - t1
+            oracle.set_num_threads(threads)
+            cpu["one_thread"] = {"value": round(n1 / el1, 1), "unit": "points/s",
+                                 "seconds": round(el1, 2),
+                                 "sample": "first %d rows, all %d trees" % (n1, T)}
+            log("cpu oracle, one thread: %d points in %.1fs" % (n1, el1))
 
     search = None
     if not args.no_search:
