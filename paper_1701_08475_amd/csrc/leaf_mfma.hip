@@ -102,13 +102,53 @@ int prep_reduced(int precision, const float* X, int64_t n, int D, ReducedRows* r
     return hipGetLastError() == hipSuccess ? kOk : kHip;
 }
 
-int leaf_run_mfma(const LeafArgs& a, const ReducedRows& rr, int* launches, char* err,
-                  size_t errlen) {
-    const int c = a.rerank < a.k ? a.k : a.rerank;
-    if (c > 128 || a.k > 128) {
-        std::snprintf(err, errlen, "rerank candidates %d (k=%d) exceed 128", c, a.k);
-        return kUnsupported;
+namespace {
+
+// Size buckets of the leaf list: leaves of at most 64, 128, 256 and 512
+// points; each bucket runs the kernel shaped for its bound (fewer waves and
+// less LDS per workgroup for the smaller ones).
+constexpr int kBuckets = 4;
+constexpr int kBucketMax[kBuckets] = {64, 128, 256, 512};
+
+__device__ __forceinline__ int bucket_of(int size) {
+    return size <= 64 ? 0 : size <= 128 ? 1 : size <= 256 ? 2 : 3;
+}
+
+// cnt[0..3] <- leaves per bucket (cnt zeroed by the caller).
+__global__ void k_bucket_count(const LeafRec* __restrict__ leaves, int64_t nl,
+                               int32_t* __restrict__ cnt) {
+    __shared__ int32_t s[kBuckets];
+    if (threadIdx.x < kBuckets) s[threadIdx.x] = 0;
+    __syncthreads();
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < nl;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        atomicAdd(&s[bucket_of(leaves[i].size)], 1);
+    __syncthreads();
+    if (threadIdx.x < kBuckets && s[threadIdx.x] != 0) atomicAdd(&cnt[threadIdx.x], s[threadIdx.x]);
+}
+
+// out <- the leaves grouped by bucket, bucket b from the sum of the counts
+// before it (cnt[0..3]); order inside a bucket is arbitrary (every leaf
+// writes only its own rows' lists).  cursor[0..3] zeroed by the caller.
+__global__ void k_bucket_fill(const LeafRec* __restrict__ leaves, int64_t nl,
+                              const int32_t* __restrict__ cnt, int32_t* __restrict__ cursor,
+                              LeafRec* __restrict__ out) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < nl;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const LeafRec r = leaves[i];
+        const int b = bucket_of(r.size);
+        int64_t base = 0;
+        for (int q = 0; q < b; ++q) base += cnt[q];
+        out[base + atomicAdd(&cursor[b], 1)] = r;
     }
+}
+
+__global__ void k_zero8(int32_t* p) {
+    if (threadIdx.x < 8) p[threadIdx.x] = 0;
+}
+
+int run_format(const LeafArgs& a, const ReducedRows& rr, int* launches, char* err,
+               size_t errlen) {
     switch (a.precision) {
         case kBF16: return leafk::run_bf16(a, rr, launches, err, errlen);
         case kF16: return leafk::run_f16(a, rr, launches, err, errlen);
@@ -117,6 +157,57 @@ int leaf_run_mfma(const LeafArgs& a, const ReducedRows& rr, int* launches, char*
             std::snprintf(err, errlen, "precision %d has no MFMA path", a.precision);
             return kUnsupported;
     }
+}
+
+}  // namespace
+
+int leaf_run_mfma(const LeafArgs& a, const ReducedRows& rr, int* launches, char* err,
+                  size_t errlen) {
+    const int c = a.rerank < a.k ? a.k : a.rerank;
+    if (c > 128 || a.k > 128) {
+        std::snprintf(err, errlen, "rerank candidates %d (k=%d) exceed 128", c, a.k);
+        return kUnsupported;
+    }
+    // one launch shaped by the largest leaf when every leaf fits 128 points
+    // or KNNG_LEAF_BUCKETS=0; else one launch per non-empty size bucket
+    const char* env = std::getenv("KNNG_LEAF_BUCKETS");
+    const bool bucketed = (env == nullptr || std::atoi(env) != 0) && a.leaf_max > 128 &&
+                          a.n_leaves > 0;
+    if (!bucketed) return run_format(a, rr, launches, err, errlen);
+    hipStream_t s = a.stream;
+    int32_t* ctr = nullptr;  // [0..3] counts, [4..7] fill cursors
+    LeafRec* grouped = nullptr;
+    hipError_t e = ws_malloc(reinterpret_cast<void**>(&ctr), 8 * sizeof(int32_t), s);
+    if (e == hipSuccess)
+        e = ws_malloc(reinterpret_cast<void**>(&grouped), sizeof(LeafRec) * a.n_leaves, s);
+    int rc = kOk;
+    int32_t h[kBuckets] = {0, 0, 0, 0};
+    if (e == hipSuccess) {
+        const unsigned g = static_cast<unsigned>(std::min<int64_t>((a.n_leaves + 255) / 256, 1024));
+        k_zero8<<<1, 64, 0, s>>>(ctr);
+        k_bucket_count<<<g, 256, 0, s>>>(a.leaves, a.n_leaves, ctr);
+        k_bucket_fill<<<g, 256, 0, s>>>(a.leaves, a.n_leaves, ctr, ctr + kBuckets, grouped);
+        e = hipMemcpyAsync(h, ctr, sizeof(h), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        *launches += 3;
+    }
+    if (e != hipSuccess) {
+        std::snprintf(err, errlen, "leaf buckets: %s", hipGetErrorString(e));
+        rc = kHip;
+    }
+    int64_t base = 0;
+    for (int b = 0; b < kBuckets && rc == kOk; ++b) {
+        if (h[b] == 0) continue;
+        LeafArgs ab = a;
+        ab.leaves = grouped + base;
+        ab.n_leaves = h[b];
+        ab.leaf_max = std::min(a.leaf_max, kBucketMax[b]);
+        rc = run_format(ab, rr, launches, err, errlen);
+        base += h[b];
+    }
+    if (grouped != nullptr) ws_free(grouped, s);
+    if (ctr != nullptr) ws_free(ctr, s);
+    return rc;
 }
 
 }  // namespace knng

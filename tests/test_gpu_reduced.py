@@ -164,3 +164,31 @@ def test_ties_fall_to_smaller_id_on_shuffled_leaves(K, orc, precision, L):
     o_ids, o_d = orc.graph_from_leaves(X, 10, perms, offs)
     assert np.array_equal(_np(ids), o_ids)
     assert np.array_equal(_np(ds).astype(np.float64), o_d)
+
+
+@pytest.mark.parametrize("precision,n,D,k,L,kind,ml", [
+    ("fp8", 8000, 96, 32, 500, "unit96", 33),      # leaves from 33 to 500 points: four buckets
+    ("fp16", 4000, 960, 20, 200, "unit960", 21),   # up to 256 points
+    ("bf16", 6000, 128, 20, 300, "int", 21),       # exact first pass (integer data)
+    ("fp8", 5000, 64, 16, 260, "unit96", 2),       # tiny leaves next to large ones
+])
+def test_leaf_size_buckets_identical(K, orc, precision, n, D, k, L, kind, ml, monkeypatch):
+    """Leaves grouped by size (at most 64, 128, 256, 512 points), each group
+    run by the kernel shaped for it, give the same lists bit for bit as one
+    launch shaped by the largest leaf."""
+    if kind == "int":
+        X = datagen.random_points(n, D, 17, "int")
+    elif kind == "unit960" and D == 960:
+        X = datagen.gmm_unit(n, D, 16, 0.35, 12)
+    else:
+        X = datagen.gmm_unit(n, D, 16, 0.35, 13)
+    perms, offs = _oracle_leaves(orc, X, 2, L, ml, 7)
+    sizes = np.concatenate([np.diff(o) for o in offs])
+    log("leaf buckets %s n=%d D=%d sizes %d..%d" % (precision, n, D, sizes.min(), sizes.max()))
+    assert sizes.max() > 128
+    monkeypatch.setenv("KNNG_LEAF_BUCKETS", "0")
+    a = _gpu_leaf_search(K, X, k, perms, offs, precision)
+    monkeypatch.setenv("KNNG_LEAF_BUCKETS", "1")
+    b = _gpu_leaf_search(K, X, k, perms, offs, precision)
+    assert np.array_equal(_np(a[0]), _np(b[0]))
+    assert np.array_equal(_np(a[1]).view(np.int32), _np(b[1]).view(np.int32))
