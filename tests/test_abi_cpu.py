@@ -114,3 +114,50 @@ def test_partition_and_leaf_search_reject_invalid_arguments(L):
 
 def test_version(L):
     assert L.knng_version() >= 100
+
+
+def test_search_and_index_reject_invalid_arguments(L):
+    """Host-side checks of knng_search, knng_rvq_train, knng_ivf_build and
+    knng_ivf_seeds: each case returns before any HIP call."""
+    f = ctypes.c_void_p(FAKE)
+    E, U = knng.KNNG_ERR_INVALID_ARG, knng.KNNG_ERR_UNSUPPORTED
+
+    def search(data=f, n=100, D=8, kg=4, nq=3, ns=2, k=5, rounds=2):
+        return L.knng_search(data, n, D, f, kg, f, nq, f, ns, k, rounds, f, f, None)
+    assert search(data=None) == E
+    assert search(n=0) == E
+    assert search(D=0) == E
+    assert search(D=5000) == U
+    assert search(kg=0) == E
+    assert search(ns=0) == E
+    assert search(k=0) == E
+    assert search(rounds=-1) == E
+    assert search(k=2048, kg=1024) == U          # k x graph degree above 2^20
+
+    def train(data=f, n=100, D=8, m=50, K1=4, K2=4, iters=5):
+        return L.knng_rvq_train(data, n, D, f, m, K1, K2, f, f, iters, f, f, None, None, None,
+                                None)
+    assert train(data=None) == E
+    assert train(m=0) == E
+    assert train(m=101) == E                      # more sample rows than points
+    assert train(K1=0) == E
+    assert train(K2=300) == U                     # at most 256 words per stage
+    assert train(iters=-1) == E
+    assert train(D=0) == E
+
+    def build(n=100, D=8, K1=4, K2=4, w1=f):
+        return L.knng_ivf_build(f, n, D, w1, K1, f, K2, None, f, f, None)
+    assert build(w1=None) == E
+    assert build(n=-1) == E
+    assert build(K1=257) == U
+    assert build(D=4097) == U
+
+    def seeds(nq=3, D=8, K1=32, K2=256, n1=4, ns=8, n_ids=100):
+        return L.knng_ivf_seeds(f, nq, D, f, K1, f, K2, f, f, n_ids, n1, ns, f, None)
+    assert seeds(n1=0) == E
+    assert seeds(n1=33) == E                      # more than K1 first-stage words
+    assert seeds(n1=17) == U                      # 17 x 256 keys above 4096
+    assert seeds(ns=0) == E
+    assert seeds(nq=-1) == E
+    assert seeds(n_ids=-5) == E
+    assert "n_ids" in L.knng_last_error().decode()
