@@ -125,6 +125,21 @@ def search_recall(ids, E):
     return hit / float(E.shape[0] * E.shape[1])
 
 
+def search_roofline(knng, xd, graph, qd, sd, k, rounds, ms):
+    """Algorithmic bytes of an E-GNNS batch from its work report (one extra,
+    untimed call; the search is deterministic): a row of D floats per distance
+    taken, kg graph entries per node expanded, plus each query, its seeds and
+    its k results."""
+    _, _, (n_dist, n_exp) = knng.search(xd, graph, qd, sd, k, rounds, work=True)
+    D, kg = xd.shape[1], graph.shape[1]
+    nq, ns = sd.shape
+    alg = n_dist * D * 4 + n_exp * kg * 4 + nq * (D * 4 + ns * 4 + k * 8)
+    gbs = alg / (ms * 1e6)
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "distances": n_dist, "expanded": n_exp,
+            "bytes": alg, "kernel": "k_egnns (row gathers of visited nodes)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -340,7 +355,8 @@ def main():
         search = {"queries": len(Qn), "k": k, "graph_degree": k, "rounds": rounds,
                   "seeds": args.search_seeds, "ms": round(s_ms, 3),
                   "queries_per_s": round(len(Qn) / (s_ms / 1e3), 1),
-                  "data": "synthetic queries from the config's mixture"}
+                  "data": "synthetic queries from the config's mixture",
+                  "roofline": search_roofline(knng, xd, ids, qd, sd, k, rounds, s_ms)}
         if not args.no_recall:
             rq = min(200, len(Qn))
             Eq, _ = exact_knn_fp64(X, Qn[:rq], k)
@@ -379,7 +395,8 @@ def main():
         tc2 = time.perf_counter()
         seed_ms = (tb - ta) * 1e3 / reps
         srch_ms = (tc2 - tb) * 1e3 / reps
-        ivf = {"words": [K1, K2], "train_rows": len(tr), "iters": args.ivf_iters,
+        ivf = {"search_roofline": search_roofline(knng, xd, ids, qd, S_ivf, k, rounds, srch_ms),
+               "words": [K1, K2], "train_rows": len(tr), "iters": args.ivf_iters,
                "rounds": list(rounds_tr), "train_ms": round((t1 - t0) * 1e3, 2),
                "build_ms": round((t2 - t1) * 1e3, 2), "n1": args.ivf_n1, "seeds": ns_ivf,
                "seeds_ms": round(seed_ms, 3), "search_ms": round(srch_ms, 3),

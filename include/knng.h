@@ -202,6 +202,17 @@ int knng_search(const float* data, int64_t n, int32_t D, const int32_t* graph, i
                 int32_t rounds, int32_t* ids_out, float* dists_out, hipStream_t stream);
 
 /*
+ * knng_search_ex -- knng_search with a work report.
+ *   work_out   host, uint64[2], nullable: [0] distances taken over all queries
+ *              (seeds included), [1] nodes expanded (each reads kg graph
+ *              entries); the bytes the search reads follow from them.
+ */
+int knng_search_ex(const float* data, int64_t n, int32_t D, const int32_t* graph, int32_t kg,
+                   const float* queries, int64_t nq, const int32_t* seeds, int32_t ns, int32_t k,
+                   int32_t rounds, int32_t* ids_out, float* dists_out, uint64_t* work_out,
+                   hipStream_t stream);
+
+/*
  * Inverted index for search seeds (Sec. 4.1-4.2, Eqns 1-3).  A point is
  * encoded by two-stage residue vector quantisation (Eqn 1 with two terms): c1
  * is its nearest word in the first vocabulary, c2 the nearest word of the

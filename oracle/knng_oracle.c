@@ -700,12 +700,15 @@ static void rank_insert(int32_t *rid, double *rd, unsigned char *rx, int *rn, in
     if (*rn < k) ++*rn;
 }
 
-/* Queries Q [nq, D], graph G [n, kg], seeds [nq, ns]; outputs [nq, k]. */
+/* Queries Q [nq, D], graph G [n, kg], seeds [nq, ns]; outputs [nq, k].
+ * work_out (nullable, [2]): distances taken over all queries (each visited
+ * node once, seeds included) and nodes expanded. */
 int orc_egnns(const float *X, int64_t n, int D, const int32_t *G, int kg, const float *Q,
               int64_t nq, const int32_t *seeds, int ns, int k, int rounds, int dist_mode,
-              int32_t *ids_out, double *d_out)
+              int32_t *ids_out, double *d_out, int64_t *work_out)
 {
     int fail = 0;
+    int64_t n_dist = 0, n_exp = 0;
 #pragma omp parallel
     {
         unsigned char *vis = (unsigned char *)calloc((size_t)n, 1);
@@ -721,7 +724,7 @@ int orc_egnns(const float *X, int64_t n, int D, const int32_t *G, int kg, const 
 #pragma omp atomic write
             fail = 1;
         } else {
-#pragma omp for schedule(dynamic, 4)
+#pragma omp for schedule(dynamic, 4) reduction(+ : n_dist, n_exp)
             for (int64_t qi = 0; qi < nq; ++qi) {
                 const float *q = Q + (size_t)qi * D;
                 int rn = 0, nt = 0;
@@ -740,6 +743,7 @@ int orc_egnns(const float *X, int64_t n, int D, const int32_t *G, int kg, const 
                             rx[p] = 1;
                         }
                     if (nf == 0) break;
+                    n_exp += nf;
                     int nT = 0;
                     for (int f = 0; f < nf; ++f)
                         for (int e = 0; e < kg; ++e) {
@@ -757,10 +761,15 @@ int orc_egnns(const float *X, int64_t n, int D, const int32_t *G, int kg, const 
                     ids_out[(size_t)qi * k + p] = p < rn ? rid[p] : -1;
                     d_out[(size_t)qi * k + p] = p < rn ? rd[p] : INFINITY;
                 }
+                n_dist += nt;
                 for (int e = 0; e < nt; ++e) vis[touched[e]] = 0;
             }
         }
         free(vis); free(touched); free(rid); free(rd); free(rx); free(front); free(tid); free(td);
+    }
+    if (work_out) {
+        work_out[0] = n_dist;
+        work_out[1] = n_exp;
     }
     return fail ? -1 : 0;
 }

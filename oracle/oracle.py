@@ -72,7 +72,7 @@ def lib():
         L.orc_d32.restype = ctypes.c_double
         L.orc_d32.argtypes = [vp, vp, i32]
         L.orc_egnns.restype = i32
-        L.orc_egnns.argtypes = [vp, i64, i32, vp, i32, vp, i64, vp, i32, i32, i32, i32, vp, vp]
+        L.orc_egnns.argtypes = [vp, i64, i32, vp, i32, vp, i64, vp, i32, i32, i32, i32, vp, vp, vp]
         L.orc_exact_knn_points.restype = i32
         L.orc_exact_knn_points.argtypes = [vp, i64, i32, vp, i64, i32, vp, vp]
         L.orc_kmeans.restype = i32
@@ -310,11 +310,12 @@ def d32(a, b):
     return lib().orc_d32(_p(a), _p(b), a.shape[1])
 
 
-def egnns(X, G, Q, seeds, k, rounds, dist_mode=1):
+def egnns(X, G, Q, seeds, k, rounds, dist_mode=1, with_work=False):
     """Alg. 2 (E-GNNS, readings R10-R13) for every query row of Q.
 
     G: [n, kg] int32 graph (-1 padding); seeds: [nq, ns] int32.
-    Returns (ids int32 [nq, k], dists float64 [nq, k])."""
+    Returns (ids int32 [nq, k], dists float64 [nq, k]) and, with with_work,
+    (distances taken, nodes expanded) over all queries."""
     X, Q = _f32(X), _f32(Q)
     G = np.ascontiguousarray(G, dtype=np.int32)
     S = np.ascontiguousarray(seeds, dtype=np.int32)
@@ -323,10 +324,13 @@ def egnns(X, G, Q, seeds, k, rounds, dist_mode=1):
     assert Q.shape[1] == D and G.shape[0] == n and S.shape[0] == nq
     ids = np.empty((nq, k), np.int32)
     ds = np.empty((nq, k), np.float64)
+    work = np.zeros(2, np.int64)
     rc = lib().orc_egnns(_p(X), n, D, _p(G), G.shape[1], _p(Q), nq, _p(S), S.shape[1], k,
-                         rounds, dist_mode, _p(ids), _p(ds))
+                         rounds, dist_mode, _p(ids), _p(ds), _p(work))
     if rc != 0:
         raise MemoryError("orc_egnns")
+    if with_work:
+        return ids, ds, (int(work[0]), int(work[1]))
     return ids, ds
 
 

@@ -674,10 +674,25 @@ done:
     return rc;
 }
 
+namespace {
+__global__ void k_zero_u64(unsigned long long* p, int count) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+}  // namespace
+
 extern "C" int knng_search(const float* data, int64_t n, int32_t D, const int32_t* graph,
                            int32_t kg, const float* queries, int64_t nq, const int32_t* seeds,
                            int32_t ns, int32_t k, int32_t rounds, int32_t* ids_out,
                            float* dists_out, hipStream_t stream) {
+    return knng_search_ex(data, n, D, graph, kg, queries, nq, seeds, ns, k, rounds, ids_out,
+                          dists_out, nullptr, stream);
+}
+
+extern "C" int knng_search_ex(const float* data, int64_t n, int32_t D, const int32_t* graph,
+                              int32_t kg, const float* queries, int64_t nq, const int32_t* seeds,
+                              int32_t ns, int32_t k, int32_t rounds, int32_t* ids_out,
+                              float* dists_out, uint64_t* work_out, hipStream_t stream) {
     g_err[0] = '\0';
     if (data == nullptr || graph == nullptr || queries == nullptr || seeds == nullptr ||
         ids_out == nullptr || dists_out == nullptr)
@@ -701,10 +716,33 @@ extern "C" int knng_search(const float* data, int64_t n, int32_t D, const int32_
     knng::SearchArgs sa{data, n, D, graph, kg, queries, nq, seeds, ns, k, rounds, ids_out,
                         dists_out, s};
     char err[400] = "";
+    if (work_out == nullptr) {
+        int rc = knng::search_run(sa, err, sizeof(err));
+        if (rc != KNNG_OK) return set_err(rc, "search: %s", err);
+        const hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "search");
+        return KNNG_OK;
+    }
+    // work report: two spread counters in scratch memory
+    knng::DeviceLock dlock;
+    unsigned long long* work = nullptr;
+    std::vector<unsigned long long> h(2 * knng::kStatWords, 0ull);
+    hipError_t e = knng::ws_malloc(reinterpret_cast<void**>(&work),
+                                   sizeof(unsigned long long) * h.size(), s);
+    if (e != hipSuccess) return hip_fail(e, "workspace allocation");
+    k_zero_u64<<<8, 256, 0, s>>>(work, static_cast<int>(h.size()));
+    sa.work = work;
     int rc = knng::search_run(sa, err, sizeof(err));
+    if (rc == KNNG_OK) {
+        e = hipMemcpyAsync(h.data(), work, sizeof(unsigned long long) * h.size(),
+                           hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    knng::ws_free(work, s);
     if (rc != KNNG_OK) return set_err(rc, "search: %s", err);
-    const hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "search");
+    work_out[0] = knng::stat_total(h.data());
+    work_out[1] = knng::stat_total(h.data() + knng::kStatWords);
     return KNNG_OK;
 }
 

@@ -273,6 +273,7 @@ struct SearchArgs {
     int32_t* ids_out;     // [nq][k]
     float* d_out;
     hipStream_t stream;
+    unsigned long long* work = nullptr;  // nullable: 2 spread counters (distances, expansions)
 };
 int search_run(const SearchArgs& a, char* err, size_t errlen);
 

@@ -16,6 +16,8 @@
 // block a sequential fused multiply-add from 0, blocks added in order -- the
 // library's output distance, so the rank order is the one the oracle takes
 // in its d32 mode.  A round without an unexpanded member ends the search.
+// work (nullable): spread counters of the distances taken and the nodes
+// expanded, for the bytes the search reads.
 #include "knng_internal.hpp"
 #include "wave.hpp"
 
@@ -100,7 +102,8 @@ struct SearchShape {
 __global__ __launch_bounds__(kSearchThreads) void k_egnns(
     const float* __restrict__ X, int64_t n, int D, const int32_t* __restrict__ G, int kg,
     const float* __restrict__ Q, const int32_t* __restrict__ seeds, int ns, int k, int rounds,
-    SearchShape sh, int32_t* __restrict__ ids_out, float* __restrict__ d_out) {
+    SearchShape sh, int32_t* __restrict__ ids_out, float* __restrict__ d_out,
+    unsigned long long* __restrict__ work) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int H = 1 << sh.hbits;
     uint64_t* keys = reinterpret_cast<uint64_t*>(smem);                  // [scap]: R then T
@@ -108,6 +111,7 @@ __global__ __launch_bounds__(kSearchThreads) void k_egnns(
     int32_t* tab = reinterpret_cast<int32_t*>(q + ((D + 3) & ~3));       // [H]
     int32_t* front = tab + H;                                            // [k]
     __shared__ int s_nr, s_nt, s_nf;
+    __shared__ unsigned long long s_dist, s_exp;  // distances taken, nodes expanded
 
     const int tid = threadIdx.x;
     const int64_t qi = blockIdx.x;
@@ -117,6 +121,8 @@ __global__ __launch_bounds__(kSearchThreads) void k_egnns(
     if (tid == 0) {
         s_nr = 0;
         s_nt = 0;
+        s_dist = 0;
+        s_exp = 0;
     }
 
     // R lives in keys[0, k) (empty slots hold the largest key), the round's
@@ -146,6 +152,7 @@ __global__ __launch_bounds__(kSearchThreads) void k_egnns(
         if (tid == 0) {
             s_nr = nr + nt < k ? nr + nt : k;
             s_nt = 0;
+            s_dist += static_cast<unsigned long long>(nt);
         }
         __syncthreads();
     };
@@ -171,6 +178,7 @@ __global__ __launch_bounds__(kSearchThreads) void k_egnns(
                 if (expand(tab, sh.hbits, id)) front[nf++] = id;
             }
             s_nf = nf;
+            s_exp += static_cast<unsigned long long>(nf);
         }
         __syncthreads();
         const int nf = s_nf;
@@ -188,6 +196,10 @@ __global__ __launch_bounds__(kSearchThreads) void k_egnns(
     }
 
     const int nr = s_nr;
+    if (work != nullptr && tid == 0) {
+        stat_add(work, static_cast<unsigned>(blockIdx.x), s_dist);
+        stat_add(work + kStatWords, static_cast<unsigned>(blockIdx.x), s_exp);
+    }
     for (int p = tid; p < k; p += kSearchThreads) {
         const bool ok = p < nr;
         ids_out[qi * k + p] = ok ? key_id(keys[p]) : -1;
@@ -219,7 +231,8 @@ int search_run(const SearchArgs& a, char* err, size_t errlen) {
     }
     if (a.nq == 0) return kOk;
     k_egnns<<<static_cast<unsigned>(a.nq), kSearchThreads, lds, a.stream>>>(
-        a.X, a.n, a.D, a.G, a.kg, a.Q, a.seeds, a.ns, a.k, a.rounds, sh, a.ids_out, a.d_out);
+        a.X, a.n, a.D, a.G, a.kg, a.Q, a.seeds, a.ns, a.k, a.rounds, sh, a.ids_out, a.d_out,
+        a.work);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         std::snprintf(err, errlen, "search launch failed: %s", hipGetErrorString(e));

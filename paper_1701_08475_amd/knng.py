@@ -87,6 +87,8 @@ def lib():
                                    ctypes.POINTER(KnngOptions), vp, vp, vp]
     L.knng_search.restype = ctypes.c_int
     L.knng_search.argtypes = [vp, i64, i32, vp, i32, vp, i64, vp, i32, i32, i32, vp, vp, vp]
+    L.knng_search_ex.argtypes = [vp, i64, i32, vp, i32, vp, i64, vp, i32, i32, i32, vp, vp,
+                                 ctypes.POINTER(ctypes.c_uint64), vp]
     L.knng_release_workspace.restype = None
     L.knng_release_workspace.argtypes = []
     L.knng_rvq_train.argtypes = [vp, i64, i32, vp, i64, i32, i32, vp, vp, i32, vp, vp, vp, vp,
@@ -218,12 +220,12 @@ def leaf_search(x, k, perms, leaf_offs, precision="fp32", rerank_factor=2, strea
     return ids, ds
 
 
-def search(x, graph, queries, seeds, k, rounds, stream=None):
+def search(x, graph, queries, seeds, k, rounds, stream=None, work=False):
     """E-GNNS (Alg. 2) for a batch of queries over a kNN graph.
 
     x: float32 CUDA [n, D]; graph: int32 CUDA [n, kg]; queries: float32 CUDA
     [nq, D]; seeds: int32 CUDA [nq, ns].  Returns (ids int32 [nq, k], dists
-    float32 [nq, k])."""
+    float32 [nq, k]) and, with work=True, (distances taken, nodes expanded)."""
     import torch
     x = _dev_f32(x)
     queries = _dev_f32(queries)
@@ -239,12 +241,16 @@ def search(x, graph, queries, seeds, k, rounds, stream=None):
     nq = queries.shape[0]
     ids = torch.empty((nq, k), dtype=torch.int32, device=x.device)
     ds = torch.empty((nq, k), dtype=torch.float32, device=x.device)
-    rc = lib().knng_search(ctypes.c_void_p(x.data_ptr()), n, D, ctypes.c_void_p(graph.data_ptr()),
-                           graph.shape[1], ctypes.c_void_p(queries.data_ptr()), nq,
-                           ctypes.c_void_p(seeds.data_ptr()), seeds.shape[1], k, rounds,
-                           ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(ds.data_ptr()),
-                           _stream(stream))
+    w = (ctypes.c_uint64 * 2)()
+    rc = lib().knng_search_ex(ctypes.c_void_p(x.data_ptr()), n, D,
+                              ctypes.c_void_p(graph.data_ptr()), graph.shape[1],
+                              ctypes.c_void_p(queries.data_ptr()), nq,
+                              ctypes.c_void_p(seeds.data_ptr()), seeds.shape[1], k, rounds,
+                              ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(ds.data_ptr()),
+                              w if work else None, _stream(stream))
     _check(rc)
+    if work:
+        return ids, ds, (int(w[0]), int(w[1]))
     return ids, ds
 
 

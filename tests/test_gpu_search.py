@@ -26,11 +26,14 @@ def _i32(a):
 
 
 def _run(K, orc, X, G, Q, S, k, rounds):
-    ids, ds = K.search(to_dev(X), _i32(G), to_dev(Q), _i32(S), k, rounds)
+    ids, ds, work = K.search(to_dev(X), _i32(G), to_dev(Q), _i32(S), k, rounds, work=True)
     ids, ds = ids.cpu().numpy(), ds.cpu().numpy()
-    o_ids, o_d = orc.egnns(X, G, Q, S, k, rounds, dist_mode=1)
+    o_ids, o_d, o_work = orc.egnns(X, G, Q, S, k, rounds, dist_mode=1, with_work=True)
     assert np.array_equal(ids, o_ids)
     assert np.array_equal(ds.astype(np.float64), o_d)
+    assert work == o_work  # distances taken and nodes expanded
+    ids2, ds2 = K.search(to_dev(X), _i32(G), to_dev(Q), _i32(S), k, rounds)  # no report
+    assert np.array_equal(ids2.cpu().numpy(), ids)
     return ids, ds
 
 

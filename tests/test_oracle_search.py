@@ -153,3 +153,25 @@ def test_query_generator_shares_the_mixture():
     # (sigma = 1, D = 32: squared distances ~ 2 * 32); an unrelated draw of
     # centres in [-10, 10]^32 would be hundreds away
     assert np.median(d) < 150
+
+
+def test_work_counts_hand_traced(orc):
+    """Chain 0..9, query 7.3, seed 0, k = 1: round t (t <= 8) expands the
+    current best and takes one new distance (its unvisited right neighbour);
+    round 8 expands 7, whose new neighbour 8 does not enter R, and round 9
+    has nothing to expand.  So r rounds take 1 + min(r, 8) distances and
+    expand min(r, 8) nodes.  A complete graph of n nodes: one round from one
+    seed takes n distances and expands one node."""
+    X, G = _chain()
+    Q = np.array([[7.3]], np.float32)
+    S = np.array([[0]], np.int32)
+    for r in range(12):
+        _, _, (nd, ne) = orc.egnns(X, G, Q, S, 1, r, dist_mode=0, with_work=True)
+        assert (nd, ne) == (1 + min(r, 8), min(r, 8)), r
+    n = 40
+    Xc = datagen.random_points(n, 3, 50, "normal")
+    Gc = np.array([[j for j in range(n) if j != i] for i in range(n)], np.int32)
+    Qc = datagen.random_points(4, 3, 51, "normal")
+    Sc = np.arange(4, dtype=np.int32).reshape(4, 1)
+    _, _, (nd, ne) = orc.egnns(Xc, Gc, Qc, Sc, 5, 1, dist_mode=0, with_work=True)
+    assert (nd, ne) == (4 * n, 4)
