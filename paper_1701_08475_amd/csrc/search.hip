@@ -9,9 +9,13 @@
 //     bit 31 of a slot marks a node already expanded;
 //   - the rank list R: the k best keys (d32 bits << 32 | id), ascending;
 //   - the round's new candidates T, appended by the threads that claimed
-//     them; R u T is ordered with a block bitonic sort and R takes the first
-//     k (the k-th distance of R never grows, so entries beyond k can never
-//     return).
+//     them; once R holds k entries only the candidates below its k-th key
+//     can enter (keys are unique), so T is cut to those first; R u T is
+//     ordered with a block bitonic sort and R takes the first k (the k-th
+//     distance of R never grows, so entries beyond k can never return).
+// The frontier (members of R not expanded yet) is marked by one thread per
+// member of R; its order does not matter (a neighbour shared by two members
+// is claimed once, with the same distance).
 // A thread computes the canonical d32 of one candidate: per 32-dimension
 // block a sequential fused multiply-add from 0, blocks added in order -- the
 // library's output distance, so the rank order is the one the oracle takes
@@ -110,7 +114,7 @@ __global__ __launch_bounds__(kSearchThreads) void k_egnns(
     float* q = reinterpret_cast<float*>(keys + sh.scap);                 // [D, padded to 4]
     int32_t* tab = reinterpret_cast<int32_t*>(q + ((D + 3) & ~3));       // [H]
     int32_t* front = tab + H;                                            // [k]
-    __shared__ int s_nr, s_nt, s_nf;
+    __shared__ int s_nr, s_nt, s_nf, s_ns;
     __shared__ unsigned long long s_dist, s_exp;  // distances taken, nodes expanded
 
     const int tid = threadIdx.x;
@@ -121,6 +125,8 @@ __global__ __launch_bounds__(kSearchThreads) void k_egnns(
     if (tid == 0) {
         s_nr = 0;
         s_nt = 0;
+        s_nf = 0;
+        s_ns = 0;
         s_dist = 0;
         s_exp = 0;
     }
@@ -129,11 +135,28 @@ __global__ __launch_bounds__(kSearchThreads) void k_egnns(
     // new candidates in keys[k, k + nt); merge = sort keys[0, m) for the
     // power of two m >= k + nt, after which keys[0, k) is the new R
     for (int i = tid; i < k; i += kSearchThreads) keys[i] = ~0ull;
+    constexpr int kCut = 8;  // candidates per thread held in registers by the cut
     auto merge = [&]() {
         const int nr = s_nr, nt = s_nt;
+        int nk = nt;  // candidates that can still enter R
+        if (nr == k && nt > 0 && nt <= kCut * kSearchThreads) {
+            const uint64_t kth = keys[k - 1];
+            uint64_t v[kCut];
+#pragma unroll
+            for (int j = 0; j < kCut; ++j) {
+                const int i = tid + j * kSearchThreads;
+                v[j] = i < nt ? keys[k + i] : ~0ull;
+            }
+            __syncthreads();  // every candidate read before any is moved
+#pragma unroll
+            for (int j = 0; j < kCut; ++j)
+                if (v[j] < kth) keys[k + atomicAdd(&s_ns, 1)] = v[j];
+            __syncthreads();
+            nk = s_ns;
+        }
         int m = 1;
-        while (m < k + nt) m <<= 1;
-        for (int i = k + nt + tid; i < m; i += kSearchThreads) keys[i] = ~0ull;
+        while (m < k + nk) m <<= 1;
+        for (int i = k + nk + tid; i < m; i += kSearchThreads) keys[i] = ~0ull;
         __syncthreads();
         for (int size = 2; size <= m; size <<= 1)
             for (int stride = size >> 1; stride >= 1; stride >>= 1) {
@@ -150,8 +173,10 @@ __global__ __launch_bounds__(kSearchThreads) void k_egnns(
                 __syncthreads();
             }
         if (tid == 0) {
-            s_nr = nr + nt < k ? nr + nt : k;
+            s_nr = nr + nk < k ? nr + nk : k;
             s_nt = 0;
+            s_ns = 0;
+            s_nf = 0;
             s_dist += static_cast<unsigned long long>(nt);
         }
         __syncthreads();
@@ -170,22 +195,24 @@ __global__ __launch_bounds__(kSearchThreads) void k_egnns(
     merge();
 
     for (int t = 0; t < rounds; ++t) {
-        // frontier: the members of R not expanded yet, in rank order
-        if (tid == 0) {
-            int nf = 0;
-            for (int p = 0; p < s_nr; ++p) {
-                const int32_t id = key_id(keys[p]);
-                if (expand(tab, sh.hbits, id)) front[nf++] = id;
-            }
-            s_nf = nf;
-            s_exp += static_cast<unsigned long long>(nf);
+        // frontier: the members of R not expanded yet (front[p] = its id, or
+        // -1 for a member expanded before)
+        const int nr = s_nr;
+        for (int p = tid; p < nr; p += kSearchThreads) {
+            const int32_t id = key_id(keys[p]);
+            const bool fresh = expand(tab, sh.hbits, id);
+            front[p] = fresh ? id : -1;
+            if (fresh) atomicAdd(&s_nf, 1);
         }
         __syncthreads();
         const int nf = s_nf;
+        if (tid == 0) s_exp += static_cast<unsigned long long>(nf);
         if (nf == 0) break;
         // neighbours of the frontier not visited before
-        for (int c = tid; c < nf * kg; c += kSearchThreads) {
-            const int32_t id = G[static_cast<size_t>(front[c / kg]) * kg + c % kg];
+        for (int c = tid; c < nr * kg; c += kSearchThreads) {
+            const int32_t f = front[c / kg];
+            if (f < 0) continue;
+            const int32_t id = G[static_cast<size_t>(f) * kg + c % kg];
             if (id >= 0 && id < n && visit(tab, sh.hbits, id)) {
                 const float d = d32_row(q, X + static_cast<size_t>(id) * D, D, vec4);
                 keys[k + atomicAdd(&s_nt, 1)] = cand_key(d, id);
