@@ -448,6 +448,71 @@ __global__ __launch_bounds__(kSeedThreads) void k_ivf_seeds(
         }
     }
     __syncthreads();
+    // The first lists by repeated block minimum of (d, key): a handful of
+    // lists usually holds ns ids.  A picked key becomes (+inf, INT_MAX);
+    // lists are taken in the order a full sort would give, so the rest
+    // (after kPicks lists) continues from a sort of what is left.
+    constexpr int kPicks = 32;
+    constexpr int kWaves = kSeedThreads / kWave;
+    __shared__ double s_md[kWaves];
+    __shared__ int32_t s_mk[kWaves], s_me[kWaves];
+    __shared__ int32_t s_pick[2];
+    const int lane = tid & (kWave - 1), wv = tid / kWave;
+    int taken = 0;
+    bool exhausted = false;
+    for (int it = 0; it < kPicks && taken < ns; ++it) {
+        double bd = __longlong_as_double(0x7ff0000000000000ll);
+        int32_t bk = INT_MAX, be = -1;
+        for (int e = tid; e < M; e += kSeedThreads)
+            if (dk_less(sd[e], sk[e], bd, bk)) {
+                bd = sd[e];
+                bk = sk[e];
+                be = e;
+            }
+#pragma unroll
+        for (int o = kWave / 2; o >= 1; o >>= 1) {
+            const double od = shfl_xor_f64(bd, o);
+            const int32_t ok = __shfl_xor(bk, o, kWave), oe = __shfl_xor(be, o, kWave);
+            if (dk_less(od, ok, bd, bk)) {
+                bd = od;
+                bk = ok;
+                be = oe;
+            }
+        }
+        if (lane == 0) {
+            s_md[wv] = bd;
+            s_mk[wv] = bk;
+            s_me[wv] = be;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int w0 = 0;
+            for (int w = 1; w < kWaves; ++w)
+                if (dk_less(s_md[w], s_mk[w], s_md[w0], s_mk[w0])) w0 = w;
+            s_pick[0] = s_mk[w0];
+            s_pick[1] = s_me[w0];
+        }
+        __syncthreads();
+        const int32_t pk = s_pick[0], pe = s_pick[1];
+        if (pk >= nk || pe < 0) {  // only padding keys are left
+            exhausted = true;
+            break;
+        }
+        const int32_t a0 = off[pk];
+        const int take = min(off[pk + 1] - a0, ns - taken);
+        for (int j = tid; j < take; j += kSeedThreads) seeds[qi * ns + taken + j] = ids[a0 + j];
+        taken += take;
+        if (tid == 0) {
+            sd[pe] = __longlong_as_double(0x7ff0000000000000ll);
+            sk[pe] = INT_MAX;
+        }
+        __syncthreads();
+    }
+    if (taken >= ns) return;
+    if (exhausted) {
+        for (int s = taken + tid; s < ns; s += kSeedThreads) seeds[qi * ns + s] = -1;
+        return;
+    }
     bitonic_dk(sd, sk, sh.p2);
     // inclusive scan of the list sizes in key order (sc overwrites sd)
     const int per = (sh.p2 + kSeedThreads - 1) / kSeedThreads;
@@ -472,7 +537,8 @@ __global__ __launch_bounds__(kSeedThreads) void k_ivf_seeds(
     }
     __syncthreads();
     const int32_t total = M > 0 ? sc[M - 1] : 0;
-    for (int s = tid; s < ns; s += kSeedThreads) {
+    for (int s0 = taken + tid; s0 < ns; s0 += kSeedThreads) {
+        const int s = s0 - taken;  // position among the ids of the lists not picked
         int32_t out = -1;
         if (s < total) {
             int a = 0, b = M - 1;  // first e with sc[e] > s
@@ -484,7 +550,7 @@ __global__ __launch_bounds__(kSeedThreads) void k_ivf_seeds(
             const int32_t before = a ? sc[a - 1] : 0;
             out = ids[off[sk[a]] + (s - before)];
         }
-        seeds[qi * ns + s] = out;
+        seeds[qi * ns + s0] = out;
     }
 }
 
