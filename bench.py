@@ -216,13 +216,16 @@ def main():
         log("warmup %d done" % w)
     torch.cuda.synchronize()
     sts = []
+    marks = []  # each build call returns after its work is done
     t0 = time.perf_counter()
     for s in range(args.steps):
         # HIP events around every kernel launch (about 300 per build) cost
         # about 2 ms per build: they are recorded in the last timed step only
         sts.append(step(timed_kernels=(s == args.steps - 1))[2])
+        marks.append(time.perf_counter())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    step_ms = [(b - a) * 1e3 for a, b in zip([t0] + marks[:-1], marks)]
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = n / (ms_per_step / 1e3)
     log("timed %d steps: %.2f ms/step, %.3e points/s" % (args.steps, ms_per_step, value))
@@ -416,6 +419,9 @@ def main():
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "points/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "step_ms": [round(v, 3) for v in step_ms],
+        "median_ms_without_kernel_events": (round(float(np.median(step_ms[:-1])), 3)
+                                            if len(step_ms) > 1 else None),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64 partition / %s leaf" % c["precision"],
         "data": "synthetic (seeded Gaussian mixture shaped like the paper's workloads)",
