@@ -4,19 +4,22 @@
 //  - k_nearest: the nearest vocabulary word of each point in FP64, every term
 //    of the squared distance added by a fused multiply-add in dimension
 //    order, the lowest index among equal distances.  One thread per point;
-//    the words pass through LDS in tiles of 32 words x 16 dimensions, stored
-//    dimension-major so all lanes read the same two words (a broadcast).  A
-//    point is a row of X (stage 1) or its stage-1 residue x - w1[c1]
-//    (stage 2), formed on the fly.
+//    the words pass through LDS in double-buffered tiles of 32 words x 16
+//    dimensions, stored dimension-major so all lanes read the same two words
+//    (a broadcast).  A point is a row of X (stage 1) or its stage-1 residue
+//    x - w1[c1] (stage 2), formed on the fly, with vector loads when the
+//    rows allow.
 //  - Lloyd's update: the training positions are bucketed by code with a
 //    stable counting sort, then one thread per (word, dimension) adds its
-//    members in increasing position and divides by their count.
+//    members in increasing position (their row ids staged in LDS 64 at a
+//    time) and divides by their count.
 //  - Inverted lists: a stable radix sort of the keys, 8 bits a pass, carries
 //    the point ids, so every list comes out in increasing id order.
 //  - Seeds: one workgroup per query computes the query's dot products with
-//    all words, term 1 of every first-stage word, the n1 best, d(q, I) of the
-//    n1 x K2 keys under them, sorts the keys, scans the list sizes in that
-//    order and takes the first ns ids.
+//    all words, term 1 of every first-stage word, the n1 best and d(q, I) of
+//    the n1 x K2 keys under them; it takes the lists in (d, key) order --
+//    the first ones by repeated block minimum, the rest (rarely needed) from
+//    a sort with a scan of the list sizes -- until ns ids are taken.
 #include "knng_internal.hpp"
 #include "wave.hpp"
 
