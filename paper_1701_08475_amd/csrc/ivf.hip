@@ -23,6 +23,7 @@
 #include "knng_internal.hpp"
 #include "wave.hpp"
 
+#include <algorithm>
 #include <climits>
 #include <cstdio>
 
@@ -43,12 +44,16 @@ constexpr int kSeedThreads = 256;
 // VEC: D % 16 == 0 and 16-byte aligned rows, so each slice of a point is read
 // as four float4 (and its stage-1 word as eight double2) instead of 16 loads
 // of single elements, each touching 64 cache lines per wave.
+// Word groups (few points): block row blockIdx.y takes word tiles
+// [y tpg, (y+1) tpg) and writes its best (distance, word) to pbest / pidx
+// [gridDim.y][m]; k_nearest_reduce then takes the minimum over the groups in
+// word order.  With pbest == nullptr the block takes every word.
 template <bool VEC>
 __global__ __launch_bounds__(kNearThreads) void k_nearest(
     const float* __restrict__ X, int D, const int32_t* __restrict__ rows, int64_t m,
     const double* __restrict__ W1, const int32_t* __restrict__ c1, const double* __restrict__ W,
     int K, int32_t* __restrict__ codes, int32_t* __restrict__ changed, int32_t* __restrict__ key_out,
-    int K2) {
+    int K2, int tpg, double* __restrict__ pbest, int32_t* __restrict__ pidx) {
     // two LDS buffers: the slice of step s+1 is loaded while step s computes
     __shared__ __align__(16) double s_w[2][kDC][kTJ];
     constexpr int kPer = kDC * kTJ / kNearThreads;  // tile values loaded per thread
@@ -61,11 +66,15 @@ __global__ __launch_bounds__(kNearThreads) void k_nearest(
     const double* r = W1 != nullptr ? W1 + static_cast<size_t>(base) * D : nullptr;
     double best = 0.0;
     int bj = 0;
+    bool have = false;  // best holds a word of this block's range
     // steps run over (word tile j0, dimension slice d0), d0 fastest
     const int nd = (D + kDC - 1) / kDC;
-    const int nsteps = ((K + kTJ - 1) / kTJ) * nd;
+    const int ntiles = (K + kTJ - 1) / kTJ;
+    const int t0 = pbest != nullptr ? static_cast<int>(blockIdx.y) * tpg : 0;
+    const int t1 = pbest != nullptr ? min(t0 + tpg, ntiles) : ntiles;
+    const int nsteps = (t1 - t0) * nd;
     auto fetch = [&](int st, double (&q)[kPer]) {
-        const int j0 = (st / nd) * kTJ, d0 = (st % nd) * kDC;
+        const int j0 = (t0 + st / nd) * kTJ, d0 = (st % nd) * kDC;
 #pragma unroll
         for (int i = 0; i < kPer; ++i) {
             const int e = threadIdx.x + i * kNearThreads;
@@ -87,7 +96,7 @@ __global__ __launch_bounds__(kNearThreads) void k_nearest(
     __syncthreads();
     double acc[kTJ];
     for (int st = 0; st < nsteps; ++st) {
-        const int j0 = (st / nd) * kTJ, d0 = (st % nd) * kDC;
+        const int j0 = (t0 + st / nd) * kTJ, d0 = (st % nd) * kDC;
         if (d0 == 0) {
 #pragma unroll
             for (int j = 0; j < kTJ; ++j) acc[j] = 0.0;
@@ -139,13 +148,21 @@ __global__ __launch_bounds__(kNearThreads) void k_nearest(
         if (d0 + kDC >= D) {  // last slice of the word tile
 #pragma unroll
             for (int j = 0; j < kTJ; ++j)
-                if (j0 + j < K && (j0 + j == 0 || acc[j] < best)) {
+                if (j0 + j < K && (!have || acc[j] < best)) {
                     best = acc[j];
                     bj = j0 + j;
+                    have = true;
                 }
         }
         if (st + 1 < nsteps) stash(buf ^ 1, q);
         __syncthreads();
+    }
+    if (pbest != nullptr) {  // this group's best; k_nearest_reduce finishes
+        if (live) {
+            pbest[blockIdx.y * m + p] = best;
+            pidx[blockIdx.y * m + p] = bj;
+        }
+        return;
     }
     if (changed != nullptr) {
         const bool ch = live && codes[p] != bj;
@@ -155,6 +172,36 @@ __global__ __launch_bounds__(kNearThreads) void k_nearest(
     if (!live) return;
     if (codes != nullptr) codes[p] = bj;
     if (key_out != nullptr) key_out[p] = base * K2 + bj;
+}
+
+// The nearest word over G word groups, taken in group (= word) order with a
+// strict comparison, so the lowest word index wins among equal distances;
+// then as the epilogue of k_nearest.
+__global__ __launch_bounds__(256) void k_nearest_reduce(
+    int64_t m, int G, const double* __restrict__ pbest, const int32_t* __restrict__ pidx,
+    const int32_t* __restrict__ c1, int32_t* __restrict__ codes, int32_t* __restrict__ changed,
+    int32_t* __restrict__ key_out, int K2) {
+    const int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    const bool live = p < m;
+    double best = 0.0;
+    int bj = 0;
+    if (live) {
+        best = pbest[p];
+        bj = pidx[p];
+        for (int g = 1; g < G; ++g)
+            if (pbest[g * m + p] < best) {
+                best = pbest[g * m + p];
+                bj = pidx[g * m + p];
+            }
+    }
+    if (changed != nullptr) {
+        const bool ch = live && codes[p] != bj;
+        const uint64_t mask = __ballot(ch);
+        if (lane_id() == 0 && mask != 0) atomicAdd(changed, static_cast<int32_t>(__popcll(mask)));
+    }
+    if (!live) return;
+    if (codes != nullptr) codes[p] = bj;
+    if (key_out != nullptr) key_out[p] = (c1 != nullptr ? c1[p] : 0) * K2 + bj;
 }
 
 // W[j] <- value of training position init[j] (as in k_nearest).
@@ -559,20 +606,42 @@ __global__ __launch_bounds__(kSeedThreads) void k_ivf_seeds(
 
 int nblocks(int64_t count, int per) { return static_cast<int>((count + per - 1) / per); }
 
+constexpr int kMaxWordGroups = 8;
+
+// Word groups for m points: enough blocks to fill the GPU (about 2048), at
+// most one group per word tile.
+int word_groups(int64_t m, int K) {
+    const int nb = nblocks(m, kNearThreads);
+    const int ntiles = (K + kTJ - 1) / kTJ;
+    int G = 1;
+    while (G < kMaxWordGroups && G < ntiles && static_cast<int64_t>(nb) * G < 2048) G <<= 1;
+    return G < ntiles ? G : ntiles;
+}
+
 // Nearest word of every point (k_nearest), with vector loads when the rows
-// allow them.
+// allow them; pbest / pidx: scratch of word_groups(m, K) x m entries (unused
+// when that is 1).
 void nearest(const float* X, int D, const int32_t* rows, int64_t m, const double* W1,
              const int32_t* c1, const double* W, int K, int32_t* codes, int32_t* changed,
-             int32_t* key_out, int K2, hipStream_t s) {
+             int32_t* key_out, int K2, double* pbest, int32_t* pidx, hipStream_t s) {
     const bool vec = D % kDC == 0 && (reinterpret_cast<uintptr_t>(X) & 15u) == 0 &&
                      (W1 == nullptr || (reinterpret_cast<uintptr_t>(W1) & 15u) == 0);
     const int nb = nblocks(m, kNearThreads);
+    const int G = word_groups(m, K);
+    const int ntiles = (K + kTJ - 1) / kTJ;
+    const int tpg = (ntiles + G - 1) / G;
+    const dim3 grid(nb, G);
+    double* pb = G > 1 ? pbest : nullptr;
+    int32_t* pi = G > 1 ? pidx : nullptr;
     if (vec)
-        k_nearest<true><<<nb, kNearThreads, 0, s>>>(X, D, rows, m, W1, c1, W, K, codes, changed,
-                                                    key_out, K2);
+        k_nearest<true><<<grid, kNearThreads, 0, s>>>(X, D, rows, m, W1, c1, W, K, codes, changed,
+                                                      key_out, K2, tpg, pb, pi);
     else
-        k_nearest<false><<<nb, kNearThreads, 0, s>>>(X, D, rows, m, W1, c1, W, K, codes, changed,
-                                                     key_out, K2);
+        k_nearest<false><<<grid, kNearThreads, 0, s>>>(X, D, rows, m, W1, c1, W, K, codes,
+                                                       changed, key_out, K2, tpg, pb, pi);
+    if (G > 1)
+        k_nearest_reduce<<<nblocks(m, 256), 256, 0, s>>>(m, G, pbest, pidx, W1 != nullptr ? c1 : nullptr,
+                                                        codes, changed, key_out, K2);
 }
 
 // Stable sort of (key, val) by the digit at shift (val nullable: index).
@@ -617,10 +686,10 @@ int finish(hipError_t e, const char* what, char* err, size_t errlen) {
 // One Lloyd run (R16) over the training positions; W holds the start words.
 int kmeans_run(const float* X, int D, const int32_t* rows, int64_t m, const double* W1,
                const int32_t* c1, double* W, int K, int iters, int32_t* codes, int32_t* skey,
-               int32_t* order, int32_t* hist, int32_t* woff, int32_t* dchanged, int* rounds_out,
-               hipStream_t s, char* err, size_t errlen) {
+               int32_t* order, int32_t* hist, int32_t* woff, int32_t* dchanged, double* pbest,
+               int32_t* pidx, int* rounds_out, hipStream_t s, char* err, size_t errlen) {
     k_fill_i32<<<nblocks(m, 256) < 1024 ? nblocks(m, 256) : 1024, 256, 0, s>>>(codes, m, -1);
-    nearest(X, D, rows, m, W1, c1, W, K, codes, nullptr, nullptr, 0, s);
+    nearest(X, D, rows, m, W1, c1, W, K, codes, nullptr, nullptr, 0, pbest, pidx, s);
     int rounds = 0;
     while (rounds < iters) {
         digit_pass(codes, nullptr, m, 0, hist, skey, order, s);
@@ -628,7 +697,7 @@ int kmeans_run(const float* X, int D, const int32_t* rows, int64_t m, const doub
             skey, m, K, woff);
         k_word_means<<<dim3(K, (D + 63) / 64), 64, 0, s>>>(X, D, rows, W1, c1, order, woff, W);
         k_fill_i32<<<1, 64, 0, s>>>(dchanged, 1, 0);
-        nearest(X, D, rows, m, W1, c1, W, K, codes, dchanged, nullptr, 0, s);
+        nearest(X, D, rows, m, W1, c1, W, K, codes, dchanged, nullptr, 0, pbest, pidx, s);
         int32_t h = 0;
         hipError_t e = hipMemcpyAsync(&h, dchanged, sizeof(h), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -661,6 +730,9 @@ int rvq_train_run(const RvqTrainArgs& a, char* err, size_t errlen) {
     int32_t* hist = ws.get<int32_t>(256 * static_cast<size_t>(nblocks(m, kSortB)));
     int32_t* woff = ws.get<int32_t>(K + 1);
     int32_t* changed = ws.get<int32_t>(1);
+    const size_t ng = static_cast<size_t>(word_groups(m, K)) * m;  // word-group partials
+    double* pbest = ws.get<double>(ng);
+    int32_t* pidx = ws.get<int32_t>(ng);
     if (ws.e != hipSuccess) {
         std::snprintf(err, errlen, "workspace: %s", hipGetErrorString(ws.e));
         return kOom;
@@ -678,11 +750,11 @@ int rvq_train_run(const RvqTrainArgs& a, char* err, size_t errlen) {
     }
     k_init_words<<<a.K1, 64, 0, s>>>(a.X, a.D, a.train_ids, nullptr, nullptr, a.init1, a.W1);
     rc = kmeans_run(a.X, a.D, a.train_ids, m, nullptr, nullptr, a.W1, a.K1, a.iters, codes1, skey,
-                    order, hist, woff, changed, a.rounds, s, err, errlen);
+                    order, hist, woff, changed, pbest, pidx, a.rounds, s, err, errlen);
     if (rc != kOk) return rc;
     k_init_words<<<a.K2, 64, 0, s>>>(a.X, a.D, a.train_ids, a.W1, codes1, a.init2, a.W2);
     rc = kmeans_run(a.X, a.D, a.train_ids, m, a.W1, codes1, a.W2, a.K2, a.iters, codes2, skey,
-                    order, hist, woff, changed, a.rounds + 1, s, err, errlen);
+                    order, hist, woff, changed, pbest, pidx, a.rounds + 1, s, err, errlen);
     if (rc != kOk) return rc;
     if (a.codes1 != nullptr)
         rc = finish(hipMemcpyAsync(a.codes1, codes1, sizeof(int32_t) * m, hipMemcpyDeviceToDevice, s),
@@ -705,13 +777,19 @@ int ivf_build_run(const IvfBuildArgs& a, char* err, size_t errlen) {
     int32_t* v2 = ws.get<int32_t>(n);
     int32_t* k3 = ws.get<int32_t>(n);
     int32_t* hist = ws.get<int32_t>(256 * static_cast<size_t>(nblocks(n, kSortB)));
+    const int G = std::max(word_groups(n, a.K1), word_groups(n, a.K2));
+    const size_t ng = G > 1 ? static_cast<size_t>(G) * n : 1;  // word-group partials
+    double* pbest = ws.get<double>(ng);
+    int32_t* pidx = ws.get<int32_t>(ng);
     if (ws.e != hipSuccess) {
         std::snprintf(err, errlen, "workspace: %s", hipGetErrorString(ws.e));
         return kOom;
     }
     if (n > 0) {
-        nearest(a.X, a.D, nullptr, n, nullptr, nullptr, a.W1, a.K1, c1, nullptr, nullptr, 0, s);
-        nearest(a.X, a.D, nullptr, n, a.W1, c1, a.W2, a.K2, nullptr, nullptr, key, a.K2, s);
+        nearest(a.X, a.D, nullptr, n, nullptr, nullptr, a.W1, a.K1, c1, nullptr, nullptr, 0, pbest,
+                pidx, s);
+        nearest(a.X, a.D, nullptr, n, a.W1, c1, a.W2, a.K2, nullptr, nullptr, key, a.K2, pbest,
+                pidx, s);
         if (nk <= 256) {
             digit_pass(key, nullptr, n, 0, hist, k3, a.ids_out, s);
         } else {
