@@ -125,15 +125,19 @@ def search_recall(ids, E):
     return hit / float(E.shape[0] * E.shape[1])
 
 
-def search_roofline(knng, xd, graph, qd, sd, k, rounds, ms):
+def search_roofline(knng, xd, graph, qd, sd, k, rounds, ms, x8=None):
     """Algorithmic bytes of an E-GNNS batch from its work report (one extra,
-    untimed call; the search is deterministic): a row of D floats per distance
-    taken, kg graph entries per node expanded, plus each query, its seeds and
-    its k results."""
-    _, _, (n_dist, n_exp) = knng.search(xd, graph, qd, sd, k, rounds, work=True)
+    untimed call; the search is deterministic): a row of D elements (4 bytes,
+    or 1 for the uint8 copy x8) per distance taken, kg graph entries per node
+    expanded, plus each query, its seeds and its k results."""
+    if x8 is None:
+        _, _, (n_dist, n_exp) = knng.search(xd, graph, qd, sd, k, rounds, work=True)
+    else:
+        _, _, (n_dist, n_exp) = knng.search_u8(x8, graph, qd, sd, k, rounds, work=True)
     D, kg = xd.shape[1], graph.shape[1]
     nq, ns = sd.shape
-    alg = n_dist * D * 4 + n_exp * kg * 4 + nq * (D * 4 + ns * 4 + k * 8)
+    eb = 1 if x8 is not None else 4
+    alg = n_dist * D * eb + n_exp * kg * 4 + nq * (D * 4 + ns * 4 + k * 8)
     gbs = alg / (ms * 1e6)
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "distances": n_dist, "expanded": n_exp,
@@ -360,6 +364,23 @@ def main():
                   "queries_per_s": round(len(Qn) / (s_ms / 1e3), 1),
                   "data": "synthetic queries from the config's mixture",
                   "roofline": search_roofline(knng, xd, ids, qd, sd, k, rounds, s_ms)}
+        if st["exact_first_pass"] or (X.min() >= 0 and X.max() <= 255 and
+                                      np.array_equal(X, np.rint(X))):
+            # integer data: the same search over the lossless uint8 copy
+            x8 = knng.to_u8(xd)
+            knng.search_u8(x8, ids, qd, sd, k, rounds)
+            torch.cuda.synchronize()
+            tu = time.perf_counter()
+            for _ in range(reps):
+                u_ids, _ = knng.search_u8(x8, ids, qd, sd, k, rounds)
+            torch.cuda.synchronize()
+            u_ms = (time.perf_counter() - tu) * 1e3 / reps
+            search["uint8_rows"] = {
+                "ms": round(u_ms, 3), "queries_per_s": round(len(Qn) / (u_ms / 1e3), 1),
+                "same_results": bool(torch.equal(u_ids, s_ids)),
+                "roofline": search_roofline(knng, xd, ids, qd, sd, k, rounds, u_ms, x8=x8)}
+            del x8
+            log("search over uint8 rows: %.2f ms" % u_ms)
         if not args.no_recall:
             rq = min(200, len(Qn))
             Eq, _ = exact_knn_fp64(X, Qn[:rq], k)

@@ -202,6 +202,27 @@ int knng_search(const float* data, int64_t n, int32_t D, const int32_t* graph, i
                 int32_t rounds, int32_t* ids_out, float* dists_out, hipStream_t stream);
 
 /*
+ * knng_to_u8 -- the lossless uint8 copy of data whose values are all integers
+ * in [0, 255] (SIFT-like descriptors stored as float).
+ *   data   device, float[count]; out device, uint8[count]
+ * Values that are not integers in [0, 255] (or NaN/Inf) give
+ * KNNG_ERR_INVALID_ARG and leave out untouched.
+ */
+int knng_to_u8(const float* data, int64_t count, uint8_t* out, hipStream_t stream);
+
+/*
+ * knng_search_u8 -- knng_search_ex over the uint8 copy of integer data
+ * (knng_to_u8): a quarter of the bytes per distance.  Each byte is the FP32
+ * value exactly, so ids, distances and the work report equal those of
+ * knng_search_ex on the FP32 rows.
+ *   data8  device, uint8[n][D] (16-byte aligned)
+ */
+int knng_search_u8(const uint8_t* data8, int64_t n, int32_t D, const int32_t* graph, int32_t kg,
+                   const float* queries, int64_t nq, const int32_t* seeds, int32_t ns, int32_t k,
+                   int32_t rounds, int32_t* ids_out, float* dists_out, uint64_t* work_out,
+                   hipStream_t stream);
+
+/*
  * knng_search_ex -- knng_search with a work report.
  *   work_out   host, uint64[2], nullable: [0] distances taken over all queries
  *              (seeds included), [1] nodes expanded (each reads kg graph

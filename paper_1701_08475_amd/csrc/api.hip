@@ -689,15 +689,19 @@ extern "C" int knng_search(const float* data, int64_t n, int32_t D, const int32_
                           dists_out, nullptr, stream);
 }
 
-extern "C" int knng_search_ex(const float* data, int64_t n, int32_t D, const int32_t* graph,
-                              int32_t kg, const float* queries, int64_t nq, const int32_t* seeds,
-                              int32_t ns, int32_t k, int32_t rounds, int32_t* ids_out,
-                              float* dists_out, uint64_t* work_out, hipStream_t stream) {
+namespace {
+// knng_search_ex (rows as FP32, data8 null) and knng_search_u8 (rows as
+// uint8, data null).
+int search_impl(const float* data, const uint8_t* data8, int64_t n, int32_t D,
+                const int32_t* graph, int32_t kg, const float* queries, int64_t nq,
+                const int32_t* seeds, int32_t ns, int32_t k, int32_t rounds, int32_t* ids_out,
+                float* dists_out, uint64_t* work_out, hipStream_t stream) {
     g_err[0] = '\0';
-    if (data == nullptr || graph == nullptr || queries == nullptr || seeds == nullptr ||
+    const void* rows = data != nullptr ? static_cast<const void*>(data) : data8;
+    if (rows == nullptr || graph == nullptr || queries == nullptr || seeds == nullptr ||
         ids_out == nullptr || dists_out == nullptr)
         return set_err(KNNG_ERR_INVALID_ARG, "null pointer argument");
-    if (!aligned16(data) || !aligned16(queries))
+    if (!aligned16(rows) || !aligned16(queries))
         return set_err(KNNG_ERR_INVALID_ARG, "data and queries must be 16-byte aligned");
     if (n < 1 || n > 2147483647LL)
         return set_err(KNNG_ERR_INVALID_ARG, "n=%lld out of [1, 2^31-1]", static_cast<long long>(n));
@@ -715,6 +719,7 @@ extern "C" int knng_search_ex(const float* data, int64_t n, int32_t D, const int
     hipStream_t s = stream;
     knng::SearchArgs sa{data, n, D, graph, kg, queries, nq, seeds, ns, k, rounds, ids_out,
                         dists_out, s};
+    sa.X8 = data8;
     char err[400] = "";
     if (work_out == nullptr) {
         int rc = knng::search_run(sa, err, sizeof(err));
@@ -743,6 +748,60 @@ extern "C" int knng_search_ex(const float* data, int64_t n, int32_t D, const int
     if (e != hipSuccess) return hip_fail(e, "search");
     work_out[0] = knng::stat_total(h.data());
     work_out[1] = knng::stat_total(h.data() + knng::kStatWords);
+    return KNNG_OK;
+}
+}  // namespace
+
+extern "C" int knng_search_ex(const float* data, int64_t n, int32_t D, const int32_t* graph,
+                              int32_t kg, const float* queries, int64_t nq, const int32_t* seeds,
+                              int32_t ns, int32_t k, int32_t rounds, int32_t* ids_out,
+                              float* dists_out, uint64_t* work_out, hipStream_t stream) {
+    if (data == nullptr) {
+        g_err[0] = '\0';
+        return set_err(KNNG_ERR_INVALID_ARG, "null pointer argument");
+    }
+    return search_impl(data, nullptr, n, D, graph, kg, queries, nq, seeds, ns, k, rounds, ids_out,
+                       dists_out, work_out, stream);
+}
+
+extern "C" int knng_search_u8(const uint8_t* data8, int64_t n, int32_t D, const int32_t* graph,
+                              int32_t kg, const float* queries, int64_t nq, const int32_t* seeds,
+                              int32_t ns, int32_t k, int32_t rounds, int32_t* ids_out,
+                              float* dists_out, uint64_t* work_out, hipStream_t stream) {
+    if (data8 == nullptr) {
+        g_err[0] = '\0';
+        return set_err(KNNG_ERR_INVALID_ARG, "null pointer argument");
+    }
+    return search_impl(nullptr, data8, n, D, graph, kg, queries, nq, seeds, ns, k, rounds, ids_out,
+                       dists_out, work_out, stream);
+}
+
+extern "C" int knng_to_u8(const float* data, int64_t count, uint8_t* out, hipStream_t stream) {
+    g_err[0] = '\0';
+    if (data == nullptr || out == nullptr)
+        return set_err(KNNG_ERR_INVALID_ARG, "null pointer argument");
+    if (count < 0) return set_err(KNNG_ERR_INVALID_ARG, "count=%lld < 0", static_cast<long long>(count));
+    if (count == 0) return KNNG_OK;
+    hipStream_t s = stream;
+    knng::DeviceLock dlock;
+    int32_t* flags = nullptr;  // [0] NaN/Inf, [1] a value not an integer in [0, 255]
+    int32_t h[2] = {0, 0};
+    hipError_t e = knng::ws_malloc(reinterpret_cast<void**>(&flags), 2 * sizeof(int32_t), s);
+    if (e != hipSuccess) return hip_fail(e, "workspace allocation");
+    int rc = knng::prep_scan(data, count, flags, s);
+    if (rc == KNNG_OK) {
+        e = hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    knng::ws_free(flags, s);
+    if (rc != KNNG_OK) return set_err(rc, "value scan failed");
+    if (e != hipSuccess) return hip_fail(e, "value scan");
+    if (h[0] || h[1])
+        return set_err(KNNG_ERR_INVALID_ARG, "the values are not all integers in [0, 255]");
+    rc = knng::prep_to_u8(data, count, out, s);
+    if (rc != KNNG_OK) return set_err(rc, "conversion launch failed");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "conversion");
     return KNNG_OK;
 }
 

@@ -274,6 +274,7 @@ struct SearchArgs {
     float* d_out;
     hipStream_t stream;
     unsigned long long* work = nullptr;  // nullable: 2 spread counters (distances, expansions)
+    const uint8_t* X8 = nullptr;         // nullable: the rows as uint8 (used instead of X)
 };
 int search_run(const SearchArgs& a, char* err, size_t errlen);
 

@@ -97,14 +97,57 @@ __device__ __forceinline__ float d32_row(const float* q, const float* __restrict
     return tot;
 }
 
+// The same d32 over a uint8 row (integer data in [0, 255]: each byte is the
+// FP32 value exactly, so the result equals d32 of the FP32 row); vec16: whole
+// 32-byte blocks read as two 16-byte loads.
+__device__ __forceinline__ float d32_row_u8(const float* q, const uint8_t* __restrict__ x, int D,
+                                            bool vec16) {
+    float tot = 0.f;
+    for (int d0 = 0; d0 < D; d0 += 32) {
+        const int dn = D - d0 < 32 ? D - d0 : 32;
+        float blk = 0.f;
+        if (vec16 && dn == 32) {
+            const uint4 v0 = reinterpret_cast<const uint4*>(x + d0)[0];
+            const uint4 v1 = reinterpret_cast<const uint4*>(x + d0)[1];
+            const uint32_t w[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float e = static_cast<float>((w[i] >> (8 * j)) & 255u);
+                    const float df = q[d0 + 4 * i + j] - e;
+                    blk = __fmaf_rn(df, df, blk);
+                }
+        } else {
+            for (int dd = 0; dd < dn; ++dd) {
+                const float df = q[d0 + dd] - static_cast<float>(x[d0 + dd]);
+                blk = __fmaf_rn(df, df, blk);
+            }
+        }
+        tot = tot + blk;
+    }
+    return tot;
+}
+
+// Row distance for the row type of the reference set.
+template <typename TX>
+__device__ __forceinline__ float d32_of(const float* q, const TX* __restrict__ X, int32_t id, int D,
+                                        bool vec) {
+    if constexpr (sizeof(TX) == 1)
+        return d32_row_u8(q, X + static_cast<size_t>(id) * D, D, vec);
+    else
+        return d32_row(q, X + static_cast<size_t>(id) * D, D, vec);
+}
+
 struct SearchShape {
     int hbits;  // visited table: 2^hbits slots
     int tcap;   // new candidates per round: k * kg (at least the seeds)
     int scap;   // sort buffer: power of two >= k + tcap
 };
 
+template <typename TX>
 __global__ __launch_bounds__(kSearchThreads) void k_egnns(
-    const float* __restrict__ X, int64_t n, int D, const int32_t* __restrict__ G, int kg,
+    const TX* __restrict__ X, int64_t n, int D, const int32_t* __restrict__ G, int kg,
     const float* __restrict__ Q, const int32_t* __restrict__ seeds, int ns, int k, int rounds,
     SearchShape sh, int32_t* __restrict__ ids_out, float* __restrict__ d_out,
     unsigned long long* __restrict__ work) {
@@ -119,7 +162,8 @@ __global__ __launch_bounds__(kSearchThreads) void k_egnns(
 
     const int tid = threadIdx.x;
     const int64_t qi = blockIdx.x;
-    const bool vec4 = (D % 4) == 0;
+    // vector loads: 16-byte aligned rows (FP32: D % 4 == 0; uint8: D % 16 == 0)
+    const bool vec4 = (D % (sizeof(TX) == 1 ? 16 : 4)) == 0;
     for (int i = tid; i < H; i += kSearchThreads) tab[i] = -1;
     for (int d = tid; d < D; d += kSearchThreads) q[d] = Q[qi * D + d];
     if (tid == 0) {
@@ -187,7 +231,7 @@ __global__ __launch_bounds__(kSearchThreads) void k_egnns(
     for (int s = tid; s < ns; s += kSearchThreads) {
         const int32_t id = seeds[qi * ns + s];
         if (id >= 0 && id < n && visit(tab, sh.hbits, id)) {
-            const float d = d32_row(q, X + static_cast<size_t>(id) * D, D, vec4);
+            const float d = d32_of(q, X, id, D, vec4);
             keys[k + atomicAdd(&s_nt, 1)] = cand_key(d, id);
         }
     }
@@ -214,7 +258,7 @@ __global__ __launch_bounds__(kSearchThreads) void k_egnns(
             if (f < 0) continue;
             const int32_t id = G[static_cast<size_t>(f) * kg + c % kg];
             if (id >= 0 && id < n && visit(tab, sh.hbits, id)) {
-                const float d = d32_row(q, X + static_cast<size_t>(id) * D, D, vec4);
+                const float d = d32_of(q, X, id, D, vec4);
                 keys[k + atomicAdd(&s_nt, 1)] = cand_key(d, id);
             }
         }
@@ -257,9 +301,14 @@ int search_run(const SearchArgs& a, char* err, size_t errlen) {
         return kUnsupported;
     }
     if (a.nq == 0) return kOk;
-    k_egnns<<<static_cast<unsigned>(a.nq), kSearchThreads, lds, a.stream>>>(
-        a.X, a.n, a.D, a.G, a.kg, a.Q, a.seeds, a.ns, a.k, a.rounds, sh, a.ids_out, a.d_out,
-        a.work);
+    if (a.X8 != nullptr)
+        k_egnns<uint8_t><<<static_cast<unsigned>(a.nq), kSearchThreads, lds, a.stream>>>(
+            a.X8, a.n, a.D, a.G, a.kg, a.Q, a.seeds, a.ns, a.k, a.rounds, sh, a.ids_out, a.d_out,
+            a.work);
+    else
+        k_egnns<float><<<static_cast<unsigned>(a.nq), kSearchThreads, lds, a.stream>>>(
+            a.X, a.n, a.D, a.G, a.kg, a.Q, a.seeds, a.ns, a.k, a.rounds, sh, a.ids_out, a.d_out,
+            a.work);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         std::snprintf(err, errlen, "search launch failed: %s", hipGetErrorString(e));

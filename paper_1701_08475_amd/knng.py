@@ -89,6 +89,9 @@ def lib():
     L.knng_search.argtypes = [vp, i64, i32, vp, i32, vp, i64, vp, i32, i32, i32, vp, vp, vp]
     L.knng_search_ex.argtypes = [vp, i64, i32, vp, i32, vp, i64, vp, i32, i32, i32, vp, vp,
                                  ctypes.POINTER(ctypes.c_uint64), vp]
+    L.knng_search_u8.argtypes = [vp, i64, i32, vp, i32, vp, i64, vp, i32, i32, i32, vp, vp,
+                                 ctypes.POINTER(ctypes.c_uint64), vp]
+    L.knng_to_u8.argtypes = [vp, i64, vp, vp]
     L.knng_release_workspace.restype = None
     L.knng_release_workspace.argtypes = []
     L.knng_rvq_train.argtypes = [vp, i64, i32, vp, i64, i32, i32, vp, vp, i32, vp, vp, vp, vp,
@@ -243,6 +246,50 @@ def search(x, graph, queries, seeds, k, rounds, stream=None, work=False):
     ds = torch.empty((nq, k), dtype=torch.float32, device=x.device)
     w = (ctypes.c_uint64 * 2)()
     rc = lib().knng_search_ex(ctypes.c_void_p(x.data_ptr()), n, D,
+                              ctypes.c_void_p(graph.data_ptr()), graph.shape[1],
+                              ctypes.c_void_p(queries.data_ptr()), nq,
+                              ctypes.c_void_p(seeds.data_ptr()), seeds.shape[1], k, rounds,
+                              ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(ds.data_ptr()),
+                              w if work else None, _stream(stream))
+    _check(rc)
+    if work:
+        return ids, ds, (int(w[0]), int(w[1]))
+    return ids, ds
+
+
+def to_u8(x, stream=None):
+    """The lossless uint8 copy of a float32 CUDA tensor whose values are all
+    integers in [0, 255] (raises KnngError otherwise)."""
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32
+            and x.is_contiguous()):
+        raise ValueError("x must be a contiguous float32 CUDA tensor")
+    out = torch.empty(x.shape, dtype=torch.uint8, device=x.device)
+    _check(lib().knng_to_u8(ctypes.c_void_p(x.data_ptr()), x.numel(),
+                            ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def search_u8(x8, graph, queries, seeds, k, rounds, stream=None, work=False):
+    """search() over the uint8 copy of integer data (to_u8): the same results
+    from a quarter of the row bytes."""
+    import torch
+    if not (isinstance(x8, torch.Tensor) and x8.is_cuda and x8.dtype == torch.uint8
+            and x8.dim() == 2 and x8.is_contiguous()):
+        raise ValueError("x8 must be a contiguous 2-D uint8 CUDA tensor")
+    queries = _dev_f32(queries)
+    n, D = x8.shape
+    if queries.shape[1] != D:
+        raise ValueError("queries must have D columns")
+    _dev_i32(graph, "graph", 2)
+    _dev_i32(seeds, "seeds", 2)
+    if graph.shape[0] != n or seeds.shape[0] != queries.shape[0]:
+        raise ValueError("graph needs n rows and seeds one row per query")
+    nq = queries.shape[0]
+    ids = torch.empty((nq, k), dtype=torch.int32, device=x8.device)
+    ds = torch.empty((nq, k), dtype=torch.float32, device=x8.device)
+    w = (ctypes.c_uint64 * 2)()
+    rc = lib().knng_search_u8(ctypes.c_void_p(x8.data_ptr()), n, D,
                               ctypes.c_void_p(graph.data_ptr()), graph.shape[1],
                               ctypes.c_void_p(queries.data_ptr()), nq,
                               ctypes.c_void_p(seeds.data_ptr()), seeds.shape[1], k, rounds,

@@ -161,3 +161,15 @@ def test_search_and_index_reject_invalid_arguments(L):
     assert seeds(nq=-1) == E
     assert seeds(n_ids=-5) == E
     assert "n_ids" in L.knng_last_error().decode()
+
+
+def test_u8_entry_points_reject_invalid_arguments(L):
+    f = ctypes.c_void_p(FAKE)
+    E = knng.KNNG_ERR_INVALID_ARG
+    assert L.knng_to_u8(None, 10, f, None) == E
+    assert L.knng_to_u8(f, -1, f, None) == E
+    assert L.knng_to_u8(f, 0, f, None) == knng.KNNG_OK      # nothing to convert
+    assert L.knng_search_u8(None, 100, 8, f, 4, f, 3, f, 2, 5, 2, f, f, None, None) == E
+    assert L.knng_search_u8(ctypes.c_void_p(FAKE + 1), 100, 8, f, 4, f, 3, f, 2, 5, 2, f, f, None,
+                            None) == E                         # not 16-byte aligned
+    assert L.knng_search_u8(f, 100, 8, f, 0, f, 3, f, 2, 5, 2, f, f, None, None) == E

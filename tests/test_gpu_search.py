@@ -105,3 +105,42 @@ def test_search_rejects_oversized_state(K):
     S = torch.zeros((1, 1), dtype=torch.int32, device="cuda")
     with pytest.raises(K.KnngError):
         K.search(X, G, X[:1].contiguous(), S, 64, 50)  # 64 x 64 x 50 visited ids
+
+
+@pytest.mark.parametrize("n,D,kg,k,rounds", [
+    (12000, 128, 20, 20, 8),   # whole 32-byte blocks, 16-byte loads
+    (5000, 24, 10, 10, 6),     # D % 16 != 0: byte loads
+    (3000, 40, 8, 12, 5),      # one whole block and a partial one
+])
+def test_search_u8_equals_float_search(K, orc, n, D, kg, k, rounds):
+    """Integer data: the uint8 copy gives the float search's ids, distances
+    and work report exactly, and the oracle's d32 search."""
+    X = datagen.random_points(n, D, n + D, "int")
+    G, _, _ = orc.graph(X, kg, 2, max(2 * kg + 2, 40), 5)
+    rng = np.random.default_rng(n)
+    Q = np.rint(np.clip(X[rng.integers(0, n, 200)] + rng.normal(0, 20, size=(200, D)), 0, 255))
+    Q = Q.astype(np.float32)
+    S = rng.integers(0, n, size=(200, 16)).astype(np.int32)
+    Xd = to_dev(X)
+    X8 = K.to_u8(Xd)
+    assert np.array_equal(X8.cpu().numpy(), X.astype(np.uint8))
+    a = K.search(Xd, _i32(G), to_dev(Q), _i32(S), k, rounds, work=True)
+    b = K.search_u8(X8, _i32(G), to_dev(Q), _i32(S), k, rounds, work=True)
+    assert np.array_equal(a[0].cpu().numpy(), b[0].cpu().numpy())
+    assert np.array_equal(a[1].cpu().numpy().view(np.int32), b[1].cpu().numpy().view(np.int32))
+    assert a[2] == b[2]
+    o_ids, o_d = orc.egnns(X, G, Q, S, k, rounds, dist_mode=1)
+    assert np.array_equal(b[0].cpu().numpy(), o_ids)
+
+
+def test_to_u8_rejects_non_integer_data(K):
+    import torch
+    x = torch.full((10, 4), 3.0, device="cuda")
+    x[2, 1] = 3.5
+    with pytest.raises(K.KnngError):
+        K.to_u8(x)
+    x[2, 1] = 256.0
+    with pytest.raises(K.KnngError):
+        K.to_u8(x)
+    x[2, 1] = 255.0
+    assert K.to_u8(x).cpu().numpy().max() == 255
