@@ -488,18 +488,61 @@ __global__ __launch_bounds__(256) void k_leaf_small(
         for (int q = 0; q < RPW; ++q)
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[q][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-        for (int k0 = 0; k0 < Dp; k0 += 32) {
-            const size_t off = static_cast<size_t>(k0) * F::kBytes;
-            FragVec<FMT> a[RPW], b[NT];
+        // When the leaf's reduced rows fit the key block (free until the keys
+        // are written), they are copied there in one coalesced pass and the
+        // Gram reads its fragments from LDS: one round trip to HBM instead of
+        // one per 32-dimension step.  Rows are padded by 16 bytes so the 16
+        // rows of a fragment fall in different banks.  Same products, same
+        // order.
+        const int rs = static_cast<int>(rstride) + 16;
+        const bool staged = static_cast<size_t>(MP) * rs <= sizeof(lds);
+        if (staged) {
+            uint8_t* L = reinterpret_cast<uint8_t*>(lds);
+            const int cpr = static_cast<int>(rstride / 16);  // 16-byte chunks per row
+            for (int c = tid; c < m * cpr; c += 256) {
+                const int r = c / cpr, j = c % cpr;
+                *reinterpret_cast<uint4*>(L + r * rs + j * 16) = *reinterpret_cast<const uint4*>(
+                    Xr + static_cast<size_t>(ids[r]) * rstride + static_cast<size_t>(j) * 16);
+            }
+            __syncthreads();
+            int ao[RPW], bo[NT];
 #pragma unroll
-            for (int q = 0; q < RPW; ++q) a[q] = load_frag<FMT>(ap[q] + off, aok[q]);
+            for (int q = 0; q < RPW; ++q) {
+                const int arow = (wv * RPW + q) * 16 + (lane & 15);
+                ao[q] = (aok[q] ? arow : 0) * rs + 8 * kg * F::kBytes;
+            }
 #pragma unroll
-            for (int t = 0; t < NT; ++t) b[t] = load_frag<FMT>(bp[t] + off, bok[t]);
+            for (int t = 0; t < NT; ++t) {
+                const int bcol = t * 16 + (lane & 15);
+                bo[t] = (bok[t] ? bcol : 0) * rs + 8 * kg * F::kBytes;
+            }
+            for (int k0 = 0; k0 < Dp; k0 += 32) {
+                const int off = k0 * F::kBytes;
+                FragVec<FMT> a[RPW], b[NT];
 #pragma unroll
-            for (int q = 0; q < RPW; ++q)
+                for (int q = 0; q < RPW; ++q) a[q] = load_frag<FMT>(L + ao[q] + off, aok[q]);
 #pragma unroll
-                for (int t = 0; t < NT; ++t) acc[q][t] = F::mma(a[q], b[t], acc[q][t]);
+                for (int t = 0; t < NT; ++t) b[t] = load_frag<FMT>(L + bo[t] + off, bok[t]);
+#pragma unroll
+                for (int q = 0; q < RPW; ++q)
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) acc[q][t] = F::mma(a[q], b[t], acc[q][t]);
+            }
+        } else {
+            for (int k0 = 0; k0 < Dp; k0 += 32) {
+                const size_t off = static_cast<size_t>(k0) * F::kBytes;
+                FragVec<FMT> a[RPW], b[NT];
+#pragma unroll
+                for (int q = 0; q < RPW; ++q) a[q] = load_frag<FMT>(ap[q] + off, aok[q]);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) b[t] = load_frag<FMT>(bp[t] + off, bok[t]);
+#pragma unroll
+                for (int q = 0; q < RPW; ++q)
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) acc[q][t] = F::mma(a[q], b[t], acc[q][t]);
+            }
         }
+        __syncthreads();  // every wave is done with the staged rows before keys overwrite them
 #pragma unroll
         for (int q = 0; q < RPW; ++q)
 #pragma unroll
