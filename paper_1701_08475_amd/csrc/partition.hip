@@ -1285,7 +1285,7 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
 
     // Nodes of at most small_max rows are split to leaves by a subtree kernel
     // that keeps their uint8 rows in LDS.  Default (KNNG_SUBTREE=3): one
-    // wavefront per subtree of at most 240 rows.  KNNG_SUBTREE=1 or 2: one
+    // wavefront per subtree of at most 144 rows.  KNNG_SUBTREE=1 or 2: one
     // eight-wave workgroup per subtree with rows in 128 or 64 KiB of LDS
     // (slower on MI355X: per-pass barriers over few rows); 0: level passes
     // down to the leaves.

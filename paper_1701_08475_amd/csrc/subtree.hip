@@ -551,13 +551,17 @@ __global__ __launch_bounds__(kSubThreads) void k_subtree_u8(
 
 // ------------------------------------------------------------- wave subtrees
 // The same splits for subtrees of at most kWaveRows rows, one wavefront each
-// (workgroup of one wavefront, rows in about 38 KiB of LDS, four per CU):
+// (workgroup of one wavefront, rows in about 25 KiB of LDS, six per CU):
 // wave-level reductions and ballots only, no block barriers.  Steps and
 // arithmetic as in k_subtree_u8: keyed pair, matrix-core margin decided
 // outside the error band and FP64 inside it, exact side sums (changes only
 // after the first pass), stop rule, margin-rank repair on FP64 margins
 // recomputed with the level kernels' order, stable partition.
-constexpr int kWaveRows = 240;
+// 144 rows of 128 dimensions: six waves per CU hide more of the latency of
+// the wave-serial steps than four waves of 240 rows, and the extra level of
+// the level kernels above them costs less (C2 build 37.0 -> 35.8 ms; 112,
+// 128, 160 and 176 rows all measured between the two).
+constexpr int kWaveRows = 144;
 
 template <int DM, int G>
 __global__ __launch_bounds__(64) void k_subtree_wave_u8(
