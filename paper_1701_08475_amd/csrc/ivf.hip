@@ -12,7 +12,10 @@
 //  - Lloyd's update: the training positions are bucketed by code with a
 //    stable counting sort, then one thread per (word, dimension) adds its
 //    members in increasing position (their row ids staged in LDS 64 at a
-//    time) and divides by their count.
+//    time) and divides by their count.  When the training rows are integers
+//    of magnitude at most 2^24 (checked on the device once per call), every
+//    first-stage sum is an exact integer below 2^53 and eight wavefronts
+//    split a word's members; the result is the same bits.
 //  - Inverted lists: a stable radix sort of the keys, 8 bits a pass, carries
 //    the point ids, so every list comes out in increasing id order.
 //  - Seeds: one workgroup per query computes the query's dot products with
@@ -26,6 +29,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstdio>
+#include <cstdlib>
 
 namespace knng {
 namespace {
@@ -232,6 +236,25 @@ __global__ void k_check_range(const int32_t* __restrict__ a, int64_t count, int6
         if (a[i] < lo || a[i] >= hi) atomicOr(bad, 1);
 }
 
+// flag <- 1 if a value of a training row is not an integer of magnitude at
+// most 2^24 (NaN included).  Ids outside [0, n) are skipped: the range check
+// reports them.  One ballot per wave and at most one atomic per wave.
+__global__ void k_check_integral(const float* __restrict__ X, int64_t n, int D,
+                                 const int32_t* __restrict__ rows, int64_t m,
+                                 int32_t* __restrict__ flag) {
+    const int64_t total = m * D;
+    bool off = false;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < total;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t r = i / D;
+        const int32_t id = rows[r];
+        if (id < 0 || id >= n) continue;
+        const float v = X[static_cast<int64_t>(id) * D + (i - r * D)];
+        if (!(fabsf(v) <= 16777216.0f) || v != rintf(v)) off = true;
+    }
+    if (__ballot(off) != 0 && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
 // bad <- 1 unless off[0] = 0, off is non-decreasing and off[nk] = total.
 __global__ void k_check_offsets(const int32_t* __restrict__ off, int nk, int64_t total,
                                 int32_t* __restrict__ bad) {
@@ -365,6 +388,44 @@ __global__ __launch_bounds__(64) void k_word_means(
         __syncthreads();
     }
     if (d < D) W[static_cast<size_t>(j) * D + d] = s / static_cast<double>(b - a);
+}
+
+// The same means of the first stage when every partial sum is an exact
+// integer: integer rows of magnitude at most 2^24 and at most 2^29 members
+// keep every sum below 2^53, so the sum is the same in any order of the
+// additions.  NW wavefronts take every NW-th batch of 64 members and their
+// sums are added at the end, which shortens the serial chain of a large word
+// NW times.
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_word_means_exact(
+    const float* __restrict__ X, int D, const int32_t* __restrict__ rows,
+    const int32_t* __restrict__ order, const int32_t* __restrict__ woff, double* __restrict__ W) {
+    __shared__ int64_t s_row[NW][64];
+    __shared__ double s_part[NW][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int j = blockIdx.x;
+    const int d = blockIdx.y * 64 + lane;
+    const int32_t a = woff[j], b = woff[j + 1];
+    if (b <= a) return;  // uniform over the block: the word keeps its value
+    double s = 0.0;
+    for (int32_t i0 = a + 64 * w; i0 < b; i0 += 64 * NW) {
+        const int cnt = b - i0 < 64 ? b - i0 : 64;
+        if (lane < cnt) s_row[w][lane] = rows[order[i0 + lane]];
+        wave_lds_sync();
+        if (d < D) {
+#pragma unroll 8
+            for (int t = 0; t < cnt; ++t) s += static_cast<double>(X[s_row[w][t] * D + d]);
+        }
+        wave_lds_sync();
+    }
+    s_part[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && d < D) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) t += s_part[q][lane];
+        W[static_cast<size_t>(j) * D + d] = t / static_cast<double>(b - a);
+    }
 }
 
 // -------------------------------------------------------------- seeds
@@ -687,7 +748,8 @@ int finish(hipError_t e, const char* what, char* err, size_t errlen) {
 int kmeans_run(const float* X, int D, const int32_t* rows, int64_t m, const double* W1,
                const int32_t* c1, double* W, int K, int iters, int32_t* codes, int32_t* skey,
                int32_t* order, int32_t* hist, int32_t* woff, int32_t* dchanged, double* pbest,
-               int32_t* pidx, int* rounds_out, hipStream_t s, char* err, size_t errlen) {
+               int32_t* pidx, bool exact, int* rounds_out, hipStream_t s, char* err,
+               size_t errlen) {
     k_fill_i32<<<nblocks(m, 256) < 1024 ? nblocks(m, 256) : 1024, 256, 0, s>>>(codes, m, -1);
     nearest(X, D, rows, m, W1, c1, W, K, codes, nullptr, nullptr, 0, pbest, pidx, s);
     int rounds = 0;
@@ -695,7 +757,10 @@ int kmeans_run(const float* X, int D, const int32_t* rows, int64_t m, const doub
         digit_pass(codes, nullptr, m, 0, hist, skey, order, s);
         k_key_offsets<<<nblocks(m + 1, 256) < 1024 ? nblocks(m + 1, 256) : 1024, 256, 0, s>>>(
             skey, m, K, woff);
-        k_word_means<<<dim3(K, (D + 63) / 64), 64, 0, s>>>(X, D, rows, W1, c1, order, woff, W);
+        if (exact)
+            k_word_means_exact<8><<<dim3(K, (D + 63) / 64), 512, 0, s>>>(X, D, rows, order, woff, W);
+        else
+            k_word_means<<<dim3(K, (D + 63) / 64), 64, 0, s>>>(X, D, rows, W1, c1, order, woff, W);
         k_fill_i32<<<1, 64, 0, s>>>(dchanged, 1, 0);
         nearest(X, D, rows, m, W1, c1, W, K, codes, dchanged, nullptr, 0, pbest, pidx, s);
         int32_t h = 0;
@@ -709,8 +774,9 @@ int kmeans_run(const float* X, int D, const int32_t* rows, int64_t m, const doub
     return finish(hipSuccess, "k-means", err, errlen);
 }
 
-int read_flag(const int32_t* dflag, int32_t* h, hipStream_t s, char* err, size_t errlen) {
-    hipError_t e = hipMemcpyAsync(h, dflag, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+int read_flag(const int32_t* dflag, int32_t* h, hipStream_t s, char* err, size_t errlen,
+              int count = 1) {
+    hipError_t e = hipMemcpyAsync(h, dflag, sizeof(int32_t) * count, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     return finish(e, "argument check", err, errlen);
 }
@@ -722,7 +788,7 @@ int rvq_train_run(const RvqTrainArgs& a, char* err, size_t errlen) {
     const int64_t m = a.m;
     const int K = a.K1 > a.K2 ? a.K1 : a.K2;
     Ws ws{s};
-    int32_t* flag = ws.get<int32_t>(1);
+    int32_t* flag = ws.get<int32_t>(2);  // [0] argument error, [1] rows not integral
     int32_t* codes1 = ws.get<int32_t>(m);
     int32_t* codes2 = ws.get<int32_t>(m);
     int32_t* skey = ws.get<int32_t>(m);
@@ -737,24 +803,29 @@ int rvq_train_run(const RvqTrainArgs& a, char* err, size_t errlen) {
         std::snprintf(err, errlen, "workspace: %s", hipGetErrorString(ws.e));
         return kOom;
     }
-    k_fill_i32<<<1, 64, 0, s>>>(flag, 1, 0);
+    k_fill_i32<<<1, 64, 0, s>>>(flag, 2, 0);
     k_check_range<<<256, 256, 0, s>>>(a.train_ids, m, 0, a.n, flag);
     k_check_range<<<1, 256, 0, s>>>(a.init1, a.K1, 0, m, flag);
     k_check_range<<<1, 256, 0, s>>>(a.init2, a.K2, 0, m, flag);
-    int32_t bad = 0;
-    int rc = read_flag(flag, &bad, s, err, errlen);
+    k_check_integral<<<512, 256, 0, s>>>(a.X, a.n, a.D, a.train_ids, m, flag + 1);
+    int32_t hf[2] = {0, 0};
+    int rc = read_flag(flag, hf, s, err, errlen, 2);
     if (rc != kOk) return rc;
+    const int32_t bad = hf[0];
+    // KNNG_MEANS_EXACT=0 keeps the in-order sums for integer rows too
+    const char* ev = std::getenv("KNNG_MEANS_EXACT");
+    const bool exact = hf[1] == 0 && m <= (int64_t{1} << 29) && !(ev != nullptr && ev[0] == '0');
     if (bad) {
         std::snprintf(err, errlen, "a training id is outside [0, n) or a starting position outside [0, m)");
         return kInvalid;
     }
     k_init_words<<<a.K1, 64, 0, s>>>(a.X, a.D, a.train_ids, nullptr, nullptr, a.init1, a.W1);
     rc = kmeans_run(a.X, a.D, a.train_ids, m, nullptr, nullptr, a.W1, a.K1, a.iters, codes1, skey,
-                    order, hist, woff, changed, pbest, pidx, a.rounds, s, err, errlen);
+                    order, hist, woff, changed, pbest, pidx, exact, a.rounds, s, err, errlen);
     if (rc != kOk) return rc;
     k_init_words<<<a.K2, 64, 0, s>>>(a.X, a.D, a.train_ids, a.W1, codes1, a.init2, a.W2);
     rc = kmeans_run(a.X, a.D, a.train_ids, m, a.W1, codes1, a.W2, a.K2, a.iters, codes2, skey,
-                    order, hist, woff, changed, pbest, pidx, a.rounds + 1, s, err, errlen);
+                    order, hist, woff, changed, pbest, pidx, false, a.rounds + 1, s, err, errlen);
     if (rc != kOk) return rc;
     if (a.codes1 != nullptr)
         rc = finish(hipMemcpyAsync(a.codes1, codes1, sizeof(int32_t) * m, hipMemcpyDeviceToDevice, s),

@@ -36,6 +36,10 @@ def _data(kind, n, D, seed):
         return datagen.make("c1", n=n)
     if kind == "c2":
         return datagen.make("c2", n=n)
+    if kind == "signed":  # integers of both signs
+        return (datagen.random_points(n, D, seed, "int") - 128.0).astype(np.float32)
+    if kind == "big":  # integers beyond 2^24
+        return (datagen.random_points(n, D, seed, "int") * 2.0 ** 26).astype(np.float32)
     if kind == "unit":  # GIST-shaped: unit-norm rows
         X = datagen.random_points(n, D, seed, "normal").astype(np.float64)
         return (X / np.linalg.norm(X, axis=1, keepdims=True)).astype(np.float32)
@@ -50,6 +54,9 @@ TRAIN_CASES = [
     ("tiny-D", "normal", 2000, 3, 1500, 5, 3, 30),
     ("one-word", "int", 500, 17, 400, 1, 2, 5),
     ("gist-like", "unit", 3000, 960, 2000, 32, 16, 6),  # 60 dimension tiles per word tile
+    ("int-heavy-words", "int", 30000, 64, 30000, 3, 2, 8),  # ~10,000 members per word
+    ("signed-int", "signed", 4000, 40, 4000, 8, 4, 10),
+    ("int-above-2^24", "big", 3000, 16, 3000, 6, 3, 10),  # integers, summed in order
 ]
 
 
@@ -191,3 +198,25 @@ def test_ivf_seeds_empty_lists_and_no_queries(K):
     assert np.all(S.cpu().numpy() == -1)
     S0 = K.ivf_seeds(Q[:0].contiguous(), W1, W2, off, ids, 2, 6)
     assert S0.shape == (0, 6)
+
+
+@pytest.mark.parametrize("kind", ["int", "c2"])
+def test_rvq_integer_means_any_order(K, orc, kind, monkeypatch):
+    """Integer rows: the first stage's sums are exact, so the split-member
+    means and the in-order means (KNNG_MEANS_EXACT=0) give the same words,
+    and both the oracle's."""
+    n = 20000
+    X = datagen.make("c2", n=n) if kind == "c2" else _data("int", n, 48, 77)
+    train, init1, init2 = datagen.rvq_sample(n, n, 16, 8, seed=78)
+    o1, o2, oc1, oc2, orounds = orc.rvq_train(X, train, init1, init2, 12)
+    outs = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("KNNG_MEANS_EXACT", flag)
+        log("rvq integer means %s KNNG_MEANS_EXACT=%s" % (kind, flag))
+        W1, W2, rounds, c1, c2 = K.rvq_train(to_dev(X), _i32(train), _i32(init1), _i32(init2), 12,
+                                             codes=True)
+        outs.append((W1.cpu().numpy(), W2.cpu().numpy(), tuple(rounds)))
+        assert tuple(rounds) == tuple(orounds.tolist())
+        assert np.array_equal(W1.cpu().numpy(), o1) and np.array_equal(W2.cpu().numpy(), o2)
+        assert np.array_equal(c1.cpu().numpy(), oc1) and np.array_equal(c2.cpu().numpy(), oc2)
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
