@@ -1,0 +1,82 @@
+"""The C2 workload at full size, in the calls the benchmark times: 10^6
+SIFT-shaped rows (integers 0..255, D = 128), k = 20, 8 trees, leaf_max =
+100, seed 2, FP32 leaves, batched trees and compact uint8 rows.
+
+- Build (Alg. 1, Sec. 3.1): the whole graph against the oracle's graph of
+  the same input, every id and every distance bit for bit.  On this integer
+  data every FP32 partial sum is an exact integer below 2^24, so d32 == d64.
+- Search (Alg. 2): the benchmark's batch of 10,000 queries with 64 random
+  seeds and 10 rounds, over the oracle's graph, on float rows and on the
+  uint8 copy; a sample of 300 queries is compared with the oracle's E-GNNS
+  query by query (each query's walk is independent of the others).
+
+The oracle's graph takes about half a minute on 16 host threads; it is
+computed once for the module.  Every input comes from the seeded
+generators."""
+import numpy as np
+import pytest
+
+from paper_1701_08475_amd import datagen
+from tests.gpu_helpers import graph_parity, log, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1701_08475_amd import knng
+    knng.lib()
+    return knng
+
+
+@pytest.fixture(scope="module")
+def c2(orc):
+    c = datagen.CONFIGS["c2"]
+    X = datagen.make("c2")
+    assert X.shape == (c["n"], 128)
+    log("full size: oracle graph of c2 (n=%d, %d trees)" % (c["n"], c["n_trees"]))
+    o_ids, o_d, _ = orc.graph(X, c["k"], c["n_trees"], c["leaf_max"], c["seed"])
+    return c, X, o_ids, o_d
+
+
+def test_c2_build_full_size(K, orc, c2):
+    import torch
+    c, X, o_ids, o_d = c2
+    n, k = c["n"], c["k"]
+    xd = to_dev(X)
+    ids = torch.empty((n, k), dtype=torch.int32, device="cuda")
+    ds = torch.empty((n, k), dtype=torch.float32, device="cuda")
+    log("full size: c2 build on the GPU")
+    r = K.build(xd, k, c["n_trees"], c["leaf_max"], seed=c["seed"], precision=c["precision"],
+                stats=True, out=(ids, ds))
+    assert r[2]["compact_used"] == 1
+    g_ids = ids.cpu().numpy()
+    g_d = ds.cpu().numpy().astype(np.float64)
+    bad = np.flatnonzero(np.any(g_ids != o_ids, axis=1))
+    assert bad.size == 0, "rows %s differ" % bad[:10].tolist()
+    assert np.array_equal(g_d, o_d)
+    rows = np.random.default_rng(3).choice(n, 2000, replace=False)
+    graph_parity(orc, X, rows, g_ids[rows], g_d[rows], o_ids[rows], o_d[rows], strict=True)
+
+
+@pytest.mark.parametrize("rows", ["float", "uint8"])
+def test_c2_search_full_size(K, orc, c2, rows):
+    import torch
+    c, X, o_ids, _ = c2
+    n, k = c["n"], c["k"]
+    Q = datagen.queries("c2", 10_000)
+    S = datagen.seeds(n, len(Q), 64)
+    xd = to_dev(X)
+    G = torch.from_numpy(np.ascontiguousarray(o_ids)).cuda()
+    qd, sd = to_dev(Q), torch.from_numpy(S).cuda()
+    log("full size: search over %s rows, %d queries" % (rows, len(Q)))
+    if rows == "uint8":
+        g_ids, g_d = K.search_u8(K.to_u8(xd), G, qd, sd, k, 10)
+    else:
+        g_ids, g_d = K.search(xd, G, qd, sd, k, 10)
+    pick = np.sort(np.random.default_rng(4).choice(len(Q), 300, replace=False))
+    e_ids, e_d = orc.egnns(X, o_ids, Q[pick], S[pick], k, 10, dist_mode=1)
+    assert np.array_equal(g_ids.cpu().numpy()[pick], e_ids)
+    assert np.array_equal(g_d.cpu().numpy()[pick].astype(np.float64), e_d)
