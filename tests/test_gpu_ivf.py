@@ -150,23 +150,31 @@ def test_ivf_argument_errors(K):
 
 
 def test_ivf_full_size(K, orc):
-    """SIFT-shaped 1M x 128 with 256 x 256 words (oracle-trained on a 16384-row
-    sample): every key, offset and list entry equals the oracle's, and the
-    seeds of a query batch over the full lists too."""
+    """The index leg as the benchmark runs it: SIFT-shaped 10^6 x 128, 256 x
+    256 words trained on a 65,536-row sample for at most 10 rounds per
+    stage, lists of every point, seeds (n1 = 8, 64 seeds) for the batch of
+    10,000 queries.  Vocabularies and round counts, every key, offset and
+    list entry, and the seeds of 200 sampled queries equal the oracle's."""
     X = datagen.make("c2")
     n = len(X)
-    train, init1, init2 = datagen.rvq_sample(n, 16384, 256, 256, seed=5)
-    W1, W2, _, _, _ = orc.rvq_train(X, train, init1, init2, 6)
-    o_key = orc.rvq_encode(X, W1, W2)
+    train, init1, init2 = datagen.rvq_sample(n, 65536, 256, 256)
+    log("ivf full size: train on %d of %d rows" % (len(train), n))
+    W1, W2, rounds = K.rvq_train(to_dev(X), _i32(train), _i32(init1), _i32(init2), 10)
+    o1, o2, _, _, orounds = orc.rvq_train(X, train, init1, init2, 10)
+    assert tuple(rounds) == tuple(orounds.tolist())
+    assert np.array_equal(W1.cpu().numpy(), o1) and np.array_equal(W2.cpu().numpy(), o2)
+    o_key = orc.rvq_encode(X, o1, o2)
     o_off, o_ids = orc.ivf_lists(o_key, 256 * 256)
-    log("ivf full size: n=%d" % n)
-    keys, offsets, ids = K.ivf_build(to_dev(X), _f64(W1), _f64(W2))
+    log("ivf full size: lists")
+    keys, offsets, ids = K.ivf_build(to_dev(X), _f64(o1), _f64(o2))
     assert np.array_equal(keys.cpu().numpy(), o_key)
     assert np.array_equal(offsets.cpu().numpy(), o_off)
     assert np.array_equal(ids.cpu().numpy(), o_ids)
-    Q = datagen.queries("c2", 200)
-    S = K.ivf_seeds(to_dev(Q), _f64(W1), _f64(W2), _i32(o_off), _i32(o_ids), 8, 64)
-    assert np.array_equal(S.cpu().numpy(), orc.ivf_seeds(Q, W1, W2, o_off, o_ids, 8, 64))
+    Q = datagen.queries("c2", 10_000)
+    S = K.ivf_seeds(to_dev(Q), _f64(o1), _f64(o2), _i32(o_off), _i32(o_ids), 8, 64)
+    pick = np.sort(np.random.default_rng(6).choice(len(Q), 200, replace=False))
+    o_S = orc.ivf_seeds(Q[pick], o1, o2, o_off, o_ids, 8, 64)
+    assert np.array_equal(S.cpu().numpy()[pick], o_S)
 
 
 def test_rvq_more_words_than_rows_and_repeated_starts(K, orc):
