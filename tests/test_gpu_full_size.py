@@ -5,6 +5,14 @@ SIFT-shaped rows (integers 0..255, D = 128), k = 20, 8 trees, leaf_max =
 - Build (Alg. 1, Sec. 3.1): the whole graph against the oracle's graph of
   the same input, every id and every distance bit for bit.  On this integer
   data every FP32 partial sum is an exact integer below 2^24, so d32 == d64.
+- The same build with BF16 leaf distances (C3): BF16 holds these integers
+  exactly, so the graph is again the oracle's bit for bit.
+- GIST-shaped (10^6 x 960, FP16 leaves, 4 trees) and Deep-shaped (10^7 x
+  96, FP8 leaves, 8 trees) builds at full size: the oracle cannot build
+  these graphs in test time, so 500 sampled rows are checked for what holds
+  at any size: ids in range, distinct and not the row itself, rows
+  ascending by (distance, id), and every distance within 1e-5 relative of
+  the FP64 distance of its pair.
 - Search (Alg. 2): the benchmark's batch of 10,000 queries with 64 random
   seeds and 10 rounds, over the oracle's graph, on float rows and on the
   uint8 copy; a sample of 300 queries is compared with the oracle's E-GNNS
@@ -17,7 +25,7 @@ import numpy as np
 import pytest
 
 from paper_1701_08475_amd import datagen
-from tests.gpu_helpers import graph_parity, log, to_dev
+from tests.gpu_helpers import TAU, graph_parity, log, rows_sorted, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -59,6 +67,39 @@ def test_c2_build_full_size(K, orc, c2):
     assert np.array_equal(g_d, o_d)
     rows = np.random.default_rng(3).choice(n, 2000, replace=False)
     graph_parity(orc, X, rows, g_ids[rows], g_d[rows], o_ids[rows], o_d[rows], strict=True)
+
+
+def test_c3_bf16_build_full_size(K, c2):
+    c, X, o_ids, o_d = c2
+    c3 = datagen.CONFIGS["c3"]
+    assert c3["precision"] == "bf16" and c3["n"] == c["n"] and c3["seed"] == c["seed"]
+    log("full size: c3 build (bf16 leaves) on the GPU")
+    ids, ds = K.build(to_dev(X), c3["k"], c3["n_trees"], c3["leaf_max"], seed=c3["seed"],
+                      precision="bf16")
+    assert np.array_equal(ids.cpu().numpy(), o_ids)
+    assert np.array_equal(ds.cpu().numpy().astype(np.float64), o_d)
+
+
+@pytest.mark.parametrize("name", ["c4", "c5"])
+def test_reduced_build_full_size_properties(K, orc, name):
+    import torch
+    c = datagen.CONFIGS[name]
+    log("full size: %s data" % name)
+    X = datagen.make(name)
+    n, k = c["n"], c["k"]
+    xd = to_dev(X)
+    log("full size: %s build (%s leaves) on the GPU" % (name, c["precision"]))
+    ids, ds = K.build(xd, k, c["n_trees"], c["leaf_max"], seed=c["seed"], precision=c["precision"])
+    rows = datagen.sample_rows(n, 500)
+    g_ids = ids[torch.from_numpy(rows).cuda()].cpu().numpy()
+    g_d = ds[torch.from_numpy(rows).cuda()].cpu().numpy().astype(np.float64)
+    del xd, ids, ds
+    assert np.all((g_ids >= 0) & (g_ids < n))
+    for q, i in enumerate(rows):
+        assert len(set(g_ids[q].tolist())) == k and i not in g_ids[q], (i, g_ids[q])
+    assert rows_sorted(g_ids, g_d)
+    d64 = orc.pair_d64(X, rows, g_ids)
+    assert np.all(np.abs(g_d - d64) <= TAU * d64), np.max(np.abs(g_d - d64) / d64)
 
 
 @pytest.mark.parametrize("rows", ["float", "uint8"])
