@@ -357,7 +357,10 @@ __global__ void k_key_offsets(const int32_t* __restrict__ skey, int64_t m, int n
 // increasing position; a word without members keeps its value.
 // Grid (K, ceil(D / 64)), one wave: the row ids (and stage-1 words) of 64
 // members at a time go to LDS in one load, so the in-order sum issues only
-// independent row loads.
+// independent row loads.  RES (stage 2: residues x - w1[c1]) is a template
+// parameter: a branch on it inside the unrolled loop would make the compiler
+// wait for every load before the branch, one memory latency per member.
+template <bool RES>
 __global__ __launch_bounds__(64) void k_word_means(
     const float* __restrict__ X, int D, const int32_t* __restrict__ rows,
     const double* __restrict__ W1, const int32_t* __restrict__ c1,
@@ -374,14 +377,14 @@ __global__ __launch_bounds__(64) void k_word_means(
         if (static_cast<int>(threadIdx.x) < cnt) {
             const int32_t p = order[i0 + threadIdx.x];
             s_row[threadIdx.x] = rows[p];
-            s_w1[threadIdx.x] = W1 != nullptr ? c1[p] : 0;
+            if (RES) s_w1[threadIdx.x] = c1[p];
         }
         __syncthreads();
         if (d < D) {
 #pragma unroll 8
             for (int t = 0; t < cnt; ++t) {  // loads in flight, adds in order
                 double v = static_cast<double>(X[s_row[t] * D + d]);
-                if (W1 != nullptr) v = __dsub_rn(v, W1[static_cast<size_t>(s_w1[t]) * D + d]);
+                if (RES) v = __dsub_rn(v, W1[static_cast<size_t>(s_w1[t]) * D + d]);
                 s = __dadd_rn(s, v);
             }
         }
@@ -759,8 +762,10 @@ int kmeans_run(const float* X, int D, const int32_t* rows, int64_t m, const doub
             skey, m, K, woff);
         if (exact)
             k_word_means_exact<8><<<dim3(K, (D + 63) / 64), 512, 0, s>>>(X, D, rows, order, woff, W);
+        else if (W1 != nullptr)
+            k_word_means<true><<<dim3(K, (D + 63) / 64), 64, 0, s>>>(X, D, rows, W1, c1, order, woff, W);
         else
-            k_word_means<<<dim3(K, (D + 63) / 64), 64, 0, s>>>(X, D, rows, W1, c1, order, woff, W);
+            k_word_means<false><<<dim3(K, (D + 63) / 64), 64, 0, s>>>(X, D, rows, W1, c1, order, woff, W);
         k_fill_i32<<<1, 64, 0, s>>>(dchanged, 1, 0);
         nearest(X, D, rows, m, W1, c1, W, K, codes, dchanged, nullptr, 0, pbest, pidx, s);
         int32_t h = 0;
