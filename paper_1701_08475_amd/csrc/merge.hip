@@ -159,7 +159,18 @@ __global__ __launch_bounds__(256) void k_merge_rows(int64_t n, int k, int T,
     uint64_t top[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) top[i] = kNoKey;
-    {
+    if (VEC) {  // k == K: the first list in K / 4 pairs of 16-byte loads
+        const size_t src = static_cast<size_t>(row) * K;
+#pragma unroll
+        for (int i = 0; i < K; i += 4) {
+            const int4 i4 = *reinterpret_cast<const int4*>(cid + src + i);
+            const float4 d4 = *reinterpret_cast<const float4*>(cd + src + i);
+            top[i] = i4.x >= 0 ? cand_key(d4.x, i4.x) : kNoKey;
+            top[i + 1] = i4.y >= 0 ? cand_key(d4.y, i4.y) : kNoKey;
+            top[i + 2] = i4.z >= 0 ? cand_key(d4.z, i4.z) : kNoKey;
+            top[i + 3] = i4.w >= 0 ? cand_key(d4.w, i4.w) : kNoKey;
+        }
+    } else {
         const size_t src = static_cast<size_t>(row) * k;
 #pragma unroll
         for (int i = 0; i < K; ++i)
@@ -182,13 +193,31 @@ __global__ __launch_bounds__(256) void k_merge_rows(int64_t n, int k, int T,
             prev = cur;
         }
     };
+    // VEC: the first four entries of the next tree's list are loaded while
+    // the current list is merged
+    int4 ni = make_int4(-1, -1, -1, -1);
+    float4 nd = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (VEC && T > 1) {
+        const size_t s1 = (static_cast<size_t>(n) + row) * K;
+        ni = *reinterpret_cast<const int4*>(cid + s1);
+        nd = *reinterpret_cast<const float4*>(cd + s1);
+    }
     for (int t = 1; t < T; ++t) {
         const size_t src = (static_cast<size_t>(t) * n + row) * k;
         if (VEC) {
+            int4 i4 = ni;
+            float4 d4 = nd;
+            if (t + 1 < T) {
+                const size_t s1 = (static_cast<size_t>(t + 1) * n + row) * K;
+                ni = *reinterpret_cast<const int4*>(cid + s1);
+                nd = *reinterpret_cast<const float4*>(cd + s1);
+            }
             // four entries per 16-byte load, loaded ahead of the tests
-            for (int j0 = 0; j0 < k; j0 += 4) {
-                const int4 i4 = *reinterpret_cast<const int4*>(cid + src + j0);
-                const float4 d4 = *reinterpret_cast<const float4*>(cd + src + j0);
+            for (int j0 = 0; j0 < K; j0 += 4) {
+                if (j0 > 0) {
+                    i4 = *reinterpret_cast<const int4*>(cid + src + j0);
+                    d4 = *reinterpret_cast<const float4*>(cd + src + j0);
+                }
                 const int32_t iv[4] = {i4.x, i4.y, i4.z, i4.w};
                 const float dv[4] = {d4.x, d4.y, d4.z, d4.w};
                 bool more = true;
@@ -215,13 +244,26 @@ __global__ __launch_bounds__(256) void k_merge_rows(int64_t n, int k, int T,
         }
     }
     const size_t dst = static_cast<size_t>(row) * k;
+    auto out_id = [&](int i) { return top[i] != kNoKey ? key_id(top[i]) : -1; };
+    auto out_d = [&](int i) {
+        return top[i] != kNoKey ? key_dist(top[i]) : __int_as_float(0x7f800000);
+    };
+    if (VEC) {  // the output rows are 16-byte aligned too (k % 4 == 0)
 #pragma unroll
-    for (int i = 0; i < K; ++i)
-        if (i < k) {
-            const bool ok = top[i] != kNoKey;
-            oid[dst + i] = ok ? key_id(top[i]) : -1;
-            od[dst + i] = ok ? key_dist(top[i]) : __int_as_float(0x7f800000);
+        for (int i = 0; i < K; i += 4) {
+            *reinterpret_cast<int4*>(oid + dst + i) =
+                make_int4(out_id(i), out_id(i + 1), out_id(i + 2), out_id(i + 3));
+            *reinterpret_cast<float4*>(od + dst + i) =
+                make_float4(out_d(i), out_d(i + 1), out_d(i + 2), out_d(i + 3));
         }
+    } else {
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if (i < k) {
+                oid[dst + i] = out_id(i);
+                od[dst + i] = out_d(i);
+            }
+    }
 }
 
 using MergeFn = void (*)(int64_t, int, int, int, const int32_t*, const float*, int32_t*, float*,
@@ -242,11 +284,12 @@ RowMergeFn pick_rows_vec(int k) {
     }
 }
 
-// 16-byte loads when every list starts 16-byte aligned (k % 4 == 0; the
-// candidate buffers come from hipMallocAsync, 256-byte aligned)
-RowMergeFn pick_rows(int k, const void* ids, const void* d) {
-    const bool vec = k % 4 == 0 && (reinterpret_cast<uintptr_t>(ids) & 15) == 0 &&
-                     (reinterpret_cast<uintptr_t>(d) & 15) == 0;
+// 16-byte loads and stores when every list and every output row starts
+// 16-byte aligned (k % 4 == 0; the candidate buffers come from
+// hipMallocAsync, 256-byte aligned; the outputs are the caller's)
+RowMergeFn pick_rows(int k, const void* ids, const void* d, const void* oid, const void* od) {
+    auto a16 = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+    const bool vec = k % 4 == 0 && a16(ids) && a16(d) && a16(oid) && a16(od);
     return vec ? pick_rows_vec<true>(k) : pick_rows_vec<false>(k);
 }
 
@@ -271,7 +314,7 @@ MergeFn pick(int slots) {
 int merge_run(const MergeArgs& a, int* launches, char* err, size_t errlen) {
     const int k = a.k;
     if (k <= 32 && std::getenv("KNNG_MERGE_NETWORK") == nullptr) {
-        const RowMergeFn f = pick_rows(k, a.cand_ids, a.cand_d);
+        const RowMergeFn f = pick_rows(k, a.cand_ids, a.cand_d, a.ids_out, a.dists_out);
         if (a.timer) a.timer->begin(kKMerge, a.stream);
         f<<<static_cast<unsigned>((a.n + 255) / 256), 256, 0, a.stream>>>(
             a.n, k, a.n_trees, a.cand_ids, a.cand_d, a.ids_out, a.dists_out);
