@@ -582,6 +582,49 @@ static int dj_cmp(const void *a, const void *b)
     return (x->j > y->j) - (x->j < y->j);
 }
 
+/* First-pass distances (R9) of member a of a leaf to every other member:
+ * the n~_a + n~_b - 2 <x~_a/s_a, x~_b/s_b> of the dequantised rows q
+ * (m x D) with squared norms nq, in FP64; r receives (d~, id) for every
+ * b != a, sorted by (d~, id).  Returns the number of entries, m - 1. */
+static int reduced_first_pass(const int32_t *ids, int64_t m, int D, int64_t a,
+                              const double *q, const double *nq, dj_rec *r)
+{
+    int nr = 0;
+    for (int64_t b = 0; b < m; ++b) {
+        if (b == a) continue;
+        double g = 0.0;
+        for (int d = 0; d < D; ++d) g += q[a * D + d] * q[b * D + d];
+        r[nr].d = nq[a] + nq[b] - 2.0 * g;
+        r[nr].j = ids[b];
+        ++nr;
+    }
+    qsort(r, (size_t)nr, sizeof(dj_rec), dj_cmp);
+    return nr;
+}
+
+/* Dequantised rows (R9) of the m points ids[0..m) into q (m x D) and their
+ * squared norms into nq. */
+static void reduced_leaf_rows(int fmt, const float *X, int D, const int32_t *ids, int64_t m,
+                              double *q, double *nq)
+{
+    for (int64_t a = 0; a < m; ++a) {
+        reduced_row(fmt, X + (size_t)ids[a] * D, D, q + a * D);
+        double acc = 0.0;
+        for (int d = 0; d < D; ++d) acc += q[a * D + d] * q[a * D + d];
+        nq[a] = acc;
+    }
+}
+
+/* Re-rank (R9): the first cc = min(c, nr) entries of the sorted first pass
+ * take the exact d64 of their pair and are sorted by (d64, id). */
+static int reduced_rerank(const float *X, int D, int64_t i, dj_rec *r, int nr, int c)
+{
+    int cc = nr < c ? nr : c;
+    for (int p = 0; p < cc; ++p) r[p].d = orc_d64(X, D, i, r[p].j);
+    qsort(r, (size_t)cc, sizeof(dj_rec), dj_cmp);
+    return cc;
+}
+
 /* Graph from given leaves with the reduced first pass (R9); arguments as
  * orc_graph_from_leaves plus the format and c candidates per row and leaf. */
 int orc_graph_from_leaves_reduced(const float *X, int64_t n, int D, int k, int n_trees,
@@ -602,27 +645,11 @@ int orc_graph_from_leaves_reduced(const float *X, int64_t n, int D, int k, int n
             double *q = (double *)malloc(sizeof(double) * (size_t)(m * D));
             double *nq = (double *)malloc(sizeof(double) * (size_t)m);
             dj_rec *r = (dj_rec *)malloc(sizeof(dj_rec) * (size_t)m);
+            reduced_leaf_rows(fmt, X, D, pm + s, m, q, nq);
             for (int64_t a = 0; a < m; ++a) {
-                reduced_row(fmt, X + (size_t)pm[s + a] * D, D, q + a * D);
-                double acc = 0.0;
-                for (int d = 0; d < D; ++d) acc += q[a * D + d] * q[a * D + d];
-                nq[a] = acc;
-            }
-            for (int64_t a = 0; a < m; ++a) {
-                int nr = 0;
-                for (int64_t b = 0; b < m; ++b) {
-                    if (b == a) continue;
-                    double g = 0.0;
-                    for (int d = 0; d < D; ++d) g += q[a * D + d] * q[b * D + d];
-                    r[nr].d = nq[a] + nq[b] - 2.0 * g;
-                    r[nr].j = pm[s + b];
-                    ++nr;
-                }
-                qsort(r, (size_t)nr, sizeof(dj_rec), dj_cmp);
-                int cc = nr < c ? nr : c;
-                for (int p = 0; p < cc; ++p) r[p].d = orc_d64(X, D, pm[s + a], r[p].j);
-                qsort(r, (size_t)cc, sizeof(dj_rec), dj_cmp);
                 int i = pm[s + a];
+                int nr = reduced_first_pass(pm + s, m, D, a, q, nq, r);
+                int cc = reduced_rerank(X, D, i, r, nr, c);
                 for (int p = 0; p < cc && p < k; ++p)
                     row_insert(ids + (size_t)i * k, ds + (size_t)i * k, cnt + i, k, r[p].j, r[p].d);
             }
@@ -632,6 +659,84 @@ int orc_graph_from_leaves_reduced(const float *X, int64_t n, int D, int k, int n
     }
     free(cnt);
     return 0;
+}
+
+/* First-pass distance d~(i, j) of one pair (R9), FP64. */
+double orc_dtilde(const float *X, int D, int fmt, int64_t i, int64_t j)
+{
+    double *q = (double *)malloc(sizeof(double) * (size_t)(2 * D));
+    if (!q) return NAN;
+    reduced_row(fmt, X + (size_t)i * D, D, q);
+    reduced_row(fmt, X + (size_t)j * D, D, q + D);
+    double ni = 0.0, nj = 0.0, g = 0.0;
+    for (int d = 0; d < D; ++d) ni += q[d] * q[d];
+    for (int d = 0; d < D; ++d) nj += q[D + d] * q[D + d];
+    for (int d = 0; d < D; ++d) g += q[d] * q[D + d];
+    free(q);
+    return ni + nj - 2.0 * g;
+}
+
+/* Rows `rows[q]` of orc_graph_from_leaves_reduced (same result restricted to
+ * those rows), for n too large for the full graph.  thr (nullable, [nq][n_trees][2])
+ * receives, per row and tree, the first-pass distances of the c-th and the
+ * (c+1)-th entry of the row's sorted first pass in its leaf: the last
+ * candidate kept and the first one dropped (+inf where the leaf has no such
+ * entry). */
+int orc_rows_from_leaves_reduced(const float *X, int64_t n, int D, int k, int n_trees,
+                                 const int32_t *perm, const int32_t *leaf_off,
+                                 const int64_t *n_leaves, int fmt, int c,
+                                 const int64_t *rows, int64_t nq, int32_t *ids, double *ds,
+                                 double *thr)
+{
+    int32_t *inv = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * n_trees);
+    const int32_t **offs = (const int32_t **)malloc(sizeof(int32_t *) * n_trees);
+    if (!inv || !offs) return -1;
+    int64_t o = 0;
+    for (int t = 0; t < n_trees; ++t) {
+        for (int64_t p = 0; p < n; ++p) inv[(size_t)t * n + perm[(size_t)t * n + p]] = (int32_t)p;
+        offs[t] = leaf_off + o;
+        o += n_leaves[t] + 1;
+    }
+    int fail = 0;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t qi = 0; qi < nq; ++qi) {
+        int64_t i = rows[qi];
+        int32_t *ri = ids + qi * k;
+        double *rd = ds + qi * k;
+        int cnt = 0;
+        for (int p = 0; p < k; ++p) { ri[p] = -1; rd[p] = INFINITY; }
+        for (int t = 0; t < n_trees; ++t) {
+            const int32_t *pm = perm + (size_t)t * n;
+            int64_t pos = inv[(size_t)t * n + i];
+            int64_t lo = 0, hi = n_leaves[t] - 1;
+            while (lo < hi) {
+                int64_t mid = (lo + hi + 1) / 2;
+                if (offs[t][mid] <= pos) lo = mid; else hi = mid - 1;
+            }
+            int64_t s = offs[t][lo], m = offs[t][lo + 1] - s;
+            double *q = (double *)malloc(sizeof(double) * (size_t)(m * D));
+            double *nqv = (double *)malloc(sizeof(double) * (size_t)m);
+            dj_rec *r = (dj_rec *)malloc(sizeof(dj_rec) * (size_t)m);
+            if (!q || !nqv || !r) {
+#pragma omp atomic write
+                fail = 1;
+                free(q); free(nqv); free(r);
+                continue;
+            }
+            reduced_leaf_rows(fmt, X, D, pm + s, m, q, nqv);
+            int nr = reduced_first_pass(pm + s, m, D, pos - s, q, nqv, r);
+            if (thr) {
+                thr[(qi * n_trees + t) * 2] = c <= nr ? r[c - 1].d : INFINITY;
+                thr[(qi * n_trees + t) * 2 + 1] = c < nr ? r[c].d : INFINITY;
+            }
+            int cc = reduced_rerank(X, D, i, r, nr, c);
+            for (int p = 0; p < cc && p < k; ++p) row_insert(ri, rd, &cnt, k, r[p].j, r[p].d);
+            free(q); free(nqv); free(r);
+        }
+    }
+    free(inv);
+    free(offs);
+    return fail ? -1 : 0;
 }
 
 /* ------------------------------------------------------------------ */

@@ -58,6 +58,11 @@ def lib():
         L.orc_graph_from_leaves.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp, vp, vp]
         L.orc_rows_from_leaves.restype = i32
         L.orc_rows_from_leaves.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp, vp, i64, vp, vp]
+        L.orc_rows_from_leaves_reduced.restype = i32
+        L.orc_rows_from_leaves_reduced.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp, i32, i32,
+                                                   vp, i64, vp, vp, vp]
+        L.orc_dtilde.restype = ctypes.c_double
+        L.orc_dtilde.argtypes = [vp, i32, i32, i64, i64]
         L.orc_round_fmt.restype = ctypes.c_double
         L.orc_round_fmt.argtypes = [ctypes.c_double, i32, i32]
         L.orc_quantize.restype = ctypes.c_double
@@ -255,6 +260,33 @@ def graph_from_leaves_reduced(X, k, perms, leaf_offs, fmt, c):
                                              FORMATS[fmt], c, _p(ids), _p(ds))
     assert rc == 0
     return ids, ds
+
+
+def rows_from_leaves_reduced(X, k, perms, leaf_offs, fmt, c, rows):
+    """Rows `rows` of graph_from_leaves_reduced, plus per row and tree the
+    first-pass distances of the c-th kept and the first dropped candidate
+    (thr [len(rows), T, 2], +inf where the leaf has no such entry)."""
+    X = _f32(X)
+    n, D = X.shape
+    perms = np.ascontiguousarray(perms, np.int32).reshape(-1, n)
+    T = perms.shape[0]
+    cat = np.ascontiguousarray(np.concatenate([np.asarray(o, np.int32) for o in leaf_offs]))
+    nl = np.array([len(o) - 1 for o in leaf_offs], np.int64)
+    rows = np.ascontiguousarray(rows, np.int64)
+    ids = np.empty((len(rows), k), np.int32)
+    ds = np.empty((len(rows), k), np.float64)
+    thr = np.empty((len(rows), T, 2), np.float64)
+    rc = lib().orc_rows_from_leaves_reduced(_p(X), n, D, k, T, _p(perms), _p(cat), _p(nl),
+                                            FORMATS[fmt], c, _p(rows), len(rows), _p(ids),
+                                            _p(ds), _p(thr))
+    assert rc == 0
+    return ids, ds, thr
+
+
+def dtilde(X, fmt, i, j):
+    """First-pass distance of the pair (i, j) under the reduced format (R9)."""
+    X = _f32(X)
+    return lib().orc_dtilde(_p(X), X.shape[1], FORMATS[fmt], int(i), int(j))
 
 
 def graph(X, k, n_trees, leaf_max, seed, min_leaf=None, max_iter=10):

@@ -105,3 +105,106 @@ def test_reduced_fp8_loses_little(orc):
     for i in range(0, 3000, 37):
         for p in range(10):
             assert b_d[i, p] == orc.d64(X, i, b_ids[i, p])
+
+
+# ---------------------------------------------------------------- hand-worked
+# One-dimensional leaves {0, 1, 2, 3} worked by hand.  Each row is scaled by
+# its own power of two before rounding (reading R9), so the dequantised
+# values below follow from the format's grid near the scaled value.
+#
+# FP8-e4m3 (3 fraction bits):
+#   x0 = 1.0   sigma 2^7: 128 is on the grid             -> 1.0
+#   x1 = 1.06  sigma 2^7: 135.68, grid 128 | 144          -> 1.0
+#   x2 = 0.95  sigma 2^8: 243.2,  grid 240 | 256          -> 0.9375
+#   x3 = 2.5   sigma 2^6: 160 is on the grid              -> 2.5
+# FP16 (10 fraction bits):
+#   x0 = 1.0      sigma 2^14: 16384 on the grid            -> 1.0
+#   x1 = 1.00045  sigma 2^14: 16391.4, grid 16384 | 16400  -> 1.0
+#   x2 = 0.9996   sigma 2^15: 32754.9, grid 32752 | 32768  -> 1 - 2^-11
+#   x3 = 3.0      sigma 2^13: 24576 on the grid            -> 3.0
+HAND = {
+    "fp8": dict(x=[1.0, 1.06, 0.95, 2.5], q=[1.0, 1.0, 0.9375, 2.5]),
+    "fp16": dict(x=[1.0, 1.00045, 0.9996, 3.0], q=[1.0, 1.0, 1.0 - 2.0 ** -11, 3.0]),
+}
+
+
+def _hand_leaf(fmt):
+    X = np.array(HAND[fmt]["x"], np.float32).reshape(4, 1)
+    perms = np.arange(4, dtype=np.int32).reshape(1, 4)
+    return X, perms, [np.array([0, 4], np.int32)]
+
+
+@pytest.mark.parametrize("fmt", ["fp8", "fp16"])
+def test_hand_worked_first_pass_distances(orc, fmt):
+    """d~ of every pair is (q_i - q_j)^2 of the dequantised values above."""
+    X, _, _ = _hand_leaf(fmt)
+    q = HAND[fmt]["q"]
+    for i in range(4):
+        for j in range(4):
+            if i != j:
+                assert orc.dtilde(X, fmt, i, j) == (q[i] - q[j]) ** 2, (i, j)
+
+
+@pytest.mark.parametrize("fmt", ["fp8", "fp16"])
+def test_hand_worked_rounding_changes_the_kept_candidate(orc, fmt):
+    """With one candidate per row (c = 1) the first pass keeps, for row 0, x1
+    (d~ = 0) while the exact nearest point is x2; row 3 sees x0 and x1 at the
+    same d~ and keeps the smaller id, x0, while x1 is nearer.  So the reduced
+    graph differs from the exact one in rows 0 and 3, and c = 2 recovers it."""
+    X, perms, offs = _hand_leaf(fmt)
+    ex_ids, ex_d = orc.graph_from_leaves(X, 1, perms, offs)
+    assert ex_ids[:, 0].tolist() == [2, 0, 0, 1]
+    r_ids, r_d = orc.graph_from_leaves_reduced(X, 1, perms, offs, fmt, 1)
+    assert r_ids[:, 0].tolist() == [1, 0, 0, 0]
+    # kept distances are the exact d64 of the kept pair
+    for i in range(4):
+        assert r_d[i, 0] == orc.d64(X, i, r_ids[i, 0])
+    r2 = orc.graph_from_leaves_reduced(X, 1, perms, offs, fmt, 2)
+    assert np.array_equal(r2[0], ex_ids) and np.array_equal(r2[1], ex_d)
+    # the sampled-rows entry gives the same rows and the selection thresholds
+    ids, ds, thr = orc.rows_from_leaves_reduced(X, 1, perms, offs, fmt, 1, [0, 3])
+    assert ids[:, 0].tolist() == [1, 0]
+    q = HAND[fmt]["q"]
+    assert thr[0, 0].tolist() == [0.0, (q[0] - q[2]) ** 2]      # kept x1, dropped x2
+    assert thr[1, 0].tolist() == [(q[3] - q[0]) ** 2] * 2       # x0 kept, x1 dropped at equal d~
+    ids3, _, thr3 = orc.rows_from_leaves_reduced(X, 1, perms, offs, fmt, 3, [1])
+    assert np.isinf(thr3[0, 0, 1]) and thr3[0, 0, 0] == max(
+        (q[1] - q[j]) ** 2 for j in (0, 2, 3))
+
+
+def test_power_of_two_scaling_commutes_with_the_first_pass(orc):
+    """The per-row scale is a power of two chosen from the row's own maximum,
+    so multiplying the data by 2^p changes no rounding: same ids, distances
+    times 4^p exactly.  Without the scale FP8 would flush 2^-12-sized values
+    to its subnormals and saturate at 448 (C1 values reach about 14 * 2^6)."""
+    X = datagen.make("c1", n=800)
+    perms, offs = _trees(orc, X, 1, 40, 11, 2)
+    ids0, d0 = orc.graph_from_leaves_reduced(X, 10, perms, offs, "fp8", 12)
+    for p in (-12, 6):
+        Xs = (X.astype(np.float64) * 2.0 ** p).astype(np.float32)
+        ids1, d1 = orc.graph_from_leaves_reduced(Xs, 10, perms, offs, "fp8", 12)
+        assert np.array_equal(ids0, ids1)
+        assert np.array_equal(d0 * 4.0 ** p, d1)
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16", "fp8"])
+def test_rows_entry_equals_graph_rows(orc, fmt):
+    X = datagen.make("c1", n=2000)
+    perms, offs = _trees(orc, X, 2, 50, 11, 8)
+    g_ids, g_d = orc.graph_from_leaves_reduced(X, 10, perms, offs, fmt, 14)
+    rows = datagen.sample_rows(len(X), 300, seed=5)
+    ids, ds, thr = orc.rows_from_leaves_reduced(X, 10, perms, offs, fmt, 14, rows)
+    assert np.array_equal(ids, g_ids[rows]) and np.array_equal(ds, g_d[rows])
+    assert np.all(thr[:, :, 0] <= thr[:, :, 1])
+    # every kept id was kept by the first pass of a tree that holds it in
+    # the row's leaf: its d~ is at most that tree's threshold
+    for q in range(0, len(rows), 17):
+        i = rows[q]
+        for j in ids[q]:
+            ok = False
+            for t in range(2):
+                pos = int(np.where(perms[t] == i)[0][0])
+                l = int(np.searchsorted(offs[t], pos, "right")) - 1
+                if j in perms[t][offs[t][l]:offs[t][l + 1]]:
+                    ok = ok or orc.dtilde(X, fmt, i, j) <= thr[q, t, 0]
+            assert ok, (i, j)

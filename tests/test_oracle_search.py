@@ -29,6 +29,49 @@ def test_d32_exact_on_integers(orc):
         assert orc.d32(x[i], x[i + 1]) == exact
 
 
+def test_d32_blocks_of_32_hand_worked(orc):
+    """Non-integer d32 at D = 33, worked by hand (u = 2^-24, FP32 round to
+    nearest even; the ulp is 2u on [1, 2) and 4u on [2, 4)).
+
+    b: dims 0, 1, 32 differ by 1, 1.5 * 2^-12, 1 + 2^-12.
+       block 0..31: fma(1,1,0) = 1; 1 + 2.25u rounds to 1 + 2u.
+       block 32:    (1 + 2^-12)^2 = 1 + 2^-11 + u, a tie, to even 1 + 2^-11.
+       total:       2 + 2^-11 + 2u, a tie, to even 2 + 2^-11.
+       One sequential chain over all 33 dims instead ends with
+       1 + 2u + (1 + 2^-11 + u) = 2 + 2^-11 + 3u, rounded up to 2 + 2^-11 + 4u.
+    c: dims 0, 16, 17, 32 differ by 1, 2^-12, 2^-12, 2^-12.
+       block 0..31: 1 + u twice, each a tie, to even 1; block 32: u;
+       total 1 + u, a tie, to even: 1.  Blocks of 16 would give
+       1 + (u + u) = 1 + 2u, then + u = 1 + 3u, a tie, to even 1 + 4u."""
+    a = np.zeros(33, np.float32)
+    b = a.copy()
+    b[0], b[1], b[32] = 1.0, 1.5 * 2.0 ** -12, 1.0 + 2.0 ** -12
+    c = a.copy()
+    c[0], c[16], c[17], c[32] = 1.0, 2.0 ** -12, 2.0 ** -12, 2.0 ** -12
+    assert orc.d32(a, b) == 2.0 + 2.0 ** -11
+    assert orc.d32(b, a) == 2.0 + 2.0 ** -11
+    assert orc.d32(a, c) == 1.0
+    assert orc.d32(c, a) == 1.0
+    # the FP64 distances differ from both (D = 33, dims in order)
+    X = np.stack([a, b, c])
+    assert orc.d64(X, 0, 1) == 1.0 + 2.25 * 2.0 ** -24 + (1.0 + 2.0 ** -12) ** 2
+    assert orc.d64(X, 0, 2) == 1.0 + 3 * 2.0 ** -24
+
+
+def test_d32_d40_last_block_partial(orc):
+    """D = 40: the second block holds 8 dimensions.  Dims 0 and 39 differ by
+    1 and 2^-12: block 0 = 1, block 1 = u, total 1 + u, a tie, to even 1
+    (a block of 40 would also give 1; dims 0, 38, 39 by 1, 2^-12, 2^-12
+    give 1 + 2u within block 1 first: 1 + 2u exactly)."""
+    a = np.zeros(40, np.float32)
+    b = a.copy()
+    b[0], b[39] = 1.0, 2.0 ** -12
+    c = a.copy()
+    c[0], c[38], c[39] = 1.0, 2.0 ** -12, 2.0 ** -12
+    assert orc.d32(a, b) == 1.0
+    assert orc.d32(a, c) == 1.0 + 2.0 ** -23
+
+
 def test_zero_rounds_is_topk_of_the_seeds(orc):
     X = datagen.random_points(300, 12, 5, "normal")
     Q = datagen.random_points(20, 12, 6, "normal")
