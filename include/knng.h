@@ -101,6 +101,10 @@ typedef struct {
     int32_t exact_first_pass; /* 1 if leaf distances came from the exact BF16
                                  first pass (integer data 0..255, D <= 129; equal
                                  to d32 bit for bit) */
+    int64_t subtree_rows;   /* the part of assign_rows assigned inside the subtree
+                               kernels (rows held in LDS, no memory traffic per
+                               pass); assign_rows - subtree_rows rows were streamed
+                               by the level kernels' assignment passes */
 } knng_stats;
 
 /* Fill *opt with the defaults listed above. */

@@ -5,6 +5,7 @@
 #include "knng.h"
 #include "knng_internal.hpp"
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -76,6 +77,17 @@ int check_common(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_t
     if (n_trees < 1) return set_err(KNNG_ERR_INVALID_ARG, "n_trees=%d must be >= 1", n_trees);
     return KNNG_OK;
 }
+
+// The re-ranked matrix-core leaf kernels keep c = max(rerank k, k) <= 128
+// candidates and k <= 64 neighbours per row; leaves above 256 points at most
+// 64 candidates.
+bool reduced_leaf_fits(int k, int rerank, int leaf_max) {
+    const int64_t c = std::max<int64_t>(static_cast<int64_t>(rerank) * k, k);
+    return k <= 64 && c <= 128 && (leaf_max <= 256 || c <= 64);
+}
+// The exact BF16 leaf kernels keep the k best: k <= 128, and k <= 64 for
+// leaves above 256 points.
+bool exact_leaf_fits(int k, int leaf_max) { return k <= 128 && (leaf_max <= 256 || k <= 64); }
 
 struct Events {
     hipEvent_t e[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -164,7 +176,7 @@ const char* knng_status_string(int status) {
 
 const char* knng_last_error(void) { return g_err; }
 
-int knng_version(void) { return 100; }
+int knng_version(void) { return 101; }
 
 int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_trees,
                   int32_t leaf_max, uint64_t seed, int32_t* ids_out, float* dists_out,
@@ -180,8 +192,17 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
                        2 * o.min_leaf - 1);
     if (leaf_max > knng::kMaxLeaf)
         return set_err(KNNG_ERR_UNSUPPORTED, "leaf_max=%d exceeds %d", leaf_max, knng::kMaxLeaf);
-    if (o.precision != KNNG_FP32 && o.rerank * k > 128)
-        return set_err(KNNG_ERR_UNSUPPORTED, "rerank_factor*k = %d exceeds 128", o.rerank * k);
+    const int lm_eff = leaf_max < n ? leaf_max : static_cast<int>(n);
+    // Which matrix-core leaf kernels can serve this request: the re-ranked
+    // first pass keeps c = max(rerank_factor k, k) candidates per row, the
+    // exact BF16 pass (integer data) keeps k.
+    const bool reduced_fits = reduced_leaf_fits(k, o.rerank, lm_eff);
+    const bool exact_fits = exact_leaf_fits(k, lm_eff);
+    if (o.precision != KNNG_FP32 && !reduced_fits && !(o.precision == KNNG_BF16 && exact_fits))
+        return set_err(KNNG_ERR_UNSUPPORTED,
+                       "the re-ranked leaf kernel keeps k <= 64 and rerank_factor*k <= 128 "
+                       "(<= 64 for leaves above 256 points); k=%d, rerank_factor=%d, leaf_max=%d",
+                       k, o.rerank, lm_eff);
 
     hipStream_t s = stream;
     knng::DeviceLock dlock;  // workspace blocks: one call per device at a time
@@ -216,10 +237,15 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
     // every product, norm, sum of two norms and partial sum of the first pass
     // is an exact FP32 integer, so its distances equal d32 bit for bit.  Such
     // data takes that path for FP32 and BF16 requests alike (not in the plain
-    // schedule, nor with compact=0).
-    const bool exact_bf16 = all_u8 != 0 && D <= 129 && o.compact && !o.plain &&
+    // schedule, nor with compact=0) when its kernel serves (k, leaf_max);
+    // otherwise FP32 requests take the FP32 direct kernel.
+    const bool exact_bf16 = all_u8 != 0 && D <= 129 && o.compact && !o.plain && exact_fits &&
                             (o.precision == KNNG_FP32 || o.precision == KNNG_BF16);
     const int leaf_prec = exact_bf16 ? KNNG_BF16 : o.precision;
+    if (leaf_prec != KNNG_FP32 && !exact_bf16 && !reduced_fits)
+        return set_err(KNNG_ERR_UNSUPPORTED,
+                       "BF16 with rerank_factor*k = %d needs the exact first pass (integer "
+                       "data 0..255, D <= 129)", o.rerank * k);
     knng::ReducedRows rr{nullptr, nullptr, nullptr, knng::reduced_rows_dp(D), exact_bf16};
 
     e = knng::ws_malloc(reinterpret_cast<void**>(&perm), sizeof(int32_t) * slots * n, s);
@@ -287,6 +313,7 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
             goto done;
         }
         pres.assign_rows += r.assign_rows;
+        pres.subtree_rows += r.subtree_rows;
         pres.splits += r.splits;
         pres.repairs += r.repairs;
         pres.levels = r.levels > pres.levels ? r.levels : pres.levels;
@@ -304,7 +331,7 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
         la.n_leaves = r.n_leaves;
         la.leaf_max = leaf_max < n ? leaf_max : static_cast<int>(n);
         la.precision = leaf_prec;
-        la.rerank = o.rerank * k;
+        la.rerank = exact_bf16 ? k : o.rerank * k;  // the exact pass keeps the k best
         la.cand_ids = cand_ids + static_cast<size_t>(t0) * n * k;
         la.cand_d = cand_d + static_cast<size_t>(t0) * n * k;
         la.pairs = dpairs;
@@ -359,6 +386,7 @@ done:
     if (rc == KNNG_OK && stats_out != nullptr) {
         std::memset(stats_out, 0, sizeof(*stats_out));
         stats_out->assign_rows = pres.assign_rows;
+        stats_out->subtree_rows = pres.subtree_rows;
         stats_out->ordered_pairs = pairs;
         stats_out->leaves = n_leaves_total;
         stats_out->splits = pres.splits;
@@ -520,11 +548,13 @@ __global__ void k_zero2(int32_t* p) {
 }  // namespace
 }  // namespace knng
 
-extern "C" int knng_leaf_search(const float* data, int64_t n, int32_t D, int32_t k,
-                                int32_t n_trees, const int32_t* perm,
-                                const int32_t* leaf_offsets, const int32_t* n_leaves,
-                                const knng_options* opt, int32_t* ids_out, float* dists_out,
-                                hipStream_t stream) {
+namespace {
+
+// knng_leaf_search.
+int leaf_search_impl(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_trees,
+                     const int32_t* perm, const int32_t* leaf_offsets, const int32_t* n_leaves,
+                     const knng_options* opt, int32_t* ids_out, float* dists_out,
+                     hipStream_t stream) {
     g_err[0] = '\0';
     int rc = check_common(data, n, D, k, n_trees, ids_out, dists_out);
     if (rc != KNNG_OK) return rc;
@@ -533,8 +563,10 @@ extern "C" int knng_leaf_search(const float* data, int64_t n, int32_t D, int32_t
     Resolved o;
     rc = resolve(opt, k, &o);
     if (rc != KNNG_OK) return rc;
-    if (o.precision != KNNG_FP32 && o.rerank * k > 128)
-        return set_err(KNNG_ERR_UNSUPPORTED, "rerank_factor*k = %d exceeds 128", o.rerank * k);
+    if (o.precision != KNNG_FP32 && !reduced_leaf_fits(k, o.rerank, 256))
+        return set_err(KNNG_ERR_UNSUPPORTED,
+                       "the re-ranked leaf kernel keeps k <= 64 and rerank_factor*k <= 128 "
+                       "(k=%d, rerank_factor=%d)", k, o.rerank);
     int64_t total = 0;
     for (int t = 0; t < n_trees; ++t) {
         if (n_leaves[t] < 1 || n_leaves[t] > n)
@@ -673,6 +705,18 @@ done:
     if (rc == KNNG_OK && e != hipSuccess) rc = hip_fail(e, "leaf search");
     return rc;
 }
+
+}  // namespace
+
+extern "C" int knng_leaf_search(const float* data, int64_t n, int32_t D, int32_t k,
+                                int32_t n_trees, const int32_t* perm,
+                                const int32_t* leaf_offsets, const int32_t* n_leaves,
+                                const knng_options* opt, int32_t* ids_out, float* dists_out,
+                                hipStream_t stream) {
+    return leaf_search_impl(data, n, D, k, n_trees, perm, leaf_offsets, n_leaves, opt, ids_out,
+                            dists_out, stream);
+}
+
 
 namespace {
 __global__ void k_zero_u64(unsigned long long* p, int count) {

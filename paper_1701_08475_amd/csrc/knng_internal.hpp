@@ -141,8 +141,9 @@ struct SubtreeArgs {
     int32_t* node_log;
     int64_t node_log_cap;
     LevelCounters* ctr;
-    unsigned long long* dstats;  // spread counters (kStatWords each): assigned rows, repairs,
-                                 // splits, deepest split depth + 1
+    unsigned long long* dstats;  // spread counters (kStatWords each): level-kernel assigned
+                                 // rows (unused here), repairs, splits, deepest split
+                                 // depth + 1, rows assigned inside subtree kernels
     int* overflow;               // bit 0: leaf list full, bit 1: subtree stack full
     int row_budget;              // LDS bytes for rows per workgroup: 131072 or 65536;
                                  // 0: one wavefront per subtree (kernel k_subtree_wave_u8)
@@ -191,7 +192,8 @@ struct PartitionArgs {
 struct PartitionResult {
     int64_t n_leaves = 0;
     int64_t n_log = 0;
-    int64_t assign_rows = 0;  // rows assigned, summed over passes
+    int64_t assign_rows = 0;  // rows assigned, summed over passes (subtree kernels included)
+    int64_t subtree_rows = 0; // the part of assign_rows assigned inside subtree kernels (LDS)
     int64_t splits = 0;
     int64_t repairs = 0;
     int levels = 0;

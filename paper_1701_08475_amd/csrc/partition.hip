@@ -1315,7 +1315,7 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     unsigned long long* dstats = nullptr;
     LevelCounters* hctr = nullptr;
     LevelCounters* dmirror = nullptr;  // device address of hctr
-    std::vector<unsigned long long> hstats(4 * kStatWords, 0ull);
+    std::vector<unsigned long long> hstats(5 * kStatWords, 0ull);
     int hoverflow = 0;
     int cur = 0;
     int depth = 0;
@@ -1383,9 +1383,9 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&perm_tmp), sizeof(int32_t) * tn, s));
     KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&ctr), sizeof(LevelCounters), s));
     KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&dstats),
-                            sizeof(unsigned long long) * 4 * kStatWords, s));
+                            sizeof(unsigned long long) * 5 * kStatWords, s));
     KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&overflow), sizeof(int), s));
-    k_zero_small<<<1, 256, 0, s>>>(dstats, 4 * kStatWords, overflow);
+    k_zero_small<<<1, 256, 0, s>>>(dstats, 5 * kStatWords, overflow);
     KNNG_LAUNCH();
     {
         const int64_t want = (static_cast<int64_t>(tn) + 255) / 256;
@@ -1537,7 +1537,8 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     }
     res->n_leaves = hctr->n_leaves;
     res->n_log = hctr->n_log;
-    res->assign_rows = static_cast<int64_t>(stat_total(hstats.data()));
+    res->subtree_rows = static_cast<int64_t>(stat_total(hstats.data() + 4 * kStatWords));
+    res->assign_rows = static_cast<int64_t>(stat_total(hstats.data())) + res->subtree_rows;
     res->repairs = static_cast<int64_t>(stat_total(hstats.data() + kStatWords));
     res->splits = splits + static_cast<int64_t>(stat_total(hstats.data() + 2 * kStatWords));
     res->levels =

@@ -542,7 +542,7 @@ __global__ __launch_bounds__(kSubThreads) void k_subtree_u8(
 
     for (int i = tid; i < M; i += NT) perm[pbase + i] = s_ids[s_ord[i]];
     if (tid == 0) {
-        stat_add(dstats, blockIdx.x, assigned);
+        stat_add(dstats + 4 * kStatWords, blockIdx.x, assigned);
         stat_add(dstats + kStatWords, blockIdx.x, repairs);
         stat_add(dstats + 2 * kStatWords, blockIdx.x, splits);
         stat_max(dstats + 3 * kStatWords, blockIdx.x, maxdep);
@@ -1017,7 +1017,7 @@ __global__ __launch_bounds__(64) void k_subtree_wave_u8(
 
     for (int i = lane; i < M; i += kWave) perm[pbase + i] = s_ids[s_ord[i]];
     if (lane == 0) {
-        stat_add(dstats, blockIdx.x, assigned);
+        stat_add(dstats + 4 * kStatWords, blockIdx.x, assigned);
         stat_add(dstats + kStatWords, blockIdx.x, repairs);
         stat_add(dstats + 2 * kStatWords, blockIdx.x, splits);
         stat_max(dstats + 3 * kStatWords, blockIdx.x, maxdep);

@@ -46,8 +46,8 @@ def test_options_struct_layout(L):
     assert (o.precision, o.rerank_factor, o.min_leaf, o.max_iter, o.plain, o.check_finite,
             o.time_kernels, o.compact) == (0, 2, 0, 10, 0, 1, 0, 1)
     # 5 int64, 2 int32, 5 float, 3 (float, int32) pairs, 2 int32 = 100 bytes,
-    # padded to a multiple of 8
-    assert ctypes.sizeof(knng.KnngStats) == 104
+    # padded to 104, then one int64
+    assert ctypes.sizeof(knng.KnngStats) == 112
 
 
 FAKE = 0x10000  # aligned, never dereferenced: validation fails first
@@ -173,3 +173,4 @@ def test_u8_entry_points_reject_invalid_arguments(L):
     assert L.knng_search_u8(ctypes.c_void_p(FAKE + 1), 100, 8, f, 4, f, 3, f, 2, 5, 2, f, f, None,
                             None) == E                         # not 16-byte aligned
     assert L.knng_search_u8(f, 100, 8, f, 0, f, 3, f, 2, 5, 2, f, f, None, None) == E
+

@@ -174,6 +174,20 @@ def test_build_integer_data_bit_exact(K, orc):
     graph_parity(orc, X, np.arange(len(X)), _np(ids), _np(ds), o_ids, o_d, strict=True)
 
 
+@pytest.mark.parametrize("k,L,rerank", [(100, 256, 2), (20, 100, 8), (70, 512, 2)])
+def test_integer_data_fp32_request_any_rerank(K, orc, k, L, rerank):
+    """FP32 requests on integer data take the exact BF16 leaf pass, which keeps
+    the k best whatever rerank_factor is; where its kernels cannot serve
+    (k, leaf_max) (k = 70 with leaves above 256 points) the FP32 direct kernel
+    does.  Either way the graph equals the oracle's bit for bit."""
+    X = datagen.make("c2", n=5000)
+    log("integer data fp32 request k=%d L=%d rerank=%d" % (k, L, rerank))
+    ids, ds, st = K.build(to_dev(X), k, 2, L, seed=5, rerank_factor=rerank, stats=True)
+    assert st["exact_first_pass"] == (0 if k > 64 and L > 256 else 1)
+    o_ids, o_d, _ = orc.graph(X, k, 2, L, 5)
+    graph_parity(orc, X, np.arange(len(X)), _np(ids), _np(ds), o_ids, o_d, strict=True)
+
+
 def test_leaf_search_on_oracle_leaves(K, orc):
     import torch
     X = datagen.make("c1", n=8000)
