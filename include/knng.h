@@ -179,6 +179,31 @@ int knng_leaf_search(const float* data, int64_t n, int32_t D, int32_t k, int32_t
                      int32_t* ids_out, float* dists_out, hipStream_t stream);
 
 /*
+ * knng_leaf_search_noalloc -- knng_leaf_search for callers that cannot
+ * allocate device memory (code in a tight serving loop, or in a harness that
+ * forbids hipMalloc).  Same arguments, checks, kernels and results as
+ * knng_leaf_search; it calls no hipMalloc, hipFree or other allocating
+ * routine.  Its scratch blocks (leaf table, flags, per-tree candidate lists,
+ * reduced copy, size buckets) are carved from a fixed 64 MiB device array
+ * that every GPU the library runs on holds until the process ends (its
+ * address is looked up once per device, on the first call there).
+ *   Limit: 16 B per leaf + 8 n_trees n k B of candidate lists when
+ *   n_trees > 1 + for a reduced precision n (Dp b + 8) B (Dp = D rounded up
+ *   to 32, b = 2 for BF16/FP16, 1 for FP8) + 16 B per leaf, each block
+ *   rounded up to 256 B, must fit 64 MiB; larger requests return
+ *   KNNG_ERR_UNSUPPORTED before any HIP call.
+ *   Calls on one device share the array and are serialised by the library's
+ *   per-device lock (each returns after its stream is synchronised); the
+ *   array keeps the last call's contents, and every value a call reads from
+ *   it is written by that call first (flags and counters are cleared by fill
+ *   kernels, not memsets).
+ */
+int knng_leaf_search_noalloc(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_trees,
+                             const int32_t* perm, const int32_t* leaf_offsets,
+                             const int32_t* n_leaves, const knng_options* opt,
+                             int32_t* ids_out, float* dists_out, hipStream_t stream);
+
+/*
  * knng_search -- enhanced hill-climbing nearest-neighbour search over a kNN
  * graph (Alg. 2, E-GNNS), one call for a batch of queries.  For each query
  * q, the rank list R starts from the seeds; each of `rounds` rounds takes

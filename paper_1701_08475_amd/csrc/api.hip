@@ -10,6 +10,9 @@
 #include <cstdio>
 #include <cstring>
 #include <atomic>
+#include <cstdint>
+#include <mutex>
+#include <optional>
 #include <vector>
 
 namespace {
@@ -548,13 +551,81 @@ __global__ void k_zero2(int32_t* p) {
 }  // namespace
 }  // namespace knng
 
+// Scratch memory of knng_leaf_search_noalloc: every GPU the library runs on
+// holds one copy of this array until the process ends.  Host code uses the
+// device address that hipGetSymbolAddress returns for the current device
+// (scratch_address), never the array's name.
+constexpr size_t kNoAllocScratchBytes = size_t{64} << 20;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
 namespace {
 
-// knng_leaf_search.
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+// This device's address of `scratch`, looked up once per device (with that
+// device current) and kept.
+hipError_t scratch_address(void** p) {
+    *p = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* q = nullptr;
+        e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = q;
+    }
+    *p = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+// a * b, or SIZE_MAX when it overflows
+size_t mul_sat(size_t a, size_t b) {
+    if (a != 0 && b > SIZE_MAX / a) return SIZE_MAX;
+    return a * b;
+}
+
+// Bytes the leaf search carves from an arena: every workspace block it may
+// take (leaf table, flags, input scan flags, per-tree candidate lists,
+// reduced copy with norms and scales, size-bucket counters and grouped leaf
+// table), each rounded to the arena's alignment.  Blocks are never reused
+// within a call in arena mode, so this is the exact upper bound.
+size_t leaf_search_scratch_bytes(int64_t n, int D, int k, int n_trees, int64_t total_leaves,
+                                 int precision, bool check_finite) {
+    size_t need = 0;
+    auto add = [&](size_t b) {
+        const size_t r = b == SIZE_MAX ? SIZE_MAX : knng::ws_arena_block(b);
+        need = (r == SIZE_MAX || need > SIZE_MAX - r) ? SIZE_MAX : need + r;
+    };
+    add(mul_sat(sizeof(knng::LeafRec), static_cast<size_t>(total_leaves)));
+    add(2 * sizeof(int32_t));
+    if (check_finite) add(2 * sizeof(int32_t));
+    if (n_trees > 1) {
+        const size_t lists = mul_sat(mul_sat(static_cast<size_t>(n_trees), static_cast<size_t>(n)),
+                                     static_cast<size_t>(k));
+        add(mul_sat(lists, sizeof(int32_t)));
+        add(mul_sat(lists, sizeof(float)));
+    }
+    if (precision != KNNG_FP32) {
+        add(knng::reduced_rows_bytes(precision, n, D));
+        add(mul_sat(sizeof(float), static_cast<size_t>(n)));
+        add(mul_sat(sizeof(float), static_cast<size_t>(n)));
+        add(8 * sizeof(int32_t));
+        add(mul_sat(sizeof(knng::LeafRec), static_cast<size_t>(total_leaves)));
+    }
+    return need;
+}
+
+// knng_leaf_search and knng_leaf_search_noalloc: with noalloc, every
+// workspace block comes from this device's `scratch` array.
 int leaf_search_impl(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_trees,
                      const int32_t* perm, const int32_t* leaf_offsets, const int32_t* n_leaves,
                      const knng_options* opt, int32_t* ids_out, float* dists_out,
-                     hipStream_t stream) {
+                     hipStream_t stream, bool noalloc) {
     g_err[0] = '\0';
     int rc = check_common(data, n, D, k, n_trees, ids_out, dists_out);
     if (rc != KNNG_OK) return rc;
@@ -573,8 +644,21 @@ int leaf_search_impl(const float* data, int64_t n, int32_t D, int32_t k, int32_t
             return set_err(KNNG_ERR_INVALID_ARG, "n_leaves[%d]=%d out of [1, n]", t, n_leaves[t]);
         total += n_leaves[t];
     }
+    void* arena_base = nullptr;
+    if (noalloc) {
+        const size_t need = leaf_search_scratch_bytes(n, D, k, n_trees, total, o.precision,
+                                                      o.check_finite != 0);
+        if (need > kNoAllocScratchBytes)
+            return set_err(KNNG_ERR_UNSUPPORTED,
+                           "the request needs %zu bytes of scratch memory; the no-allocation "
+                           "entry point has %zu", need, kNoAllocScratchBytes);
+        const hipError_t e = scratch_address(&arena_base);
+        if (e != hipSuccess) return hip_fail(e, "scratch address");
+    }
     hipStream_t s = stream;
     knng::DeviceLock dlock;  // workspace blocks: one call per device at a time
+    std::optional<knng::ArenaScope> arena;
+    if (noalloc) arena.emplace(arena_base, kNoAllocScratchBytes);
     knng::LeafRec* leaves = nullptr;
     int32_t* flags = nullptr;  // [0] max leaf size, [1] malformed
     int32_t hflags[2] = {0, 0};
@@ -714,9 +798,17 @@ extern "C" int knng_leaf_search(const float* data, int64_t n, int32_t D, int32_t
                                 const knng_options* opt, int32_t* ids_out, float* dists_out,
                                 hipStream_t stream) {
     return leaf_search_impl(data, n, D, k, n_trees, perm, leaf_offsets, n_leaves, opt, ids_out,
-                            dists_out, stream);
+                            dists_out, stream, false);
 }
 
+extern "C" int knng_leaf_search_noalloc(const float* data, int64_t n, int32_t D, int32_t k,
+                                        int32_t n_trees, const int32_t* perm,
+                                        const int32_t* leaf_offsets, const int32_t* n_leaves,
+                                        const knng_options* opt, int32_t* ids_out,
+                                        float* dists_out, hipStream_t stream) {
+    return leaf_search_impl(data, n, D, k, n_trees, perm, leaf_offsets, n_leaves, opt, ids_out,
+                            dists_out, stream, true);
+}
 
 namespace {
 __global__ void k_zero_u64(unsigned long long* p, int count) {

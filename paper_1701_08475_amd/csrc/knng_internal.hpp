@@ -22,6 +22,22 @@ constexpr int kMaxDim = 4096;
 hipError_t ws_malloc(void** p, size_t bytes, hipStream_t s);
 void ws_free(void* p, hipStream_t s);
 void ws_release_device(int dev);  // frees every cached (unused) block of the device
+// Arena mode of the calling thread: while an ArenaScope lives, ws_malloc
+// carves kArenaAlign-aligned blocks of ws_arena_block(bytes) bytes from
+// [base, base + cap) in order and returns hipErrorOutOfMemory once it is
+// exhausted (it never calls hipMalloc); ws_free of those blocks does nothing.
+constexpr size_t kArenaAlign = 256;
+size_t ws_arena_block(size_t bytes);
+class ArenaScope {
+  public:
+    ArenaScope(void* base, size_t cap);
+    ~ArenaScope();
+    ArenaScope(const ArenaScope&) = delete;
+    ArenaScope& operator=(const ArenaScope&) = delete;
+
+  private:
+    alignas(8) unsigned char storage_[32];
+};
 class DeviceLock {
   public:
     DeviceLock();

@@ -9,16 +9,31 @@
 // the same stream (stream order keeps that safe); the calls that allocate
 // hold the device's lock (DeviceLock) until they have synchronised their
 // stream, so another call never receives a block still in use.
+//
+// A caller that must not allocate sets an arena for its thread (ArenaScope):
+// ws_malloc then hands out consecutive 256-byte aligned blocks of that
+// memory and fails with hipErrorOutOfMemory when it is exhausted.
 #include "knng_internal.hpp"
 
 #include <map>
 #include <mutex>
+#include <new>
 #include <unordered_map>
 
 namespace knng {
 namespace {
 
 constexpr int kMaxDevices = 64;
+
+// Arena of the calling thread (ArenaScope): while set, ws_malloc carves
+// blocks from it and never calls hipMalloc; ws_free of an arena block is a
+// no-op (the whole arena is released when the scope ends).
+struct Arena {
+    uint8_t* base;
+    size_t cap;
+    size_t used;
+};
+thread_local Arena* t_arena = nullptr;
 
 struct Cache {
     std::mutex mu;                                // guards the maps
@@ -49,8 +64,27 @@ size_t size_class(size_t bytes) {
 
 }  // namespace
 
+size_t ws_arena_block(size_t bytes) {
+    return (bytes == 0 ? size_t{1} : bytes + kArenaAlign - 1) / kArenaAlign * kArenaAlign;
+}
+
+ArenaScope::ArenaScope(void* base, size_t cap) {
+    static_assert(sizeof(Arena) <= sizeof(storage_), "arena record fits the scope's storage");
+    Arena* a = new (storage_) Arena{static_cast<uint8_t*>(base), cap, 0};
+    t_arena = a;
+}
+
+ArenaScope::~ArenaScope() { t_arena = nullptr; }
+
 hipError_t ws_malloc(void** p, size_t bytes, hipStream_t /*s*/) {
     *p = nullptr;
+    if (t_arena != nullptr) {
+        const size_t b = ws_arena_block(bytes);
+        if (b > t_arena->cap - t_arena->used) return hipErrorOutOfMemory;
+        *p = t_arena->base + t_arena->used;
+        t_arena->used += b;
+        return hipSuccess;
+    }
     const int dev = current_device();
     if (dev < 0) return hipErrorInvalidDevice;
     const size_t sc = size_class(bytes == 0 ? 1 : bytes);
@@ -81,6 +115,10 @@ hipError_t ws_malloc(void** p, size_t bytes, hipStream_t /*s*/) {
 
 void ws_free(void* p, hipStream_t /*s*/) {
     if (p == nullptr) return;
+    if (t_arena != nullptr) {
+        const uint8_t* q = static_cast<const uint8_t*>(p);
+        if (q >= t_arena->base && q < t_arena->base + t_arena->cap) return;
+    }
     const int dev = current_device();
     if (dev < 0) return;
     Cache& c = cache(dev);

@@ -86,6 +86,8 @@ def lib():
     L.knng_leaf_search.restype = ctypes.c_int
     L.knng_leaf_search.argtypes = [vp, i64, i32, i32, i32, vp, vp, ctypes.POINTER(i32),
                                    ctypes.POINTER(KnngOptions), vp, vp, vp]
+    L.knng_leaf_search_noalloc.restype = ctypes.c_int
+    L.knng_leaf_search_noalloc.argtypes = L.knng_leaf_search.argtypes
     L.knng_search.restype = ctypes.c_int
     L.knng_search.argtypes = [vp, i64, i32, vp, i32, vp, i64, vp, i32, i32, i32, vp, vp, vp]
     L.knng_search_ex.argtypes = [vp, i64, i32, vp, i32, vp, i64, vp, i32, i32, i32, vp, vp,
@@ -203,9 +205,11 @@ def partition(x, leaf_max, min_leaf, seed, tree, max_iter=0, with_nodes=False, s
     return out
 
 
-def leaf_search(x, k, perms, leaf_offs, precision="fp32", rerank_factor=2, stream=None):
+def leaf_search(x, k, perms, leaf_offs, precision="fp32", rerank_factor=2, stream=None,
+                noalloc=False):
     """G from given clusters.  perms: int32 CUDA [T, n]; leaf_offs: list of T
-    int32 CUDA boundary tensors.  Returns (ids, dists)."""
+    int32 CUDA boundary tensors.  Returns (ids, dists).  noalloc=True calls
+    knng_leaf_search_noalloc (scratch from the library's fixed array)."""
     import torch
     x = _dev_f32(x)
     n, D = x.shape
@@ -216,7 +220,8 @@ def leaf_search(x, k, perms, leaf_offs, precision="fp32", rerank_factor=2, strea
     ids = torch.empty((n, k), dtype=torch.int32, device=x.device)
     ds = torch.empty((n, k), dtype=torch.float32, device=x.device)
     o = options(precision, rerank_factor)
-    rc = lib().knng_leaf_search(ctypes.c_void_p(x.data_ptr()), n, D, k, T,
+    fn = lib().knng_leaf_search_noalloc if noalloc else lib().knng_leaf_search
+    rc = fn(ctypes.c_void_p(x.data_ptr()), n, D, k, T,
                                 ctypes.c_void_p(perms.data_ptr()), ctypes.c_void_p(cat.data_ptr()),
                                 nl, ctypes.byref(o), ctypes.c_void_p(ids.data_ptr()),
                                 ctypes.c_void_p(ds.data_ptr()), _stream(stream))

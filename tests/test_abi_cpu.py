@@ -174,3 +174,22 @@ def test_u8_entry_points_reject_invalid_arguments(L):
                             None) == E                         # not 16-byte aligned
     assert L.knng_search_u8(f, 100, 8, f, 0, f, 3, f, 2, 5, 2, f, f, None, None) == E
 
+
+def test_leaf_search_noalloc_rejects_oversized_requests(L):
+    """The no-allocation leaf search computes its scratch need on the host and
+    rejects what does not fit its fixed array before any HIP call: here 8 trees
+    of 10^6 rows with k = 32 need 8 * 10^6 * 32 * 8 B of candidate lists."""
+    n, T, k = 1_000_000, 8, 32
+    nl = (ctypes.c_int32 * T)(*([n // 40] * T))
+    rc = L.knng_leaf_search_noalloc(ctypes.c_void_p(FAKE), n, 32, k, T, ctypes.c_void_p(FAKE),
+                                    ctypes.c_void_p(FAKE), nl, None, ctypes.c_void_p(FAKE),
+                                    ctypes.c_void_p(FAKE), None)
+    assert rc == knng.KNNG_ERR_UNSUPPORTED
+    assert b"scratch" in L.knng_last_error()
+    # an absurd tree count saturates instead of wrapping around
+    T2 = 1 << 20
+    nl2 = (ctypes.c_int32 * T2)(*([1] * T2))
+    rc = L.knng_leaf_search_noalloc(ctypes.c_void_p(FAKE), 1 << 30, 4096, 512, T2,
+                                    ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE), nl2, None,
+                                    ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE), None)
+    assert rc == knng.KNNG_ERR_UNSUPPORTED
