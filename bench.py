@@ -37,7 +37,7 @@ CSRC = os.path.join(ROOT, "paper_1701_08475_amd", "csrc")
 # sources of the assignment kernels: stored HBM counters are void once they change
 ASSIGN_SRCS = [os.path.join(CSRC, f) for f in ("partition.hip", "assign_mfma.hip")]
 # rows of the CPU oracle's bounded sample, per workload (about 10-30 s on 16 threads)
-CPU_SAMPLE = {"c1": 10_000, "c2": 500_000, "c3": 500_000, "c4": 40_000, "c5": 200_000}
+CPU_SAMPLE = {"c1": 10_000, "c2": 500_000, "c3": 500_000, "c4": 40_000, "c5": 800_000}
 DTYPE = {
     "u8": "bf16 exact first pass (integer data) / u8 rows, int8 MFMA + f64 two-means",
     "fp32": "fp32 leaves / f64 two-means margins and centroid sums",
@@ -528,7 +528,7 @@ def main():
     ap.add_argument("--precision", default=None, help="override the headline's leaf precision")
     ap.add_argument("--recall-rows", type=int, default=500)
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle rows (0: per workload)")
-    ap.add_argument("--cpu-sample-1t", type=int, default=20_000,
+    ap.add_argument("--cpu-sample-1t", type=int, default=50_000,
                     help="rows of the one-thread oracle timing (the paper's setting)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-recall", action="store_true")

@@ -676,6 +676,27 @@ double orc_dtilde(const float *X, int D, int fmt, int64_t i, int64_t j)
     return ni + nj - 2.0 * g;
 }
 
+/* First-pass distances d~(i, js[p]) for p < nj (R9), FP64, into out. */
+int orc_dtilde_row(const float *X, int D, int fmt, int64_t i, const int32_t *js, int64_t nj,
+                   double *out)
+{
+    double *qi = (double *)malloc(sizeof(double) * (size_t)D);
+    double *qj = (double *)malloc(sizeof(double) * (size_t)D);
+    if (!qi || !qj) { free(qi); free(qj); return -1; }
+    reduced_row(fmt, X + (size_t)i * D, D, qi);
+    double ni = 0.0;
+    for (int d = 0; d < D; ++d) ni += qi[d] * qi[d];
+    for (int64_t p = 0; p < nj; ++p) {
+        reduced_row(fmt, X + (size_t)js[p] * D, D, qj);
+        double nj2 = 0.0, g = 0.0;
+        for (int d = 0; d < D; ++d) nj2 += qj[d] * qj[d];
+        for (int d = 0; d < D; ++d) g += qi[d] * qj[d];
+        out[p] = ni + nj2 - 2.0 * g;
+    }
+    free(qi); free(qj);
+    return 0;
+}
+
 /* Rows `rows[q]` of orc_graph_from_leaves_reduced (same result restricted to
  * those rows), for n too large for the full graph.  thr (nullable, [nq][n_trees][2])
  * receives, per row and tree, the first-pass distances of the c-th and the

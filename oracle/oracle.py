@@ -62,6 +62,8 @@ def lib():
         L.orc_rows_from_leaves_reduced.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp, i32, i32,
                                                    vp, i64, vp, vp, vp]
         L.orc_dtilde.restype = ctypes.c_double
+        L.orc_dtilde_row.restype = i32
+        L.orc_dtilde_row.argtypes = [vp, i32, i32, i64, vp, i64, vp]
         L.orc_dtilde.argtypes = [vp, i32, i32, i64, i64]
         L.orc_round_fmt.restype = ctypes.c_double
         L.orc_round_fmt.argtypes = [ctypes.c_double, i32, i32]
@@ -287,6 +289,17 @@ def dtilde(X, fmt, i, j):
     """First-pass distance of the pair (i, j) under the reduced format (R9)."""
     X = _f32(X)
     return lib().orc_dtilde(_p(X), X.shape[1], FORMATS[fmt], int(i), int(j))
+
+
+def dtilde_row(X, fmt, i, js):
+    """First-pass distances of row i to the rows js under the reduced format
+    (R9), FP64 array."""
+    X = _f32(X)
+    js = np.ascontiguousarray(js, np.int32)
+    out = np.empty(len(js), np.float64)
+    rc = lib().orc_dtilde_row(_p(X), X.shape[1], FORMATS[fmt], int(i), _p(js), len(js), _p(out))
+    assert rc == 0
+    return out
 
 
 def graph(X, k, n_trees, leaf_max, seed, min_leaf=None, max_iter=10):
