@@ -31,7 +31,6 @@ def graph_parity(orc, X, rows, g_ids, g_d, o_ids, o_d, strict=False):
     g_d = np.asarray(g_d, np.float64)
     k = o_ids.shape[1]
     d_true = orc.pair_d64(X, rows, np.where(g_ids >= 0, g_ids, 0))
-    inv = inverse_perms(perms)
     same = 0
     for q, i in enumerate(rows):
         gi, oi = g_ids[q], o_ids[q]

@@ -208,3 +208,32 @@ def test_leaf_size_buckets_identical(K, orc, precision, n, D, k, L, kind, ml, mo
     b = _gpu_leaf_search(K, X, k, perms, offs, precision)
     assert np.array_equal(_np(a[0]), _np(b[0]))
     assert np.array_equal(_np(a[1]).view(np.int32), _np(b[1]).view(np.int32))
+
+
+@pytest.mark.parametrize("precision,n,D,k,L,rerank,kind", [
+    ("fp8", 8000, 96, 32, 500, 2, "unit"),      # 512-point tiles, c = 64
+    ("fp8", 6000, 36, 10, 300, 5, "unit"),      # D % 8 == 4, c = 50
+    ("fp16", 3000, 960, 20, 200, 2, "unit"),    # 256-point tiles, c = 40
+    ("bf16", 5000, 40, 16, 260, 4, "c1"),       # c = 64
+    ("fp8", 4000, 64, 64, 256, 1, "unit"),      # k = c = 64
+    ("fp16", 3000, 32, 8, 400, 8, "unit"),      # c = 64 with k = 8
+])
+def test_wide_leaf_kernel_equals_panel_kernel(K, orc, precision, n, D, k, L, rerank, kind,
+                                              monkeypatch):
+    """Leaves above 128 points with at most 64 candidates per row run the
+    wide kernel (batches of 64 rows, radix selection over each row's key
+    range, lane-per-candidate re-rank); its lists equal those of the panel
+    kernel (k_leaf_mfma) bit for bit: same first pass, same selection rule,
+    same d32 and order."""
+    if kind == "c1":
+        X = datagen.gmm_uniform(n, D, 20, -10, 10, 1.0, 23)
+    else:
+        X = datagen.gmm_unit(n, D, 16, 0.35, 24)
+    perms, offs = _oracle_leaves(orc, X, 2, L, k + 1, 9)
+    log("wide vs panel %s n=%d D=%d k=%d L=%d c=%d" % (precision, n, D, k, L, rerank * k))
+    monkeypatch.setenv("KNNG_LEAF_WIDE", "0")
+    a = _gpu_leaf_search(K, X, k, perms, offs, precision, rerank=rerank)
+    monkeypatch.setenv("KNNG_LEAF_WIDE", "1")
+    b = _gpu_leaf_search(K, X, k, perms, offs, precision, rerank=rerank)
+    assert np.array_equal(_np(a[0]), _np(b[0]))
+    assert np.array_equal(_np(a[1]).view(np.int32), _np(b[1]).view(np.int32))

@@ -62,3 +62,17 @@ def test_missing_sure_candidate_fails(orc, case):
     bad_ids[0], bad_d[0] = bad[order], d[order]
     with pytest.raises(AssertionError):
         reduced_parity(orc, X, "fp8", 10, 20, perms, offs, rows, bad_ids, bad_d)
+
+
+def test_graph_parity_accepts_the_oracle_graph(orc):
+    """The G1 checker of the FP32 path (tests/gpu_helpers.py: graph_parity)
+    accepts the oracle's own graph and rejects a row with a wrong id."""
+    from tests.gpu_helpers import graph_parity
+    X = datagen.make("c1", n=2000)
+    ids, ds, _ = orc.graph(X, 10, 2, 50, 1)
+    rows = np.arange(len(X))
+    assert graph_parity(orc, X, rows, ids, ds.astype(np.float32), ids, ds) == 1.0
+    bad = ids.copy()
+    bad[5, 0] = bad[5, -1]
+    with pytest.raises(AssertionError):
+        graph_parity(orc, X, rows, bad, ds.astype(np.float32), ids, ds)
