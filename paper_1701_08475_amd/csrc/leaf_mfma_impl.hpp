@@ -20,6 +20,7 @@
 #include "wave.hpp"
 
 #include <cstdio>
+#include <cstdlib>
 #include <type_traits>
 
 namespace knng {
@@ -421,6 +422,313 @@ __global__ __launch_bounds__(NW * 64) void k_leaf_mfma(
     }
 }
 
+// ------------------------------------------------------------- wide leaves
+// Leaves of up to MP (256 or 512) points with the re-ranked first pass, at
+// most 64 candidates per row (c <= 64, k <= 64), D % 4 == 0.  One
+// workgroup (4 wavefronts) per leaf, rows in batches of 64:
+//   1. per 16-row panel, the Gram of the panel against every column on MFMA
+//      (each wave takes MP/64 column tiles) gives d~ in LDS; then one wave
+//      per row selects its ce smallest (d~, position) exactly (radix
+//      selection over the row's key range, below) into the batch's
+//      candidate table;
+//   2. the batch's re-rank streams the leaf's FP32 rows through LDS in
+//      8-dimension chunks: one wave per row, lane j owns candidate j and
+//      accumulates d32 (in-block fused sum, blocks of 32 added in order);
+//   3. per row, the wave sorts its (d32, id) keys and writes the k smallest.
+// Same first-pass values (same MFMA steps in the same order), same
+// selection, same d32 and the same order as k_leaf_mfma: the lists are
+// identical bit for bit; this layout needs about a third of the LDS, so three
+// workgroups share a compute unit.
+//
+// Selection of the key of rank rem among the valid keys of a row (R per
+// lane): the keys lie in [lo, hi] (initially the row's minimum and maximum);
+// each pass counts them in 256 bins of width 2^shift over [lo, hi] (LDS
+// atomics), keeps the bin holding rank rem and narrows [lo, hi] to it.  It
+// stops when the kept bin's keys are all needed (then every key <= hi is
+// taken) or when the bin is a single value T (then the keys < T and the first
+// rem + 1 keys equal to T by position are taken).
+template <int R>
+__device__ __forceinline__ void wave_select_candidates(const uint32_t (&key)[R], int ce,
+                                                       uint32_t* hist, uint16_t* sel) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below_me = (1ull << lane) - 1ull;
+    uint32_t lo = 0xffffffffu, hi = 0u;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (key[r] != 0xffffffffu) {
+            lo = min(lo, key[r]);
+            hi = max(hi, key[r]);
+        }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        lo = min(lo, static_cast<uint32_t>(__shfl_xor(static_cast<int>(lo), o, kWave)));
+        hi = max(hi, static_cast<uint32_t>(__shfl_xor(static_cast<int>(hi), o, kWave)));
+    }
+    int rem = ce - 1;
+    bool single = false;  // [lo, hi] is the single value of the key of rank rem
+    while (true) {
+        const uint32_t span = hi - lo;
+        if (span == 0u) {
+            single = true;
+            break;
+        }
+        const int bits = 32 - __clz(static_cast<int>(span));
+        const int shift = bits > 8 ? bits - 8 : 0;
+        *reinterpret_cast<uint4*>(hist + 4 * lane) = make_uint4(0u, 0u, 0u, 0u);
+        wave_lds_sync();
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (key[r] >= lo && key[r] <= hi) atomicAdd(&hist[(key[r] - lo) >> shift], 1u);
+        wave_lds_sync();
+        const uint4 h4v = *reinterpret_cast<const uint4*>(hist + 4 * lane);
+        const int h4[4] = {static_cast<int>(h4v.x), static_cast<int>(h4v.y),
+                           static_cast<int>(h4v.z), static_cast<int>(h4v.w)};
+        const int local = h4[0] + h4[1] + h4[2] + h4[3];
+        int total;
+        const int excl = wave_excl_scan(local, &total);
+        int digit = 0, nrem = 0, cnt = 0;
+        const bool mine = excl <= rem && rem < excl + local;
+        if (mine) {
+            int cum = excl;
+            bool done = false;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (!done && rem < cum + h4[q]) {
+                    digit = 4 * lane + q;
+                    nrem = rem - cum;
+                    cnt = h4[q];
+                    done = true;
+                }
+                cum += h4[q];
+            }
+        }
+        const int src = static_cast<int>(__builtin_ctzll(__ballot(mine)));
+        digit = __shfl(digit, src, kWave);
+        nrem = __shfl(nrem, src, kWave);
+        cnt = __shfl(cnt, src, kWave);
+        wave_lds_sync();  // the histogram is read before the next pass clears it
+        const uint32_t lo2 = lo + (static_cast<uint32_t>(digit) << shift);
+        const uint32_t w = (shift == 0) ? 0u : ((1u << shift) - 1u);
+        const uint32_t hi2 = (hi - lo2 > w) ? lo2 + w : hi;
+        lo = lo2;
+        hi = hi2;
+        rem = nrem;
+        if (nrem == cnt - 1) break;  // every key of the bin is needed: take keys <= hi
+        if (shift == 0) {
+            single = true;
+            break;
+        }
+    }
+    // keys < lo (all needed), then either every key in [lo, hi] or, when the
+    // bin is the single value lo, the first rem + 1 keys equal to it
+    int taken = 0, eq_seen = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const bool lt = single ? key[r] < lo : key[r] <= hi;
+        const bool eq = single && key[r] == lo;
+        const unsigned long long beq = __ballot(eq);
+        const int eq_rank = eq_seen + __popcll(beq & below_me);
+        const bool take = lt || (eq && eq_rank <= rem);
+        const unsigned long long bt = __ballot(take);
+        if (take) sel[taken + __popcll(bt & below_me)] = static_cast<uint16_t>(r * kWave + lane);
+        taken += __popcll(bt);
+        eq_seen += __popcll(beq);
+    }
+}
+
+template <int FMT, int MP>
+__global__ __launch_bounds__(256) void k_leaf_wide(
+    const float* __restrict__ X, const uint8_t* __restrict__ Xr, int64_t n, int D, int Dp,
+    const float* __restrict__ nrm, const float* __restrict__ sinv, int k, int c,
+    const int32_t* __restrict__ perm, const LeafRec* __restrict__ leaves,
+    int32_t* __restrict__ cand_ids, float* __restrict__ cand_d,
+    unsigned long long* __restrict__ pairs) {
+    using F = Frag<FMT>;
+    constexpr int NW = 4, NTH = NW * kWave;
+    constexpr int R = MP / kWave;      // keys per lane in the selection
+    constexpr int NT = MP / 16;        // column tiles
+    constexpr int TPW = NT / NW;       // column tiles per wave
+    constexpr int RB = 64;             // rows per batch
+    constexpr int RPW = RB / NW;       // rows per wave in the re-rank
+    constexpr int CW = 8;              // dimensions per staged chunk
+    constexpr int SS = 12;             // floats per staged row (16-byte aligned)
+    constexpr int kPanel = 16 * (MP + 1);
+    constexpr int kStage = MP * SS;
+    constexpr int kRegion = kPanel > kStage ? kPanel : kStage;
+    static_assert(R >= 1 && TPW >= 1 && NT % NW == 0, "tile shape");
+
+    __shared__ __align__(16) float region[kRegion];  // d~ panel, later FP32 row chunks
+    __shared__ uint16_t csel[RB * kWave];            // per batch row its candidate positions
+    __shared__ int32_t ids[MP];
+    __shared__ float snrm[MP], ssinv[MP];
+    __shared__ __align__(16) uint32_t s_hist[NW * 256];
+    float(*dist)[MP + 1] = reinterpret_cast<float(*)[MP + 1]>(region);
+
+    const LeafRec lf = leaves[blockIdx.x];
+    const int m = lf.size;
+    const size_t base = static_cast<size_t>(lf.tree) * n + lf.start;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    load_leaf_sorted<MP, NTH>(perm + base, m, reinterpret_cast<int32_t*>(region), ids, snrm, ssinv,
+                              nrm, sinv);
+    if (tid == 0 && pairs != nullptr)
+        stat_add(pairs, blockIdx.x, static_cast<unsigned long long>(m) * static_cast<unsigned long long>(m - 1));
+    __syncthreads();
+    const int ce = c < m - 1 ? c : m - 1;  // candidates per row
+    const size_t rstride = static_cast<size_t>(Dp) * F::kBytes;
+    const int kg = lane >> 4;
+
+    for (int p0 = 0; p0 < m; p0 += RB) {
+        const int nb = m - p0 < RB ? m - p0 : RB;
+        __syncthreads();  // the previous batch's last chunk is no longer read
+        // ---- selection, one 16-row panel at a time
+        for (int pp = 0; pp < nb; pp += 16) {
+            const int prow = p0 + pp;
+            const int arow = prow + (lane & 15);
+            const uint8_t* ap = Xr + static_cast<size_t>(ids[arow < m ? arow : 0]) * rstride +
+                                static_cast<size_t>(8 * kg) * F::kBytes;
+            const uint8_t* bp[TPW];
+            bool bok[TPW];
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) {
+                const int bcol = (wv * TPW + t) * 16 + (lane & 15);
+                bok[t] = bcol < m;
+                bp[t] = Xr + static_cast<size_t>(ids[bcol < m ? bcol : 0]) * rstride +
+                        static_cast<size_t>(8 * kg) * F::kBytes;
+            }
+            f32x4 acc[TPW];
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+            FragVec<FMT> a = load_frag<FMT>(ap, arow < m);
+            FragVec<FMT> b[TPW];
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) b[t] = load_frag<FMT>(bp[t], bok[t]);
+            for (int k0 = 0; k0 < Dp; k0 += 32) {
+                const size_t nx = static_cast<size_t>(k0 + 32) * F::kBytes;
+                const bool more = k0 + 32 < Dp;
+                const FragVec<FMT> an = load_frag<FMT>(ap + nx, more && arow < m);
+                FragVec<FMT> bn[TPW];
+#pragma unroll
+                for (int t = 0; t < TPW; ++t) bn[t] = load_frag<FMT>(bp[t] + nx, more && bok[t]);
+#pragma unroll
+                for (int t = 0; t < TPW; ++t) acc[t] = F::mma(a, b[t], acc[t]);
+                a = an;
+#pragma unroll
+                for (int t = 0; t < TPW; ++t) b[t] = bn[t];
+            }
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) {
+                const int col = (wv * TPW + t) * 16 + (lane & 15);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int rl = 4 * kg + i;
+                    const int row = prow + rl;
+                    float v = __int_as_float(0x7f800000);
+                    if (row < m && col < m)
+                        v = snrm[row] + snrm[col] - 2.f * acc[t][i] * (ssinv[row] * ssinv[col]);
+                    dist[rl][col] = v;
+                }
+            }
+            __syncthreads();
+            const int prows = nb - pp < 16 ? nb - pp : 16;
+            for (int rl = wv; rl < prows; rl += NW) {
+                const int row = prow + rl;
+                uint16_t* sel = csel + (pp + rl) * kWave;
+                if (ce >= m - 1) {  // every other member is a candidate
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const int col = r * kWave + lane;
+                        const int e = col < row ? col : col - 1;
+                        if (col < m && col != row) sel[e] = static_cast<uint16_t>(col);
+                    }
+                } else if (ce > 0) {
+                    uint32_t key[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const int col = r * kWave + lane;
+                        key[r] = (col < m && col != row) ? fkey(dist[rl][col]) : 0xffffffffu;
+                    }
+                    wave_select_candidates<R>(key, ce, s_hist + wv * 256, sel);
+                }
+            }
+            __syncthreads();  // the panel is no longer read
+        }
+        // ---- re-rank of the batch: d32 from LDS-staged 8-dimension chunks
+        float tot[RPW], blk[RPW];
+        int cpos[RPW];
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) {
+            tot[q] = 0.f;
+            blk[q] = 0.f;
+            const int bi = wv + NW * q;
+            cpos[q] = (bi < nb && lane < ce) ? static_cast<int>(csel[bi * kWave + lane]) : 0;
+        }
+        for (int d0 = 0; d0 < D; d0 += CW) {
+            __syncthreads();  // the previous chunk (or the panel) is no longer read
+            for (int idx = tid; idx < 2 * m; idx += NTH) {
+                const int j = idx >> 1, hf = idx & 1;
+                const int d = d0 + 4 * hf;
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (d < D) v = *reinterpret_cast<const float4*>(X + static_cast<size_t>(ids[j]) * D + d);
+                *reinterpret_cast<float4*>(region + j * SS + 4 * hf) = v;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < RPW; ++q) {
+                const int bi = wv + NW * q;
+                if (bi < nb) {  // uniform across the wave
+                    const float* xo = region + (p0 + bi) * SS;
+                    const float* xc = region + cpos[q] * SS;
+                    const float4 o0 = *reinterpret_cast<const float4*>(xo);
+                    const float4 o1 = *reinterpret_cast<const float4*>(xo + 4);
+                    const float4 c0 = *reinterpret_cast<const float4*>(xc);
+                    const float4 c1 = *reinterpret_cast<const float4*>(xc + 4);
+                    float bq = blk[q];  // padding past D adds exact zeros
+                    float df = o0.x - c0.x;
+                    bq = __fmaf_rn(df, df, bq);
+                    df = o0.y - c0.y;
+                    bq = __fmaf_rn(df, df, bq);
+                    df = o0.z - c0.z;
+                    bq = __fmaf_rn(df, df, bq);
+                    df = o0.w - c0.w;
+                    bq = __fmaf_rn(df, df, bq);
+                    df = o1.x - c1.x;
+                    bq = __fmaf_rn(df, df, bq);
+                    df = o1.y - c1.y;
+                    bq = __fmaf_rn(df, df, bq);
+                    df = o1.z - c1.z;
+                    bq = __fmaf_rn(df, df, bq);
+                    df = o1.w - c1.w;
+                    bq = __fmaf_rn(df, df, bq);
+                    blk[q] = bq;
+                }
+            }
+            if (((d0 + CW) & 31) == 0 || d0 + CW >= D) {  // end of a 32-dimension block
+#pragma unroll
+                for (int q = 0; q < RPW; ++q) {
+                    tot[q] = tot[q] + blk[q];
+                    blk[q] = 0.f;
+                }
+            }
+        }
+        // ---- per row: the k smallest (d32, id), in order
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) {
+            const int bi = wv + NW * q;
+            if (bi < nb) {
+                uint64_t v[1];
+                v[0] = lane < ce ? cand_key(tot[q], ids[cpos[q]]) : kNoKey;
+                wave_bitonic_sort<1>(v);
+                const size_t out = (static_cast<size_t>(lf.tree) * n + ids[p0 + bi]) * k;
+                if (lane < k) {
+                    const bool ok = v[0] != kNoKey;
+                    cand_ids[out + lane] = ok ? key_id(v[0]) : -1;
+                    cand_d[out + lane] = ok ? key_dist(v[0]) : __int_as_float(0x7f800000);
+                }
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------- small leaves
 // Leaves of at most MP (64, 112 or 128) points.  The Gram on MFMA fills the
 // whole leaf's block of keys in LDS; then thread t owns row t and scans it
@@ -767,6 +1075,15 @@ int launch_fmt(const LeafArgs& a, const ReducedRows& rr, int* launches, char* er
             return go(k_leaf_mfma<FMT, MP, PR, CS, 64, false, NW>, TH);
         }
     };
+    // leaves above 128 points with at most 64 candidates per row: the wide
+    // kernel (KNNG_LEAF_WIDE=0 keeps k_leaf_mfma)
+    const char* wide_env = std::getenv("KNNG_LEAF_WIDE");
+    const bool wide = !EXACT && lm > 128 && c <= 64 && a.D % 4 == 0 &&
+                      (wide_env == nullptr || std::atoi(wide_env) != 0);
+    if (wide) {
+        if (lm <= 256) return go(k_leaf_wide<FMT, 256>);
+        return go(k_leaf_wide<FMT, 512>);
+    }
     using I4 = std::integral_constant<int, 4>;
     using I8 = std::integral_constant<int, 8>;
     using I32 = std::integral_constant<int, 32>;
