@@ -99,6 +99,19 @@ __device__ __forceinline__ void load_leaf_sorted(const int32_t* __restrict__ lp,
         ssinv[j] = 0.f;
     }
     __syncthreads();
+    // the clusters of the partition list their ids in ascending order: then
+    // the rank of entry j is j
+    int unsorted = 0;
+    for (int j = tid + 1; j < m; j += NT) unsorted |= raw[j - 1] < raw[j] ? 0 : 1;
+    if (!__syncthreads_or(unsorted)) {
+        for (int j = tid; j < m; j += NT) {
+            const int32_t id = raw[j];
+            ids[j] = id;
+            snrm[j] = nrm[id];
+            ssinv[j] = sinv[id];
+        }
+        return;
+    }
     for (int j = tid; j < m; j += NT) {
         const int32_t id = raw[j];
         int r = 0;
@@ -424,115 +437,209 @@ __global__ __launch_bounds__(NW * 64) void k_leaf_mfma(
 
 // ------------------------------------------------------------- wide leaves
 // Leaves of up to MP (256 or 512) points with the re-ranked first pass, at
-// most 64 candidates per row (c <= 64, k <= 64), D % 4 == 0.  One
-// workgroup (4 wavefronts) per leaf, rows in batches of 64:
+// most 64 candidates per row (c <= 64, k <= 64), D % 4 == 0.  One workgroup
+// (4 wavefronts) per leaf, rows in batches of 64.  After the MFMA Gram, every
+// step works on 16-lane groups, one row per group, four rows per wavefront:
 //   1. per 16-row panel, the Gram of the panel against every column on MFMA
-//      (each wave takes MP/64 column tiles) gives d~ in LDS; then one wave
-//      per row selects its ce smallest (d~, position) exactly (radix
-//      selection over the row's key range, below) into the batch's
-//      candidate table;
+//      (each wave takes MP/64 column tiles) gives d~ in LDS; each 16-lane
+//      group then selects its row's ce smallest (d~, position) exactly
+//      (group_select) into the batch's candidate table;
 //   2. the batch's re-rank streams the leaf's FP32 rows through LDS in
-//      8-dimension chunks: one wave per row, lane j owns candidate j and
-//      accumulates d32 (in-block fused sum, blocks of 32 added in order);
-//   3. per row, the wave sorts its (d32, id) keys and writes the k smallest.
+//      8-dimension chunks (the next chunk's loads in flight during this
+//      one); lane l of a row's group owns its candidates l, l+16, l+32, l+48
+//      and accumulates their d32 (in-block fused sum, blocks of 32 added in
+//      order);
+//   3. each group sorts its row's 64 (d32, id) keys (group_sort64, four per
+//      lane) and writes the k smallest.
 // Same first-pass values (same MFMA steps in the same order), same
 // selection, same d32 and the same order as k_leaf_mfma: the lists are
-// identical bit for bit; this layout needs about a third of the LDS, so three
-// workgroups share a compute unit.
-//
-// Selection of the key of rank rem among the valid keys of a row (R per
-// lane): the keys lie in [lo, hi] (initially the row's minimum and maximum);
-// each pass counts them in 256 bins of width 2^shift over [lo, hi] (LDS
-// atomics), keeps the bin holding rank rem and narrows [lo, hi] to it.  It
-// stops when the kept bin's keys are all needed (then every key <= hi is
+// identical bit for bit.  51 KB of LDS and about 200 registers per lane: two
+// workgroups per compute unit.
+
+// Minimum / maximum over the 16 lanes of each aligned group (quad exchanges,
+// then mirrors within 8 and within 16 lanes: every lane gets the result).
+__device__ __forceinline__ uint32_t group16_min(uint32_t v) {
+    v = min(v, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0xB1, 0xf, 0xf, false)));
+    v = min(v, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x4E, 0xf, 0xf, false)));
+    v = min(v, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x141, 0xf, 0xf, false)));
+    v = min(v, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x140, 0xf, 0xf, false)));
+    return v;
+}
+__device__ __forceinline__ uint32_t group16_max(uint32_t v) {
+    v = max(v, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0xB1, 0xf, 0xf, false)));
+    v = max(v, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x4E, 0xf, 0xf, false)));
+    v = max(v, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x141, 0xf, 0xf, false)));
+    v = max(v, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x140, 0xf, 0xf, false)));
+    return v;
+}
+
+// Selection, per 16-lane group (one row each; the row's keys krow[0..16 KT) in
+// LDS, invalid ones ~0; lane l reads keys t*16 + l), of the row's ce smallest
+// valid keys by (key, position).  lo, hi: the minimum and maximum of the
+// lane's valid keys.  The keys of rank < ce lie in [lo, hi] (initially the
+// row's minimum and maximum); each pass counts them in 128 bins of width
+// 2^shift over [lo, hi] and narrows [lo, hi] to the bin holding rank rem.  A
+// row stops when its kept bin's keys are all needed (then every key <= hi is
 // taken) or when the bin is a single value T (then the keys < T and the first
-// rem + 1 keys equal to T by position are taken).
-template <int R>
-__device__ __forceinline__ void wave_select_candidates(const uint32_t (&key)[R], int ce,
-                                                       uint32_t* hist, uint16_t* sel) {
+// rem + 1 keys equal to T by position are taken).  hist: 256 words per
+// wave; groups 0 and 1 count in the low and high 16 bits of words 0..127,
+// groups 2 and 3 in words 128..255 (at most 512 keys per row).  act: this
+// group's row exists (uniform within the group).  Candidate positions go to
+// sel[0..ce) of the group's row.
+template <int KT>
+__device__ __forceinline__ void group_select(const uint32_t* krow, uint32_t lo, uint32_t hi,
+                                             bool act, int ce, uint32_t* hist, uint16_t* sel) {
     const int lane = threadIdx.x & 63;
-    const unsigned long long below_me = (1ull << lane) - 1ull;
-    uint32_t lo = 0xffffffffu, hi = 0u;
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-        if (key[r] != 0xffffffffu) {
-            lo = min(lo, key[r]);
-            hi = max(hi, key[r]);
-        }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        lo = min(lo, static_cast<uint32_t>(__shfl_xor(static_cast<int>(lo), o, kWave)));
-        hi = max(hi, static_cast<uint32_t>(__shfl_xor(static_cast<int>(hi), o, kWave)));
-    }
+    const int gq = lane >> 4, gl = lane & 15;
+    const uint32_t gmask_below = (1u << gl) - 1u;
+    lo = group16_min(lo);
+    hi = group16_max(hi);
     int rem = ce - 1;
-    bool single = false;  // [lo, hi] is the single value of the key of rank rem
-    while (true) {
-        const uint32_t span = hi - lo;
-        if (span == 0u) {
+    bool single = false;
+    bool done = !act;
+    uint32_t* h = hist + (gq >> 1) * 128;
+    const uint32_t inc = (gq & 1) ? 65536u : 1u;
+    const int hsh = (gq & 1) ? 16 : 0;
+    while (__any(!done)) {
+        int shift = 0;
+        if (!done && hi == lo) {
             single = true;
-            break;
+            done = true;
         }
-        const int bits = 32 - __clz(static_cast<int>(span));
-        const int shift = bits > 8 ? bits - 8 : 0;
+        if (!done) {
+            const int bits = 32 - __clz(static_cast<int>(hi - lo));
+            shift = bits > 7 ? bits - 7 : 0;
+        }
         *reinterpret_cast<uint4*>(hist + 4 * lane) = make_uint4(0u, 0u, 0u, 0u);
         wave_lds_sync();
+        if (!done) {
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-            if (key[r] >= lo && key[r] <= hi) atomicAdd(&hist[(key[r] - lo) >> shift], 1u);
-        wave_lds_sync();
-        const uint4 h4v = *reinterpret_cast<const uint4*>(hist + 4 * lane);
-        const int h4[4] = {static_cast<int>(h4v.x), static_cast<int>(h4v.y),
-                           static_cast<int>(h4v.z), static_cast<int>(h4v.w)};
-        const int local = h4[0] + h4[1] + h4[2] + h4[3];
-        int total;
-        const int excl = wave_excl_scan(local, &total);
-        int digit = 0, nrem = 0, cnt = 0;
-        const bool mine = excl <= rem && rem < excl + local;
-        if (mine) {
-            int cum = excl;
-            bool done = false;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (!done && rem < cum + h4[q]) {
-                    digit = 4 * lane + q;
-                    nrem = rem - cum;
-                    cnt = h4[q];
-                    done = true;
-                }
-                cum += h4[q];
+            for (int t = 0; t < KT; ++t) {
+                const uint32_t kt = krow[t * 16 + gl];
+                if (kt >= lo && kt <= hi) atomicAdd(&h[(kt - lo) >> shift], inc);
             }
         }
-        const int src = static_cast<int>(__builtin_ctzll(__ballot(mine)));
+        wave_lds_sync();
+        // lane l of the group reads bins 8l .. 8l+7 of its row
+        const uint4 wa = *reinterpret_cast<const uint4*>(h + 8 * gl);
+        const uint4 wb = *reinterpret_cast<const uint4*>(h + 8 * gl + 4);
+        wave_lds_sync();  // read before the next pass clears it
+        const int cb[8] = {static_cast<int>((wa.x >> hsh) & 0xffffu), static_cast<int>((wa.y >> hsh) & 0xffffu),
+                           static_cast<int>((wa.z >> hsh) & 0xffffu), static_cast<int>((wa.w >> hsh) & 0xffffu),
+                           static_cast<int>((wb.x >> hsh) & 0xffffu), static_cast<int>((wb.y >> hsh) & 0xffffu),
+                           static_cast<int>((wb.z >> hsh) & 0xffffu), static_cast<int>((wb.w >> hsh) & 0xffffu)};
+        int local = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) local += cb[q];
+        // exclusive scan over the 16 lanes of the group
+        int incl = local;
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            const int y = __shfl_up(incl, o, 16);
+            if (gl >= o) incl += y;
+        }
+        const int excl = incl - local;
+        const bool mine = !done && excl <= rem && rem < incl;
+        int digit = 0, nrem = 0, cnt = 0;
+        if (mine) {
+            int cum = excl;
+            bool got = false;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (!got && rem < cum + cb[q]) {
+                    digit = 8 * gl + q;
+                    nrem = rem - cum;
+                    cnt = cb[q];
+                    got = true;
+                }
+                cum += cb[q];
+            }
+        }
+        const uint32_t gb = static_cast<uint32_t>(__ballot(mine) >> (16 * gq)) & 0xffffu;
+        const int src = 16 * gq + (gb ? __builtin_ctz(gb) : 0);
         digit = __shfl(digit, src, kWave);
         nrem = __shfl(nrem, src, kWave);
         cnt = __shfl(cnt, src, kWave);
-        wave_lds_sync();  // the histogram is read before the next pass clears it
-        const uint32_t lo2 = lo + (static_cast<uint32_t>(digit) << shift);
-        const uint32_t w = (shift == 0) ? 0u : ((1u << shift) - 1u);
-        const uint32_t hi2 = (hi - lo2 > w) ? lo2 + w : hi;
-        lo = lo2;
-        hi = hi2;
-        rem = nrem;
-        if (nrem == cnt - 1) break;  // every key of the bin is needed: take keys <= hi
-        if (shift == 0) {
-            single = true;
-            break;
+        if (!done) {
+            const uint32_t lo2 = lo + (static_cast<uint32_t>(digit) << shift);
+            const uint32_t w = shift == 0 ? 0u : ((1u << shift) - 1u);
+            hi = (hi - lo2 > w) ? lo2 + w : hi;
+            lo = lo2;
+            rem = nrem;
+            if (nrem == cnt - 1) {
+                done = true;  // every key of the bin is needed: take keys <= hi
+            } else if (shift == 0) {
+                single = true;
+                done = true;
+            }
         }
     }
     // keys < lo (all needed), then either every key in [lo, hi] or, when the
-    // bin is the single value lo, the first rem + 1 keys equal to it
+    // bin is the single value lo, the first rem + 1 keys equal to it; in
+    // position order (t, lane)
     int taken = 0, eq_seen = 0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const bool lt = single ? key[r] < lo : key[r] <= hi;
-        const bool eq = single && key[r] == lo;
-        const unsigned long long beq = __ballot(eq);
-        const int eq_rank = eq_seen + __popcll(beq & below_me);
+    for (int t = 0; t < KT; ++t) {
+        const uint32_t kt = krow[t * 16 + gl];
+        const bool lt = act && (single ? kt < lo : kt <= hi);
+        const bool eq = act && single && kt == lo;
+        const uint32_t beq = static_cast<uint32_t>(__ballot(eq) >> (16 * gq)) & 0xffffu;
+        const int eq_rank = eq_seen + __popc(beq & gmask_below);
         const bool take = lt || (eq && eq_rank <= rem);
-        const unsigned long long bt = __ballot(take);
-        if (take) sel[taken + __popcll(bt & below_me)] = static_cast<uint16_t>(r * kWave + lane);
-        taken += __popcll(bt);
-        eq_seen += __popcll(beq);
+        const uint32_t bt = static_cast<uint32_t>(__ballot(take) >> (16 * gq)) & 0xffffu;
+        if (take) sel[taken + __popc(bt & gmask_below)] = static_cast<uint16_t>(t * 16 + gl);
+        taken += __popc(bt);
+        eq_seen += __popc(beq);
+    }
+}
+
+// Ascending bitonic sort of NR independent rows of 64 keys per 16-lane group,
+// four keys per lane: element e of a row is lane (e >> 2) of the group,
+// register e & 3.  Distances 1 and 2 stay in registers; the others exchange
+// with lane xor (distance / 4), inside the group.  The NR rows' stages are
+// interleaved.
+template <int NR>
+__device__ __forceinline__ void group_sort64(uint64_t (&v)[NR][4]) {
+    const int gl = threadIdx.x & 15;
+#pragma unroll
+    for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
+        for (int j = size >> 1; j >= 1; j >>= 1) {
+            if (j >= 4) {
+                const int lm = j >> 2;
+                uint64_t o[NR][4];
+#pragma unroll
+                for (int q = 0; q < NR; ++q)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) o[q][r] = shfl_xor_u64(v[q][r], lm);
+                const bool lower = (gl & lm) == 0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int e = gl * 4 + r;
+                    const bool take_min = ((e & size) == 0) == lower;
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) {
+                        const bool lt = v[q][r] < o[q][r];
+                        v[q][r] = (take_min == lt) ? v[q][r] : o[q][r];
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int p = r ^ j;
+                    if (p > r) {
+                        const bool up = ((gl * 4 + r) & size) == 0;
+#pragma unroll
+                        for (int q = 0; q < NR; ++q) {
+                            const uint64_t a = v[q][r], b = v[q][p];
+                            const bool sw = up ? (a > b) : (a < b);
+                            v[q][r] = sw ? b : a;
+                            v[q][p] = sw ? a : b;
+                        }
+                    }
+                }
+            }
+        }
     }
 }
 
@@ -545,17 +652,16 @@ __global__ __launch_bounds__(256) void k_leaf_wide(
     unsigned long long* __restrict__ pairs) {
     using F = Frag<FMT>;
     constexpr int NW = 4, NTH = NW * kWave;
-    constexpr int R = MP / kWave;      // keys per lane in the selection
-    constexpr int NT = MP / 16;        // column tiles
-    constexpr int TPW = NT / NW;       // column tiles per wave
+    constexpr int KT = MP / 16;        // keys per lane in the selection (= column tiles)
+    constexpr int TPW = KT / NW;       // column tiles per wave in the Gram
     constexpr int RB = 64;             // rows per batch
-    constexpr int RPW = RB / NW;       // rows per wave in the re-rank
     constexpr int CW = 8;              // dimensions per staged chunk
     constexpr int SS = 12;             // floats per staged row (16-byte aligned)
+    constexpr int PF = (2 * MP + NTH - 1) / NTH;  // staged float4 per thread
     constexpr int kPanel = 16 * (MP + 1);
     constexpr int kStage = MP * SS;
     constexpr int kRegion = kPanel > kStage ? kPanel : kStage;
-    static_assert(R >= 1 && TPW >= 1 && NT % NW == 0, "tile shape");
+    static_assert(TPW >= 1 && KT % NW == 0, "tile shape");
 
     __shared__ __align__(16) float region[kRegion];  // d~ panel, later FP32 row chunks
     __shared__ uint16_t csel[RB * kWave];            // per batch row its candidate positions
@@ -568,6 +674,7 @@ __global__ __launch_bounds__(256) void k_leaf_wide(
     const int m = lf.size;
     const size_t base = static_cast<size_t>(lf.tree) * n + lf.start;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int gq = lane >> 4, gl = lane & 15;
     load_leaf_sorted<MP, NTH>(perm + base, m, reinterpret_cast<int32_t*>(region), ids, snrm, ssinv,
                               nrm, sinv);
     if (tid == 0 && pairs != nullptr)
@@ -577,112 +684,152 @@ __global__ __launch_bounds__(256) void k_leaf_wide(
     const size_t rstride = static_cast<size_t>(Dp) * F::kBytes;
     const int kg = lane >> 4;
 
+    // this thread's share of an 8-dimension chunk of the leaf's FP32 rows
+    auto fetch = [&](int d0, float4 (&pf)[PF]) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int idx = tid + u * NTH;
+            const int j = idx >> 1, d = d0 + 4 * (idx & 1);
+            pf[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (j < m && d < D) pf[u] = *reinterpret_cast<const float4*>(X + static_cast<size_t>(ids[j]) * D + d);
+        }
+    };
+
     for (int p0 = 0; p0 < m; p0 += RB) {
         const int nb = m - p0 < RB ? m - p0 : RB;
         __syncthreads();  // the previous batch's last chunk is no longer read
         // ---- selection, one 16-row panel at a time
         for (int pp = 0; pp < nb; pp += 16) {
             const int prow = p0 + pp;
-            const int arow = prow + (lane & 15);
-            const uint8_t* ap = Xr + static_cast<size_t>(ids[arow < m ? arow : 0]) * rstride +
-                                static_cast<size_t>(8 * kg) * F::kBytes;
-            const uint8_t* bp[TPW];
-            bool bok[TPW];
+            // Gram of the panel, in groups of GT column tiles per wave
+            constexpr int GT = TPW < 4 ? TPW : 4;
 #pragma unroll
-            for (int t = 0; t < TPW; ++t) {
-                const int bcol = (wv * TPW + t) * 16 + (lane & 15);
-                bok[t] = bcol < m;
-                bp[t] = Xr + static_cast<size_t>(ids[bcol < m ? bcol : 0]) * rstride +
-                        static_cast<size_t>(8 * kg) * F::kBytes;
-            }
-            f32x4 acc[TPW];
+            for (int tg = 0; tg < TPW; tg += GT) {
+                const int arow = prow + (lane & 15);
+                const uint8_t* ap = Xr + static_cast<size_t>(ids[arow < m ? arow : 0]) * rstride +
+                                    static_cast<size_t>(8 * kg) * F::kBytes;
+                const uint8_t* bp[GT];
+                bool bok[GT];
 #pragma unroll
-            for (int t = 0; t < TPW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-            FragVec<FMT> a = load_frag<FMT>(ap, arow < m);
-            FragVec<FMT> b[TPW];
+                for (int t = 0; t < GT; ++t) {
+                    const int bcol = (wv * TPW + tg + t) * 16 + (lane & 15);
+                    bok[t] = bcol < m;
+                    bp[t] = Xr + static_cast<size_t>(ids[bcol < m ? bcol : 0]) * rstride +
+                            static_cast<size_t>(8 * kg) * F::kBytes;
+                }
+                f32x4 acc[GT];
 #pragma unroll
-            for (int t = 0; t < TPW; ++t) b[t] = load_frag<FMT>(bp[t], bok[t]);
-            for (int k0 = 0; k0 < Dp; k0 += 32) {
-                const size_t nx = static_cast<size_t>(k0 + 32) * F::kBytes;
-                const bool more = k0 + 32 < Dp;
-                const FragVec<FMT> an = load_frag<FMT>(ap + nx, more && arow < m);
-                FragVec<FMT> bn[TPW];
+                for (int t = 0; t < GT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+                FragVec<FMT> a = load_frag<FMT>(ap, arow < m);
+                FragVec<FMT> b[GT];
 #pragma unroll
-                for (int t = 0; t < TPW; ++t) bn[t] = load_frag<FMT>(bp[t] + nx, more && bok[t]);
+                for (int t = 0; t < GT; ++t) b[t] = load_frag<FMT>(bp[t], bok[t]);
+                for (int k0 = 0; k0 < Dp; k0 += 32) {
+                    const size_t nx = static_cast<size_t>(k0 + 32) * F::kBytes;
+                    const bool more = k0 + 32 < Dp;
+                    const FragVec<FMT> an = load_frag<FMT>(ap + nx, more && arow < m);
+                    FragVec<FMT> bn[GT];
 #pragma unroll
-                for (int t = 0; t < TPW; ++t) acc[t] = F::mma(a, b[t], acc[t]);
-                a = an;
+                    for (int t = 0; t < GT; ++t) bn[t] = load_frag<FMT>(bp[t] + nx, more && bok[t]);
 #pragma unroll
-                for (int t = 0; t < TPW; ++t) b[t] = bn[t];
-            }
+                    for (int t = 0; t < GT; ++t) acc[t] = F::mma(a, b[t], acc[t]);
+                    a = an;
 #pragma unroll
-            for (int t = 0; t < TPW; ++t) {
-                const int col = (wv * TPW + t) * 16 + (lane & 15);
+                    for (int t = 0; t < GT; ++t) b[t] = bn[t];
+                }
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int rl = 4 * kg + i;
-                    const int row = prow + rl;
-                    float v = __int_as_float(0x7f800000);
-                    if (row < m && col < m)
-                        v = snrm[row] + snrm[col] - 2.f * acc[t][i] * (ssinv[row] * ssinv[col]);
-                    dist[rl][col] = v;
+                for (int t = 0; t < GT; ++t) {
+                    const int col = (wv * TPW + tg + t) * 16 + (lane & 15);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int rl = 4 * kg + i;
+                        const int row = prow + rl;
+                        float v = __int_as_float(0x7f800000);
+                        if (row < m && col < m)
+                            v = snrm[row] + snrm[col] - 2.f * acc[t][i] * (ssinv[row] * ssinv[col]);
+                        dist[rl][col] = v;
+                    }
                 }
             }
             __syncthreads();
-            const int prows = nb - pp < 16 ? nb - pp : 16;
-            for (int rl = wv; rl < prows; rl += NW) {
+            {
+                // group gq of wave wv: panel row 4 wv + gq
+                const int rl = 4 * wv + gq;
                 const int row = prow + rl;
-                uint16_t* sel = csel + (pp + rl) * kWave;
+                const bool act = rl < nb - pp;
+                uint16_t* sel = csel + (pp + (act ? rl : 0)) * kWave;
                 if (ce >= m - 1) {  // every other member is a candidate
+                    if (act) {
 #pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const int col = r * kWave + lane;
-                        const int e = col < row ? col : col - 1;
-                        if (col < m && col != row) sel[e] = static_cast<uint16_t>(col);
+                        for (int t = 0; t < KT; ++t) {
+                            const int col = t * 16 + gl;
+                            const int e = col < row ? col : col - 1;
+                            if (col < m && col != row) sel[e] = static_cast<uint16_t>(col);
+                        }
                     }
                 } else if (ce > 0) {
-                    uint32_t key[R];
+                    // the row's d~ become order keys in place (invalid: ~0)
+                    uint32_t* krow = reinterpret_cast<uint32_t*>(dist[act ? rl : 0]);
+                    uint32_t lo = 0xffffffffu, hi = 0u;
+                    if (act) {
 #pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const int col = r * kWave + lane;
-                        key[r] = (col < m && col != row) ? fkey(dist[rl][col]) : 0xffffffffu;
+                        for (int t = 0; t < KT; ++t) {
+                            const int col = t * 16 + gl;
+                            const uint32_t kt = (col < m && col != row) ? fkey(dist[rl][col])
+                                                                        : 0xffffffffu;
+                            krow[col] = kt;
+                            if (kt != 0xffffffffu) {
+                                lo = min(lo, kt);
+                                hi = max(hi, kt);
+                            }
+                        }
                     }
-                    wave_select_candidates<R>(key, ce, s_hist + wv * 256, sel);
+                    wave_lds_sync();
+                    group_select<KT>(krow, lo, hi, act, ce, s_hist + wv * 256, sel);
                 }
             }
             __syncthreads();  // the panel is no longer read
         }
-        // ---- re-rank of the batch: d32 from LDS-staged 8-dimension chunks
-        float tot[RPW], blk[RPW];
-        int cpos[RPW];
+        // ---- re-rank of the batch: d32 from LDS-staged 8-dimension chunks;
+        // the next chunk's loads are in flight while this one is computed.
+        // Wave wv, quad qq, group gq: batch row 16 wv + 4 qq + gq; lane gl
+        // owns candidates gl + 16 u.
+        float tot[4][4], blk[4][4];
+        int cpos[4][4];
 #pragma unroll
-        for (int q = 0; q < RPW; ++q) {
-            tot[q] = 0.f;
-            blk[q] = 0.f;
-            const int bi = wv + NW * q;
-            cpos[q] = (bi < nb && lane < ce) ? static_cast<int>(csel[bi * kWave + lane]) : 0;
+        for (int qq = 0; qq < 4; ++qq) {
+            const int bi = 16 * wv + 4 * qq + gq;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                tot[qq][u] = 0.f;
+                blk[qq][u] = 0.f;
+                const int e = gl + 16 * u;
+                cpos[qq][u] = (bi < nb && e < ce) ? static_cast<int>(csel[bi * kWave + e]) : 0;
+            }
         }
+        float4 pf[PF];
+        fetch(0, pf);
         for (int d0 = 0; d0 < D; d0 += CW) {
             __syncthreads();  // the previous chunk (or the panel) is no longer read
-            for (int idx = tid; idx < 2 * m; idx += NTH) {
-                const int j = idx >> 1, hf = idx & 1;
-                const int d = d0 + 4 * hf;
-                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (d < D) v = *reinterpret_cast<const float4*>(X + static_cast<size_t>(ids[j]) * D + d);
-                *reinterpret_cast<float4*>(region + j * SS + 4 * hf) = v;
+#pragma unroll
+            for (int u = 0; u < PF; ++u) {
+                const int idx = tid + u * NTH;
+                if ((idx >> 1) < m) *reinterpret_cast<float4*>(region + (idx >> 1) * SS + 4 * (idx & 1)) = pf[u];
             }
             __syncthreads();
+            if (d0 + CW < D) fetch(d0 + CW, pf);
 #pragma unroll
-            for (int q = 0; q < RPW; ++q) {
-                const int bi = wv + NW * q;
-                if (bi < nb) {  // uniform across the wave
-                    const float* xo = region + (p0 + bi) * SS;
-                    const float* xc = region + cpos[q] * SS;
-                    const float4 o0 = *reinterpret_cast<const float4*>(xo);
-                    const float4 o1 = *reinterpret_cast<const float4*>(xo + 4);
+            for (int qq = 0; qq < 4; ++qq) {
+                const int bi = 16 * wv + 4 * qq + gq;
+                const float* xo = region + (p0 + (bi < nb ? bi : 0)) * SS;
+                const float4 o0 = *reinterpret_cast<const float4*>(xo);
+                const float4 o1 = *reinterpret_cast<const float4*>(xo + 4);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float* xc = region + cpos[qq][u] * SS;
                     const float4 c0 = *reinterpret_cast<const float4*>(xc);
                     const float4 c1 = *reinterpret_cast<const float4*>(xc + 4);
-                    float bq = blk[q];  // padding past D adds exact zeros
+                    float bq = blk[qq][u];  // padding past D adds exact zeros
                     float df = o0.x - c0.x;
                     bq = __fmaf_rn(df, df, bq);
                     df = o0.y - c0.y;
@@ -699,30 +846,52 @@ __global__ __launch_bounds__(256) void k_leaf_wide(
                     bq = __fmaf_rn(df, df, bq);
                     df = o1.w - c1.w;
                     bq = __fmaf_rn(df, df, bq);
-                    blk[q] = bq;
+                    blk[qq][u] = bq;
                 }
+                // one quad's loads in flight at a time (register pressure)
+                __builtin_amdgcn_sched_barrier(0);
             }
             if (((d0 + CW) & 31) == 0 || d0 + CW >= D) {  // end of a 32-dimension block
 #pragma unroll
-                for (int q = 0; q < RPW; ++q) {
-                    tot[q] = tot[q] + blk[q];
-                    blk[q] = 0.f;
-                }
+                for (int qq = 0; qq < 4; ++qq)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        tot[qq][u] = tot[qq][u] + blk[qq][u];
+                        blk[qq][u] = 0.f;
+                    }
             }
         }
-        // ---- per row: the k smallest (d32, id), in order
+        // ---- per row: the k smallest (d32, id), in order; two quads of rows
+        // sorted together at a time
 #pragma unroll
-        for (int q = 0; q < RPW; ++q) {
-            const int bi = wv + NW * q;
-            if (bi < nb) {
-                uint64_t v[1];
-                v[0] = lane < ce ? cand_key(tot[q], ids[cpos[q]]) : kNoKey;
-                wave_bitonic_sort<1>(v);
-                const size_t out = (static_cast<size_t>(lf.tree) * n + ids[p0 + bi]) * k;
-                if (lane < k) {
-                    const bool ok = v[0] != kNoKey;
-                    cand_ids[out + lane] = ok ? key_id(v[0]) : -1;
-                    cand_d[out + lane] = ok ? key_dist(v[0]) : __int_as_float(0x7f800000);
+        for (int h = 0; h < 2; ++h) {
+            uint64_t v[2][4];
+#pragma unroll
+            for (int q2 = 0; q2 < 2; ++q2) {
+                const int qq = 2 * h + q2;
+                const int bi = 16 * wv + 4 * qq + gq;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int e = gl + 16 * u;
+                    v[q2][u] = (bi < nb && e < ce) ? cand_key(tot[qq][u], ids[cpos[qq][u]]) : kNoKey;
+                }
+            }
+            group_sort64<2>(v);
+#pragma unroll
+            for (int q2 = 0; q2 < 2; ++q2) {
+                const int qq = 2 * h + q2;
+                const int bi = 16 * wv + 4 * qq + gq;
+                if (bi < nb) {
+                    const size_t out = (static_cast<size_t>(lf.tree) * n + ids[p0 + bi]) * k;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int e = gl * 4 + r;
+                        if (e < k) {
+                            const bool ok = v[q2][r] != kNoKey;
+                            cand_ids[out + e] = ok ? key_id(v[q2][r]) : -1;
+                            cand_d[out + e] = ok ? key_dist(v[q2][r]) : __int_as_float(0x7f800000);
+                        }
+                    }
                 }
             }
         }
