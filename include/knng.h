@@ -105,6 +105,11 @@ typedef struct {
                                kernels (rows held in LDS, no memory traffic per
                                pass); assign_rows - subtree_rows rows were streamed
                                by the level kernels' assignment passes */
+    int64_t filter_rows;    /* rows of assignment passes filtered by the reduced copy
+                               (FP32 rows with a BF16/FP16/FP8 first pass): each read
+                               its reduced row first */
+    int64_t filter_exact_rows; /* rows whose FP32 values those passes also read (label
+                                  inside the filter's error band, or changed) */
 } knng_stats;
 
 /* Fill *opt with the defaults listed above. */
@@ -188,9 +193,10 @@ int knng_leaf_search(const float* data, int64_t n, int32_t D, int32_t k, int32_t
  * that every GPU the library runs on holds until the process ends (its
  * address is looked up once per device, on the first call there).
  *   Limit: 16 B per leaf + 8 n_trees n k B of candidate lists when
- *   n_trees > 1 + for a reduced precision n (Dp b + 8) B (Dp = D rounded up
- *   to 32, b = 2 for BF16/FP16, 1 for FP8) + 16 B per leaf, each block
- *   rounded up to 256 B, must fit 64 MiB; larger requests return
+ *   n_trees > 1 + for a reduced precision n (S + 8) B (S = Dp b + 4 rounded
+ *   up to a multiple of 128, Dp = D rounded up to 32, b = 2 for BF16/FP16, 1
+ *   for FP8) + 16 B per leaf, each block rounded up to 256 B, must fit
+ *   64 MiB; larger requests return
  *   KNNG_ERR_UNSUPPORTED before any HIP call.
  *   Calls on one device share the array and are serialised by the library's
  *   per-device lock (each returns after its stream is synchronised); the

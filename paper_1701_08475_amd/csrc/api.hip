@@ -179,7 +179,7 @@ const char* knng_status_string(int status) {
 
 const char* knng_last_error(void) { return g_err; }
 
-int knng_version(void) { return 101; }
+int knng_version(void) { return 102; }
 
 int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_trees,
                   int32_t leaf_max, uint64_t seed, int32_t* ids_out, float* dists_out,
@@ -249,7 +249,8 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
         return set_err(KNNG_ERR_UNSUPPORTED,
                        "BF16 with rerank_factor*k = %d needs the exact first pass (integer "
                        "data 0..255, D <= 129)", o.rerank * k);
-    knng::ReducedRows rr{nullptr, nullptr, nullptr, knng::reduced_rows_dp(D), exact_bf16};
+    knng::ReducedRows rr{nullptr, nullptr, nullptr, knng::reduced_rows_dp(D), exact_bf16,
+                         knng::reduced_rows_stride(leaf_prec, D)};
 
     e = knng::ws_malloc(reinterpret_cast<void**>(&perm), sizeof(int32_t) * slots * n, s);
     if (e == hipSuccess)
@@ -309,6 +310,10 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
         pa.node_log_cap = 0;
         pa.timer = &timer;
         pa.stream = s;
+        // FP32 rows with a reduced copy: the partition's later passes read
+        // the copy first (same labels and centres, fewer bytes)
+        pa.filter = (leaf_prec != KNNG_FP32 && !o.plain) ? &rr : nullptr;
+        pa.precision = leaf_prec;
         knng::PartitionResult r;
         rc = knng::partition_run(pa, &r, err, sizeof(err));
         if (rc != KNNG_OK) {
@@ -317,6 +322,8 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
         }
         pres.assign_rows += r.assign_rows;
         pres.subtree_rows += r.subtree_rows;
+        pres.filter_rows += r.filter_rows;
+        pres.filter_exact_rows += r.filter_exact_rows;
         pres.splits += r.splits;
         pres.repairs += r.repairs;
         pres.levels = r.levels > pres.levels ? r.levels : pres.levels;
@@ -390,6 +397,8 @@ done:
         std::memset(stats_out, 0, sizeof(*stats_out));
         stats_out->assign_rows = pres.assign_rows;
         stats_out->subtree_rows = pres.subtree_rows;
+        stats_out->filter_rows = pres.filter_rows;
+        stats_out->filter_exact_rows = pres.filter_exact_rows;
         stats_out->ordered_pairs = pairs;
         stats_out->leaves = n_leaves_total;
         stats_out->splits = pres.splits;
@@ -667,7 +676,8 @@ int leaf_search_impl(const float* data, int64_t n, int32_t D, int32_t k, int32_t
     const bool direct = (n_trees == 1);
     char err[400] = "";
     int launches = 0;
-    knng::ReducedRows rr{nullptr, nullptr, nullptr, knng::reduced_rows_dp(D), false};
+    knng::ReducedRows rr{nullptr, nullptr, nullptr, knng::reduced_rows_dp(D), false,
+                         knng::reduced_rows_stride(o.precision, D)};
     hipError_t e = knng::ws_malloc(reinterpret_cast<void**>(&leaves), sizeof(knng::LeafRec) * total, s);
     if (e == hipSuccess) e = knng::ws_malloc(reinterpret_cast<void**>(&flags), sizeof(int32_t) * 2, s);
     if (e != hipSuccess) {

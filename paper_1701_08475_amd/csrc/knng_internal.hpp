@@ -184,6 +184,29 @@ using AssignFn = void (*)(const TX*, int64_t, int, const int32_t*, const NodeRec
 // per chunk (grid: chunks).  False if D is not covered.
 bool pick_assign_u8_mfma(int D, int u, int pd, AssignFn<uint8_t>* f, AssignFn<uint8_t>* f4);
 
+// FP32-row assignment passes (assign_f32.hip, D % 4 == 0): the level's first
+// pass (chunk totals and side-1 sums), the later passes (changed rows added
+// to the side-1 sums), the later passes filtered by the reduced copy (rf[fmt -
+// 1] for BF16, FP16, FP8; extra arguments: the copy, 1/sigma, bytes per
+// row, and two spread counters: rows of filtered passes, rows whose FP32
+// values they read), and the repair's margins.
+using AssignRfFn = void (*)(const float*, int64_t, int, const int32_t*, const NodeRec*,
+                            const int32_t*, int, double*, int32_t*, int32_t*, uint8_t*, double*,
+                            int32_t*, int, int, unsigned long long*, int32_t*, int,
+                            const int32_t*, int, const uint8_t*, int, int,
+                            unsigned long long*);
+using RedotsFn = void (*)(const NodeRec*, const int32_t*, int64_t, const float*, int,
+                          const int32_t*, const double*, const int32_t*, int, double*);
+struct AssignF32Fns {
+    AssignFn<float> first = nullptr;
+    AssignFn<float> later = nullptr;
+    AssignRfFn rf[3] = {nullptr, nullptr, nullptr};
+    RedotsFn redots = nullptr;
+};
+bool pick_assign_f32_fns(int D, int u, AssignF32Fns* f);
+
+struct ReducedRows;
+
 // ---------------------------------------------------------------- partition
 struct PartitionArgs {
     const float* X;
@@ -203,6 +226,9 @@ struct PartitionArgs {
     int64_t node_log_cap;
     KernelTimer* timer;     // nullable
     hipStream_t stream;
+    const ReducedRows* filter = nullptr;  // nullable: reduced copy of X for the filtered
+                                          // passes (FP32 rows; results are unchanged)
+    int precision = 0;                    // format of `filter` (1 BF16, 2 FP16, 3 FP8)
 };
 
 struct PartitionResult {
@@ -210,6 +236,8 @@ struct PartitionResult {
     int64_t n_log = 0;
     int64_t assign_rows = 0;  // rows assigned, summed over passes (subtree kernels included)
     int64_t subtree_rows = 0; // the part of assign_rows assigned inside subtree kernels (LDS)
+    int64_t filter_rows = 0;  // rows of filtered passes (labelled from the reduced copy first)
+    int64_t filter_exact_rows = 0;  // rows whose FP32 values the filtered passes read
     int64_t splits = 0;
     int64_t repairs = 0;
     int levels = 0;
@@ -247,13 +275,22 @@ int leaf_run(const LeafArgs& a, int* launches, char* err, size_t errlen);
 
 // Reduced-precision copy of the rows for the MFMA first pass.
 struct ReducedRows {
-    uint8_t* Xr;   // [n][Dp] elements of the format (2 bytes BF16/FP16, 1 byte FP8)
+    uint8_t* Xr;   // [n] rows of `stride` bytes: Dp elements of the format (2 bytes
+                   // BF16/FP16, 1 byte FP8), zero past D and up to the stride
     float* nrm;    // [n] squared norm of the dequantised reduced row
     float* sinv;   // [n] 1/sigma (power of two)
     int Dp;        // D rounded up to 32
     bool exact;    // first pass exact (d~ == d32): skip the re-rank
+    int stride;    // bytes per row: Dp elements and the FP32 word 1/sigma, rounded up
+                   // to whole 128-byte lines, so a gathered row takes whole cache lines
 };
+// byte offset of a reduced row's 1/sigma word: just past its Dp elements (one
+// byte each for FP8-e4m3, precision 3; two for BF16 and FP16)
+__host__ __device__ constexpr int reduced_rows_scale_offset(int precision, int Dp) {
+    return Dp * (precision == 3 ? 1 : 2);
+}
 int reduced_rows_dp(int D);
+int reduced_rows_stride(int precision, int D);
 size_t reduced_rows_bytes(int precision, int64_t n, int D);
 int prep_reduced(int precision, const float* X, int64_t n, int D, ReducedRows* rr, hipStream_t s);
 int leaf_run_mfma(const LeafArgs& a, const ReducedRows& rr, int* launches, char* err,

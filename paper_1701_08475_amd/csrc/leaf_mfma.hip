@@ -13,8 +13,10 @@ using namespace leafk;
 // ------------------------------------------------------------- prep
 // Reduced copy of every row (one wave per row): sigma = 2^(E_max - floor(log2
 // max|x|) - 1) with E_max = 15 (FP16) or 8 (FP8-e4m3) so that |sigma x| <
-// 2^E_max; sigma = 1 for BF16.  x~ = round-to-nearest-even(sigma x); padding
-// to Dp elements is zero.  n~ = sum of (x~ / sigma)^2 (FP32, fixed order).
+// 2^E_max; sigma = 1 for BF16.  x~ = round-to-nearest-even(sigma x); the row
+// holds Dp elements (zero past D), then 1/sigma as an FP32 word (so that a
+// gathered row brings its scale in the same cache line), then zeros to the
+// stride.  n~ = sum of (x~ / sigma)^2 (FP32, fixed order).
 __device__ __forceinline__ uint16_t to_bf16_rne(float f) {
     const uint32_t u = __float_as_uint(f);
     return static_cast<uint16_t>((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
@@ -25,7 +27,7 @@ __device__ __forceinline__ float bf16_to_f(uint16_t h) {
 
 template <int FMT>
 __global__ __launch_bounds__(256) void k_prep_reduced(const float* __restrict__ X, int64_t n, int D,
-                                                      int Dp, uint8_t* __restrict__ Xr,
+                                                      int Dp, int rsb, uint8_t* __restrict__ Xr,
                                                       float* __restrict__ nrm,
                                                       float* __restrict__ sinv) {
     const int64_t row = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
@@ -43,9 +45,12 @@ __global__ __launch_bounds__(256) void k_prep_reduced(const float* __restrict__ 
     }
     const float isg = 1.f / sig;  // exact: sig is a power of two
     float s = 0.f;
+    const int Ds = rsb / (FMT == kFP8 ? 1 : 2);  // elements per row in memory (zeros past Dp)
+    const int Sw = Dp + (FMT == kFP8 ? 4 : 2);     // elements Dp .. Sw-1 hold 1/sigma
     if constexpr (FMT == kFP8) {
-        uint8_t* o = Xr + row * Dp;
-        for (int d0 = 2 * lane; d0 < Dp; d0 += 2 * kWave) {
+        uint8_t* o = Xr + row * rsb;
+        for (int d0 = 2 * lane; d0 < Ds; d0 += 2 * kWave) {
+            if (d0 >= Dp && d0 < Sw) continue;
             const float a = d0 < D ? x[d0] * sig : 0.f;
             const float b = d0 + 1 < D ? x[d0 + 1] * sig : 0.f;
             const uint32_t pk = static_cast<uint32_t>(__builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false));
@@ -58,8 +63,9 @@ __global__ __launch_bounds__(256) void k_prep_reduced(const float* __restrict__ 
             s = __fmaf_rn(db, db, s);
         }
     } else {
-        uint16_t* o = reinterpret_cast<uint16_t*>(Xr) + row * Dp;
-        for (int d = lane; d < Dp; d += kWave) {
+        uint16_t* o = reinterpret_cast<uint16_t*>(Xr + row * rsb);
+        for (int d = lane; d < Ds; d += kWave) {
+            if (d >= Dp && d < Sw) continue;
             const float v = d < D ? x[d] * sig : 0.f;
             float dq;
             if constexpr (FMT == kBF16) {
@@ -79,6 +85,7 @@ __global__ __launch_bounds__(256) void k_prep_reduced(const float* __restrict__ 
     if (lane == 0) {
         nrm[row] = s;
         sinv[row] = isg;
+        *reinterpret_cast<float*>(Xr + row * rsb + reduced_rows_scale_offset(FMT, Dp)) = isg;
     }
 }
 
@@ -86,17 +93,20 @@ __global__ __launch_bounds__(256) void k_prep_reduced(const float* __restrict__ 
 
 int reduced_rows_dp(int D) { return (D + 31) / 32 * 32; }
 
+int reduced_rows_stride(int precision, int D) {
+    return (reduced_rows_scale_offset(precision, reduced_rows_dp(D)) + 4 + 127) / 128 * 128;
+}
+
 size_t reduced_rows_bytes(int precision, int64_t n, int D) {
-    const size_t eb = precision == kFP8 ? 1 : 2;
-    return static_cast<size_t>(n) * reduced_rows_dp(D) * eb;
+    return static_cast<size_t>(n) * reduced_rows_stride(precision, D);
 }
 
 int prep_reduced(int precision, const float* X, int64_t n, int D, ReducedRows* rr, hipStream_t s) {
     const unsigned blocks = static_cast<unsigned>((n + 3) / 4);
     switch (precision) {
-        case kBF16: k_prep_reduced<kBF16><<<blocks, 256, 0, s>>>(X, n, D, rr->Dp, rr->Xr, rr->nrm, rr->sinv); break;
-        case kF16: k_prep_reduced<kF16><<<blocks, 256, 0, s>>>(X, n, D, rr->Dp, rr->Xr, rr->nrm, rr->sinv); break;
-        case kFP8: k_prep_reduced<kFP8><<<blocks, 256, 0, s>>>(X, n, D, rr->Dp, rr->Xr, rr->nrm, rr->sinv); break;
+        case kBF16: k_prep_reduced<kBF16><<<blocks, 256, 0, s>>>(X, n, D, rr->Dp, rr->stride, rr->Xr, rr->nrm, rr->sinv); break;
+        case kF16: k_prep_reduced<kF16><<<blocks, 256, 0, s>>>(X, n, D, rr->Dp, rr->stride, rr->Xr, rr->nrm, rr->sinv); break;
+        case kFP8: k_prep_reduced<kFP8><<<blocks, 256, 0, s>>>(X, n, D, rr->Dp, rr->stride, rr->Xr, rr->nrm, rr->sinv); break;
         default: return kUnsupported;
     }
     return hipGetLastError() == hipSuccess ? kOk : kHip;

@@ -196,7 +196,7 @@ __device__ __forceinline__ uint32_t wave_select_rank(const uint32_t (&key)[R], c
 // the k smallest (d32, id).  CS bounds the candidates per row.
 template <int FMT, int MP, int PR, int CS, int KL, bool EXACT, int NW>
 __global__ __launch_bounds__(NW * 64) void k_leaf_mfma(
-    const float* __restrict__ X, const uint8_t* __restrict__ Xr, int64_t n, int D, int Dp,
+    const float* __restrict__ X, const uint8_t* __restrict__ Xr, int64_t n, int D, int Dp, int rsb,
     const float* __restrict__ nrm, const float* __restrict__ sinv, int k, int c,
     const int32_t* __restrict__ perm, const LeafRec* __restrict__ leaves,
     int32_t* __restrict__ cand_ids, float* __restrict__ cand_d,
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(NW * 64) void k_leaf_mfma(
     __syncthreads();
     const int cc = EXACT ? k : c;          // candidates wanted per row
     const int ce = cc < m - 1 ? cc : m - 1;
-    const size_t rstride = static_cast<size_t>(Dp) * F::kBytes;
+    const size_t rstride = static_cast<size_t>(rsb);  // bytes per row
     const int rt = wv % RTP, cp = wv / RTP;
     const int kg = lane >> 4;
 
@@ -645,7 +645,7 @@ __device__ __forceinline__ void group_sort64(uint64_t (&v)[NR][4]) {
 
 template <int FMT, int MP>
 __global__ __launch_bounds__(256) void k_leaf_wide(
-    const float* __restrict__ X, const uint8_t* __restrict__ Xr, int64_t n, int D, int Dp,
+    const float* __restrict__ X, const uint8_t* __restrict__ Xr, int64_t n, int D, int Dp, int rsb,
     const float* __restrict__ nrm, const float* __restrict__ sinv, int k, int c,
     const int32_t* __restrict__ perm, const LeafRec* __restrict__ leaves,
     int32_t* __restrict__ cand_ids, float* __restrict__ cand_d,
@@ -681,7 +681,7 @@ __global__ __launch_bounds__(256) void k_leaf_wide(
         stat_add(pairs, blockIdx.x, static_cast<unsigned long long>(m) * static_cast<unsigned long long>(m - 1));
     __syncthreads();
     const int ce = c < m - 1 ? c : m - 1;  // candidates per row
-    const size_t rstride = static_cast<size_t>(Dp) * F::kBytes;
+    const size_t rstride = static_cast<size_t>(rsb);  // bytes per row
     const int kg = lane >> 4;
 
     // this thread's share of an 8-dimension chunk of the leaf's FP32 rows
@@ -912,7 +912,7 @@ __global__ __launch_bounds__(256) void k_leaf_wide(
 // in 32-dimension blocks, and the k smallest (d32, id) are kept.
 template <int FMT, int MP, int CL, int KL, bool EXACT>
 __global__ __launch_bounds__(256) void k_leaf_small(
-    const float* __restrict__ X, const uint8_t* __restrict__ Xr, int64_t n, int D, int Dp,
+    const float* __restrict__ X, const uint8_t* __restrict__ Xr, int64_t n, int D, int Dp, int rsb,
     const float* __restrict__ nrm, const float* __restrict__ sinv, int k, int c,
     const int32_t* __restrict__ perm, const LeafRec* __restrict__ leaves,
     int32_t* __restrict__ cand_ids, float* __restrict__ cand_d,
@@ -940,7 +940,7 @@ __global__ __launch_bounds__(256) void k_leaf_small(
 
     // ---- Gram: wave w has row tiles w*RPW .. w*RPW+RPW-1 and every column tile
     {
-        const size_t rstride = static_cast<size_t>(Dp) * F::kBytes;
+        const size_t rstride = static_cast<size_t>(rsb);  // bytes per row
         const int kg = lane >> 4;
         const uint8_t* ap[RPW];
         bool aok[RPW];
@@ -971,11 +971,12 @@ __global__ __launch_bounds__(256) void k_leaf_small(
         // one per 32-dimension step.  Rows are padded by 16 bytes so the 16
         // rows of a fragment fall in different banks.  Same products, same
         // order.
-        const int rs = static_cast<int>(rstride) + 16;
+        const int rb = Dp * F::kBytes;  // bytes of a row the Gram reads
+        const int rs = rb + 16;
         const bool staged = static_cast<size_t>(MP) * rs <= sizeof(lds);
         if (staged) {
             uint8_t* L = reinterpret_cast<uint8_t*>(lds);
-            const int cpr = static_cast<int>(rstride / 16);  // 16-byte chunks per row
+            const int cpr = rb / 16;  // 16-byte chunks per row
             for (int c = tid; c < m * cpr; c += 256) {
                 const int r = c / cpr, j = c % cpr;
                 *reinterpret_cast<uint4*>(L + r * rs + j * 16) = *reinterpret_cast<const uint4*>(
@@ -1192,7 +1193,7 @@ int launch_fmt(const LeafArgs& a, const ReducedRows& rr, int* launches, char* er
     auto go = [&](auto kern, unsigned threads = 256) -> int {
         if (a.timer) a.timer->begin(kKLeaf, a.stream);
         kern<<<static_cast<unsigned>(a.n_leaves), threads, 0, a.stream>>>(
-            a.X, rr.Xr, a.n, a.D, rr.Dp, rr.nrm, rr.sinv, a.k, c, a.perm, a.leaves, a.cand_ids,
+            a.X, rr.Xr, a.n, a.D, rr.Dp, rr.stride, rr.nrm, rr.sinv, a.k, c, a.perm, a.leaves, a.cand_ids,
             a.cand_d, a.pairs);
         if (a.timer) a.timer->end(kKLeaf, a.stream);
         ++*launches;

@@ -1250,7 +1250,19 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     int unroll = env_int("KNNG_ASSIGN_UNROLL", 2);
     if (epl != 4 && epl != 8 && epl != 16) epl = 8;
     if (unroll != 1 && unroll != 2 && unroll != 4) unroll = 2;
-    AssignFn<float> assign = use_u8 ? nullptr : pick_assign_f32(D, epl, unroll);
+    // FP32 rows with D % 4 == 0: first pass with chunk totals, later passes
+    // adding the changed rows (optionally filtered by the reduced copy);
+    // other D: the single FP32 kernel with full side sums every pass
+    AssignF32Fns f32{};
+    const bool new_f32 = !use_u8 && pick_assign_f32_fns(D, unroll, &f32);
+    AssignFn<float> assign = (use_u8 || new_f32) ? nullptr : pick_assign_f32(D, epl, unroll);
+    // the filter: the reduced copy (KNNG_PARTITION_FILTER=0 turns it off; the
+    // results are the same either way)
+    AssignRfFn rf = nullptr;
+    if (new_f32 && a.filter != nullptr && a.precision >= 1 && a.precision <= 3 &&
+        env_int("KNNG_PARTITION_FILTER", 1) != 0)
+        rf = f32.rf[a.precision - 1];
+    const bool totals = use_u8 || new_f32;  // P holds chunk totals and side-1 sums
     AssignFn<uint8_t> assign8[2] = {nullptr, nullptr};
     AssignFn<uint8_t> assign8w[2] = {nullptr, nullptr};  // four wavefronts per chunk
     RepairFn repair = k_repair<0, 1>;
@@ -1272,7 +1284,7 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
             }
         }
     }
-    if (assign == nullptr && assign8[0] == nullptr) {
+    if (assign == nullptr && assign8[0] == nullptr && !new_f32) {
         std::snprintf(err, errlen, "dimension %d not supported by the partition kernels", D);
         return kUnsupported;
     }
@@ -1315,7 +1327,7 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     unsigned long long* dstats = nullptr;
     LevelCounters* hctr = nullptr;
     LevelCounters* dmirror = nullptr;  // device address of hctr
-    std::vector<unsigned long long> hstats(5 * kStatWords, 0ull);
+    std::vector<unsigned long long> hstats(7 * kStatWords, 0ull);
     int hoverflow = 0;
     int cur = 0;
     int depth = 0;
@@ -1383,9 +1395,9 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&perm_tmp), sizeof(int32_t) * tn, s));
     KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&ctr), sizeof(LevelCounters), s));
     KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&dstats),
-                            sizeof(unsigned long long) * 5 * kStatWords, s));
+                            sizeof(unsigned long long) * 7 * kStatWords, s));
     KNNG_HIP(ws_malloc(reinterpret_cast<void**>(&overflow), sizeof(int), s));
-    k_zero_small<<<1, 256, 0, s>>>(dstats, 5 * kStatWords, overflow);
+    k_zero_small<<<1, 256, 0, s>>>(dstats, 7 * kStatWords, overflow);
     KNNG_LAUNCH();
     {
         const int64_t want = (static_cast<int64_t>(tn) + 255) / 256;
@@ -1445,6 +1457,16 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
                 assign8[pass == 0 ? 0 : 1]<<<agrid, 256, 0, s>>>(
                     a.X8, n, D, a.perm, nodes[cur], chunk_node, nc, C, status, n0f, labels, dots,
                     P, cnt, pass, a.max_iter, dstats, rep, a.min_leaf, ord, xper);
+            else if (new_f32 && pass > 0 && rf != nullptr)
+                rf<<<agrid, 256, 0, s>>>(a.X, n, D, a.perm, nodes[cur], chunk_node, nc, C, status,
+                                         n0f, labels, P, cnt, pass, a.max_iter, dstats, rep,
+                                         a.min_leaf, ord, xper, a.filter->Xr,
+                                         reduced_rows_scale_offset(a.precision, a.filter->Dp),
+                                         a.filter->stride, dstats + 5 * kStatWords);
+            else if (new_f32)
+                (pass == 0 ? f32.first : f32.later)<<<agrid, 256, 0, s>>>(
+                    a.X, n, D, a.perm, nodes[cur], chunk_node, nc, C, status, n0f, labels, dots, P,
+                    cnt, pass, a.max_iter, dstats, rep, a.min_leaf, ord, xper);
             else
                 assign<<<agrid, 256, 0, s>>>(a.X, n, D, a.perm, nodes[cur], chunk_node, nc, C,
                                              status, n0f, labels, dots, P, cnt, pass, a.max_iter,
@@ -1454,14 +1476,19 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
             if (nb > 0) {
                 if (few_chunks)
                     k_update_nodes<<<nb, 256, 0, s>>>(nodes[cur], big[cur], D, P, cnt, C, status,
-                                                      n0f, pass, a.max_iter, use_u8 ? 1 : 0, rep,
+                                                      n0f, pass, a.max_iter, totals ? 1 : 0, rep,
                                                       a.min_leaf);
                 else
                     k_update_big<<<nb * slices, 256, 0, s>>>(nodes[cur], big[cur], D, P, cnt, C,
                                                              status, n0f, pass, a.max_iter,
-                                                             use_u8 ? 1 : 0, rep, a.min_leaf);
+                                                             totals ? 1 : 0, rep, a.min_leaf);
                 KNNG_LAUNCH();
             }
+        }
+        if (new_f32) {  // the repair ranks by the final margins: recompute them
+            f32.redots<<<std::min(na, 2048), 256, 0, s>>>(nodes[cur], rep, n, a.X, D, a.perm, C,
+                                                          n0f, a.min_leaf, dots);
+            KNNG_LAUNCH();
         }
         repair<<<std::min(na, 2048), 256, 0, s>>>(nodes[cur], rep, n, a.X8, D, a.perm, C, dots,
                                                   labels, n0f, a.min_leaf, cnt, dstats + kStatWords);
@@ -1538,6 +1565,8 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     res->n_leaves = hctr->n_leaves;
     res->n_log = hctr->n_log;
     res->subtree_rows = static_cast<int64_t>(stat_total(hstats.data() + 4 * kStatWords));
+    res->filter_rows = static_cast<int64_t>(stat_total(hstats.data() + 5 * kStatWords));
+    res->filter_exact_rows = static_cast<int64_t>(stat_total(hstats.data() + 6 * kStatWords));
     res->assign_rows = static_cast<int64_t>(stat_total(hstats.data())) + res->subtree_rows;
     res->repairs = static_cast<int64_t>(stat_total(hstats.data() + kStatWords));
     res->splits = splits + static_cast<int64_t>(stat_total(hstats.data() + 2 * kStatWords));

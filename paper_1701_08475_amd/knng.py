@@ -44,7 +44,8 @@ class KnngStats(ctypes.Structure):
                 ("ms_k_leaf", ctypes.c_float), ("n_k_leaf", ctypes.c_int32),
                 ("ms_k_merge", ctypes.c_float), ("n_k_merge", ctypes.c_int32),
                 ("compact_used", ctypes.c_int32), ("exact_first_pass", ctypes.c_int32),
-                ("subtree_rows", ctypes.c_int64)]
+                ("subtree_rows", ctypes.c_int64), ("filter_rows", ctypes.c_int64),
+                ("filter_exact_rows", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

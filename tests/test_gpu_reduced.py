@@ -237,3 +237,40 @@ def test_wide_leaf_kernel_equals_panel_kernel(K, orc, precision, n, D, k, L, rer
     b = _gpu_leaf_search(K, X, k, perms, offs, precision, rerank=rerank)
     assert np.array_equal(_np(a[0]), _np(b[0]))
     assert np.array_equal(_np(a[1]).view(np.int32), _np(b[1]).view(np.int32))
+
+
+@pytest.mark.parametrize("precision,n,D,k,T,L,kind", [
+    ("fp8", 120_000, 96, 32, 2, 500, "unit"),    # C5-shaped rows, FP8 copy
+    ("fp16", 40_000, 960, 20, 2, 200, "unit"),   # C4-shaped rows, FP16 copy
+    ("bf16", 50_000, 64, 16, 2, 150, "c1"),      # BF16 copy of GMM rows
+    ("fp8", 30_000, 36, 10, 2, 60, "c1"),        # D % 8 == 4, wide value range
+])
+def test_partition_filter_changes_nothing(K, orc, precision, n, D, k, T, L, kind, monkeypatch):
+    """FP32 rows with a reduced copy: the partition's later passes label rows
+    from the copy where its error bound decides them and read the FP32 row
+    only inside the band or for a changed label.  The graph is bit-identical
+    with the filter off, the filter decides most rows, and tree 0 equals the
+    oracle's tree."""
+    if kind == "c1":
+        X = datagen.gmm_uniform(n, D, 40, -10, 10, 1.0, 41)
+    else:
+        X = datagen.gmm_unit(n, D, 64, 0.35, 42)
+    Xd = to_dev(X)
+    log("partition filter %s n=%d D=%d" % (precision, n, D))
+    monkeypatch.setenv("KNNG_PARTITION_FILTER", "1")
+    a = K.build(Xd, k, T, L, seed=3, precision=precision, stats=True)
+    monkeypatch.setenv("KNNG_PARTITION_FILTER", "0")
+    b = K.build(Xd, k, T, L, seed=3, precision=precision, stats=True)
+    assert a[2]["filter_rows"] > 0 and b[2]["filter_rows"] == 0
+    log("  filtered rows %d, of which read as FP32 %d; level rows %d"
+        % (a[2]["filter_rows"], a[2]["filter_exact_rows"], a[2]["assign_rows"]))
+    assert a[2]["filter_exact_rows"] < a[2]["filter_rows"]
+    assert a[2]["assign_rows"] == b[2]["assign_rows"] and a[2]["levels"] == b[2]["levels"]
+    assert np.array_equal(_np(a[0]), _np(b[0]))
+    assert np.array_equal(_np(a[1]).view(np.int32), _np(b[1]).view(np.int32))
+    # the partition itself against the oracle (knng_partition: the same kernels
+    # without a reduced copy)
+    g = K.partition(Xd, L, k + 1, 3, 0, with_nodes=True)
+    tr = orc.tree(X, L, k + 1, 10, 3, 0)
+    assert np.array_equal(_np(g["perm"]), tr["perm"])
+    assert np.array_equal(_np(g["leaf_off"]), tr["leaf_off"])
