@@ -443,18 +443,19 @@ __global__ __launch_bounds__(NW * 64) void k_leaf_mfma(
 //   1. per 16-row panel, the Gram of the panel against every column on MFMA
 //      (each wave takes MP/64 column tiles) gives d~ in LDS; each 16-lane
 //      group then selects its row's ce smallest (d~, position) exactly
-//      (group_select) into the batch's candidate table;
+//      (group_select, keys in registers) into the batch's candidate table,
+//      as a set (each lane's picks contiguous);
 //   2. the batch's re-rank streams the leaf's FP32 rows through LDS in
 //      8-dimension chunks (the next chunk's loads in flight during this
-//      one); lane l of a row's group owns its candidates l, l+16, l+32, l+48
-//      and accumulates their d32 (in-block fused sum, blocks of 32 added in
+//      one); lane l of a row's group owns its candidates 4l .. 4l+3 and
+//      accumulates their d32 (in-block fused sum, blocks of 32 added in
 //      order);
 //   3. each group sorts its row's 64 (d32, id) keys (group_sort64, four per
 //      lane) and writes the k smallest.
-// Same first-pass values (same MFMA steps in the same order), same
-// selection, same d32 and the same order as k_leaf_mfma: the lists are
-// identical bit for bit.  51 KB of LDS and about 200 registers per lane: two
-// workgroups per compute unit.
+// Same first-pass values (same MFMA steps in the same order), the same
+// candidate set, the same d32 and the same total order as k_leaf_mfma: the
+// lists are identical bit for bit.  51 KB of LDS and about 190 registers per
+// lane: two workgroups per compute unit.
 
 // Minimum / maximum over the 16 lanes of each aligned group (quad exchanges,
 // then mirrors within 8 and within 16 lanes: every lane gets the result).
@@ -473,29 +474,49 @@ __device__ __forceinline__ uint32_t group16_max(uint32_t v) {
     return v;
 }
 
-// Selection, per 16-lane group (one row each; the row's keys krow[0..16 KT) in
-// LDS, invalid ones ~0; lane l reads keys t*16 + l), of the row's ce smallest
-// valid keys by (key, position).  lo, hi: the minimum and maximum of the
-// lane's valid keys.  The keys of rank < ce lie in [lo, hi] (initially the
-// row's minimum and maximum); each pass counts them in 128 bins of width
-// 2^shift over [lo, hi] and narrows [lo, hi] to the bin holding rank rem.  A
-// row stops when its kept bin's keys are all needed (then every key <= hi is
-// taken) or when the bin is a single value T (then the keys < T and the first
-// rem + 1 keys equal to T by position are taken).  hist: 256 words per
-// wave; groups 0 and 1 count in the low and high 16 bits of words 0..127,
-// groups 2 and 3 in words 128..255 (at most 512 keys per row).  act: this
-// group's row exists (uniform within the group).  Candidate positions go to
-// sel[0..ce) of the group's row.
+// Exclusive prefix sum over the 16 lanes of each aligned group.
+__device__ __forceinline__ int group16_excl_scan(int v, int gl) {
+    int incl = v;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+        const int y = __shfl_up(incl, o, 16);
+        if (gl >= o) incl += y;
+    }
+    return incl - v;
+}
+
+// Selection, per 16-lane group (one row each; lane l holds the row's keys
+// kv[t] = key of position t*16 + l in registers, invalid ones ~0), of the
+// row's ce smallest valid keys by (key, position).  lo, hi: the minimum and
+// maximum of the lane's valid keys.  The keys of rank < ce lie in [lo, hi]
+// (initially the row's minimum and maximum); a pass counts them in 128 bins
+// of width 2^shift over [lo, hi] and narrows [lo, hi] to the bin holding rank
+// rem.  A row stops when
+//   - its kept bin's keys are all needed (then every key <= hi is taken);
+//   - the bin holds at most 32 keys: they are gathered as (key, position)
+//     pairs into lst (the group's 32 words x 2) and ranked against each other;
+//     the pair of rank rem is the threshold, and every (key, position) up to
+//     it is taken;
+//   - or the bin is a single value T (then the keys < T and the first rem + 1
+//     keys equal to T by position are taken).
+// hist: 256 words per wave; groups 0 and 1 count in the low and high 16 bits
+// of words 0..127, groups 2 and 3 in words 128..255 (at most 512 keys per
+// row).  act: this group's row exists (uniform within the group).  Candidate
+// positions go to sel[0..ce) of the group's row.
 template <int KT>
-__device__ __forceinline__ void group_select(const uint32_t* krow, uint32_t lo, uint32_t hi,
-                                             bool act, int ce, uint32_t* hist, uint16_t* sel) {
-    const int lane = threadIdx.x & 63;
+__device__ __forceinline__ void group_select(const uint32_t (&kv)[KT], uint32_t lo, uint32_t hi,
+                                             bool act, int ce, uint32_t* hist, uint64_t* lst,
+                                             uint16_t* sel) {
+    static_assert(KT <= 32, "one bit per key column");
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));  // lane-derived addresses stay local to the call
     const int gq = lane >> 4, gl = lane & 15;
     const uint32_t gmask_below = (1u << gl) - 1u;
     lo = group16_min(lo);
     hi = group16_max(hi);
     int rem = ce - 1;
-    bool single = false;
+    bool single = false, ranked = false;
+    uint64_t thr = 0;  // ranked: the (key, position) of rank rem
     bool done = !act;
     uint32_t* h = hist + (gq >> 1) * 128;
     const uint32_t inc = (gq & 1) ? 65536u : 1u;
@@ -515,7 +536,7 @@ __device__ __forceinline__ void group_select(const uint32_t* krow, uint32_t lo, 
         if (!done) {
 #pragma unroll
             for (int t = 0; t < KT; ++t) {
-                const uint32_t kt = krow[t * 16 + gl];
+                const uint32_t kt = kv[t];
                 if (kt >= lo && kt <= hi) atomicAdd(&h[(kt - lo) >> shift], inc);
             }
         }
@@ -560,6 +581,7 @@ __device__ __forceinline__ void group_select(const uint32_t* krow, uint32_t lo, 
         digit = __shfl(digit, src, kWave);
         nrem = __shfl(nrem, src, kWave);
         cnt = __shfl(cnt, src, kWave);
+        bool rank_now = false;
         if (!done) {
             const uint32_t lo2 = lo + (static_cast<uint32_t>(digit) << shift);
             const uint32_t w = shift == 0 ? 0u : ((1u << shift) - 1u);
@@ -571,17 +593,80 @@ __device__ __forceinline__ void group_select(const uint32_t* krow, uint32_t lo, 
             } else if (shift == 0) {
                 single = true;
                 done = true;
+            } else if (cnt <= 32) {
+                rank_now = true;
+                done = true;
             }
         }
+        if (__any(rank_now)) {
+            // the bin's (key, position) pairs (in any order: the pairs are
+            // distinct), then each one's rank among them; the pair of rank
+            // rem is the threshold
+            uint32_t inb = 0u;
+            int nin = 0;
+#pragma unroll
+            for (int t = 0; t < KT; ++t) {
+                const bool in = rank_now && kv[t] >= lo && kv[t] <= hi;
+                inb |= in ? (1u << t) : 0u;
+                nin += in ? 1 : 0;
+            }
+            int j = group16_excl_scan(nin, gl);
+#pragma unroll
+            for (int t = 0; t < KT; ++t)
+                if ((inb >> t) & 1u)
+                    lst[j++] = (static_cast<uint64_t>(kv[t]) << 32) | static_cast<uint32_t>(t * 16 + gl);
+            wave_lds_sync();
+            const uint64_t e0 = (rank_now && gl < cnt) ? lst[gl] : ~0ull;
+            const uint64_t e1 = (rank_now && gl + 16 < cnt) ? lst[gl + 16] : ~0ull;
+            int r0 = 0, r1 = 0;
+            for (int q = 0; q < 32; ++q) {
+                if (__all(q >= cnt || !rank_now)) break;
+                const uint64_t v = (rank_now && q < cnt) ? lst[q] : ~0ull;
+                r0 += v < e0 ? 1 : 0;
+                r1 += v < e1 ? 1 : 0;
+            }
+            const bool h0 = rank_now && gl < cnt && r0 == rem;
+            const bool h1 = rank_now && gl + 16 < cnt && r1 == rem;
+            const uint64_t mine_thr = h0 ? e0 : e1;
+            const uint32_t hb = static_cast<uint32_t>(__ballot(h0 || h1) >> (16 * gq)) & 0xffffu;
+            const int hs = 16 * gq + (hb ? __builtin_ctz(hb) : 0);
+            const uint64_t t2 = shfl_u64(mine_thr, hs);
+            if (rank_now) {
+                thr = t2;
+                ranked = true;
+            }
+            wave_lds_sync();  // the list is read before it is written again
+        }
     }
-    // keys < lo (all needed), then either every key in [lo, hi] or, when the
-    // bin is the single value lo, the first rem + 1 keys equal to it; in
-    // position order (t, lane)
+    if (__all(!single)) {
+        // every (key, position) <= thr, thr = (hi, any position) unless ranked;
+        // written in any order (the re-rank sorts the candidates)
+        const uint64_t th = ranked ? thr : ((static_cast<uint64_t>(hi) << 32) | 0xffffffffull);
+        uint32_t tb = 0u;
+        int nt = 0;
+#pragma unroll
+        for (int t = 0; t < KT; ++t) {
+            const uint64_t kp = (static_cast<uint64_t>(kv[t]) << 32) | static_cast<uint32_t>(t * 16 + gl);
+            const bool take = act && kp <= th;
+            tb |= take ? (1u << t) : 0u;
+            nt += take ? 1 : 0;
+        }
+        int j = group16_excl_scan(nt, gl);
+#pragma unroll
+        for (int t = 0; t < KT; ++t)
+            if ((tb >> t) & 1u) sel[j++] = static_cast<uint16_t>(t * 16 + gl);
+        return;
+    }
+    // some group of the wave ends on a single value: the taken keys in
+    // position order (t, lane): keys < lo (all needed), then every key in
+    // [lo, hi]; or, ranked, every (key, position) <= thr; or, when the bin is
+    // the single value lo, the first rem + 1 keys equal to it
     int taken = 0, eq_seen = 0;
 #pragma unroll
     for (int t = 0; t < KT; ++t) {
-        const uint32_t kt = krow[t * 16 + gl];
-        const bool lt = act && (single ? kt < lo : kt <= hi);
+        const uint32_t kt = kv[t];
+        const uint64_t kp = (static_cast<uint64_t>(kt) << 32) | static_cast<uint32_t>(t * 16 + gl);
+        const bool lt = act && (ranked ? kp <= thr : single ? kt < lo : kt <= hi);
         const bool eq = act && single && kt == lo;
         const uint32_t beq = static_cast<uint32_t>(__ballot(eq) >> (16 * gq)) & 0xffffu;
         const int eq_rank = eq_seen + __popc(beq & gmask_below);
@@ -655,6 +740,8 @@ __global__ __launch_bounds__(256) void k_leaf_wide(
     constexpr int KT = MP / 16;        // keys per lane in the selection (= column tiles)
     constexpr int TPW = KT / NW;       // column tiles per wave in the Gram
     constexpr int RB = 64;             // rows per batch
+    constexpr int QQ = RB / (4 * NW);  // re-rank: quads of rows per wave
+    constexpr int NSW = 4;             // waves that select (four rows of a 16-row panel each)
     constexpr int CW = 8;              // dimensions per staged chunk
     constexpr int SS = 12;             // floats per staged row (16-byte aligned)
     constexpr int PF = (2 * MP + NTH - 1) / NTH;  // staged float4 per thread
@@ -667,7 +754,7 @@ __global__ __launch_bounds__(256) void k_leaf_wide(
     __shared__ uint16_t csel[RB * kWave];            // per batch row its candidate positions
     __shared__ int32_t ids[MP];
     __shared__ float snrm[MP], ssinv[MP];
-    __shared__ __align__(16) uint32_t s_hist[NW * 256];
+    __shared__ __align__(16) uint32_t s_hist[NSW * 256];
     float(*dist)[MP + 1] = reinterpret_cast<float(*)[MP + 1]>(region);
 
     const LeafRec lf = leaves[blockIdx.x];
@@ -701,33 +788,39 @@ __global__ __launch_bounds__(256) void k_leaf_wide(
         // ---- selection, one 16-row panel at a time
         for (int pp = 0; pp < nb; pp += 16) {
             const int prow = p0 + pp;
+            // the leaf size as a per-lane value taken anew each panel: the
+            // compiler would otherwise keep one lane mask per column tile
+            // (col < m) live across the whole kernel
+            int mv = m, lnv = lane;
+            asm volatile("" : "+v"(mv), "+v"(lnv));
+            const int glp = lnv & 15;  // gl, likewise taken anew
             // Gram of the panel, in groups of GT column tiles per wave
             constexpr int GT = TPW < 4 ? TPW : 4;
 #pragma unroll
             for (int tg = 0; tg < TPW; tg += GT) {
-                const int arow = prow + (lane & 15);
-                const uint8_t* ap = Xr + static_cast<size_t>(ids[arow < m ? arow : 0]) * rstride +
+                const int arow = prow + glp;
+                const uint8_t* ap = Xr + static_cast<size_t>(ids[arow < mv ? arow : 0]) * rstride +
                                     static_cast<size_t>(8 * kg) * F::kBytes;
                 const uint8_t* bp[GT];
                 bool bok[GT];
 #pragma unroll
                 for (int t = 0; t < GT; ++t) {
-                    const int bcol = (wv * TPW + tg + t) * 16 + (lane & 15);
-                    bok[t] = bcol < m;
-                    bp[t] = Xr + static_cast<size_t>(ids[bcol < m ? bcol : 0]) * rstride +
+                    const int bcol = (wv * TPW + tg + t) * 16 + glp;
+                    bok[t] = bcol < mv;
+                    bp[t] = Xr + static_cast<size_t>(ids[bcol < mv ? bcol : 0]) * rstride +
                             static_cast<size_t>(8 * kg) * F::kBytes;
                 }
                 f32x4 acc[GT];
 #pragma unroll
                 for (int t = 0; t < GT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-                FragVec<FMT> a = load_frag<FMT>(ap, arow < m);
+                FragVec<FMT> a = load_frag<FMT>(ap, arow < mv);
                 FragVec<FMT> b[GT];
 #pragma unroll
                 for (int t = 0; t < GT; ++t) b[t] = load_frag<FMT>(bp[t], bok[t]);
                 for (int k0 = 0; k0 < Dp; k0 += 32) {
                     const size_t nx = static_cast<size_t>(k0 + 32) * F::kBytes;
                     const bool more = k0 + 32 < Dp;
-                    const FragVec<FMT> an = load_frag<FMT>(ap + nx, more && arow < m);
+                    const FragVec<FMT> an = load_frag<FMT>(ap + nx, more && arow < mv);
                     FragVec<FMT> bn[GT];
 #pragma unroll
                     for (int t = 0; t < GT; ++t) bn[t] = load_frag<FMT>(bp[t] + nx, more && bok[t]);
@@ -739,20 +832,20 @@ __global__ __launch_bounds__(256) void k_leaf_wide(
                 }
 #pragma unroll
                 for (int t = 0; t < GT; ++t) {
-                    const int col = (wv * TPW + tg + t) * 16 + (lane & 15);
+                    const int col = (wv * TPW + tg + t) * 16 + glp;
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const int rl = 4 * kg + i;
                         const int row = prow + rl;
                         float v = __int_as_float(0x7f800000);
-                        if (row < m && col < m)
+                        if (row < mv && col < mv)
                             v = snrm[row] + snrm[col] - 2.f * acc[t][i] * (ssinv[row] * ssinv[col]);
                         dist[rl][col] = v;
                     }
                 }
             }
             __syncthreads();
-            {
+            if (wv < NSW) {
                 // group gq of wave wv: panel row 4 wv + gq
                 const int rl = 4 * wv + gq;
                 const int row = prow + rl;
@@ -762,49 +855,57 @@ __global__ __launch_bounds__(256) void k_leaf_wide(
                     if (act) {
 #pragma unroll
                         for (int t = 0; t < KT; ++t) {
-                            const int col = t * 16 + gl;
+                            const int col = t * 16 + glp;
                             const int e = col < row ? col : col - 1;
-                            if (col < m && col != row) sel[e] = static_cast<uint16_t>(col);
+                            if (col < mv && col != row) sel[e] = static_cast<uint16_t>(col);
                         }
                     }
                 } else if (ce > 0) {
-                    // the row's d~ become order keys in place (invalid: ~0)
-                    uint32_t* krow = reinterpret_cast<uint32_t*>(dist[act ? rl : 0]);
+                    // the row's d~ as order keys in registers (invalid: ~0); the
+                    // row's panel line then holds the selection's pair list
+                    uint32_t kv[KT];
                     uint32_t lo = 0xffffffffu, hi = 0u;
-                    if (act) {
 #pragma unroll
-                        for (int t = 0; t < KT; ++t) {
-                            const int col = t * 16 + gl;
-                            const uint32_t kt = (col < m && col != row) ? fkey(dist[rl][col])
-                                                                        : 0xffffffffu;
-                            krow[col] = kt;
-                            if (kt != 0xffffffffu) {
-                                lo = min(lo, kt);
-                                hi = max(hi, kt);
-                            }
+                    for (int t = 0; t < KT; ++t) {
+                        const int col = t * 16 + glp;
+                        const uint32_t kt = (act && col < mv && col != row) ? fkey(dist[act ? rl : 0][col])
+                                                                            : 0xffffffffu;
+                        kv[t] = kt;
+                        if (kt != 0xffffffffu) {
+                            lo = min(lo, kt);
+                            hi = max(hi, kt);
                         }
                     }
                     wave_lds_sync();
-                    group_select<KT>(krow, lo, hi, act, ce, s_hist + wv * 256, sel);
+                    // (the list starts at the row's first 8-byte aligned word)
+                    const int lrow = ((act ? rl : 0) * (MP + 1) + 1) & ~1;
+                    group_select<KT>(kv, lo, hi, act, ce, s_hist + wv * 256,
+                                     reinterpret_cast<uint64_t*>(region + lrow), sel);
                 }
             }
             __syncthreads();  // the panel is no longer read
         }
         // ---- re-rank of the batch: d32 from LDS-staged 8-dimension chunks;
         // the next chunk's loads are in flight while this one is computed.
-        // Wave wv, quad qq, group gq: batch row 16 wv + 4 qq + gq; lane gl
-        // owns candidates gl + 16 u.
-        float tot[4][4], blk[4][4];
-        int cpos[4][4];
+        // Wave wv, quad qq, group gq: batch row 4 QQ wv + 4 qq + gq; lane gl
+        // owns candidates 4 gl + u (the selection writes each lane's picks
+        // contiguously, so the 16 lanes read rows of 16 different source
+        // lanes: positions of distinct residues mod 16, distinct LDS banks).
+        // (table entries past a row's ce, or of rows past nb, are stale: the
+        // positions are masked into the leaf and the pairs marked invalid)
+        float tot[QQ][4], blk[QQ][4];
+        int cby[QQ][4];      // byte offset of the candidate's staged row in region
+        uint32_t cval = 0u;  // bit 4 qq + u: pair (qq, u) exists
 #pragma unroll
-        for (int qq = 0; qq < 4; ++qq) {
-            const int bi = 16 * wv + 4 * qq + gq;
+        for (int qq = 0; qq < QQ; ++qq) {
+            const int bi = 4 * QQ * wv + 4 * qq + gq;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 tot[qq][u] = 0.f;
                 blk[qq][u] = 0.f;
-                const int e = gl + 16 * u;
-                cpos[qq][u] = (bi < nb && e < ce) ? static_cast<int>(csel[bi * kWave + e]) : 0;
+                const int e = 4 * gl + u;
+                cby[qq][u] = (static_cast<int>(csel[bi * kWave + e]) & (MP - 1)) * (SS * 4);
+                cval |= (bi < nb && e < ce) ? (1u << (4 * qq + u)) : 0u;
             }
         }
         float4 pf[PF];
@@ -819,14 +920,14 @@ __global__ __launch_bounds__(256) void k_leaf_wide(
             __syncthreads();
             if (d0 + CW < D) fetch(d0 + CW, pf);
 #pragma unroll
-            for (int qq = 0; qq < 4; ++qq) {
-                const int bi = 16 * wv + 4 * qq + gq;
+            for (int qq = 0; qq < QQ; ++qq) {
+                const int bi = 4 * QQ * wv + 4 * qq + gq;
                 const float* xo = region + (p0 + (bi < nb ? bi : 0)) * SS;
                 const float4 o0 = *reinterpret_cast<const float4*>(xo);
                 const float4 o1 = *reinterpret_cast<const float4*>(xo + 4);
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const float* xc = region + cpos[qq][u] * SS;
+                    const float* xc = reinterpret_cast<const float*>(reinterpret_cast<const char*>(region) + cby[qq][u]);
                     const float4 c0 = *reinterpret_cast<const float4*>(xc);
                     const float4 c1 = *reinterpret_cast<const float4*>(xc + 4);
                     float bq = blk[qq][u];  // padding past D adds exact zeros
@@ -853,7 +954,7 @@ __global__ __launch_bounds__(256) void k_leaf_wide(
             }
             if (((d0 + CW) & 31) == 0 || d0 + CW >= D) {  // end of a 32-dimension block
 #pragma unroll
-                for (int qq = 0; qq < 4; ++qq)
+                for (int qq = 0; qq < QQ; ++qq)
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         tot[qq][u] = tot[qq][u] + blk[qq][u];
@@ -864,23 +965,23 @@ __global__ __launch_bounds__(256) void k_leaf_wide(
         // ---- per row: the k smallest (d32, id), in order; two quads of rows
         // sorted together at a time
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < QQ / 2; ++h) {
             uint64_t v[2][4];
 #pragma unroll
             for (int q2 = 0; q2 < 2; ++q2) {
                 const int qq = 2 * h + q2;
-                const int bi = 16 * wv + 4 * qq + gq;
+                const int bi = 4 * QQ * wv + 4 * qq + gq;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const int e = gl + 16 * u;
-                    v[q2][u] = (bi < nb && e < ce) ? cand_key(tot[qq][u], ids[cpos[qq][u]]) : kNoKey;
+                    const int e = 4 * gl + u;
+                    v[q2][u] = ((cval >> (4 * qq + u)) & 1u) ? cand_key(tot[qq][u], ids[cby[qq][u] / (SS * 4)]) : kNoKey;
                 }
             }
             group_sort64<2>(v);
 #pragma unroll
             for (int q2 = 0; q2 < 2; ++q2) {
                 const int qq = 2 * h + q2;
-                const int bi = 16 * wv + 4 * qq + gq;
+                const int bi = 4 * QQ * wv + 4 * qq + gq;
                 if (bi < nb) {
                     const size_t out = (static_cast<size_t>(lf.tree) * n + ids[p0 + bi]) * k;
 #pragma unroll
