@@ -454,8 +454,8 @@ __global__ __launch_bounds__(NW * 64) void k_leaf_mfma(
 //      lane) and writes the k smallest.
 // Same first-pass values (same MFMA steps in the same order), the same
 // candidate set, the same d32 and the same total order as k_leaf_mfma: the
-// lists are identical bit for bit.  51 KB of LDS and about 190 registers per
-// lane: two workgroups per compute unit.
+// lists are identical bit for bit.  51 KB of LDS and at most 168 registers
+// per lane: three workgroups per compute unit.
 
 // Minimum / maximum over the 16 lanes of each aligned group (quad exchanges,
 // then mirrors within 8 and within 16 lanes: every lane gets the result).
@@ -728,8 +728,9 @@ __device__ __forceinline__ void group_sort64(uint64_t (&v)[NR][4]) {
     }
 }
 
+// (three waves per SIMD: three workgroups per compute unit, 3 x 51 KB of LDS)
 template <int FMT, int MP>
-__global__ __launch_bounds__(256) void k_leaf_wide(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_leaf_wide(
     const float* __restrict__ X, const uint8_t* __restrict__ Xr, int64_t n, int D, int Dp, int rsb,
     const float* __restrict__ nrm, const float* __restrict__ sinv, int k, int c,
     const int32_t* __restrict__ perm, const LeafRec* __restrict__ leaves,
