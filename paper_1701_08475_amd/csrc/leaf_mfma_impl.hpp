@@ -750,6 +750,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     constexpr int kStage = MP * SS;
     constexpr int kRegion = kPanel > kStage ? kPanel : kStage;
     static_assert(TPW >= 1 && KT % NW == 0, "tile shape");
+    constexpr int kShortK = 4;         // FP8 rows of Dp <= 128: one load round per Gram group
 
     __shared__ __align__(16) float region[kRegion];  // d~ panel, later FP32 row chunks
     __shared__ uint16_t csel[RB * kWave];            // per batch row its candidate positions
@@ -814,22 +815,43 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                 f32x4 acc[GT];
 #pragma unroll
                 for (int t = 0; t < GT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-                FragVec<FMT> a = load_frag<FMT>(ap, arow < mv);
-                FragVec<FMT> b[GT];
+                if (FMT == kFP8 && Dp <= 32 * kShortK) {
+                    // rows of at most kShortK 32-element steps: every step's
+                    // fragments are loaded at once (one memory round trip),
+                    // then the same MFMA steps in the same order
+                    FragVec<FMT> as[kShortK], bs[GT][kShortK];
 #pragma unroll
-                for (int t = 0; t < GT; ++t) b[t] = load_frag<FMT>(bp[t], bok[t]);
-                for (int k0 = 0; k0 < Dp; k0 += 32) {
-                    const size_t nx = static_cast<size_t>(k0 + 32) * F::kBytes;
-                    const bool more = k0 + 32 < Dp;
-                    const FragVec<FMT> an = load_frag<FMT>(ap + nx, more && arow < mv);
-                    FragVec<FMT> bn[GT];
+                    for (int q = 0; q < kShortK; ++q) {
+                        const size_t off = static_cast<size_t>(32 * q) * F::kBytes;
+                        const bool inq = 32 * q < Dp;
+                        as[q] = load_frag<FMT>(ap + off, inq && arow < mv);
 #pragma unroll
-                    for (int t = 0; t < GT; ++t) bn[t] = load_frag<FMT>(bp[t] + nx, more && bok[t]);
+                        for (int t = 0; t < GT; ++t) bs[t][q] = load_frag<FMT>(bp[t] + off, inq && bok[t]);
+                    }
 #pragma unroll
-                    for (int t = 0; t < GT; ++t) acc[t] = F::mma(a, b[t], acc[t]);
-                    a = an;
+                    for (int q = 0; q < kShortK; ++q)
+                        if (32 * q < Dp) {
 #pragma unroll
-                    for (int t = 0; t < GT; ++t) b[t] = bn[t];
+                            for (int t = 0; t < GT; ++t) acc[t] = F::mma(as[q], bs[t][q], acc[t]);
+                        }
+                } else {
+                    FragVec<FMT> a = load_frag<FMT>(ap, arow < mv);
+                    FragVec<FMT> b[GT];
+#pragma unroll
+                    for (int t = 0; t < GT; ++t) b[t] = load_frag<FMT>(bp[t], bok[t]);
+                    for (int k0 = 0; k0 < Dp; k0 += 32) {
+                        const size_t nx = static_cast<size_t>(k0 + 32) * F::kBytes;
+                        const bool more = k0 + 32 < Dp;
+                        const FragVec<FMT> an = load_frag<FMT>(ap + nx, more && arow < mv);
+                        FragVec<FMT> bn[GT];
+#pragma unroll
+                        for (int t = 0; t < GT; ++t) bn[t] = load_frag<FMT>(bp[t] + nx, more && bok[t]);
+#pragma unroll
+                        for (int t = 0; t < GT; ++t) acc[t] = F::mma(a, b[t], acc[t]);
+                        a = an;
+#pragma unroll
+                        for (int t = 0; t < GT; ++t) b[t] = bn[t];
+                    }
                 }
 #pragma unroll
                 for (int t = 0; t < GT; ++t) {
