@@ -35,7 +35,7 @@ MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "fp8": 5000.0}
 PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_1701_08475_amd", "csrc")
 # sources of the assignment kernels: stored HBM counters are void once they change
-ASSIGN_SRCS = [os.path.join(CSRC, f) for f in ("partition.hip", "assign_mfma.hip")]
+ASSIGN_SRCS = [os.path.join(CSRC, f) for f in ("partition.hip", "assign_mfma.hip", "assign_f32.hip")]
 # rows of the CPU oracle's bounded sample, per workload (about 10-30 s on 16 threads)
 CPU_SAMPLE = {"c1": 10_000, "c2": 500_000, "c3": 500_000, "c4": 40_000, "c5": 800_000}
 DTYPE = {
