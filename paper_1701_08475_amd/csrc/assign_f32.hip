@@ -464,10 +464,12 @@ __global__ __launch_bounds__(256) void k_assign_f32_later(
 // their label, rows inside the band are flagged.  Phase B: the band rows by
 // the FP64 code, in its lane layout.  Phase C: the changed rows' delta, as
 // in k_assign_f32_later.  The chunk's row ids stay in LDS from phase A on.
+template <int CPB>
 struct RfLds {
-    uint8_t flag[4][kChunkRows];
-    uint16_t list[4][kChunkRows];
-    int32_t ids[4][kChunkRows];
+    uint8_t flag[CPB][kChunkRows];
+    uint16_t list[CPB][kChunkRows];
+    int32_t ids[CPB][kChunkRows];
+    int n1[CPB][4];
 };
 
 // The 16 bytes of one lane vector as FP32 values (exact: every FP8, FP16 and
@@ -498,7 +500,7 @@ __device__ __forceinline__ float pow2_floor(float v) {
     return __uint_as_float(__float_as_uint(v) & 0x7f800000u);
 }
 
-template <int G, int NF, int U, int FMT>
+template <int G, int NF, int U, int FMT, int WPC>
 __global__ __launch_bounds__(256) void k_assign_rf(
     const float* __restrict__ X, int64_t n, int D, const int32_t* __restrict__ perm,
     const NodeRec* __restrict__ nodes, const int32_t* __restrict__ chunk_node, int nc,
@@ -508,6 +510,10 @@ __global__ __launch_bounds__(256) void k_assign_rf(
     int min_leaf, const int32_t* __restrict__ order, int xcd_per,
     const uint8_t* __restrict__ Xr, int soff, int rsb, unsigned long long* __restrict__ filt) {
     constexpr int RPW = kWave / G;
+    // WPC wavefronts per chunk (1, or 4 for wide rows: a chunk of 1024 rows
+    // of a few KB each is too much work for one wavefront when the level has
+    // few chunks); wavefront `part` filters rows [part RPC, (part+1) RPC)
+    constexpr int CPB = 4 / WPC, RPC = kChunkRows / WPC;
     // filter layout: the widest row of this FP64 layout (4 G NF elements) in
     // 16-byte vectors over at most 64 lanes
     constexpr int EB = FMT == kRfFP8 ? 1 : 2;
@@ -523,9 +529,12 @@ __global__ __launch_bounds__(256) void k_assign_rf(
     // half-spacing of the format at x~ <= 2^-p 2^floor(log2|x~|) + a
     constexpr double kP = FMT == kRfFP8 ? 0x1p-4 : FMT == kRfF16 ? 0x1p-11 : 0x1p-8;
     constexpr double kSub = FMT == kRfFP8 ? 0x1p-10 : FMT == kRfF16 ? 0x1p-25 : 0x1p-134;
-    __shared__ RfLds lds;
+    __shared__ RfLds<CPB> lds;
     const int wl = threadIdx.x >> 6;
-    const int wave = dispatch_chunk(order, xcd_per, blockIdx.x, wl, 4, nc);
+    const int slot = wl / WPC, part = wl % WPC;
+    // (with WPC > 1 every wavefront of the workgroup takes the same chunk, so
+    // the returns below are uniform over the workgroup)
+    const int wave = dispatch_chunk(order, xcd_per, blockIdx.x, slot, CPB, nc);
     if (wave < 0) return;
     const int node = chunk_node[wave];
     if (status[node]) return;
@@ -535,24 +544,30 @@ __global__ __launch_bounds__(256) void k_assign_rf(
     const int gf = lane / GF, lf = lane % GF;
     const int row0 = (wave - r.chunk0) * kChunkRows;
     const int nrows = min(r.size - row0, kChunkRows);
-    const size_t base = static_cast<size_t>(r.tree) * n + r.start + row0;
-    uint8_t* flag = lds.flag[wl];
-    int32_t* rid = lds.ids[wl];
+    const size_t cbase = static_cast<size_t>(r.tree) * n + r.start + row0;
+    uint8_t* cflag = lds.flag[slot];
+    int32_t* crid = lds.ids[slot];
+    // this wavefront's part of the chunk
+    const int p0 = part * RPC;
+    const int np = max(0, min(nrows - p0, RPC));
+    const size_t base = cbase + p0;
+    uint8_t* flag = cflag + p0;
+    int32_t* rid = crid + p0;
 
-    // the chunk's row ids and previous labels (bit 3 of the flag), coalesced
+    // the part's row ids and previous labels (bit 3 of the flag), coalesced
     {
-        int32_t idv[kChunkRows / kWave];
-        uint8_t lbv[kChunkRows / kWave];
+        int32_t idv[RPC / kWave];
+        uint8_t lbv[RPC / kWave];
 #pragma unroll
-        for (int k = 0; k < kChunkRows / kWave; ++k) {
+        for (int k = 0; k < RPC / kWave; ++k) {
             const int i = k * kWave + lane;
-            idv[k] = i < nrows ? perm[base + i] : 0;
-            lbv[k] = i < nrows ? labels[base + i] : 0;
+            idv[k] = i < np ? perm[base + i] : 0;
+            lbv[k] = i < np ? labels[base + i] : 0;
         }
 #pragma unroll
-        for (int k = 0; k < kChunkRows / kWave; ++k) {
+        for (int k = 0; k < RPC / kWave; ++k) {
             const int i = k * kWave + lane;
-            if (i < nrows) {
+            if (i < np) {
                 rid[i] = idv[k];
                 flag[i] = static_cast<uint8_t>(lbv[k] << 3);
             }
@@ -588,12 +603,12 @@ __global__ __launch_bounds__(256) void k_assign_rf(
 
     // ---- phase A: the filter
     int nfilt = 0, nfchg = 0;
-    const int steps = (nrows + RPWF * UF - 1) / (RPWF * UF);
+    const int steps = (np + RPWF * UF - 1) / (RPWF * UF);
     auto issue = [&](int st, uint4 (&x)[UF][NFF], float (&si)[UF]) {
 #pragma unroll
         for (int u = 0; u < UF; ++u) {
             const int i = (st * UF + u) * RPWF + gf;
-            const bool ok = i < nrows;
+            const bool ok = i < np;
             const uint8_t* xr = Xr + static_cast<size_t>(ok ? rid[i] : 0) * rsb;
 #pragma unroll
             for (int j = 0; j < NFF; ++j) {
@@ -631,7 +646,7 @@ __global__ __launch_bounds__(256) void k_assign_rf(
             const double m = static_cast<double>(dt) * s - h;
             const double pb = static_cast<double>(pp) * s;
             const double bnd = relb * pb + subw * s + 0x1p-40 * (2.0 * pb + hab);
-            if (i < nrows && lf == 0) {
+            if (i < np && lf == 0) {
                 const int old = flag[i] >> 3;
                 if (m < -bnd || m > bnd) {
                     const int lab = m < -bnd ? 1 : 0;
@@ -663,8 +678,8 @@ __global__ __launch_bounds__(256) void k_assign_rf(
     // g + RPW, ...), loads PB steps ahead
     double w[NF][4];
     centres_wh<G, NF>(cn, D, l, w);
-    uint16_t* list = lds.list[wl];
-    const int nband = list_rows(flag, nrows, 1, list);
+    uint16_t* list = lds.list[slot] + p0;
+    const int nband = list_rows(flag, np, 1, list);
     const int bsteps = (nband + RPW * UB - 1) / (RPW * UB);
     auto issue_b = [&](int st, float (&x)[UB][NF][4], int (&pos)[UB]) {
 #pragma unroll
@@ -705,27 +720,36 @@ __global__ __launch_bounds__(256) void k_assign_rf(
     // new labels (bit 2 of the flag) back to memory, coalesced
     int n1 = 0;
 #pragma unroll
-    for (int k = 0; k < kChunkRows / kWave; ++k) {
+    for (int k = 0; k < RPC / kWave; ++k) {
         const int i = k * kWave + lane;
-        if (i < nrows) {
+        if (i < np) {
             const int lab = (flag[i] >> 2) & 1;
             labels[base + i] = static_cast<uint8_t>(lab);
             n1 += lab;
         }
     }
-
-    // ---- phase C: the changed rows, as in the unfiltered pass
-    const int changed = list_rows(flag, nrows, 0, list);
-    double acc[NF][4];
-    chunk_delta<G, NF, NF >= 4 ? 1 : 2>(X, D, rid, list, changed, g, l, acc);
     n1 = wave_sum_i32(n1);
     nfilt = wave_sum_i32(nfilt);
     nfchg = wave_sum_i32(nfchg);
     if (lane == 0 && filt != nullptr) {  // rows read from the copy; rows read as FP32
-        stat_add(filt, static_cast<unsigned>(wave), static_cast<unsigned long long>(nrows));
-        stat_add(filt + kStatWords, static_cast<unsigned>(wave),
-                 static_cast<unsigned long long>(nrows - nfilt + nfchg));
+        stat_add(filt, static_cast<unsigned>(wave * WPC + part), static_cast<unsigned long long>(np));
+        stat_add(filt + kStatWords, static_cast<unsigned>(wave * WPC + part),
+                 static_cast<unsigned long long>(np - nfilt + nfchg));
     }
+    if constexpr (WPC > 1) {
+        // the parts' counts, then the chunk's changed rows by its first wavefront
+        if (lane == 0) lds.n1[slot][part] = n1;
+        __syncthreads();
+        if (part != 0) return;
+        n1 = 0;
+#pragma unroll
+        for (int q = 0; q < WPC; ++q) n1 += lds.n1[slot][q];
+    }
+
+    // ---- phase C: the changed rows of the chunk, as in the unfiltered pass
+    const int changed = list_rows(cflag, nrows, 0, lds.list[slot]);
+    double acc[NF][4];
+    chunk_delta<G, NF, NF >= 4 ? 1 : 2>(X, D, crid, lds.list[slot], changed, g, l, acc);
     later_epilogue<G, NF>(r, node, wave, D, g, l, lane, n1, changed, nrows, acc, C, status, n0f, P,
                           cnt, pass, max_iter, assigned, rep, min_leaf);
 }
@@ -771,20 +795,21 @@ __global__ __launch_bounds__(256) void k_redots_f32(const NodeRec* __restrict__ 
 template <int G, int NF>
 void set_f32(int u, AssignF32Fns* f) {
     f->redots = k_redots_f32<G, NF>;
+    // filtered passes: a workgroup per chunk for rows of more than 256
+    // elements (the filter phase does not depend on u)
+    constexpr int WPC = NF >= 4 ? 4 : 1;
+    f->rf_wpc = WPC;
+    f->rf[0] = k_assign_rf<G, NF, 1, kRfBF16, WPC>;
+    f->rf[1] = k_assign_rf<G, NF, 1, kRfF16, WPC>;
+    f->rf[2] = k_assign_rf<G, NF, 1, kRfFP8, WPC>;
     switch (u) {
         case 1:
             f->first = k_assign_f32_first<G, NF, 1>;
             f->later = k_assign_f32_later<G, NF, 1>;
-            f->rf[0] = k_assign_rf<G, NF, 1, kRfBF16>;
-            f->rf[1] = k_assign_rf<G, NF, 1, kRfF16>;
-            f->rf[2] = k_assign_rf<G, NF, 1, kRfFP8>;
             break;
         default:
             f->first = k_assign_f32_first<G, NF, 2>;
             f->later = k_assign_f32_later<G, NF, 2>;
-            f->rf[0] = k_assign_rf<G, NF, 2, kRfBF16>;
-            f->rf[1] = k_assign_rf<G, NF, 2, kRfF16>;
-            f->rf[2] = k_assign_rf<G, NF, 2, kRfFP8>;
             break;
     }
 }

@@ -201,6 +201,7 @@ struct AssignF32Fns {
     AssignFn<float> first = nullptr;
     AssignFn<float> later = nullptr;
     AssignRfFn rf[3] = {nullptr, nullptr, nullptr};
+    int rf_wpc = 1;  // wavefronts per chunk of rf (1: four chunks per workgroup; 4: one)
     RedotsFn redots = nullptr;
 };
 bool pick_assign_f32_fns(int D, int u, AssignF32Fns* f);

@@ -1447,6 +1447,10 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
         const int nwg = wide ? nc : cblocks;
         const int xper = (order_mode & 2) ? (nwg + 7) / 8 : 0;
         const unsigned agrid = static_cast<unsigned>(xper > 0 ? 8 * xper : nwg);
+        // the filtered pass with a workgroup per chunk (wide rows)
+        const int nwg_rf = (new_f32 && f32.rf_wpc > 1) ? nc : cblocks;
+        const int xper_rf = (order_mode & 2) ? (nwg_rf + 7) / 8 : 0;
+        const unsigned agrid_rf = static_cast<unsigned>(xper_rf > 0 ? 8 * xper_rf : nwg_rf);
         for (int pass = 0; pass < a.max_iter; ++pass) {
             if (a.timer) a.timer->begin(kKAssign, s);
             if (wide)
@@ -1458,9 +1462,9 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
                     a.X8, n, D, a.perm, nodes[cur], chunk_node, nc, C, status, n0f, labels, dots,
                     P, cnt, pass, a.max_iter, dstats, rep, a.min_leaf, ord, xper);
             else if (new_f32 && pass > 0 && rf != nullptr)
-                rf<<<agrid, 256, 0, s>>>(a.X, n, D, a.perm, nodes[cur], chunk_node, nc, C, status,
-                                         n0f, labels, P, cnt, pass, a.max_iter, dstats, rep,
-                                         a.min_leaf, ord, xper, a.filter->Xr,
+                rf<<<agrid_rf, 256, 0, s>>>(a.X, n, D, a.perm, nodes[cur], chunk_node, nc, C, status,
+                                            n0f, labels, P, cnt, pass, a.max_iter, dstats, rep,
+                                            a.min_leaf, ord, xper_rf, a.filter->Xr,
                                          reduced_rows_scale_offset(a.precision, a.filter->Dp),
                                          a.filter->stride, dstats + 5 * kStatWords);
             else if (new_f32)
