@@ -436,7 +436,7 @@ __global__ __launch_bounds__(NW * 64) void k_leaf_mfma(
 }
 
 // ------------------------------------------------------------- wide leaves
-// Leaves of up to MP (256 or 512) points with the re-ranked first pass, at
+// Leaves of up to MP (64 to 512) points with the re-ranked first pass, at
 // most 64 candidates per row (c <= 64, k <= 64), D % 4 == 0.  One workgroup
 // (4 wavefronts) per leaf, rows in batches of 64.  After the MFMA Gram, every
 // step works on 16-lane groups, one row per group, four rows per wavefront:
@@ -1369,12 +1369,14 @@ int launch_fmt(const LeafArgs& a, const ReducedRows& rr, int* launches, char* er
             return go(k_leaf_mfma<FMT, MP, PR, CS, 64, false, NW>, TH);
         }
     };
-    // leaves above 128 points with at most 64 candidates per row: the wide
-    // kernel (KNNG_LEAF_WIDE=0 keeps k_leaf_mfma)
+    // at most 64 candidates per row (and more than 32 when leaves have at most
+    // 128 points): the wide kernel (KNNG_LEAF_WIDE=0 keeps k_leaf_mfma)
     const char* wide_env = std::getenv("KNNG_LEAF_WIDE");
-    const bool wide = !EXACT && lm > 128 && c <= 64 && a.D % 4 == 0 &&
+    const bool wide = !EXACT && c <= 64 && a.D % 4 == 0 &&
                       (wide_env == nullptr || std::atoi(wide_env) != 0);
     if (wide) {
+        if (lm <= 64) return go(k_leaf_wide<FMT, 64>);
+        if (lm <= 128) return go(k_leaf_wide<FMT, 128>);
         if (lm <= 256) return go(k_leaf_wide<FMT, 256>);
         return go(k_leaf_wide<FMT, 512>);
     }
