@@ -78,6 +78,11 @@ typedef struct {
                                come from the exact BF16 matrix-core pass; the
                                values are unchanged, so are the results.  0: FP32 */
     int32_t reserved;
+    const char* tune_cache; /* nullable path of knng_autotune's cache file: the build
+                               takes the tuned choices stored for its shape (none
+                               stored, or NULL: the built-in defaults).  The choices
+                               never change results.  Read on first use per path and
+                               kept in memory; the file is owned by the caller. */
 } knng_options;
 
 typedef struct {
@@ -140,6 +145,33 @@ int knng_build(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_tre
 int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_trees,
                   int32_t leaf_max, uint64_t seed, int32_t* ids_out, float* dists_out,
                   const knng_options* opt, knng_stats* stats_out, hipStream_t stream);
+
+/*
+ * knng_autotune -- the size buckets and tile shapes of the description above
+ * are chosen by a small autotuner (not in the paper: runtime of this
+ * library).  Its knobs are the build's result-invariant choices, in this order
+ * (KNNG_TUNE_KNOBS values): FP32-row assignment rows per step (1, 2); the
+ * reduced-copy filter of FP32-row passes (0, 1); uint8-row matrix-core
+ * assignment rows per step (1, 2) and loads ahead (1, 2); chunk dispatch
+ * order (0, 1); the 16-lane-group leaf kernel (0, 1); leaf size buckets
+ * (0, 1); the bitonic merge (0, 1).  For each knob in turn it runs
+ * knng_build_ex on the caller's data with the other knobs at their best so
+ * far, checks that the graph is bit-identical to the build with default
+ * knobs (else KNNG_ERR_HIP and a message naming the knob: that would be a
+ * bug), times two builds and keeps a value that is at least 2% faster.  The
+ * choices go to cache_path (a line keyed by the build's shape: D, k, n_trees,
+ * leaf_max, the options that select the path, floor(log2 n); an existing line
+ * of that key is replaced) and, if chosen_out is not NULL, to
+ * chosen_out[KNNG_TUNE_KNOBS].  Arguments as knng_build_ex; opt->tune_cache
+ * and opt->time_kernels are ignored.  It allocates two output buffers of
+ * n*k*8 bytes with hipMalloc and runs about 2 + 3 * KNNG_TUNE_KNOBS builds.
+ *   Errors: those of knng_build_ex; KNNG_ERR_INVALID_ARG for an empty
+ *   cache_path or a file that cannot be written.
+ */
+#define KNNG_TUNE_KNOBS 8
+int knng_autotune(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_trees,
+                  int32_t leaf_max, uint64_t seed, const knng_options* opt,
+                  const char* cache_path, int32_t* chosen_out, hipStream_t stream);
 
 /*
  * knng_partition -- one round's clustering (Sec. 3.1: bisect repeatedly with

@@ -15,7 +15,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libknng.so")
 SOURCES = ["api.hip", "partition.hip", "leaf.hip", "leaf_mfma.hip", "leaf_mfma_bf16.hip",
            "leaf_mfma_f16.hip", "leaf_mfma_fp8.hip", "merge.hip", "prep.hip", "subtree.hip", "assign_mfma.hip",
-           "search.hip", "workspace.hip", "ivf.hip", "assign_f32.hip"]
+           "search.hip", "workspace.hip", "ivf.hip", "assign_f32.hip", "tune.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [

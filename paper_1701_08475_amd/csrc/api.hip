@@ -27,6 +27,20 @@ int set_err(int code, const char* fmt, ...) {
     return code;
 }
 
+}  // namespace
+
+namespace knng {
+int report_error(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+}  // namespace knng
+
+namespace {
+
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 struct Resolved {
@@ -163,6 +177,7 @@ void knng_default_options(knng_options* o) {
     o->time_kernels = 0;
     o->compact = 1;
     o->reserved = 0;
+    o->tune_cache = nullptr;
 }
 
 const char* knng_status_string(int status) {
@@ -179,7 +194,7 @@ const char* knng_status_string(int status) {
 
 const char* knng_last_error(void) { return g_err; }
 
-int knng_version(void) { return 102; }
+int knng_version(void) { return 103; }
 
 int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_trees,
                   int32_t leaf_max, uint64_t seed, int32_t* ids_out, float* dists_out,
@@ -208,6 +223,10 @@ int knng_build_ex(const float* data, int64_t n, int32_t D, int32_t k, int32_t n_
                        k, o.rerank, lm_eff);
 
     hipStream_t s = stream;
+    // tuned choices (knng_autotune's cache) for this shape, if any
+    const knng::TuneScope tune(opt != nullptr ? opt->tune_cache : nullptr,
+                               knng::tune_key(n, D, k, n_trees, leaf_max, o.precision, o.rerank,
+                                              o.compact, o.plain, o.min_leaf, o.max_iter));
     knng::DeviceLock dlock;  // workspace blocks: one call per device at a time
     Events ev(stats_out != nullptr);
     knng::KernelTimer timer(o.time_kernels != 0 && stats_out != nullptr);

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <cstddef>
+#include <string>
 
 namespace knng {
 
@@ -205,6 +206,35 @@ struct AssignF32Fns {
     RedotsFn redots = nullptr;
 };
 bool pick_assign_f32_fns(int D, int u, AssignF32Fns* f);
+
+// ---------------------------------------------------------------- tuning
+// Result-invariant choices of the build (csrc/tune.hip).  knob(): the
+// environment variable if set, else the current call's tuned value, else
+// fallback_default.
+enum Knob {
+    kKnobAssignUnroll, kKnobFilter, kKnobAssignMU, kKnobAssignMPD, kKnobChunkOrder,
+    kKnobLeafWide, kKnobLeafBuckets, kKnobMergeNetwork, kKnobs
+};
+int knob(Knob id, int fallback_default);
+int knob_default(Knob id);
+std::string tune_key(int64_t n, int D, int k, int T, int L, int precision, int rerank, int compact,
+                     int plain, int min_leaf, int max_iter);
+// The tuned knob values in force on this thread for the scope's life: the
+// cache file's entry for `key` (no entry: none), or explicit values.
+class TuneScope {
+  public:
+    TuneScope(const char* cache_path, const std::string& key);
+    explicit TuneScope(const int* vals);
+    ~TuneScope();
+    TuneScope(const TuneScope&) = delete;
+    TuneScope& operator=(const TuneScope&) = delete;
+  private:
+    int vals_[kKnobs] = {};
+    const int* prev_ = nullptr;
+    bool active_ = false;
+};
+// Sets the library's error text for the calling thread; returns code.
+int report_error(int code, const char* fmt, ...);
 
 struct ReducedRows;
 

@@ -179,10 +179,9 @@ int leaf_run_mfma(const LeafArgs& a, const ReducedRows& rr, int* launches, char*
         return kUnsupported;
     }
     // one launch shaped by the largest leaf when every leaf fits 128 points
-    // or KNNG_LEAF_BUCKETS=0; else one launch per non-empty size bucket
-    const char* env = std::getenv("KNNG_LEAF_BUCKETS");
-    const bool bucketed = (env == nullptr || std::atoi(env) != 0) && a.leaf_max > 128 &&
-                          a.n_leaves > 0;
+    // or the knob leaf_buckets is 0 (KNNG_LEAF_BUCKETS=0); else one launch per
+    // non-empty size bucket
+    const bool bucketed = knob(kKnobLeafBuckets, 1) != 0 && a.leaf_max > 128 && a.n_leaves > 0;
     if (!bucketed) return run_format(a, rr, launches, err, errlen);
     hipStream_t s = a.stream;
     int32_t* ctr = nullptr;  // [0..3] counts, [4..7] fill cursors

@@ -1370,10 +1370,9 @@ int launch_fmt(const LeafArgs& a, const ReducedRows& rr, int* launches, char* er
         }
     };
     // at most 64 candidates per row (and more than 32 when leaves have at most
-    // 128 points): the wide kernel (KNNG_LEAF_WIDE=0 keeps k_leaf_mfma)
-    const char* wide_env = std::getenv("KNNG_LEAF_WIDE");
-    const bool wide = !EXACT && c <= 64 && a.D % 4 == 0 &&
-                      (wide_env == nullptr || std::atoi(wide_env) != 0);
+    // 128 points): the wide kernel (knob leaf_wide = 0, KNNG_LEAF_WIDE=0,
+    // keeps k_leaf_mfma)
+    const bool wide = !EXACT && c <= 64 && a.D % 4 == 0 && knob(kKnobLeafWide, 1) != 0;
     if (wide) {
         if (lm <= 64) return go(k_leaf_wide<FMT, 64>);
         if (lm <= 128) return go(k_leaf_wide<FMT, 128>);

@@ -1,8 +1,8 @@
 // Union of the rounds' candidate lists into G (Alg. 1: the rows of G are
 // refined round after round; a pair already compared is not counted twice).
 //
-// k <= 32: one thread per row (k_merge_rows).  Otherwise (or with
-// KNNG_MERGE_NETWORK set) one wavefront per row: the row's candidates from every tree are ordered by
+// k <= 32: one thread per row (k_merge_rows).  Otherwise (or with the knob
+// merge_network = 1, KNNG_MERGE_NETWORK=1) one wavefront per row: the row's candidates from every tree are ordered by
 // (d32, id) with a bitonic network (a merge of the trees' sorted lists when
 // k <= 32, else a full sort), adjacent equal keys are dropped (the same id
 // always carries the same d32 bits, so duplicates are adjacent), and the
@@ -313,7 +313,7 @@ MergeFn pick(int slots) {
 
 int merge_run(const MergeArgs& a, int* launches, char* err, size_t errlen) {
     const int k = a.k;
-    if (k <= 32 && std::getenv("KNNG_MERGE_NETWORK") == nullptr) {
+    if (k <= 32 && knob(kKnobMergeNetwork, 0) == 0) {
         const RowMergeFn f = pick_rows(k, a.cand_ids, a.cand_d, a.ids_out, a.dists_out);
         if (a.timer) a.timer->begin(kKMerge, a.stream);
         f<<<static_cast<unsigned>((a.n + 255) / 256), 256, 0, a.stream>>>(

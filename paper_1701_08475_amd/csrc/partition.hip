@@ -1247,7 +1247,7 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     int epl = env_int("KNNG_ASSIGN_EPL", 8);
     // rows per lane group and step: 2 keeps more rows in flight (FP32 rows of
     // 960 dimensions: 11% faster than 1; 4 is slower, fewer waves fit)
-    int unroll = env_int("KNNG_ASSIGN_UNROLL", 2);
+    int unroll = knob(kKnobAssignUnroll, 2);
     if (epl != 4 && epl != 8 && epl != 16) epl = 8;
     if (unroll != 1 && unroll != 2 && unroll != 4) unroll = 2;
     // FP32 rows with D % 4 == 0: first pass with chunk totals, later passes
@@ -1260,7 +1260,7 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     // results are the same either way)
     AssignRfFn rf = nullptr;
     if (new_f32 && a.filter != nullptr && a.precision >= 1 && a.precision <= 3 &&
-        env_int("KNNG_PARTITION_FILTER", 1) != 0)
+        knob(kKnobFilter, 1) != 0)
         rf = f32.rf[a.precision - 1];
     const bool totals = use_u8 || new_f32;  // P holds chunk totals and side-1 sums
     AssignFn<uint8_t> assign8[2] = {nullptr, nullptr};
@@ -1275,8 +1275,8 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
         // margin on the matrix cores where D allows (KNNG_ASSIGN_MFMA=0: FP64 VALU kernel)
         if (env_int("KNNG_ASSIGN_MFMA", 1) != 0) {
             AssignFn<uint8_t> fm[2], fw[2];
-            if (pick_assign_u8_mfma(D, env_int("KNNG_ASSIGN_M_U", 1),
-                                    env_int("KNNG_ASSIGN_M_PD", 1), fm, fw)) {
+            if (pick_assign_u8_mfma(D, knob(kKnobAssignMU, 1),
+                                    knob(kKnobAssignMPD, 1), fm, fw)) {
                 assign8[0] = fm[0];
                 assign8[1] = fm[1];
                 assign8w[0] = fw[0];
@@ -1314,7 +1314,7 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
     // dispatch order of the assignment chunks: bit 0 sorted by first row id
     // (default: 2-4% faster passes, chunks that gather nearby rows run
     // together), bit 1 XCD-aware workgroup placement (slower on MI355X)
-    const int order_mode = env_int("KNNG_CHUNK_ORDER", 1);
+    const int order_mode = knob(kKnobChunkOrder, 1);
     const int order_min = env_int("KNNG_CHUNK_ORDER_MIN", 4096);  // chunks per level
     int key_shift = 0;
     while (((n - 1) >> key_shift) >= 4096) ++key_shift;

@@ -30,7 +30,12 @@ class KnngOptions(ctypes.Structure):
                 ("rerank_factor", ctypes.c_int32), ("min_leaf", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("plain", ctypes.c_int32),
                 ("check_finite", ctypes.c_int32), ("time_kernels", ctypes.c_int32),
-                ("compact", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("compact", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tune_cache", ctypes.c_char_p)]
+
+# knng_autotune's knobs, in the order of its chosen_out array
+TUNE_KNOBS = ("assign_unroll", "filter", "assign_m_u", "assign_m_pd", "chunk_order",
+              "leaf_wide", "leaf_buckets", "merge_network")
 
 
 class KnngStats(ctypes.Structure):
@@ -74,6 +79,13 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libknng.so is not built (run __graft_entry__.build() or "
                            "python -m paper_1701_08475_amd.build_lib)")
+    # torch's HIP runtime is brought up first (where a GPU is present): loaded
+    # before it, the library's HIP calls found no device on the GPU machine
+    try:
+        import torch
+        torch.cuda.is_available()
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     vp, i64, i32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64
     L.knng_build.restype = ctypes.c_int
@@ -102,6 +114,9 @@ def lib():
                                  ctypes.POINTER(i32), vp]
     L.knng_ivf_build.argtypes = [vp, i64, i32, vp, i32, vp, i32, vp, vp, vp, vp]
     L.knng_ivf_seeds.argtypes = [vp, i64, i32, vp, i32, vp, i32, vp, vp, i64, i32, i32, vp, vp]
+    L.knng_autotune.restype = ctypes.c_int
+    L.knng_autotune.argtypes = [vp, i64, i32, i32, i32, i32, u64, ctypes.POINTER(KnngOptions),
+                                ctypes.c_char_p, ctypes.POINTER(i32), vp]
     L.knng_default_options.restype = None
     L.knng_default_options.argtypes = [ctypes.POINTER(KnngOptions)]
     L.knng_status_string.restype = ctypes.c_char_p
@@ -120,7 +135,7 @@ def _check(rc):
 
 
 def options(precision="fp32", rerank_factor=2, min_leaf=0, max_iter=0, plain=False,
-            check_finite=True, time_kernels=False, compact=True):
+            check_finite=True, time_kernels=False, compact=True, tune_cache=None):
     o = KnngOptions()
     lib().knng_default_options(ctypes.byref(o))
     o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
@@ -131,6 +146,8 @@ def options(precision="fp32", rerank_factor=2, min_leaf=0, max_iter=0, plain=Fal
     o.check_finite = 1 if check_finite else 0
     o.time_kernels = 1 if time_kernels else 0
     o.compact = 1 if compact else 0
+    # the path must outlive the call: ctypes keeps this bytes object with o
+    o.tune_cache = tune_cache.encode() if isinstance(tune_cache, str) else tune_cache
     return o
 
 
@@ -150,7 +167,7 @@ def _dev_f32(x):
 
 def build(x, k, n_trees, leaf_max, seed=0, precision="fp32", rerank_factor=2, min_leaf=0,
           max_iter=0, plain=False, stats=False, time_kernels=False, compact=True, out=None,
-          stream=None):
+          stream=None, tune_cache=None):
     """kNN graph of the rows of x.  Returns (ids int32 [n,k], dists f32 [n,k])
     and a stats dict when stats=True."""
     import torch
@@ -162,7 +179,7 @@ def build(x, k, n_trees, leaf_max, seed=0, precision="fp32", rerank_factor=2, mi
     else:
         ids, ds = out
     o = options(precision, rerank_factor, min_leaf, max_iter, plain,
-                time_kernels=time_kernels, compact=compact)
+                time_kernels=time_kernels, compact=compact, tune_cache=tune_cache)
     st = KnngStats() if stats else None
     rc = lib().knng_build_ex(ctypes.c_void_p(x.data_ptr()), n, D, k, n_trees, leaf_max,
                              ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF),
@@ -171,6 +188,22 @@ def build(x, k, n_trees, leaf_max, seed=0, precision="fp32", rerank_factor=2, mi
                              _stream(stream))
     _check(rc)
     return (ids, ds, st.as_dict()) if stats else (ids, ds)
+
+
+def autotune(x, k, n_trees, leaf_max, cache_path, seed=0, precision="fp32", rerank_factor=2,
+             min_leaf=0, max_iter=0, compact=True, stream=None):
+    """knng_autotune: time the build's result-invariant choices on x, check that
+    each gives the default build's graph bit for bit, store the fastest in
+    cache_path.  Returns {knob: value}."""
+    x = _dev_f32(x)
+    n, D = x.shape
+    o = options(precision, rerank_factor, min_leaf, max_iter, compact=compact)
+    chosen = (ctypes.c_int32 * len(TUNE_KNOBS))()
+    rc = lib().knng_autotune(ctypes.c_void_p(x.data_ptr()), n, D, k, n_trees, leaf_max,
+                             ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ctypes.byref(o),
+                             str(cache_path).encode(), chosen, _stream(stream))
+    _check(rc)
+    return dict(zip(TUNE_KNOBS, list(chosen)))
 
 
 def build_plain_call(x, k, n_trees, leaf_max, seed, ids, ds, stream=None):

@@ -42,9 +42,11 @@ def test_status_codes_match_header(L):
 def test_options_struct_layout(L):
     o = knng.KnngOptions()
     L.knng_default_options(ctypes.byref(o))
-    assert o.struct_size == ctypes.sizeof(knng.KnngOptions) == 40
+    # ten int32, then the tune-cache path pointer
+    assert o.struct_size == ctypes.sizeof(knng.KnngOptions) == 48
     assert (o.precision, o.rerank_factor, o.min_leaf, o.max_iter, o.plain, o.check_finite,
             o.time_kernels, o.compact) == (0, 2, 0, 10, 0, 1, 0, 1)
+    assert o.tune_cache is None
     # 5 int64, 2 int32, 5 float, 3 (float, int32) pairs, 2 int32 = 100 bytes,
     # padded to 104, then three int64
     assert ctypes.sizeof(knng.KnngStats) == 128
@@ -193,3 +195,16 @@ def test_leaf_search_noalloc_rejects_oversized_requests(L):
                                     ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE), nl2, None,
                                     ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE), None)
     assert rc == knng.KNNG_ERR_UNSUPPORTED
+
+
+def test_autotune_knob_list_matches_header(L):
+    txt = open(os.path.join(ROOT, "include", "knng.h")).read()
+    m = re.search(r"#define\s+KNNG_TUNE_KNOBS\s+(\d+)", txt)
+    assert m and int(m.group(1)) == len(knng.TUNE_KNOBS)
+
+
+def test_autotune_rejects_empty_cache_path(L):
+    # checked before any HIP call, so it runs without a GPU
+    rc = L.knng_autotune(None, 100, 8, 5, 1, 50, 0, None, b"", None, None)
+    assert rc == knng.KNNG_ERR_INVALID_ARG
+    assert b"cache_path" in L.knng_last_error()
