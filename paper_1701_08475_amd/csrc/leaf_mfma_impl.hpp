@@ -486,7 +486,8 @@ __device__ __forceinline__ int group16_excl_scan(int v, int gl) {
 }
 
 // Selection, per 16-lane group (one row each; lane l holds the row's keys
-// kv[t] = key of position t*16 + l in registers, invalid ones ~0), of the
+// kv[t] = key of position t*16 + l in registers, invalid ones ~0, and every
+// key of t >= tmax invalid: those columns are skipped), of the
 // row's ce smallest valid keys by (key, position).  lo, hi: the minimum and
 // maximum of the lane's valid keys.  The keys of rank < ce lie in [lo, hi]
 // (initially the row's minimum and maximum); a pass counts them in 128 bins
@@ -504,7 +505,7 @@ __device__ __forceinline__ int group16_excl_scan(int v, int gl) {
 // row).  act: this group's row exists (uniform within the group).  Candidate
 // positions go to sel[0..ce) of the group's row.
 template <int KT>
-__device__ __forceinline__ void group_select(const uint32_t (&kv)[KT], uint32_t lo, uint32_t hi,
+__device__ __forceinline__ void group_select(const uint32_t (&kv)[KT], int tmax, uint32_t lo, uint32_t hi,
                                              bool act, int ce, uint32_t* hist, uint64_t* lst,
                                              uint16_t* sel) {
     static_assert(KT <= 32, "one bit per key column");
@@ -536,6 +537,7 @@ __device__ __forceinline__ void group_select(const uint32_t (&kv)[KT], uint32_t 
         if (!done) {
 #pragma unroll
             for (int t = 0; t < KT; ++t) {
+                if (t >= tmax) break;
                 const uint32_t kt = kv[t];
                 if (kt >= lo && kt <= hi) atomicAdd(&h[(kt - lo) >> shift], inc);
             }
@@ -606,15 +608,18 @@ __device__ __forceinline__ void group_select(const uint32_t (&kv)[KT], uint32_t 
             int nin = 0;
 #pragma unroll
             for (int t = 0; t < KT; ++t) {
+                if (t >= tmax) break;
                 const bool in = rank_now && kv[t] >= lo && kv[t] <= hi;
                 inb |= in ? (1u << t) : 0u;
                 nin += in ? 1 : 0;
             }
             int j = group16_excl_scan(nin, gl);
 #pragma unroll
-            for (int t = 0; t < KT; ++t)
+            for (int t = 0; t < KT; ++t) {
+                if (t >= tmax) break;
                 if ((inb >> t) & 1u)
                     lst[j++] = (static_cast<uint64_t>(kv[t]) << 32) | static_cast<uint32_t>(t * 16 + gl);
+            }
             wave_lds_sync();
             const uint64_t e0 = (rank_now && gl < cnt) ? lst[gl] : ~0ull;
             const uint64_t e1 = (rank_now && gl + 16 < cnt) ? lst[gl + 16] : ~0ull;
@@ -646,6 +651,7 @@ __device__ __forceinline__ void group_select(const uint32_t (&kv)[KT], uint32_t 
         int nt = 0;
 #pragma unroll
         for (int t = 0; t < KT; ++t) {
+                if (t >= tmax) break;
             const uint64_t kp = (static_cast<uint64_t>(kv[t]) << 32) | static_cast<uint32_t>(t * 16 + gl);
             const bool take = act && kp <= th;
             tb |= take ? (1u << t) : 0u;
@@ -653,8 +659,10 @@ __device__ __forceinline__ void group_select(const uint32_t (&kv)[KT], uint32_t 
         }
         int j = group16_excl_scan(nt, gl);
 #pragma unroll
-        for (int t = 0; t < KT; ++t)
+        for (int t = 0; t < KT; ++t) {
+            if (t >= tmax) break;
             if ((tb >> t) & 1u) sel[j++] = static_cast<uint16_t>(t * 16 + gl);
+        }
         return;
     }
     // some group of the wave ends on a single value: the taken keys in
@@ -664,6 +672,7 @@ __device__ __forceinline__ void group_select(const uint32_t (&kv)[KT], uint32_t 
     int taken = 0, eq_seen = 0;
 #pragma unroll
     for (int t = 0; t < KT; ++t) {
+                if (t >= tmax) break;
         const uint32_t kt = kv[t];
         const uint64_t kp = (static_cast<uint64_t>(kt) << 32) | static_cast<uint32_t>(t * 16 + gl);
         const bool lt = act && (ranked ? kp <= thr : single ? kt < lo : kt <= hi);
@@ -796,10 +805,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             int mv = m, lnv = lane;
             asm volatile("" : "+v"(mv), "+v"(lnv));
             const int glp = lnv & 15;  // gl, likewise taken anew
-            // Gram of the panel, in groups of GT column tiles per wave
+            // Gram of the panel, in groups of GT column tiles per wave; wave wv
+            // takes tiles wv, wv + NW, ... so that the tiles holding columns
+            // (the leaf's first m) are spread over the waves, and a group
+            // wholly past the leaf is skipped (its keys are never read)
             constexpr int GT = TPW < 4 ? TPW : 4;
 #pragma unroll
             for (int tg = 0; tg < TPW; tg += GT) {
+                if ((tg * NW + wv) * 16 >= m) continue;
                 const int arow = prow + glp;
                 const uint8_t* ap = Xr + static_cast<size_t>(ids[arow < mv ? arow : 0]) * rstride +
                                     static_cast<size_t>(8 * kg) * F::kBytes;
@@ -807,7 +820,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                 bool bok[GT];
 #pragma unroll
                 for (int t = 0; t < GT; ++t) {
-                    const int bcol = (wv * TPW + tg + t) * 16 + glp;
+                    const int bcol = ((tg + t) * NW + wv) * 16 + glp;
                     bok[t] = bcol < mv;
                     bp[t] = Xr + static_cast<size_t>(ids[bcol < mv ? bcol : 0]) * rstride +
                             static_cast<size_t>(8 * kg) * F::kBytes;
@@ -855,7 +868,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                 }
 #pragma unroll
                 for (int t = 0; t < GT; ++t) {
-                    const int col = (wv * TPW + tg + t) * 16 + glp;
+                    const int col = ((tg + t) * NW + wv) * 16 + glp;
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const int rl = 4 * kg + i;
@@ -874,10 +887,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                 const int row = prow + rl;
                 const bool act = rl < nb - pp;
                 uint16_t* sel = csel + (pp + (act ? rl : 0)) * kWave;
+                const int tmax = (m + 15) >> 4;  // key columns holding members
                 if (ce >= m - 1) {  // every other member is a candidate
                     if (act) {
 #pragma unroll
                         for (int t = 0; t < KT; ++t) {
+                            if (t >= tmax) break;
                             const int col = t * 16 + glp;
                             const int e = col < row ? col : col - 1;
                             if (col < mv && col != row) sel[e] = static_cast<uint16_t>(col);
@@ -889,7 +904,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                     uint32_t kv[KT];
                     uint32_t lo = 0xffffffffu, hi = 0u;
 #pragma unroll
+                    for (int t = 0; t < KT; ++t) kv[t] = 0xffffffffu;
+#pragma unroll
                     for (int t = 0; t < KT; ++t) {
+                        if (t >= tmax) break;
                         const int col = t * 16 + glp;
                         const uint32_t kt = (act && col < mv && col != row) ? fkey(dist[act ? rl : 0][col])
                                                                             : 0xffffffffu;
@@ -902,7 +920,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                     wave_lds_sync();
                     // (the list starts at the row's first 8-byte aligned word)
                     const int lrow = ((act ? rl : 0) * (MP + 1) + 1) & ~1;
-                    group_select<KT>(kv, lo, hi, act, ce, s_hist + wv * 256,
+                    group_select<KT>(kv, tmax, lo, hi, act, ce, s_hist + wv * 256,
                                      reinterpret_cast<uint64_t*>(region + lrow), sel);
                 }
             }
