@@ -737,9 +737,10 @@ __device__ __forceinline__ void group_sort64(uint64_t (&v)[NR][4]) {
     }
 }
 
-// (three waves per SIMD: three workgroups per compute unit, 3 x 51 KB of LDS)
+// (512-point leaves: three waves per SIMD, three workgroups per compute unit in
+// 3 x 51 KB of LDS; smaller leaves: four, in at most 4 x 32 KB)
 template <int FMT, int MP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_leaf_wide(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MP <= 256 ? 4 : 3))) void k_leaf_wide(
     const float* __restrict__ X, const uint8_t* __restrict__ Xr, int64_t n, int D, int Dp, int rsb,
     const float* __restrict__ nrm, const float* __restrict__ sinv, int k, int c,
     const int32_t* __restrict__ perm, const LeafRec* __restrict__ leaves,
