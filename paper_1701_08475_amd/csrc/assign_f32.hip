@@ -757,7 +757,8 @@ __global__ __launch_bounds__(256) void k_assign_rf(
 // ---------------------------------------------------------------- repair margins
 // FP64 margins of every member of the nodes in the repair list (rep[0]
 // count), with the labelling code's lane layout and order, into dots (the
-// repair ranks the members by them).  One block per listed node at a time.
+// repair ranks the members by them).  Every workgroup takes a share of every
+// listed node's rows (a repaired node can hold most of a level's rows).
 template <int G, int NF>
 __global__ __launch_bounds__(256) void k_redots_f32(const NodeRec* __restrict__ nodes,
                                                      const int32_t* __restrict__ rep, int64_t n,
@@ -770,16 +771,18 @@ __global__ __launch_bounds__(256) void k_redots_f32(const NodeRec* __restrict__ 
     const int nrep = rep[0];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int g = lane / G, l = lane % G;
-    for (int ri = blockIdx.x; ri < nrep; ri += gridDim.x) {
+    for (int ri = 0; ri < nrep; ++ri) {
         const int node = rep[1 + ri];
         const NodeRec r = nodes[node];
         const int m = r.size;
         const int n0 = n0f[node];
         if (n0 >= min_leaf && m - n0 >= min_leaf) continue;  // the same test as the repair
+        const int first = (blockIdx.x * 4 + wv) * RPW;
+        if (first >= m) continue;
         const size_t base = static_cast<size_t>(r.tree) * n + r.start;
         double w[NF][4];
         centres_wh<G, NF>(C + static_cast<size_t>(node) * 2 * D, D, l, w);
-        for (int p0 = wv * RPW; p0 < m; p0 += 4 * RPW) {  // uniform per wave
+        for (int p0 = first; p0 < m; p0 += gridDim.x * 4 * RPW) {  // uniform per wave
             const int p = p0 + g;
             float x[NF][4];
             const float* xr = X + static_cast<size_t>(p < m ? perm[base + p] : 0) * D;

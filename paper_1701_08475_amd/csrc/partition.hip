@@ -1490,8 +1490,8 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
             }
         }
         if (new_f32) {  // the repair ranks by the final margins: recompute them
-            f32.redots<<<std::min(na, 2048), 256, 0, s>>>(nodes[cur], rep, n, a.X, D, a.perm, C,
-                                                          n0f, a.min_leaf, dots);
+            f32.redots<<<1024, 256, 0, s>>>(nodes[cur], rep, n, a.X, D, a.perm, C, n0f,
+                                            a.min_leaf, dots);
             KNNG_LAUNCH();
         }
         repair<<<std::min(na, 2048), 256, 0, s>>>(nodes[cur], rep, n, a.X8, D, a.perm, C, dots,
