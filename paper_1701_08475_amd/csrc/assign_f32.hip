@@ -757,8 +757,9 @@ __global__ __launch_bounds__(256) void k_assign_rf(
 // ---------------------------------------------------------------- repair margins
 // FP64 margins of every member of the nodes in the repair list (rep[0]
 // count), with the labelling code's lane layout and order, into dots (the
-// repair ranks the members by them).  Every workgroup takes a share of every
-// listed node's rows (a repaired node can hold most of a level's rows).
+// repair ranks the members by them).  A node of up to 16k rows goes to one
+// workgroup; every workgroup takes a share of a larger node's rows (a
+// repaired node can hold most of a level's rows).
 template <int G, int NF>
 __global__ __launch_bounds__(256) void k_redots_f32(const NodeRec* __restrict__ nodes,
                                                      const int32_t* __restrict__ rep, int64_t n,
@@ -768,21 +769,17 @@ __global__ __launch_bounds__(256) void k_redots_f32(const NodeRec* __restrict__ 
                                                      const int32_t* __restrict__ n0f, int min_leaf,
                                                      double* __restrict__ dots) {
     constexpr int RPW = kWave / G;
+    constexpr int kBig = 16384;  // rows of a node that every workgroup shares
     const int nrep = rep[0];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int g = lane / G, l = lane % G;
-    for (int ri = 0; ri < nrep; ++ri) {
-        const int node = rep[1 + ri];
-        const NodeRec r = nodes[node];
+    // rows p0 + g, p0 + step + g, ... of one listed node
+    auto margins = [&](int node, const NodeRec& r, int p_first, int step) {
         const int m = r.size;
-        const int n0 = n0f[node];
-        if (n0 >= min_leaf && m - n0 >= min_leaf) continue;  // the same test as the repair
-        const int first = (blockIdx.x * 4 + wv) * RPW;
-        if (first >= m) continue;
         const size_t base = static_cast<size_t>(r.tree) * n + r.start;
         double w[NF][4];
         centres_wh<G, NF>(C + static_cast<size_t>(node) * 2 * D, D, l, w);
-        for (int p0 = first; p0 < m; p0 += gridDim.x * 4 * RPW) {  // uniform per wave
+        for (int p0 = p_first; p0 < m; p0 += step) {  // uniform per wave
             const int p = p0 + g;
             float x[NF][4];
             const float* xr = X + static_cast<size_t>(p < m ? perm[base + p] : 0) * D;
@@ -790,6 +787,36 @@ __global__ __launch_bounds__(256) void k_redots_f32(const NodeRec* __restrict__ 
             for (int j = 0; j < NF; ++j) load_vec(xr, (l + G * j) * 4, D, p < m, x[j]);
             const double dot = row_dot<G, NF>(x, w);
             if (p < m && l == 0) dots[base + p] = dot;
+        }
+    };
+    // the repair's own test: a side below min_leaf
+    auto repaired = [&](int node, int m) {
+        const int n0 = n0f[node];
+        return !(n0 >= min_leaf && m - n0 >= min_leaf);
+    };
+    // nodes of at most kBig rows: one workgroup each
+    for (int ri = blockIdx.x; ri < nrep; ri += gridDim.x) {
+        const int node = rep[1 + ri];
+        const NodeRec r = nodes[node];
+        if (r.size > kBig || !repaired(node, r.size)) continue;
+        margins(node, r, wv * RPW, 4 * RPW);
+    }
+    // larger nodes: every workgroup takes a share (the list is scanned 64
+    // entries at a time, one per lane)
+    for (int r0 = 0; r0 < nrep; r0 += kWave) {
+        const int ri = r0 + lane;
+        int node = -1;
+        if (ri < nrep) {
+            node = rep[1 + ri];
+            const int m = nodes[node].size;
+            if (m <= kBig || !repaired(node, m)) node = -1;
+        }
+        uint64_t big = __ballot(node >= 0);
+        while (big) {
+            const int src = __builtin_ctzll(big);
+            big &= big - 1;
+            const int bn = __shfl(node, src, kWave);
+            margins(bn, nodes[bn], (blockIdx.x * 4 + wv) * RPW, gridDim.x * 4 * RPW);
         }
     }
 }

@@ -139,17 +139,37 @@ __global__ void k_bucket_count(const LeafRec* __restrict__ leaves, int64_t nl,
 
 // out <- the leaves grouped by bucket, bucket b from the sum of the counts
 // before it (cnt[0..3]); order inside a bucket is arbitrary (every leaf
-// writes only its own rows' lists).  cursor[0..3] zeroed by the caller.
+// writes only its own rows' lists).  cursor[0..3] zeroed by the caller.  The
+// slots are taken per wavefront: one atomic per bucket and step, each lane's
+// slot from the ballot of its bucket.
 __global__ void k_bucket_fill(const LeafRec* __restrict__ leaves, int64_t nl,
                               const int32_t* __restrict__ cnt, int32_t* __restrict__ cursor,
                               LeafRec* __restrict__ out) {
-    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < nl;
-         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const LeafRec r = leaves[i];
-        const int b = bucket_of(r.size);
-        int64_t base = 0;
-        for (int q = 0; q < b; ++q) base += cnt[q];
-        out[base + atomicAdd(&cursor[b], 1)] = r;
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
+    int64_t first[kBuckets];
+    first[0] = 0;
+    for (int q = 1; q < kBuckets; ++q) first[q] = first[q - 1] + cnt[q - 1];
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i0 = blockIdx.x * static_cast<int64_t>(blockDim.x) + (threadIdx.x & ~63); i0 < nl;
+         i0 += stride) {  // uniform per wavefront
+        const int64_t i = i0 + lane;
+        const bool live = i < nl;
+        LeafRec r{};
+        int b = -1;
+        if (live) {
+            r = leaves[i];
+            b = bucket_of(r.size);
+        }
+#pragma unroll
+        for (int q = 0; q < kBuckets; ++q) {
+            const uint64_t m = __ballot(b == q);
+            if (m == 0) continue;
+            int slot0 = 0;
+            if (lane == __builtin_ctzll(m)) slot0 = atomicAdd(&cursor[q], __popcll(m));
+            slot0 = __shfl(slot0, __builtin_ctzll(m), kWave);
+            if (b == q) out[first[q] + slot0 + __popcll(m & below)] = r;
+        }
     }
 }
 
