@@ -757,8 +757,8 @@ __global__ __launch_bounds__(256) void k_assign_rf(
 // ---------------------------------------------------------------- repair margins
 // FP64 margins of every member of the nodes in the repair list (rep[0]
 // count), with the labelling code's lane layout and order, into dots (the
-// repair ranks the members by them).  A node of up to 16k rows goes to one
-// workgroup; every workgroup takes a share of a larger node's rows (a
+// repair ranks the members by them).  A node of up to 2^20 elements goes to
+// one workgroup; every workgroup takes a share of a larger node's rows (a
 // repaired node can hold most of a level's rows).
 template <int G, int NF>
 __global__ __launch_bounds__(256) void k_redots_f32(const NodeRec* __restrict__ nodes,
@@ -769,7 +769,8 @@ __global__ __launch_bounds__(256) void k_redots_f32(const NodeRec* __restrict__ 
                                                      const int32_t* __restrict__ n0f, int min_leaf,
                                                      double* __restrict__ dots) {
     constexpr int RPW = kWave / G;
-    constexpr int kBig = 16384;  // rows of a node that every workgroup shares
+    // a node of more than 2^20 elements (rows x D) is shared by every workgroup
+    const int big_rows = (1 << 20) / D;
     const int nrep = rep[0];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int g = lane / G, l = lane % G;
@@ -794,11 +795,11 @@ __global__ __launch_bounds__(256) void k_redots_f32(const NodeRec* __restrict__ 
         const int n0 = n0f[node];
         return !(n0 >= min_leaf && m - n0 >= min_leaf);
     };
-    // nodes of at most kBig rows: one workgroup each
+    // smaller nodes: one workgroup each
     for (int ri = blockIdx.x; ri < nrep; ri += gridDim.x) {
         const int node = rep[1 + ri];
         const NodeRec r = nodes[node];
-        if (r.size > kBig || !repaired(node, r.size)) continue;
+        if (r.size > big_rows || !repaired(node, r.size)) continue;
         margins(node, r, wv * RPW, 4 * RPW);
     }
     // larger nodes: every workgroup takes a share (the list is scanned 64
@@ -809,7 +810,7 @@ __global__ __launch_bounds__(256) void k_redots_f32(const NodeRec* __restrict__ 
         if (ri < nrep) {
             node = rep[1 + ri];
             const int m = nodes[node].size;
-            if (m <= kBig || !repaired(node, m)) node = -1;
+            if (m <= big_rows || !repaired(node, m)) node = -1;
         }
         uint64_t big = __ballot(node >= 0);
         while (big) {
