@@ -535,11 +535,20 @@ __device__ __forceinline__ void group_select(const uint32_t (&kv)[KT], int tmax,
         *reinterpret_cast<uint4*>(hist + 4 * lane) = make_uint4(0u, 0u, 0u, 0u);
         wave_lds_sync();
         if (!done) {
+            // blocks of eight key columns, a block wholly past the leaf
+            // skipped; inside a block every key adds inc to its bin when it
+            // lies in [lo, hi] (the invalid key ~0 never does), else 0 to a
+            // bin of the lane's own (no branch per key)
+            const uint32_t span = hi - lo;
 #pragma unroll
-            for (int t = 0; t < KT; ++t) {
-                if (t >= tmax) break;
-                const uint32_t kt = kv[t];
-                if (kt >= lo && kt <= hi) atomicAdd(&h[(kt - lo) >> shift], inc);
+            for (int t0 = 0; t0 < KT; t0 += 8) {
+                if (t0 >= tmax) continue;
+#pragma unroll
+                for (int u = 0; u < 8 && t0 + u < KT; ++u) {
+                    const uint32_t off = kv[t0 + u] - lo;
+                    const bool in = off <= span;
+                    atomicAdd(&h[in ? (off >> shift) : static_cast<uint32_t>(8 * gl + u)], in ? inc : 0u);
+                }
             }
         }
         wave_lds_sync();
@@ -893,7 +902,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MP <= 256 ?
                     if (act) {
 #pragma unroll
                         for (int t = 0; t < KT; ++t) {
-                            if (t >= tmax) break;
+                            if ((t & ~7) >= tmax) continue;  // (~0 keys past the leaf are inert)
                             const int col = t * 16 + glp;
                             const int e = col < row ? col : col - 1;
                             if (col < mv && col != row) sel[e] = static_cast<uint16_t>(col);
@@ -908,7 +917,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MP <= 256 ?
                     for (int t = 0; t < KT; ++t) kv[t] = 0xffffffffu;
 #pragma unroll
                     for (int t = 0; t < KT; ++t) {
-                        if (t >= tmax) break;
+                        if ((t & ~7) >= tmax) continue;  // (~0 keys past the leaf are inert)
                         const int col = t * 16 + glp;
                         const uint32_t kt = (act && col < mv && col != row) ? fkey(dist[act ? rl : 0][col])
                                                                             : 0xffffffffu;
