@@ -1308,6 +1308,7 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
                               : L;
     // KNNG_TRACE_LEVELS=1: one line per level on stderr (nodes, chunks)
     const bool trace_levels = env_int("KNNG_TRACE_LEVELS", 0) != 0;
+    unsigned long long trace_f0 = 0, trace_e0 = 0;  // filter counters at the previous level's end
     NodeRec* sub = nullptr;
     NodeRec* nodes[2] = {nullptr, nullptr};
     int32_t* big[2] = {nullptr, nullptr};
@@ -1502,9 +1503,25 @@ int partition_run(const PartitionArgs& a, PartitionResult* res, char* err, size_
         KNNG_LAUNCH();
         k_copyback<<<cblocks, 256, 0, s>>>(n, nodes[cur], chunk_node, nc, perm_tmp, a.perm);
         KNNG_LAUNCH();
-        if (trace_levels)
-            std::fprintf(stderr, "[knng] level %d: %d nodes, %d chunks, %d multi-chunk\n", depth,
-                         na, nc, nb);
+        if (trace_levels) {
+            // (the trace waits for the level: its filter counters are copied
+            // back and the level's share printed)
+            std::vector<unsigned long long> ts(7 * kStatWords, 0ull);
+            unsigned long long f = 0, e = 0;
+            if (hipMemcpyAsync(ts.data(), dstats, sizeof(unsigned long long) * ts.size(),
+                               hipMemcpyDeviceToHost, s) == hipSuccess &&
+                hipStreamSynchronize(s) == hipSuccess) {
+                f = stat_total(ts.data() + 5 * kStatWords);
+                e = stat_total(ts.data() + 6 * kStatWords);
+            }
+            std::fprintf(stderr,
+                         "[knng] level %d: %d nodes, %d chunks, %d multi-chunk; filtered rows %llu, "
+                         "in the band or changed %llu (%.2f%%)\n",
+                         depth, na, nc, nb, f - trace_f0, e - trace_e0,
+                         f > trace_f0 ? 100.0 * static_cast<double>(e - trace_e0) / static_cast<double>(f - trace_f0) : 0.0);
+            trace_f0 = f;
+            trace_e0 = e;
+        }
         k_next_level<<<1, 1024, 0, s>>>(nodes[cur], na, n0f, L, small_max, depth, nodes[cur ^ 1],
                                         big[cur ^ 1], sub, a.leaves, a.leaves_cap, a.node_log,
                                         a.node_log_cap, ctr, overflow, dmirror, depth);
