@@ -264,13 +264,13 @@ def run_workload(args, name, steps, warmup, headline):
     # the subtree kernels (rows held in LDS); kernel times from the last timed
     # step, the one with per-launch events.
     # Filtered passes (FP32 rows with a reduced leaf copy) read each row's
-    # reduced copy (D elements and its 4-byte scale) and the FP32 values of
+    # reduced copy (D elements, its 4-byte scale and 4-byte error norm) and the FP32 values of
     # the rows the filter leaves undecided or that changed side.
     elem_bytes = 1.0 if u8 else 4.0  # uint8 copy or FP32 rows
     red_bytes = {"bf16": 2.0, "fp16": 2.0, "fp8": 1.0}.get(prec, 0.0)
     level_rows = st["assign_rows"] - st["subtree_rows"]
     f_rows, fx_rows = st.get("filter_rows", 0), st.get("filter_exact_rows", 0)
-    a_bytes = ((level_rows - f_rows) * D * elem_bytes + f_rows * (D * red_bytes + 4.0)
+    a_bytes = ((level_rows - f_rows) * D * elem_bytes + f_rows * (D * red_bytes + 8.0)
                + fx_rows * D * 4.0)
     a_ms, a_launches = st["ms_k_assign"], st["n_k_assign"]
     achieved = a_bytes / (a_ms / 1e3) / 1e9
@@ -282,7 +282,7 @@ def run_workload(args, name, steps, warmup, headline):
         "bytes_per_launch": a_bytes / a_launches, "avg_launch_ms": a_ms / a_launches,
         "algorithmic_bytes": ("rows streamed by the level kernels x D x %d B" % elem_bytes
                               if not f_rows else
-                              "unfiltered rows x D x 4 B + filtered rows x (D x %d B + 4 B) + "
+                              "unfiltered rows x D x 4 B + filtered rows x (D x %d B + 8 B: 1/sigma and e) + "
                               "rows read as FP32 by filtered passes x D x 4 B" % red_bytes),
         "row_storage": ("uint8 (lossless: integer data)" if u8 else
                         "fp32, %s filter copy" % prec if f_rows else "fp32"),

@@ -35,7 +35,15 @@
 //     |dt - sigma x.w| <= (2^-p + 2 gam + 2^-22)(1 + 2 gam) pp + a |w|_1,
 // so B = 1/sigma times that, plus 2^-40 (2 pp / sigma + |h|) for the FP64
 // code's own error (far smaller) and a tiny absolute term for FP32
-// underflow.  A non-finite dt or pp never decides a row.
+// underflow.  The rounding term 2^-p pp + a |w|_1 is the worst case over the
+// row; the copy also stores e >= |sigma x - x~|_2 (computed exactly and
+// rounded up), and by Cauchy-Schwarz the same sum is at most e |w32|_2, so
+//     |dt - sigma x.w| <= e |w32|_2 + (2 gam + 2^-22)(1 + 2 gam) pp + a |w|_1
+// holds too (the terms for the FP32 sum and for w32 are those above); for an
+// FP8 copy the filter takes the smaller of the two (for FP16 and BF16 the
+// first is already tight and the second's arithmetic costs more than it
+// saves).  A non-finite dt, pp or e never decides a row through the bound it
+// enters.
 #include "knng_internal.hpp"
 #include "partition_dev.hpp"
 #include "wave.hpp"
@@ -578,7 +586,7 @@ __global__ __launch_bounds__(256) void k_assign_rf(
     // w in FP32 in the filter layout, |w|_1 in FP64, and h (in the FP64
     // code's layout and order; its w is taken again after phase A)
     float wf[NFF][EV];
-    double w1 = 0.0;
+    double w1 = 0.0, w2 = 0.0;  // |w|_1; then |w32|_2 (squares exact in FP64)
 #pragma unroll
     for (int j = 0; j < NFF; ++j)
 #pragma unroll
@@ -587,9 +595,15 @@ __global__ __launch_bounds__(256) void k_assign_rf(
             const double we = e < D ? cn[e] - cn[D + e] : 0.0;
             wf[j][t] = static_cast<float>(we);
             w1 += fabs(we);
+            if constexpr (FMT == kRfFP8) w2 += static_cast<double>(wf[j][t]) * static_cast<double>(wf[j][t]);
         }
 #pragma unroll
-    for (int o = GF / 2; o >= 1; o >>= 1) w1 += shfl_xor_f64(w1, o);
+    for (int o = GF / 2; o >= 1; o >>= 1) {
+        w1 += shfl_xor_f64(w1, o);
+        if constexpr (FMT == kRfFP8) w2 += shfl_xor_f64(w2, o);
+    }
+    // |w32|_2 rounded up, with the slack for the FP64 product e |w32|_2 / sigma
+    w2 = sqrt(w2 * (1.0 + 0x1p-40)) * (1.0 + 0x1p-30);
     double h;
     {
         double w[NF][4];
@@ -597,6 +611,7 @@ __global__ __launch_bounds__(256) void k_assign_rf(
     }
     const double gam = (D + 8) * 0x1p-24;
     const double relb = (kP + 2.0 * gam + 0x1p-22) * (1.0 + 2.0 * gam);
+    const double rel2 = (2.0 * gam + 0x1p-22) * (1.0 + 2.0 * gam);
     const double subw = kSub * w1 * (1.0 + 0x1p-40) + 0x1p-100;
     const double hab = fabs(h);
     wave_lds_sync();
@@ -604,7 +619,7 @@ __global__ __launch_bounds__(256) void k_assign_rf(
     // ---- phase A: the filter
     int nfilt = 0, nfchg = 0;
     const int steps = (np + RPWF * UF - 1) / (RPWF * UF);
-    auto issue = [&](int st, uint4 (&x)[UF][NFF], float (&si)[UF]) {
+    auto issue = [&](int st, uint4 (&x)[UF][NFF], float (&si)[UF], float (&ei)[UF]) {
 #pragma unroll
         for (int u = 0; u < UF; ++u) {
             const int i = (st * UF + u) * RPWF + gf;
@@ -616,10 +631,19 @@ __global__ __launch_bounds__(256) void k_assign_rf(
                 x[u][j] = (ok && v * EV < D) ? *reinterpret_cast<const uint4*>(xr + 16 * v)
                                              : make_uint4(0u, 0u, 0u, 0u);
             }
-            si[u] = ok ? *reinterpret_cast<const float*>(xr + soff) : 0.f;
+            if constexpr (FMT == kRfFP8) {
+                // 1/sigma and e in one load (soff = Dp bytes, a multiple of 32)
+                const float2 se = ok ? *reinterpret_cast<const float2*>(xr + soff) : make_float2(0.f, 0.f);
+                si[u] = se.x;
+                ei[u] = se.y;
+            } else {
+                si[u] = ok ? *reinterpret_cast<const float*>(xr + soff) : 0.f;
+                ei[u] = 0.f;
+            }
         }
     };
-    auto decide = [&](int st, const uint4 (&x)[UF][NFF], const float (&si)[UF]) {
+    auto decide = [&](int st, const uint4 (&x)[UF][NFF], const float (&si)[UF],
+                      const float (&ei)[UF]) {
 #pragma unroll
         for (int u = 0; u < UF; ++u) {
             const int i = (st * UF + u) * RPWF + gf;
@@ -639,13 +663,19 @@ __global__ __launch_bounds__(256) void k_assign_rf(
                 dt += __shfl_xor(dt, o, kWave);
                 pp += __shfl_xor(pp, o, kWave);
             }
-            // sigma-scaled error bound relb pp + a |w|_1, in row units (times
-            // 1/sigma), and the FP64 code's own error; a non-finite dt or pp
-            // leaves the row in the band
+            // sigma-scaled error bound relb pp (FP8: the smaller of that and
+            // e |w32|_2 + rel2 pp) + a |w|_1, in row units (times 1/sigma),
+            // and the FP64 code's own error; a non-finite dt or pp leaves the
+            // row in the band, a non-finite e keeps the first bound
             const double s = static_cast<double>(si[u]);
             const double m = static_cast<double>(dt) * s - h;
             const double pb = static_cast<double>(pp) * s;
-            const double bnd = relb * pb + subw * s + 0x1p-40 * (2.0 * pb + hab);
+            double eb = relb * pb;
+            if constexpr (FMT == kRfFP8) {
+                const double b2 = static_cast<double>(ei[u]) * s * w2 + rel2 * pb;
+                eb = b2 < eb ? b2 : eb;
+            }
+            const double bnd = eb + subw * s + 0x1p-40 * (2.0 * pb + hab);
             if (i < np && lf == 0) {
                 const int old = flag[i] >> 3;
                 if (m < -bnd || m > bnd) {
@@ -661,14 +691,14 @@ __global__ __launch_bounds__(256) void k_assign_rf(
     };
     {
         uint4 xb[NB][UF][NFF];
-        float sb[NB][UF];
+        float sb[NB][UF], eb[NB][UF];
 #pragma unroll
-        for (int b = 0; b < PF; ++b) issue(b, xb[b], sb[b]);
+        for (int b = 0; b < PF; ++b) issue(b, xb[b], sb[b], eb[b]);
         for (int st0 = 0; st0 < steps; st0 += NB) {
 #pragma unroll
             for (int k = 0; k < NB; ++k) {
-                issue(st0 + k + PF, xb[(k + PF) % NB], sb[(k + PF) % NB]);
-                decide(st0 + k, xb[k], sb[k]);
+                issue(st0 + k + PF, xb[(k + PF) % NB], sb[(k + PF) % NB], eb[(k + PF) % NB]);
+                decide(st0 + k, xb[k], sb[k], eb[k]);
             }
         }
     }

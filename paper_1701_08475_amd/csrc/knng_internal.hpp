@@ -312,13 +312,19 @@ struct ReducedRows {
     float* sinv;   // [n] 1/sigma (power of two)
     int Dp;        // D rounded up to 32
     bool exact;    // first pass exact (d~ == d32): skip the re-rank
-    int stride;    // bytes per row: Dp elements and the FP32 word 1/sigma, rounded up
-                   // to whole 128-byte lines, so a gathered row takes whole cache lines
+    int stride;    // bytes per row: Dp elements, the FP32 words 1/sigma and e (below),
+                   // rounded up to whole 128-byte lines, so a gathered row takes whole
+                   // cache lines
 };
 // byte offset of a reduced row's 1/sigma word: just past its Dp elements (one
 // byte each for FP8-e4m3, precision 3; two for BF16 and FP16)
 __host__ __device__ constexpr int reduced_rows_scale_offset(int precision, int Dp) {
     return Dp * (precision == 3 ? 1 : 2);
+}
+// byte offset of the FP32 word e that follows 1/sigma: an upper bound of the
+// row's rounding error |sigma x - x~|_2 (Euclidean norm over the row)
+__host__ __device__ constexpr int reduced_rows_err_offset(int precision, int Dp) {
+    return reduced_rows_scale_offset(precision, Dp) + 4;
 }
 int reduced_rows_dp(int D);
 int reduced_rows_stride(int precision, int D);

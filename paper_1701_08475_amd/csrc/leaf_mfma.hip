@@ -45,8 +45,12 @@ __global__ __launch_bounds__(256) void k_prep_reduced(const float* __restrict__ 
     }
     const float isg = 1.f / sig;  // exact: sig is a power of two
     float s = 0.f;
+    // e2: sum of (sigma x_i - x~_i)^2 in FP64; sigma x_i is exact in FP64 (a
+    // power-of-two scaling), each difference is exact (both lie on the grid
+    // of sigma x_i's last place, within two of its binades), so are the squares
+    double e2 = 0.0;
     const int Ds = rsb / (FMT == kFP8 ? 1 : 2);  // elements per row in memory (zeros past Dp)
-    const int Sw = Dp + (FMT == kFP8 ? 4 : 2);     // elements Dp .. Sw-1 hold 1/sigma
+    const int Sw = Dp + (FMT == kFP8 ? 8 : 4);     // elements Dp .. Sw-1 hold 1/sigma and e
     if constexpr (FMT == kFP8) {
         uint8_t* o = Xr + row * rsb;
         for (int d0 = 2 * lane; d0 < Ds; d0 += 2 * kWave) {
@@ -57,8 +61,13 @@ __global__ __launch_bounds__(256) void k_prep_reduced(const float* __restrict__ 
             o[d0] = static_cast<uint8_t>(pk & 255u);
             o[d0 + 1] = static_cast<uint8_t>((pk >> 8) & 255u);
             // dequantised values, to the same FP32 the MFMA multiplies
-            const float da = __builtin_amdgcn_cvt_f32_fp8(static_cast<int>(pk), 0) * isg;
-            const float db = __builtin_amdgcn_cvt_f32_fp8(static_cast<int>(pk), 1) * isg;
+            const float qa = __builtin_amdgcn_cvt_f32_fp8(static_cast<int>(pk), 0);
+            const float qb = __builtin_amdgcn_cvt_f32_fp8(static_cast<int>(pk), 1);
+            const double ea = (d0 < D ? static_cast<double>(x[d0]) * sig : 0.0) - qa;
+            const double eb = (d0 + 1 < D ? static_cast<double>(x[d0 + 1]) * sig : 0.0) - qb;
+            e2 += ea * ea + eb * eb;
+            const float da = qa * isg;
+            const float db = qb * isg;
             s = __fmaf_rn(da, da, s);
             s = __fmaf_rn(db, db, s);
         }
@@ -67,25 +76,37 @@ __global__ __launch_bounds__(256) void k_prep_reduced(const float* __restrict__ 
         for (int d = lane; d < Ds; d += kWave) {
             if (d >= Dp && d < Sw) continue;
             const float v = d < D ? x[d] * sig : 0.f;
-            float dq;
+            float q;
             if constexpr (FMT == kBF16) {
                 const uint16_t h = to_bf16_rne(v);
                 o[d] = h;
-                dq = bf16_to_f(h) * isg;
+                q = bf16_to_f(h);
             } else {
                 const _Float16 h = static_cast<_Float16>(v);
                 o[d] = __builtin_bit_cast(uint16_t, h);
-                dq = static_cast<float>(h) * isg;
+                q = static_cast<float>(h);
             }
+            const double e = (d < D ? static_cast<double>(x[d]) * sig : 0.0) - q;
+            e2 += e * e;
+            const float dq = q * isg;
             s = __fmaf_rn(dq, dq, s);
         }
     }
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, kWave);
+    for (int o = 32; o >= 1; o >>= 1) {
+        s += __shfl_xor(s, o, kWave);
+        e2 += shfl_xor_f64(e2, o);
+    }
     if (lane == 0) {
         nrm[row] = s;
         sinv[row] = isg;
         *reinterpret_cast<float*>(Xr + row * rsb + reduced_rows_scale_offset(FMT, Dp)) = isg;
+        // e: |sigma x - x~|_2 rounded up to FP32 (the FP64 sum of at most 2^11
+        // exact squares is within 2^-42 of the true one)
+        const double ed = sqrt(e2 * (1.0 + 0x1p-40));
+        float ef = static_cast<float>(ed);
+        if (static_cast<double>(ef) < ed) ef = nextafterf(ef, __int_as_float(0x7f800000));
+        *reinterpret_cast<float*>(Xr + row * rsb + reduced_rows_err_offset(FMT, Dp)) = ef;
     }
 }
 
@@ -94,7 +115,7 @@ __global__ __launch_bounds__(256) void k_prep_reduced(const float* __restrict__ 
 int reduced_rows_dp(int D) { return (D + 31) / 32 * 32; }
 
 int reduced_rows_stride(int precision, int D) {
-    return (reduced_rows_scale_offset(precision, reduced_rows_dp(D)) + 4 + 127) / 128 * 128;
+    return (reduced_rows_err_offset(precision, reduced_rows_dp(D)) + 4 + 127) / 128 * 128;
 }
 
 size_t reduced_rows_bytes(int precision, int64_t n, int D) {
