@@ -79,8 +79,9 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libknng.so is not built (run __graft_entry__.build() or "
                            "python -m paper_1701_08475_amd.build_lib)")
-    # torch's HIP runtime is brought up first (where a GPU is present): loaded
-    # before it, the library's HIP calls found no device on the GPU machine
+    # torch's HIP runtime is brought up first (where a GPU is present): when
+    # the library was loaded before it, its HIP calls found no device (the
+    # process then holds two HIP runtimes and the library's saw none)
     try:
         import torch
         torch.cuda.is_available()
