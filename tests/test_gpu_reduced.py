@@ -244,6 +244,7 @@ def test_wide_leaf_kernel_equals_panel_kernel(K, orc, precision, n, D, k, L, rer
     ("fp16", 40_000, 960, 20, 2, 200, "unit"),   # C4-shaped rows, FP16 copy
     ("bf16", 50_000, 64, 16, 2, 150, "c1"),      # BF16 copy of GMM rows
     ("fp8", 30_000, 36, 10, 2, 60, "c1"),        # D % 8 == 4, wide value range
+    ("fp8", 60_000, 64, 16, 2, 120, "offset"),   # a large common offset: the per-row bound decides
 ])
 def test_partition_filter_changes_nothing(K, orc, precision, n, D, k, T, L, kind, monkeypatch):
     """FP32 rows with a reduced copy: the partition's later passes label rows
@@ -253,10 +254,14 @@ def test_partition_filter_changes_nothing(K, orc, precision, n, D, k, T, L, kind
     oracle's tree."""
     if kind == "c1":
         X = datagen.gmm_uniform(n, D, 40, -10, 10, 1.0, 41)
+    elif kind == "offset":
+        # every row near (4, ..., 4): margins are small against |x||w|, as in
+        # the deep levels of unit-norm data
+        X = datagen.gmm_uniform(n, D, 40, 3, 5, 0.3, 43)
     else:
         X = datagen.gmm_unit(n, D, 64, 0.35, 42)
     Xd = to_dev(X)
-    log("partition filter %s n=%d D=%d" % (precision, n, D))
+    log("partition filter %s n=%d D=%d %s" % (precision, n, D, kind))
     monkeypatch.setenv("KNNG_PARTITION_FILTER", "1")
     a = K.build(Xd, k, T, L, seed=3, precision=precision, stats=True)
     monkeypatch.setenv("KNNG_PARTITION_FILTER", "0")
