@@ -696,6 +696,21 @@ __device__ __forceinline__ void group_select(const uint32_t (&kv)[KT], int tmax,
     }
 }
 
+// exchange with lane ^ lm inside a 16-lane row: DPP for 1, 2 and 8 (quad
+// permutes; a rotation by 8 within the row), ds_bpermute for 4
+__device__ __forceinline__ uint32_t xchg16(uint32_t v, int lm) {
+    switch (lm) {
+        case 1: return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0xB1, 0xf, 0xf, false));
+        case 2: return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x4E, 0xf, 0xf, false));
+        case 8: return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x128, 0xf, 0xf, false));
+        default: return static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), lm, kWave));
+    }
+}
+__device__ __forceinline__ uint64_t xchg16_u64(uint64_t v, int lm) {
+    const uint32_t lo = xchg16(static_cast<uint32_t>(v), lm), hi = xchg16(static_cast<uint32_t>(v >> 32), lm);
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
 // Ascending bitonic sort of NR independent rows of 64 keys per 16-lane group,
 // four keys per lane: element e of a row is lane (e >> 2) of the group,
 // register e & 3.  Distances 1 and 2 stay in registers; the others exchange
@@ -714,7 +729,7 @@ __device__ __forceinline__ void group_sort64(uint64_t (&v)[NR][4]) {
 #pragma unroll
                 for (int q = 0; q < NR; ++q)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) o[q][r] = shfl_xor_u64(v[q][r], lm);
+                    for (int r = 0; r < 4; ++r) o[q][r] = xchg16_u64(v[q][r], lm);
                 const bool lower = (gl & lm) == 0;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
