@@ -474,12 +474,24 @@ __device__ __forceinline__ uint32_t group16_max(uint32_t v) {
     return v;
 }
 
-// Exclusive prefix sum over the 16 lanes of each aligned group.
+// Value of lane gl - o of the lane's aligned 16-lane group (o = 1, 2, 4, 8;
+// lanes gl < o get 0): a DPP row shift, no LDS instruction.
+__device__ __forceinline__ int group16_up(int v, int o) {
+    switch (o) {
+        case 1: return __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);
+        case 2: return __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);
+        case 4: return __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);
+        default: return __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);
+    }
+}
+
+// Exclusive prefix sum over the 16 lanes of each aligned group (every lane
+// of the wavefront active).
 __device__ __forceinline__ int group16_excl_scan(int v, int gl) {
     int incl = v;
 #pragma unroll
     for (int o = 1; o < 16; o <<= 1) {
-        const int y = __shfl_up(incl, o, 16);
+        const int y = group16_up(incl, o);
         if (gl >= o) incl += y;
     }
     return incl - v;
@@ -567,7 +579,7 @@ __device__ __forceinline__ void group_select(const uint32_t (&kv)[KT], int tmax,
         int incl = local;
 #pragma unroll
         for (int o = 1; o < 16; o <<= 1) {
-            const int y = __shfl_up(incl, o, 16);
+            const int y = group16_up(incl, o);
             if (gl >= o) incl += y;
         }
         const int excl = incl - local;
