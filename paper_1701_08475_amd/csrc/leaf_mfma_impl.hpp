@@ -708,14 +708,19 @@ __device__ __forceinline__ void group_select(const uint32_t (&kv)[KT], int tmax,
     }
 }
 
-// exchange with lane ^ lm inside a 16-lane row: DPP for 1, 2 and 8 (quad
-// permutes; a rotation by 8 within the row), ds_bpermute for 4
+// exchange with lane ^ lm inside a 16-lane row, by DPP: quad permutes for 1
+// and 2, a rotation by 8 within the row for 8, and for 4 the rotation by 4
+// (lanes with bit 2 set) or by 12 (the others)
 __device__ __forceinline__ uint32_t xchg16(uint32_t v, int lm) {
     switch (lm) {
         case 1: return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0xB1, 0xf, 0xf, false));
         case 2: return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x4E, 0xf, 0xf, false));
         case 8: return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x128, 0xf, 0xf, false));
-        default: return static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), lm, kWave));
+        default: {
+            const uint32_t a = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x124, 0xf, 0xf, false));
+            const uint32_t b = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x12C, 0xf, 0xf, false));
+            return (threadIdx.x & 4) ? a : b;
+        }
     }
 }
 __device__ __forceinline__ uint64_t xchg16_u64(uint64_t v, int lm) {
