@@ -50,6 +50,13 @@
 
 namespace knng {
 namespace {
+
+// DPP permute of an FP32 value within each 16-lane row (CTRL: a row mirror
+// 0x140, half-row mirror 0x141 or a quad permute); every lane active.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
 using namespace pdev;
 
 // reduced-copy formats (the leaf search's: 1 BF16, 2 FP16, 3 FP8-e4m3)
@@ -658,10 +665,33 @@ __global__ __launch_bounds__(256) void k_assign_rf(
                     pp = __fmaf_rn(pow2_floor(v[t]), fabsf(wf[j][t]), pp);
                 }
             }
+            if constexpr (GF <= 16) {
+                // sums over the GF-lane group by DPP (every lane active):
+                // mirrors within the 16-lane row and its halves, then the
+                // quad permutes; each lane ends with the group's sum (in an
+                // order the bound's gam covers, like any other)
+                if constexpr (GF == 16) {
+                    dt += dpp_f32<0x140>(dt);
+                    pp += dpp_f32<0x140>(pp);
+                }
+                if constexpr (GF >= 8) {
+                    dt += dpp_f32<0x141>(dt);
+                    pp += dpp_f32<0x141>(pp);
+                }
+                if constexpr (GF >= 4) {
+                    dt += dpp_f32<0x4E>(dt);
+                    pp += dpp_f32<0x4E>(pp);
+                }
+                if constexpr (GF >= 2) {
+                    dt += dpp_f32<0xB1>(dt);
+                    pp += dpp_f32<0xB1>(pp);
+                }
+            } else {
 #pragma unroll
-            for (int o = GF / 2; o >= 1; o >>= 1) {
-                dt += __shfl_xor(dt, o, kWave);
-                pp += __shfl_xor(pp, o, kWave);
+                for (int o = GF / 2; o >= 1; o >>= 1) {
+                    dt += __shfl_xor(dt, o, kWave);
+                    pp += __shfl_xor(pp, o, kWave);
+                }
             }
             // sigma-scaled error bound relb pp (FP8: the smaller of that and
             // e |w32|_2 + rel2 pp) + a |w|_1, in row units (times 1/sigma),
