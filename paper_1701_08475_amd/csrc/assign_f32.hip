@@ -86,16 +86,14 @@ __device__ __forceinline__ double centres_wh(const double* cn, int D, int l, dou
             q0 = fma(c0, c0, q0);
             q1 = fma(c1, c1, q1);
         }
-#pragma unroll
-    for (int o = G / 2; o >= 1; o >>= 1) {
-        q0 += shfl_xor_f64(q0, o);
-        q1 += shfl_xor_f64(q1, o);
-    }
+    q0 = group_sum_f64<G>(q0);
+    q1 = group_sum_f64<G>(q1);
     return 0.5 * (q0 - q1);
 }
 
 // The FP64 margin dot of one row: the lane's fused chain, then the group's
-// butterfly.
+// sum (group_sum_f64: DPP within 16-lane rows, the same bits in every lane;
+// every kernel that compares margins takes them from here).
 template <int G, int NF>
 __device__ __forceinline__ double row_dot(const float (&x)[NF][4], const double (&w)[NF][4]) {
     double dot = 0.0;
@@ -103,9 +101,7 @@ __device__ __forceinline__ double row_dot(const float (&x)[NF][4], const double 
     for (int j = 0; j < NF; ++j)
 #pragma unroll
         for (int v = 0; v < 4; ++v) dot = fma(static_cast<double>(x[j][v]), w[j][v], dot);
-#pragma unroll
-    for (int o = G / 2; o >= 1; o >>= 1) dot += shfl_xor_f64(dot, o);
-    return dot;
+    return group_sum_f64<G>(dot);
 }
 
 // Per-wave LDS of the later passes: one flag byte per row of the chunk (bit 0

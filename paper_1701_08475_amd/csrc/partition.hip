@@ -228,11 +228,8 @@ __global__ __launch_bounds__(256) void k_assign(
             a0[j][v] = Acc(0);
             a1[j][v] = Acc(0);
         }
-#pragma unroll
-    for (int o = G / 2; o >= 1; o >>= 1) {
-        q0 += shfl_xor_f64(q0, o);
-        q1 += shfl_xor_f64(q1, o);
-    }
+    q0 = group_sum_f64<G>(q0);
+    q1 = group_sum_f64<G>(q1);
     const double h = 0.5 * (q0 - q1);
     int n1 = 0, changed = 0;
 
@@ -283,8 +280,7 @@ __global__ __launch_bounds__(256) void k_assign(
 #pragma unroll
                 for (int v = 0; v < VEC; ++v)
                     dot = fma(static_cast<double>(xc[u][j][v]), w[j][v], dot);
-#pragma unroll
-            for (int o = G / 2; o >= 1; o >>= 1) dot += shfl_xor_f64(dot, o);
+            dot = group_sum_f64<G>(dot);  // (the FP32-row kernels' order)
             const bool lab = dot < h;
             if (idc[u] >= 0) {
                 if (l == 0) {
