@@ -661,33 +661,34 @@ __global__ __launch_bounds__(256) void k_assign_rf(
                     pp = __fmaf_rn(pow2_floor(v[t]), fabsf(wf[j][t]), pp);
                 }
             }
-            if constexpr (GF <= 16) {
-                // sums over the GF-lane group by DPP (every lane active):
-                // mirrors within the 16-lane row and its halves, then the
-                // quad permutes; each lane ends with the group's sum (in an
-                // order the bound's gam covers, like any other)
-                if constexpr (GF == 16) {
-                    dt += dpp_f32<0x140>(dt);
-                    pp += dpp_f32<0x140>(pp);
-                }
-                if constexpr (GF >= 8) {
-                    dt += dpp_f32<0x141>(dt);
-                    pp += dpp_f32<0x141>(pp);
-                }
-                if constexpr (GF >= 4) {
-                    dt += dpp_f32<0x4E>(dt);
-                    pp += dpp_f32<0x4E>(pp);
-                }
-                if constexpr (GF >= 2) {
-                    dt += dpp_f32<0xB1>(dt);
-                    pp += dpp_f32<0xB1>(pp);
-                }
-            } else {
-#pragma unroll
-                for (int o = GF / 2; o >= 1; o >>= 1) {
-                    dt += __shfl_xor(dt, o, kWave);
-                    pp += __shfl_xor(pp, o, kWave);
-                }
+            // sums over the GF-lane group (every lane active): quad permutes
+            // and the half-row and row mirrors by DPP, then lane xor 16 and
+            // xor 32 through ds_bpermute for wider groups; each lane ends
+            // with the group's sum, in an order the bound's gam covers like
+            // any other
+            if constexpr (GF >= 2) {
+                dt += dpp_f32<0xB1>(dt);
+                pp += dpp_f32<0xB1>(pp);
+            }
+            if constexpr (GF >= 4) {
+                dt += dpp_f32<0x4E>(dt);
+                pp += dpp_f32<0x4E>(pp);
+            }
+            if constexpr (GF >= 8) {
+                dt += dpp_f32<0x141>(dt);
+                pp += dpp_f32<0x141>(pp);
+            }
+            if constexpr (GF >= 16) {
+                dt += dpp_f32<0x140>(dt);
+                pp += dpp_f32<0x140>(pp);
+            }
+            if constexpr (GF >= 32) {
+                dt += __shfl_xor(dt, 16, kWave);
+                pp += __shfl_xor(pp, 16, kWave);
+            }
+            if constexpr (GF >= 64) {
+                dt += __shfl_xor(dt, 32, kWave);
+                pp += __shfl_xor(pp, 32, kWave);
             }
             // sigma-scaled error bound relb pp (FP8: the smaller of that and
             // e |w32|_2 + rel2 pp) + a |w|_1, in row units (times 1/sigma),
